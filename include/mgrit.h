@@ -1,0 +1,173 @@
+/*
+ * mgrit.h -- C ABI of the MI355X (gfx950) library for multigrid reduction in
+ * time (MGRIT) applied to method-of-lines discretizations of periodic linear
+ * advection, following De Sterck, Falgout, Krzysik and Schroder,
+ * "Efficient multigrid reduction-in-time for method-of-lines discretizations
+ * of linear advection" (arXiv 2209.06916).
+ *
+ * Problem (Sec. 2.1, eq. ad):  u_t + alpha u_x = 0 on the periodic interval
+ * [x_lo, x_hi), u(x,0) = u0(x).  Mesh x_i = x_lo + i h, i = 0..nx-1,
+ * h = (x_hi - x_lo)/nx; time points t_n = n dt, n = 0..nt, dt = cfl*h/alpha.
+ * Fine time-stepper (Sec. 4.3, eq. MOL_M_def): one Runge-Kutta step (ERKq or
+ * SDIRKq) of the p-th order upwind semi-discretisation (Sec. 4.1), giving the
+ * one-step system u_{n+1} = Phi u_n (eq. one-step-general).
+ * Coarse time-steppers (Sec. 6.1-6.2, eqs. MOL-SL-corrected and
+ * MOL-SL-corrected-multilevel): a semi-Lagrangian step followed by one
+ * implicit periodic banded solve with I - phi_l D^(p+1).
+ * Solver (Sec. 2.2): linear MGRIT, two-level or V-cycle, F(CF)^nu relaxation.
+ *
+ * Conventions for every entry point:
+ *  - Every array is float64, row-major, time-major: row n of a space-time
+ *    array [nt+1][nx] is time point t_n, contiguous in space.
+ *  - Pointers named *_dev are device (HBM) pointers, owned by the caller and
+ *    valid for the duration of the call; the library never frees them.
+ *  - Work is queued on the HIP stream given to mgrit_setup (NULL = the
+ *    default stream).  Calls that return host-visible results (stats, norms)
+ *    synchronise that stream before returning.
+ *  - A handle may be used by one host thread at a time.
+ *  - Errors: a negative mgrit_status; mgrit_last_error(handle) describes the
+ *    most recent failure on that handle.  Device-side failures are reported as
+ *    MGRIT_EDEVICE with the HIP error string.
+ */
+#ifndef MGRIT_H
+#define MGRIT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MGRIT_MAX_LEVELS 16
+#define MGRIT_MAX_NX 16384 /* one spatial slab per workgroup, kept in LDS */
+
+typedef enum {
+  MGRIT_OK = 0,
+  MGRIT_ENOTCONVERGED = 1, /* max_iter reached; stats and outputs valid       */
+  MGRIT_EINVAL = -1,       /* invalid argument or unsupported combination     */
+  MGRIT_EUNSTABLE = -2,    /* explicit scheme above its CFL limit (Table 2)   */
+  MGRIT_ENOMEM = -3,       /* device allocation failed                        */
+  MGRIT_EDEVICE = -4,      /* HIP runtime error                               */
+  MGRIT_EDIVERGED = -5     /* non-finite residual or growth past the limit    */
+} mgrit_status;
+
+typedef enum { MGRIT_ERK = 0, MGRIT_SDIRK = 1 } mgrit_rk_kind;
+
+typedef enum {
+  /* Psi_l = (I - phi_l D^(p+1))^{-1} S_p^(Delta_l), eq. MOL-SL-corrected-multilevel */
+  MGRIT_CG_SL_CORRECTED = 0,
+  /* Psi = Phi^m, the ideal coarse operator (Sec. 2.2); two levels only        */
+  MGRIT_CG_IDEAL = 1,
+  /* Psi_l = S_p^(Delta_l) with phi = 0 (uncorrected semi-Lagrangian)          */
+  MGRIT_CG_SL_PLAIN = 2
+} mgrit_cg_kind;
+
+/* The paper's problem statement (Sec. 2.1, 4.1-4.3). */
+typedef struct {
+  double velocity;      /* alpha > 0                                          */
+  double x_lo, x_hi;    /* periodic domain [x_lo, x_hi), x_hi > x_lo          */
+  int64_t nx;           /* spatial points, 1 <= nx <= MGRIT_MAX_NX            */
+  int64_t nt;           /* fine time steps; nt+1 time points                  */
+  double cfl;           /* c = alpha dt / h > 0                               */
+  int32_t upwind_order; /* p in 1..5; the SL coarse operators need odd p      */
+  int32_t rk_kind;      /* mgrit_rk_kind                                      */
+  int32_t rk_order;     /* q: ERK 1..5, SDIRK 1..3                            */
+} mgrit_problem;
+
+/* MGRIT parameters (Sec. 2.2, 6.3). */
+typedef struct {
+  int32_t max_levels;    /* 2 = two-level; more = V-cycle (<= MGRIT_MAX_LEVELS) */
+  int32_t m[MGRIT_MAX_LEVELS - 1]; /* m[l] coarsens level l to l+1; a zero entry
+                                      repeats the previous factor; m[0] >= 2   */
+  int32_t min_coarse_nt; /* stop coarsening once nt_l <= min_coarse_nt       */
+  int32_t nu;            /* CF sweeps after the first F: 0 = F, 1 = FCF      */
+  int32_t cg_kind;       /* mgrit_cg_kind                                     */
+  double rtol;           /* stop when ||r_it|| <= rtol ||r_0|| (e.g. 1e-10)   */
+  int32_t max_iter;      /* upper bound on coarse-grid corrections           */
+  double diverge_factor; /* ||r_it|| > diverge_factor ||r_0|| => EDIVERGED;
+                            <= 0 disables the check                          */
+} mgrit_options;
+
+typedef struct {
+  int32_t iterations;   /* coarse-grid corrections performed                 */
+  double res0;          /* ||r_0||: 2-norm over all C-points, first residual */
+  double res_final;     /* ||r|| at the stop                                 */
+  double conv_factor;   /* res_final / previous residual (NaN if none)      */
+  double *res_history;  /* caller-owned host array or NULL                   */
+  int32_t res_history_cap;
+  int32_t res_history_len; /* entries written (iterations + 1, capped)       */
+  double t_solve_s;     /* host wall time of the solve call                  */
+} mgrit_stats;
+
+typedef struct {
+  int64_t nt;           /* time steps on this level                          */
+  int32_t m;            /* coarsening factor to the next level (0 = coarsest) */
+  double shift;         /* semi-Lagrangian shift alpha*Delta_l/h (level >= 1) */
+  int64_t K;            /* floor(shift)                                       */
+  double eps;           /* shift - K, in [0,1)  (Sec. 3)                     */
+  double phi_p;         /* coefficient of D^(p+1) in Psi_l                    */
+  double phi_q;         /* coefficient of D^(q+1) (q != p only)               */
+} mgrit_level_desc;
+
+typedef struct mgrit_handle mgrit_handle;
+
+/* Validate the problem and options, build the level hierarchy (nt_0 = nt,
+ * nt_{l+1} = nt_l / m_l), compute the time-stepper coefficients of every
+ * level (eqs. MOL_M_def, varphi-constant-MOL-SL, MOL-SL-corrected-multilevel),
+ * factorise every periodic banded operator that a step solves with, upload
+ * them, and allocate the per-level device workspace (owned by the handle).
+ * Returns MGRIT_EINVAL for nt % m[0] != 0, nx outside 1..MGRIT_MAX_NX, even p
+ * with a semi-Lagrangian coarse operator, or an unsupported (kind, order);
+ * MGRIT_EUNSTABLE for ERK above its CFL limit.  *out is NULL on failure. */
+mgrit_status mgrit_setup(const mgrit_problem *problem, const mgrit_options *options,
+                         void *hip_stream, mgrit_handle **out);
+
+/* Solve the one-step system u_{n+1} = Phi u_n, u_0 = u0 (eq. one-step-general)
+ * with MGRIT.
+ *   u0_dev      [nx], required.
+ *   v_init_dev  [nt+1][nx] initial iterate, or NULL for zero; only its
+ *               C-points (rows k*m[0]) are read, row 0 is replaced by u0.
+ *   u_out_dev   [nt+1][nx] receives the final iterate at every time point,
+ *               or NULL.
+ *   u_final_dev [nx] receives row nt of the final iterate, or NULL.
+ *   stats       optional.
+ * Returns MGRIT_OK on convergence, MGRIT_ENOTCONVERGED at max_iter (outputs
+ * hold the last iterate), MGRIT_EDIVERGED on a non-finite or growing residual. */
+mgrit_status mgrit_solve(mgrit_handle *h, const double *u0_dev, const double *v_init_dev,
+                         double *u_out_dev, double *u_final_dev, mgrit_stats *stats);
+
+/* Space-time residual of an arbitrary iterate u_dev [nt+1][nx] of the fine
+ * system: r_n = Phi u_{n-1} - u_n, n = 1..nt, one fine step per time point,
+ * all in parallel.  r_dev [nt][nx] (row n-1 holds r_n) or NULL;
+ * *norm2_host (optional) receives ||r||_2 over all n and i. */
+mgrit_status mgrit_residual(mgrit_handle *h, const double *u_dev, double *r_dev, double *norm2_host);
+
+/* Sequential time-stepping (eq. one-step-general): u_out_dev [nt+1][nx] with
+ * row 0 = u0 and row n = Phi row n-1.  The baseline MGRIT is compared with. */
+mgrit_status mgrit_sequential(mgrit_handle *h, const double *u0_dev, double *u_out_dev);
+
+/* Apply the level-l time-stepper nsteps times to each of `count` independent
+ * vectors: v_out[b] = Phi_l^nsteps v_in[b]; v_in_dev, v_out_dev [count][nx]
+ * (may alias).  Level 0 is the fine step; level l >= 1 is Psi_l. */
+mgrit_status mgrit_apply_step(mgrit_handle *h, int32_t level, const double *v_in_dev,
+                              double *v_out_dev, int64_t count, int32_t nsteps);
+
+/* Number of levels of the hierarchy built by mgrit_setup (>= 2). */
+int32_t mgrit_num_levels(const mgrit_handle *h);
+
+/* Description of level `level` (0 = fine). */
+mgrit_status mgrit_level_info(const mgrit_handle *h, int32_t level, mgrit_level_desc *out);
+
+/* Host-only: two-level LFA convergence estimate of eq. (rho-asym) for the
+ * problem's fine step and the options' first coarsening factor and coarse
+ * operator, with 2^11 spatial frequencies minus the 11 nearest omega = 0. */
+mgrit_status mgrit_lfa_rho(const mgrit_problem *problem, const mgrit_options *options, double *rho);
+
+const char *mgrit_status_string(mgrit_status s);
+const char *mgrit_last_error(const mgrit_handle *h);
+void mgrit_destroy(mgrit_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGRIT_H */

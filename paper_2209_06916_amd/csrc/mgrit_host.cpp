@@ -1,0 +1,1126 @@
+// Host side of the MGRIT library: problem setup (coefficients, level
+// hierarchy, factorisations of the periodic banded operators), the MGRIT
+// schedule, and the C ABI declared in include/mgrit.h.
+#include "mgrit.h"
+#include "mgrit_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+using namespace mgrit;
+
+namespace {
+
+using ld = long double;
+using cld = std::complex<long double>;
+
+// ---------------------------------------------------------------------------
+// Dense helpers (tiny systems only)
+// ---------------------------------------------------------------------------
+
+// Solve A x = b (n x n, row-major) by Gaussian elimination with partial pivoting.
+bool dense_solve(std::vector<ld> A, std::vector<ld> &b, int n) {
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+    if (A[piv * n + c] == 0) return false;
+    if (piv != c) {
+      for (int k = 0; k < n; ++k) std::swap(A[c * n + k], A[piv * n + k]);
+      std::swap(b[c], b[piv]);
+    }
+    for (int r = c + 1; r < n; ++r) {
+      const ld f = A[r * n + c] / A[c * n + c];
+      for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+      b[r] -= f * b[c];
+    }
+  }
+  for (int c = n - 1; c >= 0; --c) {
+    ld s = b[c];
+    for (int k = c + 1; k < n; ++k) s -= A[c * n + k] * b[k];
+    b[c] = s / A[c * n + c];
+  }
+  return true;
+}
+
+std::vector<ld> matmul(const std::vector<ld> &A, const std::vector<ld> &B, int k) {
+  std::vector<ld> C(k * k, 0);
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      ld s = 0;
+      for (int t = 0; t < k; ++t) s += A[i * k + t] * B[t * k + j];
+      C[i * k + j] = s;
+    }
+  return C;
+}
+
+std::vector<ld> identity(int k) {
+  std::vector<ld> I(k * k, 0);
+  for (int i = 0; i < k; ++i) I[i * k + i] = 1;
+  return I;
+}
+
+bool invert(const std::vector<ld> &A, int k, std::vector<ld> &inv) {
+  inv.assign(k * k, 0);
+  for (int c = 0; c < k; ++c) {
+    std::vector<ld> e(k, 0);
+    e[c] = 1;
+    if (!dense_solve(A, e, k)) return false;
+    for (int r = 0; r < k; ++r) inv[r * k + c] = e[r];
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Upwind stencil L_p (Sec. 4.1): differentiate the degree-p interpolant at
+// x_i.  Weights from the moment conditions sum_j w_j j^k = [k == 1], k = 0..p.
+// ---------------------------------------------------------------------------
+
+void upwind_stencil(int p, int &l, int &r, std::vector<double> &w) {
+  if (p % 2) {
+    l = (p + 1) / 2;
+    r = l - 1;
+  } else {
+    l = p / 2 + 1;
+    r = l - 2;
+  }
+  const int n = p + 1;
+  std::vector<ld> V(n * n), rhs(n, 0);
+  for (int k = 0; k < n; ++k)
+    for (int c = 0; c < n; ++c) {
+      const int j = c - l;
+      ld v = 1;
+      for (int e = 0; e < k; ++e) v *= j;
+      V[k * n + c] = v;
+    }
+  rhs[1] = 1;
+  dense_solve(V, rhs, n);
+  w.assign(n, 0.0);
+  for (int c = 0; c < n; ++c) w[c] = (double)rhs[c];
+}
+
+// ---------------------------------------------------------------------------
+// Runge-Kutta tableaux (Sec. 4.2).  ERK1-4: forward Euler, Heun, the
+// three-stage SSP method, classical RK4 (R = Taylor polynomial of exp).
+// ERK5: six stages, sub-diagonal coupling (3/32, 1/5, 1/4, 1/3, 1/2), b = e_6,
+// so R = T_5 + z^6/1280, matching Table 1's e_RK.  SDIRK1-3: backward Euler;
+// gamma = 1 - 1/sqrt(2); the L-stable three-stage method with
+// 6 g^3 - 18 g^2 + 9 g - 1 = 0.
+// ---------------------------------------------------------------------------
+
+struct Tableau {
+  int s = 0;
+  std::vector<ld> A, b;
+  ld gamma = 0;  // SDIRK diagonal
+};
+
+ld sdirk3_gamma() {
+  ld g = 0.4358665215L;  // Newton on the cubic from a bracketing start
+  for (int i = 0; i < 60; ++i) {
+    const ld f = ((6 * g - 18) * g + 9) * g - 1;
+    const ld df = (18 * g - 36) * g + 9;
+    g -= f / df;
+  }
+  return g;
+}
+
+bool make_tableau(int kind, int q, Tableau &T) {
+  auto set = [&](int s) {
+    T.s = s;
+    T.A.assign(s * s, 0);
+    T.b.assign(s, 0);
+  };
+  if (kind == MGRIT_ERK) {
+    switch (q) {
+      case 1: set(1); T.b[0] = 1; return true;
+      case 2: set(2); T.A[1 * 2 + 0] = 1; T.b[0] = 0.5L; T.b[1] = 0.5L; return true;
+      case 3:
+        set(3);
+        T.A[1 * 3 + 0] = 1;
+        T.A[2 * 3 + 0] = 0.25L;
+        T.A[2 * 3 + 1] = 0.25L;
+        T.b[0] = 1.0L / 6;
+        T.b[1] = 1.0L / 6;
+        T.b[2] = 2.0L / 3;
+        return true;
+      case 4:
+        set(4);
+        T.A[1 * 4 + 0] = 0.5L;
+        T.A[2 * 4 + 1] = 0.5L;
+        T.A[3 * 4 + 2] = 1;
+        T.b[0] = 1.0L / 6;
+        T.b[1] = 1.0L / 3;
+        T.b[2] = 1.0L / 3;
+        T.b[3] = 1.0L / 6;
+        return true;
+      case 5: {
+        set(6);
+        const ld sub[5] = {3.0L / 32, 1.0L / 5, 1.0L / 4, 1.0L / 3, 1.0L / 2};
+        for (int i = 0; i < 5; ++i) T.A[(i + 1) * 6 + i] = sub[i];
+        T.b[5] = 1;
+        return true;
+      }
+      default: return false;
+    }
+  }
+  if (kind == MGRIT_SDIRK) {
+    switch (q) {
+      case 1: set(1); T.A[0] = 1; T.b[0] = 1; T.gamma = 1; return true;
+      case 2: {
+        set(2);
+        const ld g = 1 - 1 / std::sqrt((ld)2);
+        T.A[0] = g;
+        T.A[1 * 2 + 0] = 1 - g;
+        T.A[1 * 2 + 1] = g;
+        T.b[0] = 1 - g;
+        T.b[1] = g;
+        T.gamma = g;
+        return true;
+      }
+      case 3: {
+        set(3);
+        const ld g = sdirk3_gamma();
+        const ld b1 = -(6 * g * g - 16 * g + 1) / 4, b2 = (6 * g * g - 20 * g + 5) / 4;
+        T.A[0] = g;
+        T.A[1 * 3 + 0] = (1 - g) / 2;
+        T.A[1 * 3 + 1] = g;
+        T.A[2 * 3 + 0] = b1;
+        T.A[2 * 3 + 1] = b2;
+        T.A[2 * 3 + 2] = g;
+        T.b[0] = b1;
+        T.b[1] = b2;
+        T.b[2] = g;
+        T.gamma = g;
+        return true;
+      }
+      default: return false;
+    }
+  }
+  return false;
+}
+
+// Taylor coefficients beta_j of R(z) = 1 + z b^T (I - zA)^{-1} 1:
+// beta_0 = 1, beta_j = b^T A^{j-1} 1 (eq. RK_stab_def).
+std::vector<ld> rk_series(const Tableau &T, int jmax) {
+  std::vector<ld> beta(jmax + 1, 0);
+  beta[0] = 1;
+  std::vector<ld> v(T.s, 1);  // A^{j-1} 1
+  for (int j = 1; j <= jmax; ++j) {
+    ld s = 0;
+    for (int i = 0; i < T.s; ++i) s += T.b[i] * v[i];
+    beta[j] = s;
+    std::vector<ld> nv(T.s, 0);
+    for (int i = 0; i < T.s; ++i)
+      for (int k = 0; k < T.s; ++k) nv[i] += T.A[i * T.s + k] * v[k];
+    v = nv;
+  }
+  return beta;
+}
+
+// R(z) for complex z (lower-triangular A: forward substitution).
+std::complex<double> rk_R(const Tableau &T, std::complex<double> z) {
+  std::vector<std::complex<double>> y(T.s);
+  for (int i = 0; i < T.s; ++i) {
+    std::complex<double> s = 1.0;
+    for (int k = 0; k < i; ++k) s += z * (double)T.A[i * T.s + k] * y[k];
+    y[i] = s / (1.0 - z * (double)T.A[i * T.s + i]);
+  }
+  std::complex<double> acc = 0.0;
+  for (int i = 0; i < T.s; ++i) acc += (double)T.b[i] * y[i];
+  return 1.0 + z * acc;
+}
+
+ld factorial(int n) {
+  ld f = 1;
+  for (int i = 2; i <= n; ++i) f *= i;
+  return f;
+}
+
+// ---------------------------------------------------------------------------
+// Semi-Lagrangian interpolation (Sec. 3) and f_{p+1} (eq. fpoly_def), odd p:
+// nodes j = -(p+1)/2 .. (p-1)/2 around the east neighbour of the departure
+// point x_i - shift*h = x_{i-K} - eps*h.
+// ---------------------------------------------------------------------------
+
+void sl_weights(int p, ld eps, int &l, int &r, std::vector<double> &w) {
+  l = (p + 1) / 2;
+  r = (p - 1) / 2;
+  w.assign(l + r + 1, 0.0);
+  const ld x = -eps;
+  for (int j = -l; j <= r; ++j) {
+    ld v = 1;
+    for (int k = -l; k <= r; ++k)
+      if (k != j) v *= (x - k) / (ld)(j - k);
+    w[j + l] = (double)v;
+  }
+}
+
+ld f_poly(int p, ld z) {
+  const int l = (p + 1) / 2, r = (p - 1) / 2;
+  ld v = 1;
+  for (int j = -l; j <= r; ++j) v *= (j + z);
+  return v / factorial(p + 1);
+}
+
+// Symmetric second-order D^(k) for even k: centred k-th difference.
+std::map<int, ld> dmat(int k) {
+  std::map<int, ld> d;
+  ld binom = 1;
+  for (int n = 0; n <= k; ++n) {
+    d[k / 2 - n] = (n % 2 ? -binom : binom);
+    binom = binom * (k - n) / (n + 1);
+  }
+  return d;
+}
+
+// ---------------------------------------------------------------------------
+// Factorisation of a periodic banded (circulant) operator
+//   (T v)_i = sum_j t_j v_{i+j},  symbol T(w) = sum_j t_j w^j,
+// as T = C * F(S^-1) * B(S): F(x) = prod(1 - rho x) over the roots |rho| < 1
+// of w^{l} T(w), B(w) = prod(1 - w/sigma) over the roots |sigma| > 1.
+// Requires winding number zero (exactly l roots inside the unit circle).
+// ---------------------------------------------------------------------------
+
+std::vector<cld> poly_roots(const std::vector<ld> &c) {
+  const int n = (int)c.size() - 1;
+  std::vector<cld> mon(n + 1);
+  for (int i = 0; i <= n; ++i) mon[i] = c[i] / c[n];
+  auto eval = [&](cld z, cld &p, cld &dp) {
+    p = mon[n];
+    dp = 0;
+    for (int i = n - 1; i >= 0; --i) {
+      dp = dp * z + p;
+      p = p * z + mon[i];
+    }
+  };
+  const ld rad = std::pow(std::abs(mon[0]) + 1e-300L, 1.0L / n);
+  std::vector<cld> z(n);
+  for (int k = 0; k < n; ++k) z[k] = std::polar(rad * (1 + 0.1L * k), (ld)(2 * M_PI * k / n + 0.4));
+  for (int it = 0; it < 500; ++it) {
+    ld maxstep = 0;
+    for (int k = 0; k < n; ++k) {
+      cld p, dp;
+      eval(z[k], p, dp);
+      if (p == cld(0)) continue;
+      const cld ratio = p / dp;
+      cld sum = 0;
+      for (int j = 0; j < n; ++j)
+        if (j != k) sum += 1.0L / (z[k] - z[j]);
+      const cld step = ratio / (1.0L - ratio * sum);
+      z[k] -= step;
+      maxstep = std::max(maxstep, std::abs(step) / (1 + std::abs(z[k])));
+    }
+    if (maxstep < 1e-19L) break;
+  }
+  for (int k = 0; k < n; ++k)  // Newton polish
+    for (int it = 0; it < 3; ++it) {
+      cld p, dp;
+      eval(z[k], p, dp);
+      if (dp != cld(0)) z[k] -= p / dp;
+    }
+  return z;
+}
+
+struct Factor {
+  int kf = 0, kb = 0;
+  ld a[KMAX] = {0, 0, 0};  // forward: y_i = x_i + sum a_m y_{i-m}
+  ld b[KMAX] = {0, 0, 0};  // backward: y_i = x_i + sum b_m y_{i+m}
+  ld C = 1;
+};
+
+bool factorize(const std::map<int, ld> &taps_in, Factor &F, std::string &err) {
+  std::map<int, ld> taps;
+  ld tmax = 0;
+  for (auto &kv : taps_in) tmax = std::max(tmax, std::fabs(kv.second));
+  for (auto &kv : taps_in)
+    if (std::fabs(kv.second) > 1e-18L * tmax) taps[kv.first] = kv.second;
+  if (taps.empty()) {
+    err = "zero operator";
+    return false;
+  }
+  const int jmin = taps.begin()->first, jmax = taps.rbegin()->first;
+  if (jmin > 0 || jmax < 0) {
+    err = "operator is not diagonally centred";
+    return false;
+  }
+  if (jmin == 0 && jmax == 0) {
+    F.C = taps[0];
+    return true;
+  }
+  const int n = jmax - jmin;
+  std::vector<ld> c(n + 1, 0);
+  for (auto &kv : taps) c[kv.first - jmin] = kv.second;
+  std::vector<cld> rts = poly_roots(c);
+  std::vector<cld> in, out;
+  for (auto &z : rts) {
+    const ld a = std::abs(z);
+    if (std::fabs(a - 1) < 1e-12L) {
+      err = "operator is singular or nearly so (root on the unit circle)";
+      return false;
+    }
+    (a < 1 ? in : out).push_back(z);
+  }
+  if ((int)in.size() != -jmin) {
+    err = "operator has nonzero winding number";
+    return false;
+  }
+  if ((int)in.size() > KMAX || (int)out.size() > KMAX) {
+    err = "band too wide";
+    return false;
+  }
+  // F(x) = prod (1 - rho x)
+  std::vector<cld> pf(1, 1), pb(1, 1);
+  for (auto &rho : in) {
+    std::vector<cld> nx(pf.size() + 1, 0);
+    for (size_t i = 0; i < pf.size(); ++i) {
+      nx[i] += pf[i];
+      nx[i + 1] -= rho * pf[i];
+    }
+    pf = nx;
+  }
+  for (auto &sg : out) {
+    std::vector<cld> nx(pb.size() + 1, 0);
+    for (size_t i = 0; i < pb.size(); ++i) {
+      nx[i] += pb[i];
+      nx[i + 1] -= pb[i] / sg;
+    }
+    pb = nx;
+  }
+  cld C = taps[jmax];
+  for (auto &sg : out) C *= -sg;
+  F.kf = (int)in.size();
+  F.kb = (int)out.size();
+  for (int m = 1; m <= F.kf; ++m) F.a[m - 1] = -pf[m].real();
+  for (int m = 1; m <= F.kb; ++m) F.b[m - 1] = -pb[m].real();
+  F.C = C.real();
+  // verify: C * F(w^-1) * B(w) reproduces the taps
+  std::map<int, ld> back;
+  for (int i = 0; i <= F.kf; ++i)
+    for (int k = 0; k <= F.kb; ++k) {
+      const ld fi = i == 0 ? 1 : -F.a[i - 1];
+      const ld bk = k == 0 ? 1 : -F.b[k - 1];
+      back[k - i] += F.C * fi * bk;
+    }
+  ld worst = 0;
+  for (int j = jmin; j <= jmax; ++j) {
+    const ld want = taps.count(j) ? taps[j] : 0;
+    worst = std::max(worst, std::fabs(back[j] - want));
+  }
+  if (worst > 1e-13L * tmax) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "factorisation check failed (error %.3Le)", worst);
+    err = buf;
+    return false;
+  }
+  return true;
+}
+
+// Scan tables of one recurrence for a chunk layout (see mgrit_internal.h).
+void recurrence_tables(int k, const ld *a, const Layout &lay, std::vector<double> &out) {
+  std::vector<ld> M(k * k, 0);
+  for (int m = 0; m < k; ++m) M[m] = a[m];
+  for (int i = 1; i < k; ++i) M[i * k + (i - 1)] = 1;
+  auto mpow = [&](int e) {
+    std::vector<ld> R = identity(k), B = M;
+    while (e > 0) {
+      if (e & 1) R = matmul(R, B, k);
+      B = matmul(B, B, k);
+      e >>= 1;
+    }
+    return R;
+  };
+  const std::vector<ld> H = mpow(lay.L);
+  std::vector<ld> P = identity(k);
+  std::vector<std::vector<ld>> pw;
+  for (int t = 0; t <= lay.T; ++t) {
+    pw.push_back(P);
+    P = matmul(H, P, k);
+  }
+  const std::vector<ld> Hlast = mpow(lay.Llast);
+  std::vector<ld> Iw = identity(k);
+  const std::vector<ld> HH = matmul(Hlast, pw[lay.A - 1], k);
+  for (int i = 0; i < k * k; ++i) Iw[i] -= HH[i];
+  std::vector<ld> Wwrap;
+  invert(Iw, k, Wwrap);
+  out.clear();
+  for (auto &Mt : pw)
+    for (ld v : Mt) out.push_back((double)v);
+  for (ld v : Hlast) out.push_back((double)v);
+  for (ld v : Wwrap) out.push_back((double)v);
+}
+
+// Work distribution: L points per thread (a kernel template parameter).
+Layout choose_layout(int nx, int Lpref) {
+  static const int Ls[5] = {16, 8, 4, 2, 1};
+  Layout best{};
+  bool found = false;
+  int bestdist = 1 << 30;
+  for (int L : Ls) {
+    if (nx % (WAVE * L) == 0 && nx / L <= 1024) {
+      const int dist = std::abs(L - Lpref);
+      if (dist < bestdist) {
+        bestdist = dist;
+        best = Layout{nx, L, nx / L, nx / L, L, 0};
+        found = true;
+      }
+    }
+  }
+  if (found) return best;
+  int L = 16;
+  for (int cand : Ls)
+    if ((nx + cand - 1) / cand <= 1024 && std::abs(cand - Lpref) <= std::abs(L - Lpref)) L = cand;
+  const int A = (nx + L - 1) / L;
+  const int T = ((A + WAVE - 1) / WAVE) * WAVE;
+  return Layout{nx, L, A, T, nx - (A - 1) * L, 1};
+}
+
+int env_int(const char *name, int def) {
+  const char *v = std::getenv(name);
+  return (v && *v) ? std::atoi(v) : def;
+}
+
+struct Level {
+  int64_t nt = 0;
+  int m = 0;  // to the next level, 0 on the coarsest
+  StepOp op{};
+  Layout lay{};
+  double shift = 0, eps = 0, phi_p = 0, phi_q = 0;
+  int64_t K = 0;
+  double *tabs = nullptr;
+  LevelDesc *desc = nullptr;  // device copy of (op, lay)
+  double *c[2] = {nullptr, nullptr};
+  double *r = nullptr;
+};
+
+}  // namespace
+
+struct mgrit_handle {
+  mgrit_problem prob{};
+  mgrit_options opt{};
+  hipStream_t stream = nullptr;
+  std::vector<Level> lv;
+  double *normpart = nullptr;
+  int64_t normpart_len = 0;
+  double *normsum = nullptr;
+  double *normsum_host = nullptr;
+  std::string err;
+};
+
+namespace {
+
+mgrit_status fail(mgrit_handle *h, mgrit_status s, const std::string &msg) {
+  if (h) h->err = msg;
+  return s;
+}
+
+mgrit_status hipfail(mgrit_handle *h, hipError_t e, const char *where) {
+  return fail(h, MGRIT_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(h, expr)                                 \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) return hipfail((h), e_, #expr); \
+  } while (0)
+
+thread_local std::string g_setup_error;
+
+// Build the StepOp of a solve-free or solve-carrying operator.
+bool attach_solve(StepOp &op, const std::map<int, ld> &taps, const Layout &lay, std::vector<double> &tabs,
+                  std::vector<size_t> &offsets, std::string &err) {
+  Factor F;
+  if (!factorize(taps, F, err)) return false;
+  op.has_solve = (F.kf + F.kb) > 0 || std::fabs(F.C - 1) > 0;
+  op.cinv = (double)(1 / F.C);
+  op.fw.k = F.kf;
+  op.bw.k = F.kb;
+  for (int m = 0; m < KMAX; ++m) {
+    op.fw.a[m] = (double)F.a[m];
+    op.bw.a[m] = (double)F.b[m];
+  }
+  std::vector<double> t;
+  if (F.kf > 0) {
+    recurrence_tables(F.kf, F.a, lay, t);
+    offsets.push_back(tabs.size());
+    tabs.insert(tabs.end(), t.begin(), t.end());
+  } else {
+    offsets.push_back((size_t)-1);
+  }
+  if (F.kb > 0) {
+    recurrence_tables(F.kb, F.b, lay, t);
+    offsets.push_back(tabs.size());
+    tabs.insert(tabs.end(), t.begin(), t.end());
+  } else {
+    offsets.push_back((size_t)-1);
+  }
+  return true;
+}
+
+struct FineInfo {
+  int l = 0, r = 0;
+  std::vector<double> w;  // upwind weights, offsets -l..r
+  Tableau tab;
+  std::vector<ld> beta;
+  ld efd = 0, erk = 0;
+};
+
+mgrit_status fine_info(const mgrit_problem &P, FineInfo &fi, std::string &err) {
+  if (P.upwind_order < 1 || P.upwind_order > 5) {
+    err = "upwind_order must be in 1..5";
+    return MGRIT_EINVAL;
+  }
+  if (!make_tableau(P.rk_kind, P.rk_order, fi.tab)) {
+    err = "unsupported Runge-Kutta method (ERK 1..5, SDIRK 1..3)";
+    return MGRIT_EINVAL;
+  }
+  upwind_stencil(P.upwind_order, fi.l, fi.r, fi.w);
+  const int q = P.rk_order, p = P.upwind_order;
+  fi.beta = rk_series(fi.tab, std::max(q + 1, fi.tab.s + 1));
+  fi.erk = fi.beta[q + 1] - 1 / factorial(q + 1);
+  // eq. (e_FD_def)
+  fi.efd = ((fi.r % 2) ? -1 : 1) * factorial(fi.l) * factorial(fi.r) / factorial(p + 1);
+  return MGRIT_OK;
+}
+
+std::complex<double> upwind_symbol(const FineInfo &fi, double om) {
+  std::complex<double> s = 0;
+  for (int j = -fi.l; j <= fi.r; ++j) s += fi.w[j + fi.l] * std::polar(1.0, j * om);
+  return s;
+}
+
+// ERK stability: max over omega of |R(-c Lhat(omega))| <= 1 (Sec. 4.3, Table 2).
+bool erk_stable(const FineInfo &fi, double c) {
+  const int N = 16384;
+  for (int k = 1; k <= N; ++k) {
+    const double om = M_PI * k / N;
+    if (std::abs(rk_R(fi.tab, -c * upwind_symbol(fi, om))) > 1 + 1e-10) return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mgrit_status_string(mgrit_status s) {
+  switch (s) {
+    case MGRIT_OK: return "ok";
+    case MGRIT_ENOTCONVERGED: return "not converged within max_iter";
+    case MGRIT_EINVAL: return "invalid argument";
+    case MGRIT_EUNSTABLE: return "explicit scheme above its CFL limit";
+    case MGRIT_ENOMEM: return "device allocation failed";
+    case MGRIT_EDEVICE: return "HIP runtime error";
+    case MGRIT_EDIVERGED: return "diverged";
+  }
+  return "unknown status";
+}
+
+const char *mgrit_last_error(const mgrit_handle *h) {
+  if (!h) return g_setup_error.c_str();
+  return h->err.c_str();
+}
+
+void mgrit_destroy(mgrit_handle *h) {
+  if (!h) return;
+  for (auto &L : h->lv) {
+    if (L.tabs) (void)hipFree(L.tabs);
+    if (L.desc) (void)hipFree(L.desc);
+    for (int i = 0; i < 2; ++i)
+      if (L.c[i]) (void)hipFree(L.c[i]);
+    if (L.r) (void)hipFree(L.r);
+  }
+  if (h->normpart) (void)hipFree(h->normpart);
+  if (h->normsum) (void)hipFree(h->normsum);
+  if (h->normsum_host) (void)hipHostFree(h->normsum_host);
+  delete h;
+}
+
+mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *stream, mgrit_handle **out) {
+  g_setup_error.clear();
+  if (out) *out = nullptr;
+  if (!P || !O || !out) {
+    g_setup_error = "null argument";
+    return MGRIT_EINVAL;
+  }
+  auto bad = [&](mgrit_status s, const std::string &m) {
+    g_setup_error = m;
+    return s;
+  };
+  if (!(P->velocity > 0) || !(P->x_hi > P->x_lo) || !(P->cfl > 0)) return bad(MGRIT_EINVAL, "need velocity > 0, x_hi > x_lo, cfl > 0");
+  if (P->nx < 1 || P->nx > MGRIT_MAX_NX) return bad(MGRIT_EINVAL, "nx must be in 1..16384");
+  if (P->nt < 1) return bad(MGRIT_EINVAL, "nt must be >= 1");
+  if (O->max_levels < 2 || O->max_levels > MGRIT_MAX_LEVELS) return bad(MGRIT_EINVAL, "max_levels must be in 2..16");
+  if (O->nu < 0 || O->nu > 8) return bad(MGRIT_EINVAL, "nu must be in 0..8");
+  if (O->max_iter < 0) return bad(MGRIT_EINVAL, "max_iter must be >= 0");
+  if (!(O->rtol >= 0)) return bad(MGRIT_EINVAL, "rtol must be >= 0");
+  if (O->cg_kind < 0 || O->cg_kind > 2) return bad(MGRIT_EINVAL, "unknown coarse operator");
+  if (O->cg_kind != MGRIT_CG_IDEAL && P->upwind_order % 2 == 0)
+    return bad(MGRIT_EINVAL, "semi-Lagrangian coarse operators need odd upwind order");
+  if (O->cg_kind == MGRIT_CG_IDEAL && O->max_levels != 2) return bad(MGRIT_EINVAL, "ideal coarse operator: two levels only");
+
+  FineInfo fi;
+  std::string err;
+  mgrit_status st = fine_info(*P, fi, err);
+  if (st != MGRIT_OK) return bad(st, err);
+  const double c = P->cfl;
+  const int p = P->upwind_order, q = P->rk_order;
+  if (P->rk_kind == MGRIT_ERK && !erk_stable(fi, c)) return bad(MGRIT_EUNSTABLE, "CFL number above the stability limit of the explicit scheme");
+  if (P->rk_kind == MGRIT_SDIRK && q != p && (q % 2 == 0) && O->cg_kind != MGRIT_CG_IDEAL)
+    return bad(MGRIT_EINVAL, "mixed orders need an odd Runge-Kutta order for the correction");
+  if (P->rk_kind == MGRIT_ERK && q != p && (q % 2 == 0) && O->cg_kind != MGRIT_CG_IDEAL)
+    return bad(MGRIT_EINVAL, "mixed orders need an odd Runge-Kutta order for the correction");
+
+  // level hierarchy
+  std::vector<int64_t> nts{P->nt};
+  std::vector<int> ms;
+  int mprev = 0;
+  for (int l = 0; l < O->max_levels - 1; ++l) {
+    int m = O->m[l] > 0 ? O->m[l] : mprev;
+    if (m < 2) {
+      if (l == 0) return bad(MGRIT_EINVAL, "m[0] must be >= 2");
+      break;
+    }
+    mprev = m;
+    const int64_t cur = nts.back();
+    if (l > 0 && cur <= O->min_coarse_nt) break;
+    if (cur % m != 0) {
+      if (l == 0) return bad(MGRIT_EINVAL, "nt must be divisible by m[0]");
+      break;
+    }
+    ms.push_back(m);
+    nts.push_back(cur / m);
+  }
+  const int nlev = (int)nts.size();
+
+  mgrit_handle *h = new mgrit_handle();
+  h->prob = *P;
+  h->opt = *O;
+  h->stream = (hipStream_t)stream;
+  h->lv.resize(nlev);
+  const int nx = (int)P->nx;
+  const int Lfine = env_int("MGRIT_L_FINE", 16), Lcoarse = env_int("MGRIT_L_COARSE", 8);
+
+  // ---- fine operator (eq. MOL_M_def)
+  std::vector<std::vector<double>> tabs(nlev);
+  std::vector<std::vector<size_t>> offs(nlev);
+  {
+    Level &L0 = h->lv[0];
+    L0.nt = nts[0];
+    L0.m = ms[0];
+    StepOp &op = L0.op;
+    op = StepOp{};
+    op.repeat = 1;
+    if (P->rk_kind == MGRIT_ERK) {
+      L0.lay = choose_layout(nx, Lfine);
+      op.kind = OP_POLY_Z;
+      op.ncoef = fi.tab.s + 1;
+      for (int i = 0; i <= fi.tab.s; ++i) op.coef[i] = (double)fi.beta[i];
+      op.st_l = fi.l;
+      op.st_r = fi.r;
+      for (int j = 0; j <= fi.l + fi.r; ++j) op.taps[j] = -c * fi.w[j];
+    } else {
+      // R(z) = P(z) / (1 - g z)^s as a polynomial in w = 1/(1 - g z):
+      // z = (w - 1)/(g w)  =>  R = sum_n P_n g^-n (w - 1)^n w^(s-n).
+      L0.lay = choose_layout(nx, Lcoarse);
+      const int s = fi.tab.s;
+      const ld g = fi.tab.gamma;
+      std::vector<ld> beta = rk_series(fi.tab, s);
+      std::vector<ld> Q(s + 1, 0), Pc(s + 1, 0), coefw(s + 1, 0);
+      for (int n = 0; n <= s; ++n) {
+        ld bin = 1;
+        for (int i = 0; i < n; ++i) bin = bin * (s - i) / (i + 1);
+        Q[n] = bin * std::pow(-g, (ld)n);
+      }
+      for (int n = 0; n <= s; ++n)
+        for (int j = 0; j <= n; ++j) Pc[n] += beta[j] * Q[n - j];
+      for (int n = 0; n <= s; ++n) {
+        ld bin = 1;
+        for (int k = 0; k <= n; ++k) {
+          coefw[k + s - n] += Pc[n] * std::pow(g, (ld)-n) * bin * (((n - k) % 2) ? -1 : 1);
+          bin = bin * (n - k) / (k + 1);
+        }
+      }
+      op.kind = OP_POLY_W;
+      op.ncoef = s + 1;
+      for (int i = 0; i <= s; ++i) op.coef[i] = (double)coefw[i];
+      std::map<int, ld> taps;
+      taps[0] += 1;
+      for (int j = -fi.l; j <= fi.r; ++j) taps[j] += g * c * fi.w[j + fi.l];
+      if (!attach_solve(op, taps, L0.lay, tabs[0], offs[0], err)) {
+        mgrit_destroy(h);
+        return bad(MGRIT_EINVAL, "SDIRK stage operator: " + err);
+      }
+      // self-check of the w-polynomial against R(z)
+      for (double zr : {-0.3, -2.0, -7.5}) {
+        const std::complex<double> z(zr, 0.7);
+        const std::complex<double> w = 1.0 / (1.0 - (double)g * z);
+        std::complex<double> acc = 0;
+        for (int i = s; i >= 0; --i) acc = acc * w + (double)coefw[i];
+        const std::complex<double> ref = rk_R(fi.tab, z);
+        if (std::abs(acc - ref) > 1e-11 * (1 + std::abs(ref))) {
+          mgrit_destroy(h);
+          return bad(MGRIT_EINVAL, "internal: SDIRK rational form check failed");
+        }
+      }
+    }
+  }
+
+  // ---- coarse operators (eqs. MOL-SL-corrected, MOL-SL-corrected-multilevel)
+  {
+    const int sgn = ((p + 1) % 2) ? -1 : 1;  // (-1)^{p+1}
+    ld prod = 1, phi_p = 0, phi_q = 0, eps_prev = 0;
+    for (int l = 1; l < nlev; ++l) {
+      Level &Lv = h->lv[l];
+      Lv.nt = nts[l];
+      Lv.m = (l < nlev - 1) ? ms[l] : 0;
+      const int mcur = ms[l - 1];
+      prod *= mcur;
+      if (O->cg_kind == MGRIT_CG_IDEAL) {
+        Lv.op = h->lv[0].op;
+        Lv.op.repeat = ms[0];
+        Lv.lay = h->lv[0].lay;
+        tabs[l] = tabs[0];
+        offs[l] = offs[0];
+        continue;
+      }
+      const ld shift = (ld)c * prod;
+      const ld Kf = std::floor(shift);
+      const ld eps = shift - Kf;
+      if (l == 1) {
+        if (q == p) {
+          phi_p = mcur * ((ld)c * fi.efd + std::pow(-(ld)c, (ld)(p + 1)) * fi.erk) + sgn * f_poly(p, eps);
+          phi_q = 0;
+        } else {
+          phi_p = mcur * (ld)c * fi.efd + sgn * f_poly(p, eps);
+          phi_q = mcur * std::pow(-(ld)c, (ld)(q + 1)) * fi.erk;
+        }
+      } else {
+        phi_p = sgn * (-mcur * f_poly(p, eps_prev) + f_poly(p, eps)) + mcur * phi_p;
+        phi_q = mcur * phi_q;
+      }
+      eps_prev = eps;
+      Lv.shift = (double)shift;
+      Lv.K = (int64_t)Kf;
+      Lv.eps = (double)eps;
+      Lv.phi_p = O->cg_kind == MGRIT_CG_SL_PLAIN ? 0.0 : (double)phi_p;
+      Lv.phi_q = O->cg_kind == MGRIT_CG_SL_PLAIN ? 0.0 : (double)phi_q;
+      Lv.lay = choose_layout(nx, Lcoarse);
+      StepOp &op = Lv.op;
+      op = StepOp{};
+      op.kind = OP_SLC;
+      op.repeat = 1;
+      std::vector<double> slw;
+      sl_weights(p, eps, op.sl_l, op.sl_r, slw);
+      for (size_t j = 0; j < slw.size(); ++j) op.slw[j] = slw[j];
+      op.sl_K = (int)(((int64_t)Kf) % nx);
+      std::map<int, ld> taps;
+      taps[0] += 1;
+      for (auto &kv : dmat(p + 1)) taps[kv.first] -= (ld)Lv.phi_p * kv.second;
+      if (Lv.phi_q != 0)
+        for (auto &kv : dmat(q + 1)) taps[kv.first] -= (ld)Lv.phi_q * kv.second;
+      if (!attach_solve(op, taps, Lv.lay, tabs[l], offs[l], err)) {
+        mgrit_destroy(h);
+        return bad(MGRIT_EINVAL, "coarse operator: " + err);
+      }
+    }
+  }
+
+  // ---- device data
+  auto dalloc = [&](double **p, size_t n) -> hipError_t { return hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(double)); };
+  size_t maxlds = 0;
+  for (int l = 0; l < nlev; ++l) maxlds = std::max(maxlds, lds_bytes_for(h->lv[l].lay));
+  if (hipError_t e = configure_kernels(maxlds)) {
+    mgrit_destroy(h);
+    return bad(MGRIT_EDEVICE, std::string("configure: ") + hipGetErrorString(e));
+  }
+  for (int l = 0; l < nlev; ++l) {
+    Level &Lv = h->lv[l];
+    if (!tabs[l].empty()) {
+      if (dalloc(&Lv.tabs, tabs[l].size()) != hipSuccess) {
+        mgrit_destroy(h);
+        return bad(MGRIT_ENOMEM, "tables");
+      }
+      if (hipMemcpy(Lv.tabs, tabs[l].data(), tabs[l].size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        mgrit_destroy(h);
+        return bad(MGRIT_EDEVICE, "table upload");
+      }
+    }
+    if (offs[l].size() == 2) {
+      Lv.op.fw.tab = offs[l][0] == (size_t)-1 ? nullptr : Lv.tabs + offs[l][0];
+      Lv.op.bw.tab = offs[l][1] == (size_t)-1 ? nullptr : Lv.tabs + offs[l][1];
+    }
+    {
+      LevelDesc hd{Lv.op, Lv.lay};
+      if (hipMalloc((void **)&Lv.desc, sizeof(LevelDesc)) != hipSuccess) {
+        mgrit_destroy(h);
+        return bad(MGRIT_ENOMEM, "level descriptor");
+      }
+      if (hipMemcpy(Lv.desc, &hd, sizeof(LevelDesc), hipMemcpyHostToDevice) != hipSuccess) {
+        mgrit_destroy(h);
+        return bad(MGRIT_EDEVICE, "descriptor upload");
+      }
+    }
+    if (l < nlev - 1) {
+      const int64_t nc = Lv.nt / Lv.m;
+      for (int i = 0; i < 2; ++i)
+        if (dalloc(&Lv.c[i], (size_t)(nc + 1) * nx) != hipSuccess) {
+          mgrit_destroy(h);
+          return bad(MGRIT_ENOMEM, "C-point arrays");
+        }
+      if (dalloc(&Lv.r, (size_t)nc * nx) != hipSuccess) {
+        mgrit_destroy(h);
+        return bad(MGRIT_ENOMEM, "residual arrays");
+      }
+    }
+  }
+  h->normpart_len = std::max<int64_t>(P->nt, 1);
+  if (dalloc(&h->normpart, h->normpart_len) != hipSuccess || dalloc(&h->normsum, 1) != hipSuccess ||
+      hipHostMalloc((void **)&h->normsum_host, sizeof(double)) != hipSuccess) {
+    mgrit_destroy(h);
+    return bad(MGRIT_ENOMEM, "norm buffers");
+  }
+  *out = h;
+  return MGRIT_OK;
+}
+
+int32_t mgrit_num_levels(const mgrit_handle *h) { return h ? (int32_t)h->lv.size() : 0; }
+
+mgrit_status mgrit_level_info(const mgrit_handle *h, int32_t level, mgrit_level_desc *out) {
+  if (!h || !out || level < 0 || level >= (int32_t)h->lv.size()) return MGRIT_EINVAL;
+  const Level &L = h->lv[level];
+  out->nt = L.nt;
+  out->m = L.m;
+  out->shift = L.shift;
+  out->K = L.K;
+  out->eps = L.eps;
+  out->phi_p = L.phi_p;
+  out->phi_q = L.phi_q;
+  return MGRIT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+hipError_t run_pass(mgrit_handle *h, const Level &L, int mode, int m, int64_t nint, const double *cin, double *cout,
+                    const double *g, double *r, double *parent, double *out, int zero_init) {
+  PassArgs pa{};
+  pa.mode = mode;
+  pa.m = m;
+  pa.zero_init = zero_init;
+  pa.nint = nint;
+  pa.cin = cin;
+  pa.cout = cout;
+  pa.g = g;
+  pa.r = r;
+  pa.parent = parent;
+  pa.out = out;
+  pa.normpart = h->normpart;
+  return launch_pass(L.desc, L.op, L.lay, pa, h->stream);
+}
+
+// Approximate solve of level l >= 1 with rhs g (rows 1..nt_l) and zero initial
+// guess; the result is added into `parent` rows 0..nt_l (the C-points of
+// level l-1).
+mgrit_status vcycle(mgrit_handle *h, int l, const double *g, double *parent) {
+  Level &L = h->lv[l];
+  const int nlev = (int)h->lv.size();
+  const int nx = (int)h->prob.nx;
+  if (l == nlev - 1) {
+    HIPCHK(h, run_pass(h, L, MODE_SEQ, (int)L.nt, 1, nullptr, nullptr, g, nullptr, parent, nullptr, 1));
+    return MGRIT_OK;
+  }
+  const int64_t nc = L.nt / L.m;
+  int cur = 0;
+  if (h->opt.nu == 0) {
+    HIPCHK(h, launch_fill(L.c[0], (nc + 1) * (int64_t)nx, 0.0, h->stream));
+  }
+  for (int s = 0; s < h->opt.nu; ++s) {
+    HIPCHK(h, run_pass(h, L, MODE_PASS_A, L.m, nc, s == 0 ? nullptr : L.c[cur], L.c[1 - cur], g, nullptr, nullptr,
+                       nullptr, s == 0));
+    cur = 1 - cur;
+  }
+  HIPCHK(h, run_pass(h, L, MODE_PASS_B, L.m, nc, L.c[cur], nullptr, g, L.r, nullptr, nullptr, 0));
+  mgrit_status st = vcycle(h, l + 1, L.r, L.c[cur]);
+  if (st != MGRIT_OK) return st;
+  HIPCHK(h, run_pass(h, L, MODE_POST_F, L.m, nc, L.c[cur], nullptr, g, nullptr, parent, nullptr, 0));
+  return MGRIT_OK;
+}
+
+double reduce_norm(mgrit_handle *h, int64_t n, hipError_t &e) {
+  e = launch_reduce(h->normpart, n, h->normsum, h->stream);
+  if (e) return NAN;
+  e = hipMemcpyAsync(h->normsum_host, h->normsum, sizeof(double), hipMemcpyDeviceToHost, h->stream);
+  if (e) return NAN;
+  e = hipStreamSynchronize(h->stream);
+  if (e) return NAN;
+  return std::sqrt(*h->normsum_host);
+}
+
+}  // namespace
+
+extern "C" {
+
+mgrit_status mgrit_solve(mgrit_handle *h, const double *u0, const double *v_init, double *u_out, double *u_final,
+                         mgrit_stats *stats) {
+  if (!h) return MGRIT_EINVAL;
+  if (!u0) return fail(h, MGRIT_EINVAL, "u0 is required");
+  const auto t0 = std::chrono::steady_clock::now();
+  Level &L0 = h->lv[0];
+  const int nx = (int)h->prob.nx;
+  const int64_t nc = L0.nt / L0.m;
+  const int m0 = L0.m;
+  // initial C-points
+  if (v_init) {
+    HIPCHK(h, launch_gather_rows(v_init, m0, L0.c[0], nc + 1, nx, h->stream));
+  } else {
+    HIPCHK(h, launch_fill(L0.c[0], (nc + 1) * (int64_t)nx, 0.0, h->stream));
+  }
+  HIPCHK(h, hipMemcpyAsync(L0.c[0], u0, nx * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+
+  int cur = 0, it = 0;
+  double res0 = NAN, prev = NAN, rho = NAN;
+  int hist_len = 0;
+  mgrit_status status = MGRIT_OK;
+  for (;;) {
+    for (int s = 0; s < h->opt.nu; ++s) {
+      HIPCHK(h, run_pass(h, L0, MODE_PASS_A, m0, nc, L0.c[cur], L0.c[1 - cur], nullptr, nullptr, nullptr, nullptr, 0));
+      cur = 1 - cur;
+    }
+    HIPCHK(h, run_pass(h, L0, MODE_PASS_B, m0, nc, L0.c[cur], nullptr, nullptr, L0.r, nullptr, nullptr, 0));
+    hipError_t e;
+    prev = rho;
+    rho = reduce_norm(h, nc, e);
+    if (e) return hipfail(h, e, "residual norm");
+    if (stats && stats->res_history && hist_len < stats->res_history_cap) stats->res_history[hist_len] = rho;
+    ++hist_len;
+    if (it == 0) res0 = rho;
+    if (!std::isfinite(rho)) {
+      status = fail(h, MGRIT_EDIVERGED, "non-finite residual");
+      break;
+    }
+    if (rho <= h->opt.rtol * res0) break;
+    if (it >= h->opt.max_iter) {
+      status = MGRIT_ENOTCONVERGED;
+      h->err = "max_iter reached";
+      break;
+    }
+    if (h->opt.diverge_factor > 0 && rho > h->opt.diverge_factor * res0) {
+      status = fail(h, MGRIT_EDIVERGED, "residual grew past diverge_factor * res0");
+      break;
+    }
+    mgrit_status st = vcycle(h, 1, L0.r, L0.c[cur]);
+    if (st != MGRIT_OK) return st;
+    ++it;
+  }
+  if (u_out) {
+    HIPCHK(h, run_pass(h, L0, MODE_FINAL_F, m0, nc, L0.c[cur], nullptr, nullptr, nullptr, nullptr, u_out, 0));
+  }
+  if (u_final) {
+    HIPCHK(h, hipMemcpyAsync(u_final, L0.c[cur] + nc * (int64_t)nx, nx * sizeof(double), hipMemcpyDeviceToDevice,
+                             h->stream));
+  }
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (stats) {
+    stats->iterations = it;
+    stats->res0 = res0;
+    stats->res_final = rho;
+    stats->conv_factor = prev > 0 ? rho / prev : NAN;
+    stats->res_history_len = std::min(hist_len, std::max(stats->res_history_cap, 0));
+    stats->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return status;
+}
+
+mgrit_status mgrit_residual(mgrit_handle *h, const double *u, double *r, double *norm2) {
+  if (!h || !u) return MGRIT_EINVAL;
+  const Level &L0 = h->lv[0];
+  HIPCHK(h, run_pass(h, L0, MODE_RESID, 1, h->prob.nt, u, nullptr, nullptr, r, nullptr, nullptr, 0));
+  hipError_t e;
+  const double n = reduce_norm(h, h->prob.nt, e);
+  if (e) return hipfail(h, e, "residual norm");
+  if (norm2) *norm2 = n;
+  return MGRIT_OK;
+}
+
+mgrit_status mgrit_sequential(mgrit_handle *h, const double *u0, double *u_out) {
+  if (!h || !u0 || !u_out) return MGRIT_EINVAL;
+  const Level &L0 = h->lv[0];
+  HIPCHK(h, run_pass(h, L0, MODE_SEQ, (int)h->prob.nt, 1, u0, nullptr, nullptr, nullptr, nullptr, u_out, 0));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return MGRIT_OK;
+}
+
+mgrit_status mgrit_apply_step(mgrit_handle *h, int32_t level, const double *v_in, double *v_out, int64_t count,
+                              int32_t nsteps) {
+  if (!h || level < 0 || level >= (int32_t)h->lv.size() || !v_in || !v_out || count < 0 || nsteps < 0)
+    return fail(h, MGRIT_EINVAL, "bad apply_step arguments");
+  if (count == 0) return MGRIT_OK;
+  const Level &L = h->lv[level];
+  HIPCHK(h, run_pass(h, L, MODE_APPLY, nsteps, count, v_in, v_out, nullptr, nullptr, nullptr, nullptr, 0));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return MGRIT_OK;
+}
+
+mgrit_status mgrit_lfa_rho(const mgrit_problem *P, const mgrit_options *O, double *rho) {
+  if (!P || !O || !rho) return MGRIT_EINVAL;
+  FineInfo fi;
+  std::string err;
+  if (fine_info(*P, fi, err) != MGRIT_OK) return MGRIT_EINVAL;
+  const int p = P->upwind_order, q = P->rk_order, m = O->m[0], nu = O->nu;
+  if (m < 2) return MGRIT_EINVAL;
+  const double c = P->cfl;
+  const int sgn = ((p + 1) % 2) ? -1 : 1;
+  const ld shift = (ld)c * m;
+  const ld eps = shift - std::floor(shift);
+  const long K = (long)std::floor(shift);
+  ld phi_p, phi_q;
+  if (q == p) {
+    phi_p = m * ((ld)c * fi.efd + std::pow(-(ld)c, (ld)(p + 1)) * fi.erk) + sgn * f_poly(p, eps);
+    phi_q = 0;
+  } else {
+    phi_p = m * (ld)c * fi.efd + sgn * f_poly(p, eps);
+    phi_q = m * std::pow(-(ld)c, (ld)(q + 1)) * fi.erk;
+  }
+  if (O->cg_kind == MGRIT_CG_SL_PLAIN) phi_p = phi_q = 0;
+  int sl_l = 0, sl_r = 0;
+  std::vector<double> slw;
+  if (O->cg_kind != MGRIT_CG_IDEAL) sl_weights(p, eps, sl_l, sl_r, slw);
+  const int N = 1 << 11;
+  std::vector<std::pair<double, double>> oms;  // (|omega|, omega)
+  for (int k = 0; k < N; ++k) {
+    const double om = -M_PI + 2 * M_PI * k / N;
+    oms.push_back({std::fabs(om), om});
+  }
+  std::sort(oms.begin(), oms.end());
+  double best = 0;
+  for (size_t i = 11; i < oms.size(); ++i) {
+    const double om = oms[i].second;
+    const std::complex<double> lam = rk_R(fi.tab, -c * upwind_symbol(fi, om));
+    std::complex<double> mu;
+    const std::complex<double> lamm = std::pow(lam, m);
+    if (O->cg_kind == MGRIT_CG_IDEAL) {
+      mu = lamm;
+    } else {
+      std::complex<double> S = 0;
+      for (int j = -sl_l; j <= sl_r; ++j) S += slw[j + sl_l] * std::polar(1.0, (double)(j - K) * om);
+      const double dp = std::pow(2 * std::cos(om) - 2, (p + 1) / 2);
+      const double dq = q % 2 ? std::pow(2 * std::cos(om) - 2, (q + 1) / 2) : 0.0;
+      mu = S / (1.0 - (double)phi_p * dp - (double)phi_q * dq);
+    }
+    const double val = std::pow(std::abs(lam), m * nu) * std::abs(lamm - mu) / (1 - std::abs(mu));
+    best = std::max(best, val);
+  }
+  *rho = best;
+  return MGRIT_OK;
+}
+
+}  // extern "C"

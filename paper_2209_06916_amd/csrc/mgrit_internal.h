@@ -1,0 +1,114 @@
+// Internal types shared by the host driver (mgrit_host.cpp) and the gfx950
+// kernels (mgrit_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace mgrit {
+
+constexpr int KMAX = 3;       // max order of one periodic recurrence
+constexpr int MAXTAPS = 8;    // max stencil / interpolation taps
+constexpr int MAXCOEF = 8;    // max Horner coefficients (degree + 1)
+constexpr int MAXWAVES = 16;  // 1024 threads / 64
+constexpr int WAVE = 64;
+
+// How one time step Phi acts on a spatial vector u.
+//  OP_POLY_Z: Phi u = sum_i coef[i] Z^i u,  Z = stencil (taps) = -c L_p.
+//             Explicit RK: R(z) is a polynomial (Sec. 4.2).
+//  OP_POLY_W: Phi u = sum_i coef[i] W^i u,  W = (I + gamma c L_p)^{-1} = T^{-1}.
+//             SDIRK: R(z) = P(z)/(1 - gamma z)^s is a polynomial in
+//             w = 1/(1 - gamma z) (every stage solves with the same matrix).
+//  OP_SLC:    Phi u = T^{-1} S u, S the semi-Lagrangian interpolation and
+//             T = I - phi_p D^(p+1) - phi_q D^(q+1)  (eq. MOL-SL-corrected).
+// T^{-1} is applied through the factorisation T = C * F(S^-1) * B(S) into a
+// causal and an anti-causal banded factor; each factor's inverse is a linear
+// recurrence on the periodic mesh (see the kernels).
+enum OpKind : int { OP_POLY_Z = 0, OP_POLY_W = 1, OP_SLC = 2 };
+
+// One periodic linear recurrence y_i = x_i + sum_{m=1..k} a[m-1] y_{i-m}
+// (forward) or y_{i+m} (backward), run over T threads that each own a chunk
+// of L consecutive points.  tab holds, for this chunk layout:
+//   Hpow[t] = (M^L)^t, t = 0..T  (k*k each, M the companion matrix),
+//   Hlast   = M^{Llast},
+//   Wwrap   = (I - Hlast * Hpow[A-1])^{-1}.
+struct Recurrence {
+  int k;
+  double a[KMAX];
+  const double *tab;
+};
+
+struct StepOp {
+  int kind;
+  int repeat;             // apply the whole operator `repeat` times per step
+  int ncoef;              // Horner: coef[0..ncoef-1]
+  double coef[MAXCOEF];
+  int st_l, st_r;         // OP_POLY_Z stencil offsets -st_l..st_r
+  double taps[MAXTAPS];   // taps[j + st_l]
+  int sl_l, sl_r;         // OP_SLC interpolation nodes -sl_l..sl_r around i-K
+  int sl_K;               // floor(shift) mod nx
+  double slw[MAXTAPS];    // slw[j + sl_l]
+  int has_solve;          // T != I
+  double cinv;            // 1/C of the factorisation
+  Recurrence fw, bw;
+};
+
+// Work distribution of one nx-vector over a workgroup.
+struct Layout {
+  int nx;
+  int L;      // points per thread (template parameter of the kernels)
+  int A;      // threads that own points: ceil(nx / L)
+  int T;      // workgroup size, multiple of 64, >= A
+  int Llast;  // points of thread A-1
+  int ragged; // 0: nx == A*L and A == T (backward recurrence runs in reversed
+              //    thread order); 1: redistribute through LDS instead
+};
+
+// Per-level descriptor, uploaded once to device memory; kernels read it
+// through a pointer so every field is a uniform (scalar) load.
+struct LevelDesc {
+  StepOp op;
+  Layout lay;
+};
+
+enum PassMode : int {
+  MODE_PASS_A = 0,   // F-relaxation then C-relaxation of every CF-interval
+  MODE_PASS_B = 1,   // F-relaxation then the C-point residual (+ norm partials)
+  MODE_POST_F = 2,   // F-relaxation, every point added into the parent level
+  MODE_FINAL_F = 3,  // F-relaxation writing every time point to the output
+  MODE_SEQ = 4,      // sequential stepping over all steps (one workgroup)
+  MODE_APPLY = 5,    // independent vectors, nsteps applications each
+  MODE_RESID = 6     // one step per time point: space-time residual
+};
+
+struct PassArgs {
+  int mode;
+  int m;              // steps per interval (MODE_SEQ: total steps; APPLY: nsteps)
+  int zero_init;      // start every interval from 0 instead of cin
+  int64_t nint;       // intervals / vectors / time points = gridDim.x
+  const double *cin;  // [nint+1][nx] C-points (APPLY/RESID: [nint(+1)][nx])
+  double *cout;       // PASS_A: [nint+1][nx]; APPLY: [nint][nx]
+  const double *g;    // right-hand side rows, g[n-1] for level point n; NULL = 0
+  double *r;          // PASS_B: [nint][nx] residual; RESID: [nint][nx] or NULL
+  double *parent;     // POST_F / SEQ: parent C-point rows to add into
+  double *out;        // FINAL_F / SEQ: output rows
+  double *normpart;   // PASS_B / RESID: per-workgroup partial sum of squares
+};
+
+// Launch the step kernel for one pass (mgrit_kernels.hip).  lds_bytes is
+// computed by the launcher.  Returns the HIP error of the launch.
+// `desc` is the device copy of (op, lay); op.kind and lay are read on the host
+// to select the kernel instance and launch shape.
+hipError_t launch_pass(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs &pa,
+                       hipStream_t stream);
+// Deterministic reduction of n partial sums into out[0] (sum) on the device.
+hipError_t launch_reduce(const double *part, int64_t n, double *out, hipStream_t stream);
+// dst rows k = src rows k*stride (k = 0..rows-1), row length nx.
+hipError_t launch_gather_rows(const double *src, int64_t stride, double *dst, int64_t rows, int nx,
+                              hipStream_t stream);
+hipError_t launch_fill(double *dst, int64_t n, double value, hipStream_t stream);
+// Allow the step kernels to use up to `bytes` of dynamic LDS.
+hipError_t configure_kernels(size_t bytes);
+size_t lds_bytes_for(const Layout &lay);
+
+}  // namespace mgrit

@@ -1,0 +1,201 @@
+"""Thin ctypes binding of libmgrit.so (include/mgrit.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+Device arrays are torch float64 CUDA tensors (contiguous); torch provides the
+device memory and the stream, nothing else.  If the library has not been
+built, every entry point raises instead of falling back to anything else.
+"""
+import ctypes
+import os
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmgrit.so")
+_lib = None
+
+MAX_LEVELS = 16
+MAX_NX = 16384
+
+OK, ENOTCONVERGED, EINVAL, EUNSTABLE, ENOMEM, EDEVICE, EDIVERGED = 0, 1, -1, -2, -3, -4, -5
+ERK, SDIRK = 0, 1
+CG_SL_CORRECTED, CG_IDEAL, CG_SL_PLAIN = 0, 1, 2
+
+
+class MgritError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"mgrit status {status}: {message}")
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("velocity", ctypes.c_double), ("x_lo", ctypes.c_double), ("x_hi", ctypes.c_double),
+                ("nx", ctypes.c_int64), ("nt", ctypes.c_int64), ("cfl", ctypes.c_double),
+                ("upwind_order", ctypes.c_int32), ("rk_kind", ctypes.c_int32), ("rk_order", ctypes.c_int32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("max_levels", ctypes.c_int32), ("m", ctypes.c_int32 * (MAX_LEVELS - 1)),
+                ("min_coarse_nt", ctypes.c_int32), ("nu", ctypes.c_int32), ("cg_kind", ctypes.c_int32),
+                ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("diverge_factor", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("res0", ctypes.c_double), ("res_final", ctypes.c_double),
+                ("conv_factor", ctypes.c_double), ("res_history", ctypes.POINTER(ctypes.c_double)),
+                ("res_history_cap", ctypes.c_int32), ("res_history_len", ctypes.c_int32),
+                ("t_solve_s", ctypes.c_double)]
+
+
+class LevelDesc(ctypes.Structure):
+    _fields_ = [("nt", ctypes.c_int64), ("m", ctypes.c_int32), ("shift", ctypes.c_double),
+                ("K", ctypes.c_int64), ("eps", ctypes.c_double), ("phi_p", ctypes.c_double),
+                ("phi_q", ctypes.c_double)]
+
+
+EXPORTED = ["mgrit_setup", "mgrit_solve", "mgrit_residual", "mgrit_sequential", "mgrit_apply_step",
+            "mgrit_num_levels", "mgrit_level_info", "mgrit_lfa_rho", "mgrit_status_string",
+            "mgrit_last_error", "mgrit_destroy"]
+
+
+def library_path():
+    return _LIB_PATH
+
+
+def lib():
+    """Load libmgrit.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "or python -m paper_2209_06916_amd.build")
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+        L.mgrit_setup.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options), vp, ctypes.POINTER(vp)]
+        L.mgrit_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(Stats)]
+        L.mgrit_residual.argtypes = [vp, vp, vp, dp]
+        L.mgrit_sequential.argtypes = [vp, vp, vp]
+        L.mgrit_apply_step.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_int64, ctypes.c_int32]
+        L.mgrit_num_levels.argtypes = [vp]
+        L.mgrit_num_levels.restype = ctypes.c_int32
+        L.mgrit_level_info.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(LevelDesc)]
+        L.mgrit_lfa_rho.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options), dp]
+        L.mgrit_status_string.argtypes = [ctypes.c_int]
+        L.mgrit_status_string.restype = ctypes.c_char_p
+        L.mgrit_last_error.argtypes = [vp]
+        L.mgrit_last_error.restype = ctypes.c_char_p
+        L.mgrit_destroy.argtypes = [vp]
+        L.mgrit_destroy.restype = None
+        for name in ("mgrit_setup", "mgrit_solve", "mgrit_residual", "mgrit_sequential", "mgrit_apply_step",
+                     "mgrit_level_info", "mgrit_lfa_rho"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def make_problem(nx, nt, cfl, p, kind="erk", q=None, velocity=1.0, x_lo=-1.0, x_hi=1.0):
+    q = p if q is None else q
+    return Problem(velocity, x_lo, x_hi, nx, nt, cfl, p, ERK if kind == "erk" else SDIRK, q)
+
+
+def make_options(m, max_levels=2, min_coarse_nt=0, nu=1, coarse="sl_corrected", rtol=1e-10, max_iter=30,
+                 diverge_factor=1e8):
+    o = Options()
+    o.max_levels = max_levels
+    ms = list(m) if isinstance(m, (list, tuple)) else [m]
+    for i, v in enumerate(ms[:MAX_LEVELS - 1]):
+        o.m[i] = v
+    o.min_coarse_nt = min_coarse_nt
+    o.nu = nu
+    o.cg_kind = {"sl_corrected": CG_SL_CORRECTED, "ideal": CG_IDEAL, "sl_plain": CG_SL_PLAIN}[coarse]
+    o.rtol = rtol
+    o.max_iter = max_iter
+    o.diverge_factor = diverge_factor
+    return o
+
+
+def lfa_rho(problem, options):
+    rho = ctypes.c_double()
+    st = lib().mgrit_lfa_rho(ctypes.byref(problem), ctypes.byref(options), ctypes.byref(rho))
+    if st != OK:
+        raise MgritError(st, "lfa")
+    return rho.value
+
+
+def _ptr(t, shape=None):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One mgrit_handle: a problem + options set up on the current device."""
+
+    def __init__(self, problem, options, stream=None):
+        self.problem, self.options = problem, options
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = lib().mgrit_setup(ctypes.byref(problem), ctypes.byref(options), ctypes.c_void_p(stream.cuda_stream),
+                               ctypes.byref(h))
+        if st != OK:
+            raise MgritError(st, lib().mgrit_last_error(None).decode())
+        self.h = h
+        self.nx, self.nt = problem.nx, problem.nt
+
+    def _check(self, st, allow=(OK,)):
+        if st not in allow:
+            raise MgritError(st, lib().mgrit_last_error(self.h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mgrit_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_levels(self):
+        return lib().mgrit_num_levels(self.h)
+
+    def level_info(self, level):
+        d = LevelDesc()
+        self._check(lib().mgrit_level_info(self.h, level, ctypes.byref(d)))
+        return dict(nt=d.nt, m=d.m, shift=d.shift, K=d.K, eps=d.eps, phi_p=d.phi_p, phi_q=d.phi_q)
+
+    def solve(self, u0, v_init=None, u_out=None, u_final=None, history_cap=128,
+              allow=(OK, ENOTCONVERGED)):
+        nx, nt = self.nx, self.nt
+        hist = (ctypes.c_double * history_cap)()
+        stats = Stats()
+        stats.res_history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+        stats.res_history_cap = history_cap
+        st = lib().mgrit_solve(self.h, _ptr(u0, (nx,)), _ptr(v_init, (nt + 1, nx)), _ptr(u_out, (nt + 1, nx)),
+                               _ptr(u_final, (nx,)), ctypes.byref(stats))
+        self._check(st, allow)
+        return dict(status=st, iterations=stats.iterations, res0=stats.res0, res_final=stats.res_final,
+                    conv_factor=stats.conv_factor, res_history=list(hist[:stats.res_history_len]),
+                    t_solve_s=stats.t_solve_s)
+
+    def residual(self, u, r=None):
+        n = ctypes.c_double()
+        self._check(lib().mgrit_residual(self.h, _ptr(u, (self.nt + 1, self.nx)), _ptr(r, (self.nt, self.nx)),
+                                         ctypes.byref(n)))
+        return n.value
+
+    def sequential(self, u0, u_out):
+        self._check(lib().mgrit_sequential(self.h, _ptr(u0, (self.nx,)), _ptr(u_out, (self.nt + 1, self.nx))))
+
+    def apply_step(self, level, v_in, v_out, nsteps=1):
+        count = v_in.shape[0]
+        self._check(lib().mgrit_apply_step(self.h, level, _ptr(v_in, (count, self.nx)),
+                                           _ptr(v_out, (count, self.nx)), count, nsteps))
