@@ -109,6 +109,22 @@ typedef struct {
   double phi_q;         /* coefficient of D^(q+1) (q != p only)               */
 } mgrit_level_desc;
 
+/* Phases timed by the optional profiler (mgrit_profile_enable). */
+typedef enum {
+  MGRIT_PROF_FINE_RELAX = 0, /* level-0 F/C relaxation and C-point residual   */
+  MGRIT_PROF_COARSE = 1,     /* relaxation, residual and correction, levels >= 1 */
+  MGRIT_PROF_FINAL = 2,      /* final F-relaxation writing the solution        */
+  MGRIT_PROF_SEQUENTIAL = 3, /* mgrit_sequential                               */
+  MGRIT_PROF_RESIDUAL = 4,   /* mgrit_residual                                 */
+  MGRIT_PROF_OTHER = 5,      /* norm reductions, copies                        */
+  MGRIT_PROF_NPHASES = 6
+} mgrit_prof_phase;
+
+typedef struct {
+  int64_t launches[MGRIT_PROF_NPHASES]; /* kernel launches timed             */
+  double total_ms[MGRIT_PROF_NPHASES];  /* sum of their GPU durations         */
+} mgrit_profile;
+
 typedef struct mgrit_handle mgrit_handle;
 
 /* Validate the problem and options, build the level hierarchy (nt_0 = nt,
@@ -162,6 +178,14 @@ mgrit_status mgrit_level_info(const mgrit_handle *h, int32_t level, mgrit_level_
  * problem's fine step and the options' first coarsening factor and coarse
  * operator, with 2^11 spatial frequencies minus the 11 nearest omega = 0. */
 mgrit_status mgrit_lfa_rho(const mgrit_problem *problem, const mgrit_options *options, double *rho);
+
+/* Tracing: time every kernel launch of the phases in `phase_mask` (bit
+ * 1 << mgrit_prof_phase) with a pair of HIP events on the handle's stream;
+ * 0 disables.  Durations are collected whenever the library synchronises the
+ * stream.  Adds two event records per timed launch, nothing else. */
+mgrit_status mgrit_profile_enable(mgrit_handle *h, uint32_t phase_mask);
+/* Copy the accumulated counts and durations; reset them if reset != 0. */
+mgrit_status mgrit_profile_read(mgrit_handle *h, mgrit_profile *out, int32_t reset);
 
 const char *mgrit_status_string(mgrit_status s);
 const char *mgrit_last_error(const mgrit_handle *h);

@@ -428,8 +428,8 @@ void recurrence_tables(int k, const ld *a, const Layout &lay, std::vector<double
   std::vector<ld> M(k * k, 0);
   for (int m = 0; m < k; ++m) M[m] = a[m];
   for (int i = 1; i < k; ++i) M[i * k + (i - 1)] = 1;
-  auto mpow = [&](int e) {
-    std::vector<ld> R = identity(k), B = M;
+  auto mpow = [&](const std::vector<ld> &B0, long e) {
+    std::vector<ld> R = identity(k), B = B0;
     while (e > 0) {
       if (e & 1) R = matmul(R, B, k);
       B = matmul(B, B, k);
@@ -437,29 +437,26 @@ void recurrence_tables(int k, const ld *a, const Layout &lay, std::vector<double
     }
     return R;
   };
-  const std::vector<ld> H = mpow(lay.L);
+  const std::vector<ld> H = mpow(M, lay.L);
   std::vector<ld> P = identity(k);
-  std::vector<std::vector<ld>> pw;
-  for (int t = 0; t <= lay.T; ++t) {
-    pw.push_back(P);
+  out.clear();
+  for (int t = 0; t <= WAVE; ++t) {
+    for (ld v : P) out.push_back((double)v);
     P = matmul(H, P, k);
   }
-  const std::vector<ld> Hlast = mpow(lay.Llast);
+  const std::vector<ld> Hlast = mpow(M, lay.Llast);
   std::vector<ld> Iw = identity(k);
-  const std::vector<ld> HH = matmul(Hlast, pw[lay.A - 1], k);
+  const std::vector<ld> HH = matmul(Hlast, mpow(H, lay.A - 1), k);
   for (int i = 0; i < k * k; ++i) Iw[i] -= HH[i];
   std::vector<ld> Wwrap;
   invert(Iw, k, Wwrap);
-  out.clear();
-  for (auto &Mt : pw)
-    for (ld v : Mt) out.push_back((double)v);
   for (ld v : Hlast) out.push_back((double)v);
   for (ld v : Wwrap) out.push_back((double)v);
 }
 
 // Work distribution: L points per thread (a kernel template parameter).
 Layout choose_layout(int nx, int Lpref) {
-  static const int Ls[5] = {16, 8, 4, 2, 1};
+  static const int Ls[4] = {16, 8, 4, 2};
   Layout best{};
   bool found = false;
   int bestdist = 1 << 30;
@@ -468,7 +465,7 @@ Layout choose_layout(int nx, int Lpref) {
       const int dist = std::abs(L - Lpref);
       if (dist < bestdist) {
         bestdist = dist;
-        best = Layout{nx, L, nx / L, nx / L, L, 0};
+        best = Layout{nx, L, nx / L, nx / L, L, 0, 0};
         found = true;
       }
     }
@@ -479,8 +476,10 @@ Layout choose_layout(int nx, int Lpref) {
     if ((nx + cand - 1) / cand <= 1024 && std::abs(cand - Lpref) <= std::abs(L - Lpref)) L = cand;
   const int A = (nx + L - 1) / L;
   const int T = ((A + WAVE - 1) / WAVE) * WAVE;
-  return Layout{nx, L, A, T, nx - (A - 1) * L, 1};
+  return Layout{nx, L, A, T, nx - (A - 1) * L, 1, 0};
 }
+
+constexpr size_t LDS_LIMIT = 160 * 1024;
 
 int env_int(const char *name, int def) {
   const char *v = std::getenv(name);
@@ -512,6 +511,11 @@ struct mgrit_handle {
   double *normsum = nullptr;
   double *normsum_host = nullptr;
   std::string err;
+  // profiler
+  uint32_t prof_mask = 0;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  mgrit_profile prof{};
 };
 
 namespace {
@@ -640,6 +644,11 @@ void mgrit_destroy(mgrit_handle *h) {
   if (h->normpart) (void)hipFree(h->normpart);
   if (h->normsum) (void)hipFree(h->normsum);
   if (h->normsum_host) (void)hipHostFree(h->normsum_host);
+  for (auto &pe : h->ev_pending) {
+    (void)hipEventDestroy(pe.second.first);
+    (void)hipEventDestroy(pe.second.second);
+  }
+  for (auto e : h->ev_free) (void)hipEventDestroy(e);
   delete h;
 }
 
@@ -720,6 +729,8 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
     op.repeat = 1;
     if (P->rk_kind == MGRIT_ERK) {
       L0.lay = choose_layout(nx, Lfine);
+      L0.lay.dbuf = 1;
+      if (lds_bytes_for(L0.lay, 0) > LDS_LIMIT) L0.lay.dbuf = 0;
       op.kind = OP_POLY_Z;
       op.ncoef = fi.tab.s + 1;
       for (int i = 0; i <= fi.tab.s; ++i) op.coef[i] = (double)fi.beta[i];
@@ -836,7 +847,7 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
   // ---- device data
   auto dalloc = [&](double **p, size_t n) -> hipError_t { return hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(double)); };
   size_t maxlds = 0;
-  for (int l = 0; l < nlev; ++l) maxlds = std::max(maxlds, lds_bytes_for(h->lv[l].lay));
+  for (int l = 0; l < nlev; ++l) maxlds = std::max(maxlds, lds_bytes_for(h->lv[l].lay, h->lv[l].op.has_solve));
   if (hipError_t e = configure_kernels(maxlds)) {
     mgrit_destroy(h);
     return bad(MGRIT_EDEVICE, std::string("configure: ") + hipGetErrorString(e));
@@ -910,8 +921,33 @@ mgrit_status mgrit_level_info(const mgrit_handle *h, int32_t level, mgrit_level_
 
 namespace {
 
-hipError_t run_pass(mgrit_handle *h, const Level &L, int mode, int m, int64_t nint, const double *cin, double *cout,
-                    const double *g, double *r, double *parent, double *out, int zero_init) {
+hipEvent_t take_event(mgrit_handle *h) {
+  if (!h->ev_free.empty()) {
+    hipEvent_t e = h->ev_free.back();
+    h->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Fold finished event pairs into the profile (call after a stream sync).
+void harvest_events(mgrit_handle *h) {
+  for (auto &pe : h->ev_pending) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess) {
+      h->prof.launches[pe.first] += 1;
+      h->prof.total_ms[pe.first] += ms;
+    }
+    h->ev_free.push_back(pe.second.first);
+    h->ev_free.push_back(pe.second.second);
+  }
+  h->ev_pending.clear();
+}
+
+hipError_t run_pass(mgrit_handle *h, const Level &L, int phase, int mode, int m, int64_t nint, const double *cin,
+                    double *cout, const double *g, double *r, double *parent, double *out, int zero_init) {
   PassArgs pa{};
   pa.mode = mode;
   pa.m = m;
@@ -924,7 +960,18 @@ hipError_t run_pass(mgrit_handle *h, const Level &L, int mode, int m, int64_t ni
   pa.parent = parent;
   pa.out = out;
   pa.normpart = h->normpart;
-  return launch_pass(L.desc, L.op, L.lay, pa, h->stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->prof_mask & (1u << phase)) {
+    e0 = take_event(h);
+    e1 = take_event(h);
+    if (e0 && e1) (void)hipEventRecord(e0, h->stream);
+  }
+  hipError_t err = launch_pass(L.desc, L.op, L.lay, pa, h->stream);
+  if (e0 && e1) {
+    (void)hipEventRecord(e1, h->stream);
+    h->ev_pending.push_back({phase, {e0, e1}});
+  }
+  return err;
 }
 
 // Approximate solve of level l >= 1 with rhs g (rows 1..nt_l) and zero initial
@@ -935,7 +982,7 @@ mgrit_status vcycle(mgrit_handle *h, int l, const double *g, double *parent) {
   const int nlev = (int)h->lv.size();
   const int nx = (int)h->prob.nx;
   if (l == nlev - 1) {
-    HIPCHK(h, run_pass(h, L, MODE_SEQ, (int)L.nt, 1, nullptr, nullptr, g, nullptr, parent, nullptr, 1));
+    HIPCHK(h, run_pass(h, L, MGRIT_PROF_COARSE, MODE_SEQ, (int)L.nt, 1, nullptr, nullptr, g, nullptr, parent, nullptr, 1));
     return MGRIT_OK;
   }
   const int64_t nc = L.nt / L.m;
@@ -944,14 +991,14 @@ mgrit_status vcycle(mgrit_handle *h, int l, const double *g, double *parent) {
     HIPCHK(h, launch_fill(L.c[0], (nc + 1) * (int64_t)nx, 0.0, h->stream));
   }
   for (int s = 0; s < h->opt.nu; ++s) {
-    HIPCHK(h, run_pass(h, L, MODE_PASS_A, L.m, nc, s == 0 ? nullptr : L.c[cur], L.c[1 - cur], g, nullptr, nullptr,
+    HIPCHK(h, run_pass(h, L, MGRIT_PROF_COARSE, MODE_PASS_A, L.m, nc, s == 0 ? nullptr : L.c[cur], L.c[1 - cur], g, nullptr, nullptr,
                        nullptr, s == 0));
     cur = 1 - cur;
   }
-  HIPCHK(h, run_pass(h, L, MODE_PASS_B, L.m, nc, L.c[cur], nullptr, g, L.r, nullptr, nullptr, 0));
+  HIPCHK(h, run_pass(h, L, MGRIT_PROF_COARSE, MODE_PASS_B, L.m, nc, L.c[cur], nullptr, g, L.r, nullptr, nullptr, 0));
   mgrit_status st = vcycle(h, l + 1, L.r, L.c[cur]);
   if (st != MGRIT_OK) return st;
-  HIPCHK(h, run_pass(h, L, MODE_POST_F, L.m, nc, L.c[cur], nullptr, g, nullptr, parent, nullptr, 0));
+  HIPCHK(h, run_pass(h, L, MGRIT_PROF_COARSE, MODE_POST_F, L.m, nc, L.c[cur], nullptr, g, nullptr, parent, nullptr, 0));
   return MGRIT_OK;
 }
 
@@ -962,6 +1009,7 @@ double reduce_norm(mgrit_handle *h, int64_t n, hipError_t &e) {
   if (e) return NAN;
   e = hipStreamSynchronize(h->stream);
   if (e) return NAN;
+  harvest_events(h);
   return std::sqrt(*h->normsum_host);
 }
 
@@ -992,10 +1040,10 @@ mgrit_status mgrit_solve(mgrit_handle *h, const double *u0, const double *v_init
   mgrit_status status = MGRIT_OK;
   for (;;) {
     for (int s = 0; s < h->opt.nu; ++s) {
-      HIPCHK(h, run_pass(h, L0, MODE_PASS_A, m0, nc, L0.c[cur], L0.c[1 - cur], nullptr, nullptr, nullptr, nullptr, 0));
+      HIPCHK(h, run_pass(h, L0, MGRIT_PROF_FINE_RELAX, MODE_PASS_A, m0, nc, L0.c[cur], L0.c[1 - cur], nullptr, nullptr, nullptr, nullptr, 0));
       cur = 1 - cur;
     }
-    HIPCHK(h, run_pass(h, L0, MODE_PASS_B, m0, nc, L0.c[cur], nullptr, nullptr, L0.r, nullptr, nullptr, 0));
+    HIPCHK(h, run_pass(h, L0, MGRIT_PROF_FINE_RELAX, MODE_PASS_B, m0, nc, L0.c[cur], nullptr, nullptr, L0.r, nullptr, nullptr, 0));
     hipError_t e;
     prev = rho;
     rho = reduce_norm(h, nc, e);
@@ -1022,13 +1070,14 @@ mgrit_status mgrit_solve(mgrit_handle *h, const double *u0, const double *v_init
     ++it;
   }
   if (u_out) {
-    HIPCHK(h, run_pass(h, L0, MODE_FINAL_F, m0, nc, L0.c[cur], nullptr, nullptr, nullptr, nullptr, u_out, 0));
+    HIPCHK(h, run_pass(h, L0, MGRIT_PROF_FINAL, MODE_FINAL_F, m0, nc, L0.c[cur], nullptr, nullptr, nullptr, nullptr, u_out, 0));
   }
   if (u_final) {
     HIPCHK(h, hipMemcpyAsync(u_final, L0.c[cur] + nc * (int64_t)nx, nx * sizeof(double), hipMemcpyDeviceToDevice,
                              h->stream));
   }
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  harvest_events(h);
   if (stats) {
     stats->iterations = it;
     stats->res0 = res0;
@@ -1043,7 +1092,7 @@ mgrit_status mgrit_solve(mgrit_handle *h, const double *u0, const double *v_init
 mgrit_status mgrit_residual(mgrit_handle *h, const double *u, double *r, double *norm2) {
   if (!h || !u) return MGRIT_EINVAL;
   const Level &L0 = h->lv[0];
-  HIPCHK(h, run_pass(h, L0, MODE_RESID, 1, h->prob.nt, u, nullptr, nullptr, r, nullptr, nullptr, 0));
+  HIPCHK(h, run_pass(h, L0, MGRIT_PROF_RESIDUAL, MODE_RESID, 1, h->prob.nt, u, nullptr, nullptr, r, nullptr, nullptr, 0));
   hipError_t e;
   const double n = reduce_norm(h, h->prob.nt, e);
   if (e) return hipfail(h, e, "residual norm");
@@ -1054,8 +1103,9 @@ mgrit_status mgrit_residual(mgrit_handle *h, const double *u, double *r, double 
 mgrit_status mgrit_sequential(mgrit_handle *h, const double *u0, double *u_out) {
   if (!h || !u0 || !u_out) return MGRIT_EINVAL;
   const Level &L0 = h->lv[0];
-  HIPCHK(h, run_pass(h, L0, MODE_SEQ, (int)h->prob.nt, 1, u0, nullptr, nullptr, nullptr, nullptr, u_out, 0));
+  HIPCHK(h, run_pass(h, L0, MGRIT_PROF_SEQUENTIAL, MODE_SEQ, (int)h->prob.nt, 1, u0, nullptr, nullptr, nullptr, nullptr, u_out, 0));
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  harvest_events(h);
   return MGRIT_OK;
 }
 
@@ -1065,8 +1115,24 @@ mgrit_status mgrit_apply_step(mgrit_handle *h, int32_t level, const double *v_in
     return fail(h, MGRIT_EINVAL, "bad apply_step arguments");
   if (count == 0) return MGRIT_OK;
   const Level &L = h->lv[level];
-  HIPCHK(h, run_pass(h, L, MODE_APPLY, nsteps, count, v_in, v_out, nullptr, nullptr, nullptr, nullptr, 0));
+  HIPCHK(h, run_pass(h, L, MGRIT_PROF_OTHER, MODE_APPLY, nsteps, count, v_in, v_out, nullptr, nullptr, nullptr, nullptr, 0));
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  harvest_events(h);
+  return MGRIT_OK;
+}
+
+mgrit_status mgrit_profile_enable(mgrit_handle *h, uint32_t mask) {
+  if (!h) return MGRIT_EINVAL;
+  h->prof_mask = mask;
+  return MGRIT_OK;
+}
+
+mgrit_status mgrit_profile_read(mgrit_handle *h, mgrit_profile *out, int32_t reset) {
+  if (!h || !out) return MGRIT_EINVAL;
+  if (hipError_t e = hipStreamSynchronize(h->stream)) return hipfail(h, e, "profile sync");
+  harvest_events(h);
+  *out = h->prof;
+  if (reset) h->prof = mgrit_profile{};
   return MGRIT_OK;
 }
 

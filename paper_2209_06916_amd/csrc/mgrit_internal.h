@@ -28,10 +28,11 @@ enum OpKind : int { OP_POLY_Z = 0, OP_POLY_W = 1, OP_SLC = 2 };
 
 // One periodic linear recurrence y_i = x_i + sum_{m=1..k} a[m-1] y_{i-m}
 // (forward) or y_{i+m} (backward), run over T threads that each own a chunk
-// of L consecutive points.  tab holds, for this chunk layout:
-//   Hpow[t] = (M^L)^t, t = 0..T  (k*k each, M the companion matrix),
-//   Hlast   = M^{Llast},
-//   Wwrap   = (I - Hlast * Hpow[A-1])^{-1}.
+// of L consecutive points.  tab holds RTAB matrices of k*k doubles, for this
+// chunk layout (M the companion matrix, H = M^L, A threads own points):
+//   Hpow[t] = H^t, t = 0..64, then Hlast = M^{Llast},
+//   then Wwrap = (I - Hlast * H^{A-1})^{-1}.
+constexpr int RTAB = WAVE + 3;
 struct Recurrence {
   int k;
   double a[KMAX];
@@ -62,7 +63,35 @@ struct Layout {
   int Llast;  // points of thread A-1
   int ragged; // 0: nx == A*L and A == T (backward recurrence runs in reversed
               //    thread order); 1: redistribute through LDS instead
+  int dbuf;   // explicit stencils alternate between two LDS vectors
 };
+
+// LDS layout of one launch (in doubles): padded vector(s), the forward and
+// backward recurrence tables, their scan scratch, and the reduction scratch.
+struct LdsOffsets {
+  int vec1, tab_f, tab_b, scr_f, scr_b, red, total;
+};
+
+__host__ __device__ inline LdsOffsets lds_offsets(const Layout &lay, int has_solve) {
+  LdsOffsets o;
+  const int pv = lay.nx + (lay.nx >> 4) + 1;
+  int off = pv;
+  o.vec1 = lay.dbuf ? off : 0;
+  if (lay.dbuf) off += pv;
+  const int tabsz = has_solve ? RTAB * KMAX * KMAX : 0;
+  o.tab_f = off;
+  off += tabsz;
+  o.tab_b = off;
+  off += tabsz;
+  o.scr_f = off;
+  off += 2 * MAXWAVES * KMAX;
+  o.scr_b = off;
+  off += 2 * MAXWAVES * KMAX;
+  o.red = off;
+  off += MAXWAVES;
+  o.total = off;
+  return o;
+}
 
 // Per-level descriptor, uploaded once to device memory; kernels read it
 // through a pointer so every field is a uniform (scalar) load.
@@ -109,6 +138,6 @@ hipError_t launch_gather_rows(const double *src, int64_t stride, double *dst, in
 hipError_t launch_fill(double *dst, int64_t n, double value, hipStream_t stream);
 // Allow the step kernels to use up to `bytes` of dynamic LDS.
 hipError_t configure_kernels(size_t bytes);
-size_t lds_bytes_for(const Layout &lay);
+size_t lds_bytes_for(const Layout &lay, int has_solve);
 
 }  // namespace mgrit

@@ -52,9 +52,16 @@ class LevelDesc(ctypes.Structure):
                 ("phi_q", ctypes.c_double)]
 
 
+PROF_PHASES = ["fine_relax", "coarse", "final", "sequential", "residual", "other"]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * len(PROF_PHASES)), ("total_ms", ctypes.c_double * len(PROF_PHASES))]
+
+
 EXPORTED = ["mgrit_setup", "mgrit_solve", "mgrit_residual", "mgrit_sequential", "mgrit_apply_step",
-            "mgrit_num_levels", "mgrit_level_info", "mgrit_lfa_rho", "mgrit_status_string",
-            "mgrit_last_error", "mgrit_destroy"]
+            "mgrit_num_levels", "mgrit_level_info", "mgrit_lfa_rho", "mgrit_profile_enable",
+            "mgrit_profile_read", "mgrit_status_string", "mgrit_last_error", "mgrit_destroy"]
 
 
 def library_path():
@@ -79,6 +86,8 @@ def lib():
         L.mgrit_num_levels.restype = ctypes.c_int32
         L.mgrit_level_info.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(LevelDesc)]
         L.mgrit_lfa_rho.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options), dp]
+        L.mgrit_profile_enable.argtypes = [vp, ctypes.c_uint32]
+        L.mgrit_profile_read.argtypes = [vp, ctypes.POINTER(Profile), ctypes.c_int32]
         L.mgrit_status_string.argtypes = [ctypes.c_int]
         L.mgrit_status_string.restype = ctypes.c_char_p
         L.mgrit_last_error.argtypes = [vp]
@@ -86,7 +95,7 @@ def lib():
         L.mgrit_destroy.argtypes = [vp]
         L.mgrit_destroy.restype = None
         for name in ("mgrit_setup", "mgrit_solve", "mgrit_residual", "mgrit_sequential", "mgrit_apply_step",
-                     "mgrit_level_info", "mgrit_lfa_rho"):
+                     "mgrit_level_info", "mgrit_lfa_rho", "mgrit_profile_enable", "mgrit_profile_read"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -194,6 +203,17 @@ class Solver:
 
     def sequential(self, u0, u_out):
         self._check(lib().mgrit_sequential(self.h, _ptr(u0, (self.nx,)), _ptr(u_out, (self.nt + 1, self.nx))))
+
+    def profile_enable(self, phases):
+        mask = 0
+        for ph in phases:
+            mask |= 1 << PROF_PHASES.index(ph)
+        self._check(lib().mgrit_profile_enable(self.h, mask))
+
+    def profile_read(self, reset=True):
+        p = Profile()
+        self._check(lib().mgrit_profile_read(self.h, ctypes.byref(p), 1 if reset else 0))
+        return {ph: dict(launches=p.launches[i], total_ms=p.total_ms[i]) for i, ph in enumerate(PROF_PHASES)}
 
     def apply_step(self, level, v_in, v_out, nsteps=1):
         count = v_in.shape[0]
