@@ -481,12 +481,35 @@ Layout choose_layout(int nx, int Lpref) {
 
 constexpr size_t LDS_LIMIT = 160 * 1024;
 
+// Tile geometry of the level-0 explicit relaxation: the halo is what m steps
+// of (Horner depth) stencil applications consume; pick the points per lane
+// that minimise redundant lane-work (ties: fewer points, more wavefronts).
+bool choose_tiles(int nx, int m, int depth, int sl, int sr, int Pforce, TileGeom &tg) {
+  static const int Ps[3] = {8, 16, 32};
+  const int HL = m * depth * sl, HR = m * depth * sr;
+  long best = -1;
+  for (int P : Ps) {
+    if (Pforce && P != Pforce) continue;
+    const int avail = WAVE * P - HL - HR;
+    if (avail < 32) continue;
+    const int ntiles = (nx + avail - 1) / avail;
+    const long work = (long)ntiles * WAVE * P;
+    if (best < 0 || work < best) {
+      best = work;
+      tg = TileGeom{P, HL, HR, (nx + ntiles - 1) / ntiles, ntiles, sl, sr};
+    }
+  }
+  return best >= 0;
+}
+
 int env_int(const char *name, int def) {
   const char *v = std::getenv(name);
   return (v && *v) ? std::atoi(v) : def;
 }
 
 struct Level {
+  bool tiles = false;  // level-0 explicit relaxation through tile_kernel
+  TileGeom tg{};
   int64_t nt = 0;
   int m = 0;  // to the next level, 0 on the coarsest
   StepOp op{};
@@ -715,7 +738,7 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
   h->stream = (hipStream_t)stream;
   h->lv.resize(nlev);
   const int nx = (int)P->nx;
-  const int Lfine = env_int("MGRIT_L_FINE", 16), Lcoarse = env_int("MGRIT_L_COARSE", 8);
+  const int Lfine = env_int("MGRIT_L_FINE", 16), Lcoarse = env_int("MGRIT_L_COARSE", 16);
 
   // ---- fine operator (eq. MOL_M_def)
   std::vector<std::vector<double>> tabs(nlev);
@@ -731,6 +754,8 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
       L0.lay = choose_layout(nx, Lfine);
       L0.lay.dbuf = 1;
       if (lds_bytes_for(L0.lay, 0) > LDS_LIMIT) L0.lay.dbuf = 0;
+      L0.tiles = env_int("MGRIT_NO_TILES", 0) == 0 &&
+                 choose_tiles(nx, ms[0], fi.tab.s, fi.l, fi.r, env_int("MGRIT_TILE_P", 0), L0.tg);
       op.kind = OP_POLY_Z;
       op.ncoef = fi.tab.s + 1;
       for (int i = 0; i <= fi.tab.s; ++i) op.coef[i] = (double)fi.beta[i];
@@ -823,7 +848,6 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
       Lv.eps = (double)eps;
       Lv.phi_p = O->cg_kind == MGRIT_CG_SL_PLAIN ? 0.0 : (double)phi_p;
       Lv.phi_q = O->cg_kind == MGRIT_CG_SL_PLAIN ? 0.0 : (double)phi_q;
-      Lv.lay = choose_layout(nx, Lcoarse);
       StepOp &op = Lv.op;
       op = StepOp{};
       op.kind = OP_SLC;
@@ -837,6 +861,9 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
       for (auto &kv : dmat(p + 1)) taps[kv.first] -= (ld)Lv.phi_p * kv.second;
       if (Lv.phi_q != 0)
         for (auto &kv : dmat(q + 1)) taps[kv.first] -= (ld)Lv.phi_q * kv.second;
+      Lv.lay = choose_layout(nx, Lcoarse);
+      Lv.lay.dbuf = 1;
+      if (lean_lds_offsets(nx, 1, KMAX).total * sizeof(double) > LDS_LIMIT) Lv.lay.dbuf = 0;
       if (!attach_solve(op, taps, Lv.lay, tabs[l], offs[l], err)) {
         mgrit_destroy(h);
         return bad(MGRIT_EINVAL, "coarse operator: " + err);
@@ -847,7 +874,10 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
   // ---- device data
   auto dalloc = [&](double **p, size_t n) -> hipError_t { return hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(double)); };
   size_t maxlds = 0;
-  for (int l = 0; l < nlev; ++l) maxlds = std::max(maxlds, lds_bytes_for(h->lv[l].lay, h->lv[l].op.has_solve));
+  for (int l = 0; l < nlev; ++l) {
+    maxlds = std::max(maxlds, lds_bytes_for(h->lv[l].lay, h->lv[l].op.has_solve));
+    maxlds = std::max(maxlds, lean_lds_offsets(nx, h->lv[l].lay.dbuf, KMAX).total * sizeof(double));
+  }
   if (hipError_t e = configure_kernels(maxlds)) {
     mgrit_destroy(h);
     return bad(MGRIT_EDEVICE, std::string("configure: ") + hipGetErrorString(e));
@@ -893,6 +923,7 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
     }
   }
   h->normpart_len = std::max<int64_t>(P->nt, 1);
+  if (h->lv[0].tiles) h->normpart_len = std::max<int64_t>(h->normpart_len, (P->nt / ms[0]) * h->lv[0].tg.ntiles);
   if (dalloc(&h->normpart, h->normpart_len) != hipSuccess || dalloc(&h->normsum, 1) != hipSuccess ||
       hipHostMalloc((void **)&h->normsum_host, sizeof(double)) != hipSuccess) {
     mgrit_destroy(h);
@@ -974,6 +1005,39 @@ hipError_t run_pass(mgrit_handle *h, const Level &L, int phase, int mode, int m,
   return err;
 }
 
+// Level-0 pass through the tile kernel when it applies, else the slab kernel.
+hipError_t run_fine(mgrit_handle *h, int phase, int mode, const double *cin, double *cout, double *r, double *out) {
+  const Level &L0 = h->lv[0];
+  const int64_t nc = L0.nt / L0.m;
+  if (!L0.tiles) return run_pass(h, L0, phase, mode, L0.m, nc, cin, cout, nullptr, r, nullptr, out, 0);
+  TileArgs ta{};
+  ta.mode = mode;
+  ta.m = L0.m;
+  ta.nint = nc;
+  ta.cin = cin;
+  ta.cout = cout;
+  ta.r = r;
+  ta.out = out;
+  ta.normpart = h->normpart;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->prof_mask & (1u << phase)) {
+    e0 = take_event(h);
+    e1 = take_event(h);
+    if (e0 && e1) (void)hipEventRecord(e0, h->stream);
+  }
+  hipError_t err = launch_tiles(L0.desc, L0.tg, ta, h->stream);
+  if (e0 && e1) {
+    (void)hipEventRecord(e1, h->stream);
+    h->ev_pending.push_back({phase, {e0, e1}});
+  }
+  return err;
+}
+
+int64_t fine_norm_parts(const mgrit_handle *h) {
+  const Level &L0 = h->lv[0];
+  return (L0.nt / L0.m) * (L0.tiles ? L0.tg.ntiles : 1);
+}
+
 // Approximate solve of level l >= 1 with rhs g (rows 1..nt_l) and zero initial
 // guess; the result is added into `parent` rows 0..nt_l (the C-points of
 // level l-1).
@@ -1040,13 +1104,13 @@ mgrit_status mgrit_solve(mgrit_handle *h, const double *u0, const double *v_init
   mgrit_status status = MGRIT_OK;
   for (;;) {
     for (int s = 0; s < h->opt.nu; ++s) {
-      HIPCHK(h, run_pass(h, L0, MGRIT_PROF_FINE_RELAX, MODE_PASS_A, m0, nc, L0.c[cur], L0.c[1 - cur], nullptr, nullptr, nullptr, nullptr, 0));
+      HIPCHK(h, run_fine(h, MGRIT_PROF_FINE_RELAX, MODE_PASS_A, L0.c[cur], L0.c[1 - cur], nullptr, nullptr));
       cur = 1 - cur;
     }
-    HIPCHK(h, run_pass(h, L0, MGRIT_PROF_FINE_RELAX, MODE_PASS_B, m0, nc, L0.c[cur], nullptr, nullptr, L0.r, nullptr, nullptr, 0));
+    HIPCHK(h, run_fine(h, MGRIT_PROF_FINE_RELAX, MODE_PASS_B, L0.c[cur], nullptr, L0.r, nullptr));
     hipError_t e;
     prev = rho;
-    rho = reduce_norm(h, nc, e);
+    rho = reduce_norm(h, fine_norm_parts(h), e);
     if (e) return hipfail(h, e, "residual norm");
     if (stats && stats->res_history && hist_len < stats->res_history_cap) stats->res_history[hist_len] = rho;
     ++hist_len;
@@ -1070,7 +1134,7 @@ mgrit_status mgrit_solve(mgrit_handle *h, const double *u0, const double *v_init
     ++it;
   }
   if (u_out) {
-    HIPCHK(h, run_pass(h, L0, MGRIT_PROF_FINAL, MODE_FINAL_F, m0, nc, L0.c[cur], nullptr, nullptr, nullptr, nullptr, u_out, 0));
+    HIPCHK(h, run_fine(h, MGRIT_PROF_FINAL, MODE_FINAL_F, L0.c[cur], nullptr, nullptr, u_out));
   }
   if (u_final) {
     HIPCHK(h, hipMemcpyAsync(u_final, L0.c[cur] + nc * (int64_t)nx, nx * sizeof(double), hipMemcpyDeviceToDevice,

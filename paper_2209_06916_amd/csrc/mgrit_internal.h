@@ -100,6 +100,40 @@ struct LevelDesc {
   Layout lay;
 };
 
+// LDS layout of the lean coarse-step kernel (in doubles).
+struct LeanLds {
+  int vec1, tab_f, tab_b, qf, qb, red, total;
+};
+
+__host__ __device__ inline LeanLds lean_lds_offsets(int nx, int dbuf, int K) {
+  LeanLds o;
+  const int pv = nx + (nx >> 4) + 1;
+  int off = pv;
+  o.vec1 = dbuf ? off : 0;
+  if (dbuf) off += pv;
+  o.tab_f = off;
+  off += RTAB * K * K;
+  o.tab_b = off;
+  off += RTAB * K * K;
+  o.qf = off;
+  off += (MAXWAVES + 2) * K;
+  o.qb = off;
+  off += (MAXWAVES + 2) * K;
+  o.red = off;
+  off += MAXWAVES;
+  o.total = off;
+  return o;
+}
+
+// The lean kernel takes semi-Lagrangian steps with a solve on full chunks:
+// W = 2K interpolation taps (odd p, K = (p+1)/2 for the single-term
+// correction), equal forward/backward orders, no repetition.
+inline bool lean_slc_applies(const StepOp &op, const Layout &lay) {
+  const int W = op.sl_l + op.sl_r + 1;
+  return op.kind == OP_SLC && op.has_solve && op.repeat == 1 && !lay.ragged && lay.A == lay.T &&
+         (lay.L == 4 || lay.L == 8 || lay.L == 16) && op.fw.k == op.bw.k && op.fw.k >= 1 && W == 2 * op.fw.k;
+}
+
 enum PassMode : int {
   MODE_PASS_A = 0,   // F-relaxation then C-relaxation of every CF-interval
   MODE_PASS_B = 1,   // F-relaxation then the C-point residual (+ norm partials)
@@ -123,6 +157,32 @@ struct PassArgs {
   double *out;        // FINAL_F / SEQ: output rows
   double *normpart;   // PASS_B / RESID: per-workgroup partial sum of squares
 };
+
+// Level-0 explicit relaxation with wavefront tiles (temporal blocking): one
+// wavefront owns the output range [x0, x0 + TW) of one CF-interval plus a halo
+// of HL points on the left and HR on the right, P points per lane (64 P =
+// TW + HL + HR), and advances all steps of the interval in registers; the
+// halo shrinks by the stencil extent at every stencil application.
+struct TileGeom {
+  int P;       // points per lane (kernel template parameter)
+  int HL, HR;  // halo widths: steps * (Horner depth) * stencil extent
+  int TW;      // output points per tile (last tile may have fewer)
+  int ntiles;  // tiles per interval
+  int sl, sr;  // stencil extents (kernel template parameters)
+};
+
+struct TileArgs {
+  int mode;           // MODE_PASS_A, MODE_PASS_B or MODE_FINAL_F
+  int m;              // steps per interval
+  int64_t nint;       // intervals
+  const double *cin;  // [nint+1][nx]
+  double *cout;       // PASS_A: [nint+1][nx]
+  double *r;          // PASS_B: [nint][nx]
+  double *out;        // FINAL_F: [nint*m+1][nx]
+  double *normpart;   // PASS_B: [nint*ntiles]
+};
+
+hipError_t launch_tiles(const LevelDesc *desc, const TileGeom &tg, const TileArgs &ta, hipStream_t stream);
 
 // Launch the step kernel for one pass (mgrit_kernels.hip).  lds_bytes is
 // computed by the launcher.  Returns the HIP error of the launch.

@@ -40,30 +40,60 @@ __device__ __forceinline__ int wrap_lo(int i, int nx) {
 
 template <int L>
 __device__ __forceinline__ void load_chunk(const double *__restrict__ row, int base, int cnt, double (&x)[L]) {
+  if (cnt == L) {
 #pragma unroll
-  for (int j = 0; j < L; ++j) x[j] = (j < cnt) ? row[base + j] : 0.0;
+    for (int j = 0; j < L; ++j) x[j] = row[base + j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < L; ++j) x[j] = (j < cnt) ? row[base + j] : 0.0;
+  }
 }
 
 template <int L>
 __device__ __forceinline__ void store_chunk(double *__restrict__ row, int base, int cnt, const double (&x)[L]) {
+  if (cnt == L) {
 #pragma unroll
-  for (int j = 0; j < L; ++j)
-    if (j < cnt) row[base + j] = x[j];
+    for (int j = 0; j < L; ++j) row[base + j] = x[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < L; ++j)
+      if (j < cnt) row[base + j] = x[j];
+  }
 }
 
 template <int L>
 __device__ __forceinline__ void chunk_to_lds(double *vec, int base, int cnt, const double (&x)[L]) {
+  if (cnt == L) {
 #pragma unroll
-  for (int j = 0; j < L; ++j)
-    if (j < cnt) vec[padix(base + j)] = x[j];
+    for (int j = 0; j < L; ++j) vec[padix(base + j)] = x[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < L; ++j)
+      if (j < cnt) vec[padix(base + j)] = x[j];
+  }
 }
 
 // out[j] += w[0] * v[start+j] + ... + w[width-1] * v[start+j+width-1]
 // (indices periodic), reading the padded LDS copy v; 0 <= start < nx.  Each
-// LDS value is read once and scattered into the outputs it feeds.
+// LDS value is read once and scattered into the outputs it feeds.  Full
+// chunks whose window does not wrap take a branch-free path.
 template <int L>
 __device__ __forceinline__ void window_combine(const double *vec, int start, int cnt, int width, int nx,
                                                const double (&w)[MAXTAPS], double (&out)[L]) {
+  if (cnt == L && start + L + width - 1 <= nx) {
+#pragma unroll
+    for (int e = 0; e < L + MAXTAPS - 1; ++e) {
+      if (e < L + width - 1) {  // uniform
+        const double v = vec[padix(start + e)];
+#pragma unroll
+        for (int t = 0; t < MAXTAPS; ++t) {
+          const int j = e - t;
+          if (j >= 0 && j < L && t < width) out[j] = fma(w[t], v, out[j]);
+        }
+      }
+    }
+    return;
+  }
   int idx = start;
 #pragma unroll
   for (int e = 0; e < L + MAXTAPS - 1; ++e) {
@@ -103,22 +133,22 @@ __device__ __forceinline__ void recurrence(double (&x)[L], int cnt, int vt, int 
 #pragma unroll
   for (int m = 0; m < K; ++m) a[m] = ain[m];
 
-  // 1. zero-state pass over the chunk
+  // 1. zero-state pass over the chunk (branch-free when the chunk is full)
+  const bool full = (cnt == L);
   double s[K];
 #pragma unroll
   for (int m = 0; m < K; ++m) s[m] = 0.0;
 #pragma unroll
   for (int e = 0; e < L; ++e) {
     const int j = REV ? (L - 1 - e) : e;
-    if (e < cnt) {
-      double y = x[j];
+    double y = x[j];
 #pragma unroll
-      for (int m = 0; m < K; ++m) y = fma(a[m], s[m], y);
+    for (int m = 0; m < K; ++m) y = fma(a[m], s[m], y);
+    const bool on = full || e < cnt;
 #pragma unroll
-      for (int m = K - 1; m > 0; --m) s[m] = s[m - 1];
-      s[0] = y;
-      x[j] = y;
-    }
+    for (int m = K - 1; m > 0; --m) s[m] = on ? s[m - 1] : s[m];
+    s[0] = on ? y : s[0];
+    x[j] = on ? y : x[j];
   }
 
   // 2. inclusive scan of chunk states within the wavefront
@@ -136,7 +166,13 @@ __device__ __forceinline__ void recurrence(double (&x)[L], int cnt, int vt, int 
     double o[K];
 #pragma unroll
     for (int m = 0; m < K; ++m) o[m] = __shfl(inc[m], src, WAVE);
-    if (vl >= d) matvec_add<K>(tab + d * KK, o, inc);
+    double t[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) t[m] = inc[m];
+    matvec_add<K>(tab + d * KK, o, t);
+    const bool take = vl >= d;
+#pragma unroll
+    for (int m = 0; m < K; ++m) inc[m] = take ? t[m] : inc[m];
   }
   // exclusive value within the wavefront
   double ex[K];
@@ -204,7 +240,7 @@ __device__ __forceinline__ void recurrence(double (&x)[L], int cnt, int vt, int 
   __syncthreads();
 
   // 5. state entering this chunk, 6. homogeneous correction
-  if (cnt > 0) {
+  {
     double xc[K];
 #pragma unroll
     for (int m = 0; m < K; ++m) xc[m] = Xc[vw * K + m];
@@ -215,15 +251,13 @@ __device__ __forceinline__ void recurrence(double (&x)[L], int cnt, int vt, int 
 #pragma unroll
     for (int e = 0; e < L; ++e) {
       const int j = REV ? (L - 1 - e) : e;
-      if (e < cnt) {
-        double hv = 0.0;
+      double hv = 0.0;
 #pragma unroll
-        for (int m = 0; m < K; ++m) hv = fma(a[m], st[m], hv);
+      for (int m = 0; m < K; ++m) hv = fma(a[m], st[m], hv);
 #pragma unroll
-        for (int m = K - 1; m > 0; --m) st[m] = st[m - 1];
-        st[0] = hv;
-        x[j] += hv;
-      }
+      for (int m = K - 1; m > 0; --m) st[m] = st[m - 1];
+      st[0] = hv;
+      x[j] = (full || e < cnt) ? x[j] + hv : x[j];
     }
   }
 }
@@ -365,6 +399,122 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return tot;
 }
 
+// The chain of time steps of one pass (see PassMode): load the start vector,
+// advance it step by step with step(u) (all threads together), and do the
+// mode's per-step and final memory work.  cnt: points of this thread.
+template <int L, class Step>
+__device__ __forceinline__ void run_chain(const PassArgs &pa, int nx, int cnt, double *red, Step step) {
+  const int tid = threadIdx.x;
+  const int base = tid * L;
+  const int64_t b = blockIdx.x;
+  const int64_t nxl = nx;
+  const int m = pa.m;
+  const int mode = pa.mode;
+  double u[L];
+
+  int nsteps;
+  switch (mode) {
+    case MODE_PASS_A: nsteps = m; break;
+    case MODE_PASS_B: nsteps = m; break;
+    case MODE_POST_F: nsteps = m - 1; break;
+    case MODE_FINAL_F: nsteps = m - 1; break;
+    case MODE_SEQ: nsteps = m; break;
+    case MODE_APPLY: nsteps = m; break;
+    default: nsteps = 1; break;  // MODE_RESID
+  }
+  const int64_t row0 = (mode == MODE_SEQ) ? 0 : b;
+  if (pa.zero_init) {
+#pragma unroll
+    for (int j = 0; j < L; ++j) u[j] = 0.0;
+  } else {
+    load_chunk<L>(pa.cin + row0 * nxl, base, cnt, u);
+  }
+  if (mode == MODE_PASS_A && b == 0) store_chunk<L>(pa.cout, base, cnt, u);
+  if (mode == MODE_FINAL_F) store_chunk<L>(pa.out + (b * m) * nxl, base, cnt, u);
+  if (mode == MODE_SEQ && pa.out) store_chunk<L>(pa.out, base, cnt, u);
+  const bool add_g = pa.g && mode != MODE_APPLY && mode != MODE_RESID && mode != MODE_FINAL_F;
+  const bool add_parent = mode == MODE_POST_F || (mode == MODE_SEQ && pa.parent);
+  const bool store_out = mode == MODE_FINAL_F || (mode == MODE_SEQ && pa.out);
+  if (mode == MODE_POST_F) {
+    double pv[L];
+    load_chunk<L>(pa.parent + (b * m) * nxl, base, cnt, pv);
+#pragma unroll
+    for (int j = 0; j < L; ++j) pv[j] += u[j];
+    store_chunk<L>(pa.parent + (b * m) * nxl, base, cnt, pv);
+  }
+
+  // the chain of time steps (single call site of the step); for short chunks
+  // the rows this step adds are loaded before the step so their latency
+  // overlaps it
+  constexpr bool PREFETCH = L <= 16;
+  for (int j = 1; j <= nsteps; ++j) {
+    const int64_t n = (mode == MODE_SEQ) ? (int64_t)j : b * m + j;  // level point index
+    double gv[PREFETCH ? L : 1], pv[PREFETCH ? L : 1];
+    if (PREFETCH) {
+      if (add_g) load_chunk<PREFETCH ? L : 1>(pa.g + (n - 1) * nxl, base, cnt, gv);
+      if (add_parent) load_chunk<PREFETCH ? L : 1>(pa.parent + n * nxl, base, cnt, pv);
+    }
+    step(u);
+    if (add_g) {
+      if (PREFETCH) {
+#pragma unroll
+        for (int q = 0; q < (PREFETCH ? L : 1); ++q) u[q] += gv[q];
+      } else {
+        const double *gr = pa.g + (n - 1) * nxl + base;
+#pragma unroll
+        for (int q = 0; q < L; ++q)
+          if (q < cnt) u[q] += gr[q];
+      }
+    }
+    if (add_parent) {
+      double *pr = pa.parent + n * nxl + base;
+      if (PREFETCH) {
+#pragma unroll
+        for (int q = 0; q < (PREFETCH ? L : 1); ++q) pv[q] += u[q];
+        store_chunk<PREFETCH ? L : 1>(pa.parent + n * nxl, base, cnt, pv);
+      } else {
+#pragma unroll
+        for (int q = 0; q < L; ++q)
+          if (q < cnt) pr[q] += u[q];
+      }
+    }
+    if (store_out) store_chunk<L>(pa.out + n * nxl, base, cnt, u);
+  }
+
+  // post-chain actions
+  if (mode == MODE_PASS_A) {
+    store_chunk<L>(pa.cout + (b + 1) * nxl, base, cnt, u);
+  } else if (mode == MODE_PASS_B || mode == MODE_RESID) {
+    const double *__restrict__ c1 = pa.cin + (b + 1) * nxl;
+    double ss = 0.0;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      if (j < cnt) {
+        u[j] -= c1[base + j];
+        ss = fma(u[j], u[j], ss);
+      }
+    }
+    if (pa.r) store_chunk<L>(pa.r + b * nxl, base, cnt, u);
+    const double tot = block_sum(ss, red);
+    if (tid == 0) pa.normpart[b] = tot;
+  } else if (mode == MODE_POST_F || mode == MODE_FINAL_F) {
+    if (b == pa.nint - 1) {
+      load_chunk<L>(pa.cin + pa.nint * nxl, base, cnt, u);
+      double *row = (mode == MODE_POST_F ? pa.parent : pa.out) + (pa.nint * m) * nxl;
+      if (mode == MODE_POST_F) {
+        double pv[L];
+        load_chunk<L>(row, base, cnt, pv);
+#pragma unroll
+        for (int j = 0; j < L; ++j) u[j] += pv[j];
+      }
+      store_chunk<L>(row, base, cnt, u);
+    }
+  } else if (mode == MODE_APPLY) {
+    __syncthreads();  // in-place use: every thread has read its input row
+    store_chunk<L>(pa.cout + b * nxl, base, cnt, u);
+  }
+}
+
 template <int L, int KIND, int MAXT>
 __global__ void __launch_bounds__(MAXT) step_kernel(const LevelDesc *__restrict__ desc, PassArgs pa) {
   extern __shared__ double smem[];
@@ -416,99 +566,374 @@ __global__ void __launch_bounds__(MAXT) step_kernel(const LevelDesc *__restrict_
   __syncthreads();
 
   const int tid = threadIdx.x;
-  const int base = tid * L;
-  const int cnt = min(max(nx - base, 0), L);
-  const int64_t b = blockIdx.x;
-  const int64_t nxl = nx;
-  const int m = pa.m;
-  const int mode = pa.mode;
-  double u[L];
+  const int cnt = min(max(nx - tid * L, 0), L);
   int buf = 0;
+  run_chain<L>(pa, nx, cnt, S.red, [&](double (&u)[L]) { apply_step<L, KIND>(u, cnt, R, lay, S, buf); });
+}
 
-  int nsteps;
-  switch (mode) {
-    case MODE_PASS_A: nsteps = m; break;
-    case MODE_PASS_B: nsteps = m; break;
-    case MODE_POST_F: nsteps = m - 1; break;
-    case MODE_FINAL_F: nsteps = m - 1; break;
-    case MODE_SEQ: nsteps = m; break;
-    case MODE_APPLY: nsteps = m; break;
-    default: nsteps = 1; break;  // MODE_RESID
-  }
-  const int64_t row0 = (mode == MODE_SEQ) ? 0 : b;
-  if (pa.zero_init) {
-#pragma unroll
-    for (int j = 0; j < L; ++j) u[j] = 0.0;
-  } else {
-    load_chunk<L>(pa.cin + row0 * nxl, base, cnt, u);
-  }
-  if (mode == MODE_PASS_A && b == 0) store_chunk<L>(pa.cout, base, cnt, u);
-  if (mode == MODE_FINAL_F) store_chunk<L>(pa.out + (b * m) * nxl, base, cnt, u);
-  if (mode == MODE_SEQ && pa.out) store_chunk<L>(pa.out, base, cnt, u);
-  const bool add_g = pa.g && mode != MODE_APPLY && mode != MODE_RESID && mode != MODE_FINAL_F;
-  const bool add_parent = mode == MODE_POST_F || (mode == MODE_SEQ && pa.parent);
-  const bool store_out = mode == MODE_FINAL_F || (mode == MODE_SEQ && pa.out);
-  if (mode == MODE_POST_F) {
-    double pv[L];
-    load_chunk<L>(pa.parent + (b * m) * nxl, base, cnt, pv);
-#pragma unroll
-    for (int j = 0; j < L; ++j) pv[j] += u[j];
-    store_chunk<L>(pa.parent + (b * m) * nxl, base, cnt, pv);
-  }
+// ---------------------------------------------------------------------------
+// Level-0 explicit relaxation, one wavefront per (CF-interval, spatial tile).
+// Lane l holds the P consecutive points starting at x0 - HL + l P (periodic).
+// Each application of Z = -c L_p reads SL points from the left neighbour lane
+// and SR from the right one; lane 0's left and lane 63's right inputs are
+// stale, which only invalidates points inside the halo.  No LDS, no barriers.
+// ---------------------------------------------------------------------------
+template <int P, int SL, int SR>
+__global__ void __launch_bounds__(256) tile_kernel(const LevelDesc *__restrict__ desc, TileGeom tg, TileArgs ta) {
+  const StepOp &op = desc->op;
+  const int nx = desc->lay.nx;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t item = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (item >= ta.nint * tg.ntiles) return;  // whole wavefront leaves together
+  const int64_t b = item / tg.ntiles;
+  const int tau = (int)(item - b * tg.ntiles);
+  const int x0 = tau * tg.TW;
+  const int tw = min(tg.TW, nx - x0);
+  const int64_t nxl = nx;
 
-  // the chain of time steps (single call site of apply_step); the rows this
-  // step adds are loaded before the step so their latency overlaps it
+  // coefficients -> registers
+  const int ncoef = op.ncoef;
+  double taps[SL + SR + 1];
+#pragma unroll
+  for (int t = 0; t <= SL + SR; ++t) taps[t] = op.taps[t];
+  const double top = op.coef[ncoef - 1];
+
+  // this lane's first global position (periodic) and its local index
+  const int li0 = lane * P;              // local index of point 0 of this lane
+  int g0 = x0 - tg.HL + li0;             // global position, may be outside [0, nx)
+  g0 %= nx;
+  if (g0 < 0) g0 += nx;
+
+  double u[P];
+  {
+    const double *row = ta.cin + b * nxl;
+    int g = g0;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      u[k] = row[g];
+      g = wrap_hi(g + 1, nx);
+    }
+  }
+  // output window of this lane: local indices [HL, HL + tw)
+  const int lo = tg.HL - li0, hi = tg.HL + tw - li0;  // k in [lo, hi) is output
+
+  auto store_out = [&](double *row, const double (&v)[P]) {
+    int g = g0;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      if (k >= lo && k < hi) row[g] = v[k];
+      g = wrap_hi(g + 1, nx);
+    }
+  };
+
+  if (ta.mode == MODE_PASS_A && b == 0) store_out(ta.cout, u);
+  if (ta.mode == MODE_FINAL_F) store_out(ta.out + (b * ta.m) * nxl, u);
+
+  const int nsteps = (ta.mode == MODE_FINAL_F) ? ta.m - 1 : ta.m;
   for (int j = 1; j <= nsteps; ++j) {
-    const int64_t n = (mode == MODE_SEQ) ? (int64_t)j : b * m + j;  // level point index
-    double gv[L], pv[L];
-    if (add_g) load_chunk<L>(pa.g + (n - 1) * nxl, base, cnt, gv);
-    if (add_parent) load_chunk<L>(pa.parent + n * nxl, base, cnt, pv);
-    apply_step<L, KIND>(u, cnt, R, lay, S, buf);
-    if (add_g) {
+    double y[P];
 #pragma unroll
-      for (int q = 0; q < L; ++q) u[q] += gv[q];
-    }
-    if (add_parent) {
+    for (int k = 0; k < P; ++k) y[k] = top * u[k];
+    for (int i = ncoef - 2; i >= 0; --i) {
+      double lh[SL > 0 ? SL : 1], rh[SR > 0 ? SR : 1];
 #pragma unroll
-      for (int q = 0; q < L; ++q) pv[q] += u[q];
-      store_chunk<L>(pa.parent + n * nxl, base, cnt, pv);
+      for (int q = 0; q < SL; ++q) lh[q] = __shfl(y[P - SL + q], (lane - 1) & (WAVE - 1), WAVE);
+#pragma unroll
+      for (int q = 0; q < SR; ++q) rh[q] = __shfl(y[q], (lane + 1) & (WAVE - 1), WAVE);
+      const double ci = op.coef[i];
+      double yn[P];
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        double acc = ci * u[k];
+#pragma unroll
+        for (int t = 0; t <= SL + SR; ++t) {
+          const int src = k + t - SL;
+          const double v = src < 0 ? lh[(src + SL) < 0 ? 0 : (src + SL)]
+                                   : (src >= P ? rh[(src - P) < SR ? (src - P) : 0] : y[src < P ? src : 0]);
+          acc = fma(taps[t], v, acc);
+        }
+        yn[k] = acc;
+      }
+#pragma unroll
+      for (int k = 0; k < P; ++k) y[k] = yn[k];
     }
-    if (store_out) store_chunk<L>(pa.out + n * nxl, base, cnt, u);
+#pragma unroll
+    for (int k = 0; k < P; ++k) u[k] = y[k];
+    if (ta.mode == MODE_FINAL_F) store_out(ta.out + (b * ta.m + j) * nxl, u);
   }
 
-  // post-chain actions
-  if (mode == MODE_PASS_A) {
-    store_chunk<L>(pa.cout + (b + 1) * nxl, base, cnt, u);
-  } else if (mode == MODE_PASS_B || mode == MODE_RESID) {
-    const double *__restrict__ c1 = pa.cin + (b + 1) * nxl;
+  if (ta.mode == MODE_PASS_A) {
+    store_out(ta.cout + (b + 1) * nxl, u);
+  } else if (ta.mode == MODE_PASS_B) {
+    const double *c1 = ta.cin + (b + 1) * nxl;
     double ss = 0.0;
+    int g = g0;
 #pragma unroll
-    for (int j = 0; j < L; ++j) {
-      if (j < cnt) {
-        u[j] -= c1[base + j];
-        ss = fma(u[j], u[j], ss);
+    for (int k = 0; k < P; ++k) {
+      if (k >= lo && k < hi) {
+        const double rv = u[k] - c1[g];
+        ta.r[b * nxl + g] = rv;
+        ss = fma(rv, rv, ss);
       }
+      g = wrap_hi(g + 1, nx);
     }
-    if (pa.r) store_chunk<L>(pa.r + b * nxl, base, cnt, u);
-    const double tot = block_sum(ss, S.red);
-    if (tid == 0) pa.normpart[b] = tot;
-  } else if (mode == MODE_POST_F || mode == MODE_FINAL_F) {
-    if (b == pa.nint - 1) {
-      load_chunk<L>(pa.cin + pa.nint * nxl, base, cnt, u);
-      double *row = (mode == MODE_POST_F ? pa.parent : pa.out) + (pa.nint * m) * nxl;
-      if (mode == MODE_POST_F) {
-        double pv[L];
-        load_chunk<L>(row, base, cnt, pv);
 #pragma unroll
-        for (int j = 0; j < L; ++j) u[j] += pv[j];
-      }
-      store_chunk<L>(row, base, cnt, u);
+    for (int d = WAVE / 2; d > 0; d >>= 1) ss += __shfl_down(ss, d, WAVE);
+    if (lane == 0) ta.normpart[item] = ss;
+  } else if (ta.mode == MODE_FINAL_F && b == ta.nint - 1) {
+    double c[P];
+    const double *row = ta.cin + ta.nint * nxl;
+    int g = g0;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      c[k] = row[g];
+      g = wrap_hi(g + 1, nx);
     }
-  } else if (mode == MODE_APPLY) {
-    __syncthreads();  // in-place use: every thread has read its input row
-    store_chunk<L>(pa.cout + b * nxl, base, cnt, u);
+    store_out(ta.out + (ta.nint * ta.m) * nxl, c);
   }
 }
+
+template <int P>
+hipError_t launch_tiles_p(const LevelDesc *desc, const TileGeom &tg, const TileArgs &ta, hipStream_t stream) {
+  const int64_t items = ta.nint * tg.ntiles;
+  const dim3 grid((unsigned)((items + 3) / 4)), block(256);
+  switch (tg.sl * 4 + tg.sr) {
+    case 1 * 4 + 0: hipLaunchKernelGGL((tile_kernel<P, 1, 0>), grid, block, 0, stream, desc, tg, ta); break;
+    case 2 * 4 + 0: hipLaunchKernelGGL((tile_kernel<P, 2, 0>), grid, block, 0, stream, desc, tg, ta); break;
+    case 2 * 4 + 1: hipLaunchKernelGGL((tile_kernel<P, 2, 1>), grid, block, 0, stream, desc, tg, ta); break;
+    case 3 * 4 + 1: hipLaunchKernelGGL((tile_kernel<P, 3, 1>), grid, block, 0, stream, desc, tg, ta); break;
+    case 3 * 4 + 2: hipLaunchKernelGGL((tile_kernel<P, 3, 2>), grid, block, 0, stream, desc, tg, ta); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// Coarse time step Psi = T^{-1} S on full chunks (nx = T L, T a multiple of
+// 64): W interpolation taps, order-K forward and backward recurrences.  One
+// barrier per recurrence: after the wavefront totals are published, every
+// wavefront folds them and the periodic wrap into its own carry (the same
+// short chain, computed redundantly), so no thread waits for a serial one.
+// ---------------------------------------------------------------------------
+template <int L, int K, bool REV>
+__device__ __forceinline__ void lean_recurrence(double (&x)[L], int vt, int T, const double (&a)[K],
+                                                const double *tab, double *Q) {
+  constexpr int KK = K * K;
+  // zero-state pass
+  double s[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) s[m] = 0.0;
+#pragma unroll
+  for (int e = 0; e < L; ++e) {
+    const int j = REV ? (L - 1 - e) : e;
+    double y = x[j];
+#pragma unroll
+    for (int m = 0; m < K; ++m) y = fma(a[m], s[m], y);
+#pragma unroll
+    for (int m = K - 1; m > 0; --m) s[m] = s[m - 1];
+    s[0] = y;
+    x[j] = y;
+  }
+  // inclusive scan within the wavefront
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int nw = T >> 6;
+  const int vl = REV ? (WAVE - 1 - lane) : lane;
+  const int vw = vt >> 6;
+  double inc[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) inc[m] = s[m];
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const int src = (REV ? (lane + d) : (lane - d)) & (WAVE - 1);
+    double o[K], t[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      o[m] = __shfl(inc[m], src, WAVE);
+      t[m] = inc[m];
+    }
+    matvec_add<K>(tab + d * KK, o, t);
+    const bool take = vl >= d;
+#pragma unroll
+    for (int m = 0; m < K; ++m) inc[m] = take ? t[m] : inc[m];
+  }
+  double ex[K];
+  {
+    const int src = (REV ? (lane + 1) : (lane - 1)) & (WAVE - 1);
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      const double o = __shfl(inc[m], src, WAVE);
+      ex[m] = (vl >= 1) ? o : 0.0;
+    }
+  }
+  // publish: wavefront totals, and for the last chunk its exclusive value
+  // within its wavefront and its own zero-state result
+  if (vl == WAVE - 1) {
+#pragma unroll
+    for (int m = 0; m < K; ++m) Q[vw * K + m] = inc[m];
+  }
+  if (vt == T - 2) {
+#pragma unroll
+    for (int m = 0; m < K; ++m) Q[MAXWAVES * K + m] = inc[m];
+  }
+  if (vt == T - 1) {
+#pragma unroll
+    for (int m = 0; m < K; ++m) Q[(MAXWAVES + 1) * K + m] = s[m];
+  }
+  __syncthreads();
+  const double *H64 = tab + WAVE * KK;
+  const double *Hlast = tab + (WAVE + 1) * KK;
+  const double *Wwrap = tab + (WAVE + 2) * KK;
+  // carry into the last wavefront (without the wrap)
+  double X[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) X[m] = 0.0;
+#pragma unroll
+  for (int w2 = 0; w2 < MAXWAVES - 1; ++w2) {
+    if (w2 < nw - 1) {
+      double nxt[K];
+#pragma unroll
+      for (int m = 0; m < K; ++m) nxt[m] = Q[w2 * K + m];
+      matvec_add<K>(H64, X, nxt);
+#pragma unroll
+      for (int m = 0; m < K; ++m) X[m] = nxt[m];
+    }
+  }
+  // E_{A-1}, the wrap s_0 = W (Hlast E + q), then this wavefront's carry
+  double E[K], tq[K], xp[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    E[m] = (nw > 1 || T > 1) ? Q[MAXWAVES * K + m] : 0.0;
+    tq[m] = Q[(MAXWAVES + 1) * K + m];
+    xp[m] = 0.0;
+  }
+  matvec_add<K>(tab + (WAVE - 1) * KK, X, E);
+  matvec_add<K>(Hlast, E, tq);
+  matvec_add<K>(Wwrap, tq, xp);
+#pragma unroll
+  for (int w2 = 0; w2 < MAXWAVES - 1; ++w2) {
+    if (w2 < vw) {
+      double nxt[K];
+#pragma unroll
+      for (int m = 0; m < K; ++m) nxt[m] = Q[w2 * K + m];
+      matvec_add<K>(H64, xp, nxt);
+#pragma unroll
+      for (int m = 0; m < K; ++m) xp[m] = nxt[m];
+    }
+  }
+  double st[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) st[m] = ex[m];
+  matvec_add<K>(tab + vl * KK, xp, st);
+#pragma unroll
+  for (int e = 0; e < L; ++e) {
+    const int j = REV ? (L - 1 - e) : e;
+    double hv = 0.0;
+#pragma unroll
+    for (int m = 0; m < K; ++m) hv = fma(a[m], st[m], hv);
+#pragma unroll
+    for (int m = K - 1; m > 0; --m) st[m] = st[m - 1];
+    st[0] = hv;
+    x[j] += hv;
+  }
+}
+
+template <int L, int W, int K, int MAXT>
+__global__ void __launch_bounds__(MAXT) slc_kernel(const LevelDesc *__restrict__ desc, PassArgs pa) {
+  extern __shared__ double smem[];
+  const int nx = desc->lay.nx;
+  const int T = desc->lay.T;
+  const int dbuf = desc->lay.dbuf;
+  const StepOp &op = desc->op;
+  const LeanLds lo = lean_lds_offsets(nx, dbuf, K);
+  double *vec0 = smem;
+  double *vec1 = smem + lo.vec1;
+  double *tab_f = smem + lo.tab_f;
+  double *tab_b = smem + lo.tab_b;
+  double *qf = smem + lo.qf;
+  double *qb = smem + lo.qb;
+  double *red = smem + lo.red;
+
+  double w[W], af[K], ab[K];
+#pragma unroll
+  for (int t = 0; t < W; ++t) w[t] = op.slw[t];
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    af[m] = op.fw.a[m];
+    ab[m] = op.bw.a[m];
+  }
+  const int off = op.sl_K + op.sl_l;
+  const double cinv = op.cinv;
+  for (int i = threadIdx.x; i < RTAB * K * K; i += blockDim.x) {
+    tab_f[i] = op.fw.tab[i];
+    tab_b[i] = op.bw.tab[i];
+  }
+  __syncthreads();
+
+  const int tid = threadIdx.x;
+  const int base = tid * L;
+  int start = base - off;
+  while (start < 0) start += nx;
+  int buf = 0;
+  run_chain<L>(pa, nx, L, red, [=](double (&u)[L]) mutable {
+    double *v = buf ? vec1 : vec0;
+    buf ^= dbuf;
+    if (!dbuf) __syncthreads();
+#pragma unroll
+    for (int j = 0; j < L; ++j) v[padix(base + j)] = u[j];
+    __syncthreads();
+    double y[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) y[j] = 0.0;
+#pragma unroll
+    for (int e = 0; e < L + W - 1; ++e) {
+      int idx = start + e;
+      idx = idx >= nx ? idx - nx : idx;
+      const double val = v[padix(idx)];
+#pragma unroll
+      for (int t = 0; t < W; ++t) {
+        const int j = e - t;
+        if (j >= 0 && j < L) y[j] = fma(w[t], val, y[j]);
+      }
+    }
+    lean_recurrence<L, K, false>(y, tid, T, af, tab_f, qf);
+    lean_recurrence<L, K, true>(y, T - 1 - tid, T, ab, tab_b, qb);
+#pragma unroll
+    for (int j = 0; j < L; ++j) u[j] = y[j] * cinv;
+  });
+}
+
+template <int L, int W, int K>
+hipError_t slc_launch(const LevelDesc *desc, const Layout &lay, const PassArgs &pa, hipStream_t stream) {
+  const size_t lds = (size_t)lean_lds_offsets(lay.nx, lay.dbuf, K).total * sizeof(double);
+  const dim3 grid((unsigned)pa.nint), block((unsigned)lay.T);
+  if (lay.T <= 256)
+    hipLaunchKernelGGL((slc_kernel<L, W, K, 256>), grid, block, lds, stream, desc, pa);
+  else
+    hipLaunchKernelGGL((slc_kernel<L, W, K, 1024>), grid, block, lds, stream, desc, pa);
+  return hipGetLastError();
+}
+
+template <int L, int W, int K>
+hipError_t slc_set_lds(size_t bytes) {
+  hipError_t e = hipFuncSetAttribute((const void *)slc_kernel<L, W, K, 256>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e) return e;
+  return hipFuncSetAttribute((const void *)slc_kernel<L, W, K, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+template <int L>
+hipError_t slc_launch_l(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs &pa,
+                        hipStream_t stream) {
+  const int W = op.sl_l + op.sl_r + 1;
+  if (W == 2 && op.fw.k == 1) return slc_launch<L, 2, 1>(desc, lay, pa, stream);
+  if (W == 4 && op.fw.k == 2) return slc_launch<L, 4, 2>(desc, lay, pa, stream);
+  if (W == 6 && op.fw.k == 3) return slc_launch<L, 6, 3>(desc, lay, pa, stream);
+  return hipErrorInvalidValue;
+}
+
+
 
 __global__ void __launch_bounds__(256) reduce_kernel(const double *__restrict__ part, int64_t n,
                                                       double *__restrict__ out) {
@@ -590,6 +1015,14 @@ size_t lds_bytes_for(const Layout &lay, int has_solve) {
 
 hipError_t configure_kernels(size_t bytes) {
   hipError_t e;
+#define MGRIT_SLC_SET(L)                                        \
+  if ((e = slc_set_lds<L, 2, 1>(bytes))) return e;              \
+  if ((e = slc_set_lds<L, 4, 2>(bytes))) return e;              \
+  if ((e = slc_set_lds<L, 6, 3>(bytes))) return e;
+  MGRIT_SLC_SET(4)
+  MGRIT_SLC_SET(8)
+  MGRIT_SLC_SET(16)
+#undef MGRIT_SLC_SET
   if ((e = set_lds_all<OP_POLY_Z>(bytes))) return e;
   if ((e = set_lds_all<OP_POLY_W>(bytes))) return e;
   return set_lds_all<OP_SLC>(bytes);
@@ -598,11 +1031,29 @@ hipError_t configure_kernels(size_t bytes) {
 hipError_t launch_pass(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs &pa,
                        hipStream_t stream) {
   if (pa.nint <= 0) return hipSuccess;
+  if (lean_slc_applies(op, lay)) {
+    switch (lay.L) {
+      case 4: return slc_launch_l<4>(desc, op, lay, pa, stream);
+      case 8: return slc_launch_l<8>(desc, op, lay, pa, stream);
+      case 16: return slc_launch_l<16>(desc, op, lay, pa, stream);
+      default: break;
+    }
+  }
   const size_t lds = lds_bytes_for(lay, op.has_solve);
   switch (op.kind) {
     case OP_POLY_Z: return launch_kind<OP_POLY_Z>(desc, lay, pa, lds, stream);
     case OP_POLY_W: return launch_kind<OP_POLY_W>(desc, lay, pa, lds, stream);
     case OP_SLC: return launch_kind<OP_SLC>(desc, lay, pa, lds, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_tiles(const LevelDesc *desc, const TileGeom &tg, const TileArgs &ta, hipStream_t stream) {
+  if (ta.nint <= 0) return hipSuccess;
+  switch (tg.P) {
+    case 8: return launch_tiles_p<8>(desc, tg, ta, stream);
+    case 16: return launch_tiles_p<16>(desc, tg, ta, stream);
+    case 32: return launch_tiles_p<32>(desc, tg, ta, stream);
     default: return hipErrorInvalidValue;
   }
 }

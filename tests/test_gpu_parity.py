@@ -256,3 +256,35 @@ def test_config3_full_size_properties():
     np.testing.assert_allclose(out[:4].cpu().numpy(), seq, atol=1e-9)
     # whole-solution residual from the library equals a sampled recomputation's scale
     assert s.residual(out) <= 1e-8 * np.linalg.norm(u0) * np.sqrt(nt)
+
+
+# --------------------------------------------------------------------------
+# level-0 explicit relaxation through wavefront tiles (temporal blocking)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tile_p", [8, 16, 32])
+@pytest.mark.parametrize("p,q,c,coarse,ms", [(1, 1, 0.85, "sl_corrected", [4]), (2, 2, 0.45, "ideal", [4]),
+                                             (3, 3, 1.2, "sl_corrected", [8, 4]), (4, 4, 0.9, "ideal", [2]),
+                                             (5, 5, 0.9, "sl_corrected", [4, 4])])
+def test_tiled_relaxation_matches_oracle(monkeypatch, tile_p, p, q, c, coarse, ms):
+    _announce("tiles", tile_p, p, q, c, coarse, ms)
+    monkeypatch.setenv("MGRIT_TILE_P", str(tile_p))
+    nx, nt = 300, 128
+    s, info, got, fin, ref, rinfo = _solve_both(nx, nt, p, "erk", q, c, ms, coarse=coarse, u0kind="fourier")
+    _check_parity(info, got, fin, ref, rinfo, ms[0])
+
+
+def test_tiled_and_slab_relaxation_agree(monkeypatch):
+    _announce("tiles vs slab")
+    nx, nt = 1024, 512
+    u0 = inputs.u0_fourier(nx, 21)
+    v0 = _t(inputs.initial_iterate(nt, nx, u0, 21))
+    outs = []
+    for flag in ("0", "1"):
+        monkeypatch.setenv("MGRIT_NO_TILES", flag)
+        s = mgrit.Solver(mgrit.make_problem(nx, nt, 0.85, 3), mgrit.make_options([8, 8], max_levels=3))
+        o = torch.empty((nt + 1, nx), dtype=torch.float64, device=DEV)
+        info = s.solve(_t(u0), v0, u_out=o)
+        outs.append((info["iterations"], _np(o)))
+    assert outs[0][0] == outs[1][0]
+    np.testing.assert_allclose(outs[0][1], outs[1][1], rtol=0, atol=1e-14 * np.max(np.abs(outs[1][1])))
