@@ -452,6 +452,7 @@ void recurrence_tables(int k, const ld *a, const Layout &lay, std::vector<double
   invert(Iw, k, Wwrap);
   for (ld v : Hlast) out.push_back((double)v);
   for (ld v : Wwrap) out.push_back((double)v);
+  for (ld v : mpow(M, lay.L / 2)) out.push_back((double)v);
 }
 
 // Work distribution: L points per thread (a kernel template parameter).
@@ -864,6 +865,7 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
       Lv.lay = choose_layout(nx, Lcoarse);
       Lv.lay.dbuf = 1;
       if (lean_lds_offsets(nx, 1, KMAX).total * sizeof(double) > LDS_LIMIT) Lv.lay.dbuf = 0;
+      if (lds_bytes_for(Lv.lay, 1) > LDS_LIMIT) Lv.lay.dbuf = 0;
       if (!attach_solve(op, taps, Lv.lay, tabs[l], offs[l], err)) {
         mgrit_destroy(h);
         return bad(MGRIT_EINVAL, "coarse operator: " + err);
@@ -876,7 +878,8 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
   size_t maxlds = 0;
   for (int l = 0; l < nlev; ++l) {
     maxlds = std::max(maxlds, lds_bytes_for(h->lv[l].lay, h->lv[l].op.has_solve));
-    maxlds = std::max(maxlds, lean_lds_offsets(nx, h->lv[l].lay.dbuf, KMAX).total * sizeof(double));
+    const size_t lean = lean_lds_offsets(nx, h->lv[l].lay.dbuf, KMAX).total * sizeof(double);
+    if (lean <= LDS_LIMIT) maxlds = std::max(maxlds, lean);
   }
   if (hipError_t e = configure_kernels(maxlds)) {
     mgrit_destroy(h);

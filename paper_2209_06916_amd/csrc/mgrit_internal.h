@@ -31,8 +31,8 @@ enum OpKind : int { OP_POLY_Z = 0, OP_POLY_W = 1, OP_SLC = 2 };
 // of L consecutive points.  tab holds RTAB matrices of k*k doubles, for this
 // chunk layout (M the companion matrix, H = M^L, A threads own points):
 //   Hpow[t] = H^t, t = 0..64, then Hlast = M^{Llast},
-//   then Wwrap = (I - Hlast * H^{A-1})^{-1}.
-constexpr int RTAB = WAVE + 3;
+//   then Wwrap = (I - Hlast * H^{A-1})^{-1}, then Hhalf = M^{L/2}.
+constexpr int RTAB = WAVE + 4;
 struct Recurrence {
   int k;
   double a[KMAX];
@@ -102,7 +102,7 @@ struct LevelDesc {
 
 // LDS layout of the lean coarse-step kernel (in doubles).
 struct LeanLds {
-  int vec1, tab_f, tab_b, qf, qb, red, total;
+  int vec1, gbuf, tab_f, tab_b, qf, qb, red, total;
 };
 
 __host__ __device__ inline LeanLds lean_lds_offsets(int nx, int dbuf, int K) {
@@ -111,6 +111,8 @@ __host__ __device__ inline LeanLds lean_lds_offsets(int nx, int dbuf, int K) {
   int off = pv;
   o.vec1 = dbuf ? off : 0;
   if (dbuf) off += pv;
+  o.gbuf = off;  // right-hand-side row staged for the chunked add
+  off += pv;
   o.tab_f = off;
   off += RTAB * K * K;
   o.tab_b = off;
@@ -131,7 +133,8 @@ __host__ __device__ inline LeanLds lean_lds_offsets(int nx, int dbuf, int K) {
 inline bool lean_slc_applies(const StepOp &op, const Layout &lay) {
   const int W = op.sl_l + op.sl_r + 1;
   return op.kind == OP_SLC && op.has_solve && op.repeat == 1 && !lay.ragged && lay.A == lay.T &&
-         (lay.L == 4 || lay.L == 8 || lay.L == 16) && op.fw.k == op.bw.k && op.fw.k >= 1 && W == 2 * op.fw.k;
+         (lay.L == 4 || lay.L == 8 || lay.L == 16) && op.fw.k == op.bw.k && op.fw.k >= 1 && W == 2 * op.fw.k &&
+         lean_lds_offsets(lay.nx, lay.dbuf, op.fw.k).total * sizeof(double) <= 160 * 1024;
 }
 
 enum PassMode : int {

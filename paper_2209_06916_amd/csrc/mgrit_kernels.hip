@@ -716,75 +716,137 @@ hipError_t launch_tiles_p(const LevelDesc *desc, const TileGeom &tg, const TileA
 // wavefront folds them and the periodic wrap into its own carry (the same
 // short chain, computed redundantly), so no thread waits for a serial one.
 // ---------------------------------------------------------------------------
-template <int L, int K, bool REV>
-__device__ __forceinline__ void lean_recurrence(double (&x)[L], int vt, int T, const double (&a)[K],
-                                                const double *tab, double *Q) {
+// Cross-lane move of a double with a DPP row shift (bound_ctrl: lanes whose
+// source lies outside their 16-lane row read 0).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(bits & 0xffffffff), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffff), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), lane);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+// One Kogge-Stone step inside 16-lane rows: take the state D lanes back in
+// processing order (row_shr for the forward direction, row_shl backward).
+template <int K, bool REV, int D>
+__device__ __forceinline__ void row_scan_step(double (&inc)[K], const double *tab, int lr) {
   constexpr int KK = K * K;
-  // zero-state pass
-  double s[K];
+  double o[K], t[K];
 #pragma unroll
-  for (int m = 0; m < K; ++m) s[m] = 0.0;
-#pragma unroll
-  for (int e = 0; e < L; ++e) {
-    const int j = REV ? (L - 1 - e) : e;
-    double y = x[j];
-#pragma unroll
-    for (int m = 0; m < K; ++m) y = fma(a[m], s[m], y);
-#pragma unroll
-    for (int m = K - 1; m > 0; --m) s[m] = s[m - 1];
-    s[0] = y;
-    x[j] = y;
+  for (int m = 0; m < K; ++m) {
+    o[m] = REV ? dpp_d<0x100 + D>(inc[m]) : dpp_d<0x110 + D>(inc[m]);
+    t[m] = inc[m];
   }
-  // inclusive scan within the wavefront
+  matvec_add<K>(tab + D * KK, o, t);
+  const bool take = lr >= D;
+#pragma unroll
+  for (int m = 0; m < K; ++m) inc[m] = take ? t[m] : inc[m];
+}
+
+template <int L, int K, bool REV, class Hook>
+__device__ __forceinline__ void lean_recurrence(double (&x)[L], int vt, int T, const double (&a)[K],
+                                                const double *tab, double *Q, Hook pre_barrier) {
+  constexpr int KK = K * K;
+  constexpr int LH = L / 2;  // two interleaved sub-chains per lane
+  const double *Hhalf = tab + (WAVE + 3) * KK;
+  // zero-state passes of both halves (processing order: REV walks down)
+  double sa[K], sb[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) sa[m] = sb[m] = 0.0;
+#pragma unroll
+  for (int e = 0; e < LH; ++e) {
+    const int ja = REV ? (L - 1 - e) : e;
+    const int jb = REV ? (LH - 1 - e) : (LH + e);
+    double ya = x[ja], yb = x[jb];
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      ya = fma(a[m], sa[m], ya);
+      yb = fma(a[m], sb[m], yb);
+    }
+#pragma unroll
+    for (int m = K - 1; m > 0; --m) {
+      sa[m] = sa[m - 1];
+      sb[m] = sb[m - 1];
+    }
+    sa[0] = ya;
+    sb[0] = yb;
+    x[ja] = ya;
+    x[jb] = yb;
+  }
+  // chunk total q = Hhalf sa + sb
+  double q[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) q[m] = sb[m];
+  matvec_add<K>(Hhalf, sa, q);
+
+  // scan inside 16-lane rows (DPP), then fold the row totals (readlane)
   const int lane = threadIdx.x & (WAVE - 1);
   const int nw = T >> 6;
   const int vl = REV ? (WAVE - 1 - lane) : lane;
   const int vw = vt >> 6;
+  const int lr = vl & 15, vrow = vl >> 4;
   double inc[K];
 #pragma unroll
-  for (int m = 0; m < K; ++m) inc[m] = s[m];
+  for (int m = 0; m < K; ++m) inc[m] = q[m];
+  row_scan_step<K, REV, 1>(inc, tab, lr);
+  row_scan_step<K, REV, 2>(inc, tab, lr);
+  row_scan_step<K, REV, 4>(inc, tab, lr);
+  row_scan_step<K, REV, 8>(inc, tab, lr);
+  double exr[K];
 #pragma unroll
-  for (int d = 1; d < WAVE; d <<= 1) {
-    const int src = (REV ? (lane + d) : (lane - d)) & (WAVE - 1);
-    double o[K], t[K];
-#pragma unroll
-    for (int m = 0; m < K; ++m) {
-      o[m] = __shfl(inc[m], src, WAVE);
-      t[m] = inc[m];
-    }
-    matvec_add<K>(tab + d * KK, o, t);
-    const bool take = vl >= d;
-#pragma unroll
-    for (int m = 0; m < K; ++m) inc[m] = take ? t[m] : inc[m];
+  for (int m = 0; m < K; ++m) {
+    const double o = REV ? dpp_d<0x101>(inc[m]) : dpp_d<0x111>(inc[m]);
+    exr[m] = lr >= 1 ? o : 0.0;
   }
+  // row carries C_r (state entering virtual row r), uniform over the wavefront
+  double C1[K], C2[K], C3[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    C1[m] = readlane_d(inc[m], REV ? 48 : 15);
+    C2[m] = readlane_d(inc[m], REV ? 32 : 31);
+    C3[m] = readlane_d(inc[m], REV ? 16 : 47);
+  }
+  const double *H16 = tab + 16 * KK;
+  matvec_add<K>(H16, C1, C2);
+  matvec_add<K>(H16, C2, C3);
+  double cr[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) cr[m] = vrow == 0 ? 0.0 : (vrow == 1 ? C1[m] : (vrow == 2 ? C2[m] : C3[m]));
+  // exclusive prefix within the wavefront: ex = exr + H^lr C_row
   double ex[K];
-  {
-    const int src = (REV ? (lane + 1) : (lane - 1)) & (WAVE - 1);
 #pragma unroll
-    for (int m = 0; m < K; ++m) {
-      const double o = __shfl(inc[m], src, WAVE);
-      ex[m] = (vl >= 1) ? o : 0.0;
-    }
-  }
-  // publish: wavefront totals, and for the last chunk its exclusive value
-  // within its wavefront and its own zero-state result
+  for (int m = 0; m < K; ++m) ex[m] = exr[m];
+  matvec_add<K>(tab + lr * KK, cr, ex);
+
+  // publish: wavefront totals q + H ex (virtual lane 63), and the last
+  // chunk's exclusive value and own zero-state total
   if (vl == WAVE - 1) {
+    double tot[K];
 #pragma unroll
-    for (int m = 0; m < K; ++m) Q[vw * K + m] = inc[m];
-  }
-  if (vt == T - 2) {
+    for (int m = 0; m < K; ++m) tot[m] = q[m];
+    matvec_add<K>(tab + KK, ex, tot);
 #pragma unroll
-    for (int m = 0; m < K; ++m) Q[MAXWAVES * K + m] = inc[m];
+    for (int m = 0; m < K; ++m) Q[vw * K + m] = tot[m];
   }
   if (vt == T - 1) {
 #pragma unroll
-    for (int m = 0; m < K; ++m) Q[(MAXWAVES + 1) * K + m] = s[m];
+    for (int m = 0; m < K; ++m) {
+      Q[MAXWAVES * K + m] = ex[m];
+      Q[(MAXWAVES + 1) * K + m] = q[m];
+    }
   }
+  pre_barrier();
   __syncthreads();
   const double *H64 = tab + WAVE * KK;
   const double *Hlast = tab + (WAVE + 1) * KK;
   const double *Wwrap = tab + (WAVE + 2) * KK;
-  // carry into the last wavefront (without the wrap)
   double X[K];
 #pragma unroll
   for (int m = 0; m < K; ++m) X[m] = 0.0;
@@ -799,11 +861,10 @@ __device__ __forceinline__ void lean_recurrence(double (&x)[L], int vt, int T, c
       for (int m = 0; m < K; ++m) X[m] = nxt[m];
     }
   }
-  // E_{A-1}, the wrap s_0 = W (Hlast E + q), then this wavefront's carry
   double E[K], tq[K], xp[K];
 #pragma unroll
   for (int m = 0; m < K; ++m) {
-    E[m] = (nw > 1 || T > 1) ? Q[MAXWAVES * K + m] : 0.0;
+    E[m] = Q[MAXWAVES * K + m];
     tq[m] = Q[(MAXWAVES + 1) * K + m];
     xp[m] = 0.0;
   }
@@ -821,21 +882,43 @@ __device__ __forceinline__ void lean_recurrence(double (&x)[L], int vt, int T, c
       for (int m = 0; m < K; ++m) xp[m] = nxt[m];
     }
   }
-  double st[K];
+  // states entering the two halves, then the homogeneous corrections
+  double ta[K], tb[K];
 #pragma unroll
-  for (int m = 0; m < K; ++m) st[m] = ex[m];
-  matvec_add<K>(tab + vl * KK, xp, st);
-#pragma unroll
-  for (int e = 0; e < L; ++e) {
-    const int j = REV ? (L - 1 - e) : e;
-    double hv = 0.0;
-#pragma unroll
-    for (int m = 0; m < K; ++m) hv = fma(a[m], st[m], hv);
-#pragma unroll
-    for (int m = K - 1; m > 0; --m) st[m] = st[m - 1];
-    st[0] = hv;
-    x[j] += hv;
+  for (int m = 0; m < K; ++m) {
+    ta[m] = ex[m];
+    tb[m] = sa[m];
   }
+  matvec_add<K>(tab + vl * KK, xp, ta);
+  matvec_add<K>(Hhalf, ta, tb);
+#pragma unroll
+  for (int e = 0; e < LH; ++e) {
+    const int ja = REV ? (L - 1 - e) : e;
+    const int jb = REV ? (LH - 1 - e) : (LH + e);
+    double ha = 0.0, hb = 0.0;
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      ha = fma(a[m], ta[m], ha);
+      hb = fma(a[m], tb[m], hb);
+    }
+#pragma unroll
+    for (int m = K - 1; m > 0; --m) {
+      ta[m] = ta[m - 1];
+      tb[m] = tb[m - 1];
+    }
+    ta[0] = ha;
+    tb[0] = hb;
+    x[ja] += ha;
+    x[jb] += hb;
+  }
+}
+
+// Coalesced row segments: thread t owns the 16-byte pairs t + T q, q < L/2.
+template <int L>
+__device__ __forceinline__ void load_segs(const double *__restrict__ row, int T, double2 (&seg)[L / 2]) {
+  const double2 *r2 = reinterpret_cast<const double2 *>(row);
+#pragma unroll
+  for (int q = 0; q < L / 2; ++q) seg[q] = r2[threadIdx.x + T * q];
 }
 
 template <int L, int W, int K, int MAXT>
@@ -848,6 +931,7 @@ __global__ void __launch_bounds__(MAXT) slc_kernel(const LevelDesc *__restrict__
   const LeanLds lo = lean_lds_offsets(nx, dbuf, K);
   double *vec0 = smem;
   double *vec1 = smem + lo.vec1;
+  double *gbuf = smem + lo.gbuf;
   double *tab_f = smem + lo.tab_f;
   double *tab_b = smem + lo.tab_b;
   double *qf = smem + lo.qf;
@@ -874,17 +958,64 @@ __global__ void __launch_bounds__(MAXT) slc_kernel(const LevelDesc *__restrict__
   const int base = tid * L;
   int start = base - off;
   while (start < 0) start += nx;
+  const int64_t b = blockIdx.x;
+  const int64_t nxl = nx;
+  const int m = pa.m;
+  const int mode = pa.mode;
+  int nsteps;
+  switch (mode) {
+    case MODE_POST_F: nsteps = m - 1; break;
+    default: nsteps = m; break;  // PASS_A, PASS_B, SEQ, APPLY
+  }
+  const int64_t row0 = (mode == MODE_SEQ) ? 0 : b;
+  double u[L];
+  if (pa.zero_init) {
+#pragma unroll
+    for (int j = 0; j < L; ++j) u[j] = 0.0;
+  } else {
+    load_chunk<L>(pa.cin + row0 * nxl, base, L, u);
+  }
+  if (mode == MODE_PASS_A && b == 0) store_chunk<L>(pa.cout, base, L, u);
+  const bool add_g = pa.g && mode != MODE_APPLY;
+  const bool add_parent = mode == MODE_POST_F || (mode == MODE_SEQ && pa.parent);
+  if (mode == MODE_POST_F) {
+    double pv[L];
+    load_chunk<L>(pa.parent + (b * m) * nxl, base, L, pv);
+#pragma unroll
+    for (int j = 0; j < L; ++j) pv[j] += u[j];
+    store_chunk<L>(pa.parent + (b * m) * nxl, base, L, pv);
+  }
+
+  // parent[row] += (vector in v), coalesced, with the row's segments in pseg
+  auto parent_update = [&](const double *v, int64_t prow, const double2 (&pseg)[L / 2]) {
+    double2 *p2 = reinterpret_cast<double2 *>(pa.parent + prow * nxl);
+#pragma unroll
+    for (int q = 0; q < L / 2; ++q) {
+      const int i = 2 * (tid + T * q);
+      double2 r = pseg[q];
+      r.x += v[padix(i)];
+      r.y += v[padix(i + 1)];
+      p2[tid + T * q] = r;
+    }
+  };
+
   int buf = 0;
-  run_chain<L>(pa, nx, L, red, [=](double (&u)[L]) mutable {
+  int64_t pend = -1;  // parent row whose update waits for the next LDS copy
+  for (int j = 1; j <= nsteps; ++j) {
+    const int64_t n = (mode == MODE_SEQ) ? (int64_t)j : b * m + j;  // level point index
+    double2 gseg[L / 2], pseg[L / 2];
+    if (add_g) load_segs<L>(pa.g + (n - 1) * nxl, T, gseg);
+    if (pend >= 0) load_segs<L>(pa.parent + pend * nxl, T, pseg);
     double *v = buf ? vec1 : vec0;
     buf ^= dbuf;
     if (!dbuf) __syncthreads();
 #pragma unroll
-    for (int j = 0; j < L; ++j) v[padix(base + j)] = u[j];
+    for (int jj = 0; jj < L; ++jj) v[padix(base + jj)] = u[jj];
     __syncthreads();
+    if (pend >= 0) parent_update(v, pend, pseg);
     double y[L];
 #pragma unroll
-    for (int j = 0; j < L; ++j) y[j] = 0.0;
+    for (int jj = 0; jj < L; ++jj) y[jj] = 0.0;
 #pragma unroll
     for (int e = 0; e < L + W - 1; ++e) {
       int idx = start + e;
@@ -892,15 +1023,67 @@ __global__ void __launch_bounds__(MAXT) slc_kernel(const LevelDesc *__restrict__
       const double val = v[padix(idx)];
 #pragma unroll
       for (int t = 0; t < W; ++t) {
-        const int j = e - t;
-        if (j >= 0 && j < L) y[j] = fma(w[t], val, y[j]);
+        const int jj = e - t;
+        if (jj >= 0 && jj < L) y[jj] = fma(w[t], val, y[jj]);
       }
     }
-    lean_recurrence<L, K, false>(y, tid, T, af, tab_f, qf);
-    lean_recurrence<L, K, true>(y, T - 1 - tid, T, ab, tab_b, qb);
+    lean_recurrence<L, K, false>(y, tid, T, af, tab_f, qf, [] {});
+    lean_recurrence<L, K, true>(y, T - 1 - tid, T, ab, tab_b, qb, [&] {
+      if (add_g) {
 #pragma unroll
-    for (int j = 0; j < L; ++j) u[j] = y[j] * cinv;
-  });
+        for (int q = 0; q < L / 2; ++q) {
+          const int i = 2 * (tid + T * q);
+          gbuf[padix(i)] = gseg[q].x;
+          gbuf[padix(i + 1)] = gseg[q].y;
+        }
+      }
+    });
+#pragma unroll
+    for (int jj = 0; jj < L; ++jj) u[jj] = y[jj] * cinv;
+    if (add_g) {
+#pragma unroll
+      for (int jj = 0; jj < L; ++jj) u[jj] += gbuf[padix(base + jj)];
+    }
+    pend = add_parent ? n : -1;
+  }
+  if (pend >= 0) {  // the last step's parent update
+    double2 pseg[L / 2];
+    load_segs<L>(pa.parent + pend * nxl, T, pseg);
+    double *v = buf ? vec1 : vec0;
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < L; ++jj) v[padix(base + jj)] = u[jj];
+    __syncthreads();
+    parent_update(v, pend, pseg);
+  }
+
+  if (mode == MODE_PASS_A) {
+    store_chunk<L>(pa.cout + (b + 1) * nxl, base, L, u);
+  } else if (mode == MODE_PASS_B) {
+    const double *__restrict__ c1 = pa.cin + (b + 1) * nxl;
+    double ss = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < L; ++jj) {
+      u[jj] -= c1[base + jj];
+      ss = fma(u[jj], u[jj], ss);
+    }
+    store_chunk<L>(pa.r + b * nxl, base, L, u);
+    const double tot = block_sum(ss, red);
+    if (tid == 0) pa.normpart[b] = tot;
+  } else if (mode == MODE_POST_F) {
+    if (b == pa.nint - 1) {
+      load_chunk<L>(pa.cin + pa.nint * nxl, base, L, u);
+      double *row = pa.parent + (pa.nint * m) * nxl;
+      double pv[L];
+      load_chunk<L>(row, base, L, pv);
+#pragma unroll
+      for (int jj = 0; jj < L; ++jj) u[jj] += pv[jj];
+      store_chunk<L>(row, base, L, u);
+    }
+  } else if (mode == MODE_APPLY) {
+    __syncthreads();  // in-place use: every thread has read its input row
+    store_chunk<L>(pa.cout + b * nxl, base, L, u);
+  }
 }
 
 template <int L, int W, int K>
