@@ -453,6 +453,12 @@ void recurrence_tables(int k, const ld *a, const Layout &lay, std::vector<double
   for (ld v : Hlast) out.push_back((double)v);
   for (ld v : Wwrap) out.push_back((double)v);
   for (ld v : mpow(M, lay.L / 2)) out.push_back((double)v);
+  const std::vector<ld> H64 = mpow(H, WAVE);
+  P = identity(k);
+  for (int w = 0; w < MAXWAVES; ++w) {
+    for (ld v : P) out.push_back((double)v);
+    P = matmul(H64, P, k);
+  }
 }
 
 // Work distribution: L points per thread (a kernel template parameter).
@@ -486,7 +492,7 @@ constexpr size_t LDS_LIMIT = 160 * 1024;
 // of (Horner depth) stencil applications consume; pick the points per lane
 // that minimise redundant lane-work (ties: fewer points, more wavefronts).
 bool choose_tiles(int nx, int m, int depth, int sl, int sr, int Pforce, TileGeom &tg) {
-  static const int Ps[3] = {8, 16, 32};
+  static const int Ps[2] = {8, 16};
   const int HL = m * depth * sl, HR = m * depth * sr;
   long best = -1;
   for (int P : Ps) {
@@ -864,7 +870,6 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
         for (auto &kv : dmat(q + 1)) taps[kv.first] -= (ld)Lv.phi_q * kv.second;
       Lv.lay = choose_layout(nx, Lcoarse);
       Lv.lay.dbuf = 1;
-      if (lean_lds_offsets(nx, 1, KMAX).total * sizeof(double) > LDS_LIMIT) Lv.lay.dbuf = 0;
       if (lds_bytes_for(Lv.lay, 1) > LDS_LIMIT) Lv.lay.dbuf = 0;
       if (!attach_solve(op, taps, Lv.lay, tabs[l], offs[l], err)) {
         mgrit_destroy(h);
@@ -875,13 +880,9 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
 
   // ---- device data
   auto dalloc = [&](double **p, size_t n) -> hipError_t { return hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(double)); };
-  size_t maxlds = 0;
-  for (int l = 0; l < nlev; ++l) {
-    maxlds = std::max(maxlds, lds_bytes_for(h->lv[l].lay, h->lv[l].op.has_solve));
-    const size_t lean = lean_lds_offsets(nx, h->lv[l].lay.dbuf, KMAX).total * sizeof(double);
-    if (lean <= LDS_LIMIT) maxlds = std::max(maxlds, lean);
-  }
-  if (hipError_t e = configure_kernels(maxlds)) {
+  // Every layout chosen above needs at most LDS_LIMIT bytes; the attribute is
+  // per kernel and process-wide, so it is always raised to that limit.
+  if (hipError_t e = configure_kernels(LDS_LIMIT)) {
     mgrit_destroy(h);
     return bad(MGRIT_EDEVICE, std::string("configure: ") + hipGetErrorString(e));
   }

@@ -28,11 +28,16 @@ enum OpKind : int { OP_POLY_Z = 0, OP_POLY_W = 1, OP_SLC = 2 };
 
 // One periodic linear recurrence y_i = x_i + sum_{m=1..k} a[m-1] y_{i-m}
 // (forward) or y_{i+m} (backward), run over T threads that each own a chunk
-// of L consecutive points.  tab holds RTAB matrices of k*k doubles, for this
-// chunk layout (M the companion matrix, H = M^L, A threads own points):
+// of L consecutive points.  tab holds RTAB_ALL matrices of k*k doubles, for
+// this chunk layout (M the companion matrix, H = M^L, A threads own points):
 //   Hpow[t] = H^t, t = 0..64, then Hlast = M^{Llast},
-//   then Wwrap = (I - Hlast * H^{A-1})^{-1}, then Hhalf = M^{L/2}.
+//   then Wwrap = (I - Hlast * H^{A-1})^{-1}, then Hhalf = M^{L/2},
+//   then Hwave[w] = H^{64 w}, w = 0..MAXWAVES-1.
+// The generic step kernel stages the first RTAB of them in LDS, the lean
+// coarse-step kernel all RTAB_ALL.
 constexpr int RTAB = WAVE + 4;
+constexpr int TAB_HLAST = WAVE + 1, TAB_WWRAP = WAVE + 2, TAB_HHALF = WAVE + 3, TAB_HWAVE = WAVE + 4;
+constexpr int RTAB_ALL = RTAB + MAXWAVES;
 struct Recurrence {
   int k;
   double a[KMAX];
@@ -100,23 +105,25 @@ struct LevelDesc {
   Layout lay;
 };
 
-// LDS layout of the lean coarse-step kernel (in doubles).
+// The lean coarse-step kernel: 16 points per lane, NW full wavefronts
+// (nx = 1024 NW, NW = 1, 2, 4 or 8; at 16 wavefronts the 128-register
+// budget of a 1024-thread workgroup would spill).
+constexpr int LEAN_L = 16;
+
+// LDS layout of the lean coarse-step kernel (in doubles): one padded vector,
+// the forward and backward tables, the two wavefront-total arrays, and the
+// reduction scratch.
 struct LeanLds {
-  int vec1, gbuf, tab_f, tab_b, qf, qb, red, total;
+  int tab_f, tab_b, qf, qb, red, total;
 };
 
-__host__ __device__ inline LeanLds lean_lds_offsets(int nx, int dbuf, int K) {
-  LeanLds o;
-  const int pv = nx + (nx >> 4) + 1;
-  int off = pv;
-  o.vec1 = dbuf ? off : 0;
-  if (dbuf) off += pv;
-  o.gbuf = off;  // right-hand-side row staged for the chunked add
-  off += pv;
+constexpr __host__ __device__ inline LeanLds lean_lds_offsets(int nx, int K) {
+  LeanLds o{};
+  int off = nx + (nx >> 4) + 1;
   o.tab_f = off;
-  off += RTAB * K * K;
+  off += RTAB_ALL * K * K;
   o.tab_b = off;
-  off += RTAB * K * K;
+  off += RTAB_ALL * K * K;
   o.qf = off;
   off += (MAXWAVES + 2) * K;
   o.qb = off;
@@ -127,14 +134,17 @@ __host__ __device__ inline LeanLds lean_lds_offsets(int nx, int dbuf, int K) {
   return o;
 }
 
-// The lean kernel takes semi-Lagrangian steps with a solve on full chunks:
-// W = 2K interpolation taps (odd p, K = (p+1)/2 for the single-term
-// correction), equal forward/backward orders, no repetition.
+// The lean kernel takes semi-Lagrangian steps with a solve: W = 2K
+// interpolation taps (odd p, K = (p+1)/2 for the single-term correction),
+// equal forward/backward orders, no repetition, and recurrence tables built
+// for 16-point chunks that cover nx exactly.
 inline bool lean_slc_applies(const StepOp &op, const Layout &lay) {
   const int W = op.sl_l + op.sl_r + 1;
-  return op.kind == OP_SLC && op.has_solve && op.repeat == 1 && !lay.ragged && lay.A == lay.T &&
-         (lay.L == 4 || lay.L == 8 || lay.L == 16) && op.fw.k == op.bw.k && op.fw.k >= 1 && W == 2 * op.fw.k &&
-         lean_lds_offsets(lay.nx, lay.dbuf, op.fw.k).total * sizeof(double) <= 160 * 1024;
+  const int nw = lay.nx / (WAVE * LEAN_L);
+  return op.kind == OP_SLC && op.has_solve && op.repeat == 1 && !lay.ragged && lay.L == LEAN_L &&
+         lay.A == lay.T && lay.nx == nw * WAVE * LEAN_L && (nw == 1 || nw == 2 || nw == 4 || nw == 8) &&
+         op.fw.k == op.bw.k && op.fw.k >= 1 && W == 2 * op.fw.k &&
+         lean_lds_offsets(lay.nx, op.fw.k).total * sizeof(double) <= 160 * 1024;
 }
 
 enum PassMode : int {
@@ -186,6 +196,8 @@ struct TileArgs {
 };
 
 hipError_t launch_tiles(const LevelDesc *desc, const TileGeom &tg, const TileArgs &ta, hipStream_t stream);
+hipError_t launch_tiles_8(const LevelDesc *desc, const TileGeom &tg, const TileArgs &ta, hipStream_t stream);
+hipError_t launch_tiles_16(const LevelDesc *desc, const TileGeom &tg, const TileArgs &ta, hipStream_t stream);
 
 // Launch the step kernel for one pass (mgrit_kernels.hip).  lds_bytes is
 // computed by the launcher.  Returns the HIP error of the launch.
@@ -199,6 +211,21 @@ hipError_t launch_reduce(const double *part, int64_t n, double *out, hipStream_t
 hipError_t launch_gather_rows(const double *src, int64_t stride, double *dst, int64_t rows, int nx,
                               hipStream_t stream);
 hipError_t launch_fill(double *dst, int64_t n, double value, hipStream_t stream);
+// The lean coarse-step kernel (mgrit_lean.hip) for layouts where
+// lean_slc_applies() holds, and its LDS attribute.
+hipError_t launch_lean(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs &pa,
+                       hipStream_t stream);
+hipError_t configure_lean_kernels(size_t bytes);
+// The generic step kernel, one translation unit per operator kind.
+hipError_t launch_step_poly_z(const LevelDesc *desc, const Layout &lay, const PassArgs &pa, size_t lds,
+                              hipStream_t stream);
+hipError_t launch_step_poly_w(const LevelDesc *desc, const Layout &lay, const PassArgs &pa, size_t lds,
+                              hipStream_t stream);
+hipError_t launch_step_slc(const LevelDesc *desc, const Layout &lay, const PassArgs &pa, size_t lds,
+                           hipStream_t stream);
+hipError_t configure_step_poly_z(size_t bytes);
+hipError_t configure_step_poly_w(size_t bytes);
+hipError_t configure_step_slc(size_t bytes);
 // Allow the step kernels to use up to `bytes` of dynamic LDS.
 hipError_t configure_kernels(size_t bytes);
 size_t lds_bytes_for(const Layout &lay, int has_solve);

@@ -1,0 +1,492 @@
+// gfx950 kernel for the coarse-level time step of MGRIT (Sec. 2.2 with the
+// corrected semi-Lagrangian operator, eqs. MOL-SL-corrected and
+// MOL-SL-corrected-multilevel) on vectors of 1024 NW points, NW = 1, 2, 4, 8.
+#include "mgrit_internal.h"
+
+namespace mgrit {
+
+namespace {
+
+#include "mgrit_device.h"
+
+// ---------------------------------------------------------------------------
+// Coarse time step Psi = T^{-1} S (eq. MOL-SL-corrected-multilevel) for
+// nx = 1024 NW: 16 points per lane, NW full wavefronts, W interpolation taps,
+// order-K forward and backward recurrences.  Per step: one barrier after the
+// vector is written to LDS, one per recurrence.  After a recurrence's
+// wavefront totals are published, every wavefront folds them and the
+// periodic wrap into its own carry (a short chain computed redundantly), so
+// no thread waits for a serial one.  The scan's lane-dependent matrix powers
+// are loaded into registers once per launch for K <= 2.
+// ---------------------------------------------------------------------------
+// Cross-lane move of a double with a DPP row shift (bound_ctrl: lanes whose
+// source lies outside their 16-lane row read 0).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(bits & 0xffffffff), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffff), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), lane);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+template <int K>
+__device__ __forceinline__ void ld_mat(const double *p, double (&M)[K * K]) {
+#pragma unroll
+  for (int i = 0; i < K * K; ++i) M[i] = p[i];
+}
+
+// acc += M x (M row-major K x K)
+template <int K>
+__device__ __forceinline__ void mv_acc(const double (&M)[K * K], const double (&x)[K], double (&acc)[K]) {
+#pragma unroll
+  for (int r = 0; r < K; ++r) {
+    double s = acc[r];
+#pragma unroll
+    for (int c = 0; c < K; ++c) s = fma(M[r * K + c], x[c], s);
+    acc[r] = s;
+  }
+}
+
+// Lane-dependent matrices of one recurrence direction: H^{lr} (lr = position
+// in the 16-lane row, processing order), H^{vl} (position in the wavefront)
+// and H^{64 vw} (vw = wavefront position).  HOIST keeps them in registers;
+// otherwise they are read from the LDS table where used.
+template <int K, bool HOIST>
+struct LaneMats {
+  static constexpr int N = HOIST ? K * K : 1;
+  double lr_[N], vl_[N], vw_[N];
+  const double *tab;
+  int lr, vl, vw;
+  __device__ __forceinline__ void init(const double *t, int lr0, int vl0, int vw0) {
+    tab = t;
+    lr = lr0;
+    vl = vl0;
+    vw = vw0;
+    if constexpr (HOIST) {
+      ld_mat<K>(t + lr * K * K, lr_);
+      ld_mat<K>(t + vl * K * K, vl_);
+      ld_mat<K>(t + (TAB_HWAVE + vw) * K * K, vw_);
+    }
+  }
+  __device__ __forceinline__ void get(int which, double (&M)[K * K]) const {
+    if constexpr (HOIST) {
+      const double *src = which == 0 ? lr_ : (which == 1 ? vl_ : vw_);
+#pragma unroll
+      for (int i = 0; i < K * K; ++i) M[i] = src[i];
+    } else {
+      const int idx = which == 0 ? lr : (which == 1 ? vl : TAB_HWAVE + vw);
+      ld_mat<K>(tab + idx * K * K, M);
+    }
+  }
+};
+
+// One Kogge-Stone step inside 16-lane rows: add H^D times the state D lanes
+// back in processing order (row_shr forward, row_shl backward; lanes without
+// such a neighbour receive 0 and keep their value).
+template <int K, bool REV, int D>
+__device__ __forceinline__ void row_step(double (&inc)[K], const double *tab) {
+  double M[K * K];
+  ld_mat<K>(tab + D * K * K, M);
+  double o[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) o[m] = REV ? dpp_d<0x100 + D>(inc[m]) : dpp_d<0x110 + D>(inc[m]);
+  mv_acc<K>(M, o, inc);
+}
+
+// Periodic recurrence x_i += sum_m a[m] x_{i-1-m} (REV: x_{i+1+m}) over the
+// workgroup's 16-point chunks; pre_barrier() runs just before the barrier.
+template <int L, int K, int NW, bool REV, bool HOIST, class Hook>
+__device__ __forceinline__ void lean_rec(double (&x)[L], const double (&a)[K], const double *tab,
+                                         const LaneMats<K, HOIST> &lm, double *Q, Hook pre_barrier) {
+  constexpr int KK = K * K;
+  constexpr int LH = L / 2;  // two interleaved sub-chains per lane
+  const int vl = lm.vl, vw = lm.vw, vrow = vl >> 4;
+  // zero-state passes of both halves (processing order: REV walks down)
+  double sa[K], sb[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) sa[m] = sb[m] = 0.0;
+#pragma unroll
+  for (int e = 0; e < LH; ++e) {
+    const int ja = REV ? (L - 1 - e) : e;
+    const int jb = REV ? (LH - 1 - e) : (LH + e);
+    double ya = x[ja], yb = x[jb];
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      ya = fma(a[m], sa[m], ya);
+      yb = fma(a[m], sb[m], yb);
+    }
+#pragma unroll
+    for (int m = K - 1; m > 0; --m) {
+      sa[m] = sa[m - 1];
+      sb[m] = sb[m - 1];
+    }
+    sa[0] = ya;
+    sb[0] = yb;
+    x[ja] = ya;
+    x[jb] = yb;
+  }
+  double M[KK];
+  // chunk total q = Hhalf sa + sb
+  double q[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) q[m] = sb[m];
+  ld_mat<K>(tab + TAB_HHALF * KK, M);
+  mv_acc<K>(M, sa, q);
+
+  // inclusive scan inside 16-lane rows
+  double inc[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) inc[m] = q[m];
+  row_step<K, REV, 1>(inc, tab);
+  row_step<K, REV, 2>(inc, tab);
+  row_step<K, REV, 4>(inc, tab);
+  row_step<K, REV, 8>(inc, tab);
+  // exclusive value in the row, then the row carries (uniform over the
+  // wavefront): ex = ex_row + H^{lr} C_row
+  double ex[K], C1[K], C2[K], C3[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    ex[m] = REV ? dpp_d<0x101>(inc[m]) : dpp_d<0x111>(inc[m]);
+    C1[m] = readlane_d(inc[m], REV ? 48 : 15);
+    C2[m] = readlane_d(inc[m], REV ? 32 : 31);
+    C3[m] = readlane_d(inc[m], REV ? 16 : 47);
+  }
+  ld_mat<K>(tab + 16 * KK, M);
+  mv_acc<K>(M, C1, C2);
+  mv_acc<K>(M, C2, C3);
+  double cr[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) cr[m] = vrow == 0 ? 0.0 : (vrow == 1 ? C1[m] : (vrow == 2 ? C2[m] : C3[m]));
+  double P[KK];
+  lm.get(0, P);
+  mv_acc<K>(P, cr, ex);
+
+  // publish the wavefront total (last lane: q + H ex) and, from the last
+  // chunk of the vector, its exclusive state and zero-state total
+  if (vl == WAVE - 1) {
+    double tot[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) tot[m] = q[m];
+    ld_mat<K>(tab + KK, M);
+    mv_acc<K>(M, ex, tot);
+#pragma unroll
+    for (int m = 0; m < K; ++m) Q[vw * K + m] = tot[m];
+    if (vw == NW - 1) {
+#pragma unroll
+      for (int m = 0; m < K; ++m) {
+        Q[NW * K + m] = ex[m];
+        Q[(NW + 1) * K + m] = q[m];
+      }
+    }
+  }
+  pre_barrier();
+  __syncthreads();
+
+  // zero-start carries X_w entering each wavefront; keep X_vw and X_{NW-1}
+  double X[K], Xv[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) X[m] = Xv[m] = 0.0;
+  ld_mat<K>(tab + WAVE * KK, M);
+#pragma unroll
+  for (int w2 = 0; w2 < NW - 1; ++w2) {
+    double nxt[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) nxt[m] = Q[w2 * K + m];
+    mv_acc<K>(M, X, nxt);
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      X[m] = nxt[m];
+      Xv[m] = (vw == w2 + 1) ? nxt[m] : Xv[m];
+    }
+  }
+  // periodic wrap: state entering point 0, s0 = Wwrap (Hlast E + q_last)
+  double E[K], tq[K], s0[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    E[m] = Q[NW * K + m];
+    tq[m] = Q[(NW + 1) * K + m];
+    s0[m] = 0.0;
+  }
+  ld_mat<K>(tab + (WAVE - 1) * KK, M);
+  mv_acc<K>(M, X, E);
+  ld_mat<K>(tab + TAB_HLAST * KK, M);
+  mv_acc<K>(M, E, tq);
+  ld_mat<K>(tab + TAB_WWRAP * KK, M);
+  mv_acc<K>(M, tq, s0);
+  // carry into this wavefront, this lane, and both halves of its chunk
+  lm.get(2, P);
+  mv_acc<K>(P, s0, Xv);
+  double ta[K], tb[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    ta[m] = ex[m];
+    tb[m] = sa[m];
+  }
+  lm.get(1, P);
+  mv_acc<K>(P, Xv, ta);
+  ld_mat<K>(tab + TAB_HHALF * KK, M);
+  mv_acc<K>(M, ta, tb);
+  // homogeneous corrections
+#pragma unroll
+  for (int e = 0; e < LH; ++e) {
+    const int ja = REV ? (L - 1 - e) : e;
+    const int jb = REV ? (LH - 1 - e) : (LH + e);
+    double ha = 0.0, hb = 0.0;
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      ha = fma(a[m], ta[m], ha);
+      hb = fma(a[m], tb[m], hb);
+    }
+#pragma unroll
+    for (int m = K - 1; m > 0; --m) {
+      ta[m] = ta[m - 1];
+      tb[m] = tb[m - 1];
+    }
+    ta[0] = ha;
+    tb[0] = hb;
+    x[ja] += ha;
+    x[jb] += hb;
+  }
+}
+
+// Coalesced row segments: thread t owns the 16-byte pairs t + T q, q < L/2.
+template <int L, int T>
+__device__ __forceinline__ void load_segs(const double *__restrict__ row, double2 (&seg)[L / 2]) {
+  const double2 *r2 = reinterpret_cast<const double2 *>(row);
+#pragma unroll
+  for (int q = 0; q < L / 2; ++q) seg[q] = r2[threadIdx.x + T * q];
+}
+
+template <int W, int K, int NW>
+__global__ void __launch_bounds__(WAVE * NW) slc_kernel(const LevelDesc *__restrict__ desc, PassArgs pa) {
+  constexpr int L = LEAN_L;
+  constexpr int T = WAVE * NW;
+  constexpr int NX = L * T;
+  constexpr int KK = K * K;
+  constexpr bool HOIST = K <= 2;
+  extern __shared__ double smem[];
+  const StepOp &op = desc->op;
+  constexpr LeanLds lo = lean_lds_offsets(NX, K);
+  double *v = smem;  // padded vector; also stages the right-hand-side row
+  double *tab_f = smem + lo.tab_f;
+  double *tab_b = smem + lo.tab_b;
+  double *qf = smem + lo.qf;
+  double *qb = smem + lo.qb;
+  double *red = smem + lo.red;
+
+  // interpolation weights with the 1/C of the factorisation folded in
+  double w[W], af[K], ab[K];
+  const double cinv = op.cinv;
+#pragma unroll
+  for (int t = 0; t < W; ++t) w[t] = op.slw[t] * cinv;
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    af[m] = op.fw.a[m];
+    ab[m] = op.bw.a[m];
+  }
+  for (int i = threadIdx.x; i < RTAB_ALL * KK; i += T) {
+    tab_f[i] = op.fw.tab[i];
+    tab_b[i] = op.bw.tab[i];
+  }
+  __syncthreads();
+
+  const int tid = threadIdx.x;
+  const int lane = tid & (WAVE - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  LaneMats<K, HOIST> lmf, lmb;
+  lmf.init(tab_f, lane & 15, lane, wave);
+  lmb.init(tab_b, (WAVE - 1 - lane) & 15, WAVE - 1 - lane, NW - 1 - wave);
+
+  const int base = tid * L;
+  int start = base - (op.sl_K + op.sl_l) % NX;
+  if (start < 0) start += NX;
+  const int64_t b = blockIdx.x;
+  const int64_t nxl = NX;
+  const int m = pa.m;
+  const int mode = pa.mode;
+  const int nsteps = (mode == MODE_POST_F) ? m - 1 : m;  // PASS_A, PASS_B, SEQ, APPLY: m
+  const int64_t row0 = (mode == MODE_SEQ) ? 0 : b;
+  double u[L];
+  if (pa.zero_init) {
+#pragma unroll
+    for (int j = 0; j < L; ++j) u[j] = 0.0;
+  } else {
+    load_chunk<L>(pa.cin + row0 * nxl, base, L, u);
+  }
+  if (mode == MODE_PASS_A && b == 0) store_chunk<L>(pa.cout, base, L, u);
+  const bool add_g = pa.g && mode != MODE_APPLY;
+  const bool add_parent = mode == MODE_POST_F || (mode == MODE_SEQ && pa.parent);
+  if (mode == MODE_POST_F) {
+    double pv[L];
+    load_chunk<L>(pa.parent + (b * m) * nxl, base, L, pv);
+#pragma unroll
+    for (int j = 0; j < L; ++j) pv[j] += u[j];
+    store_chunk<L>(pa.parent + (b * m) * nxl, base, L, pv);
+  }
+
+  // parent[prow] += the vector in v, coalesced, with the row's segments in pseg
+  auto parent_update = [&](int64_t prow, const double2 (&pseg)[L / 2]) {
+    double2 *p2 = reinterpret_cast<double2 *>(pa.parent + prow * nxl);
+#pragma unroll
+    for (int q = 0; q < L / 2; ++q) {
+      const int i = 2 * (tid + T * q);
+      double2 r = pseg[q];
+      r.x += v[padix(i)];
+      r.y += v[padix(i + 1)];
+      p2[tid + T * q] = r;
+    }
+  };
+
+  // One LDS vector serves every step.  Each thread writes only its own chunk
+  // of it at the start of a step and reads only its own chunk at the end; the
+  // cross-thread reads (gather, parent update) precede the forward
+  // recurrence's barrier and the cross-thread writes (right-hand side, in the
+  // backward recurrence's hook) follow it.
+  int64_t pend = -1;  // parent row whose update waits for the next LDS copy
+  for (int j = 1; j <= nsteps; ++j) {
+    const int64_t n = (mode == MODE_SEQ) ? (int64_t)j : b * m + j;  // level point index
+    double2 gseg[L / 2], pseg[L / 2];
+    if (add_g) load_segs<L, T>(pa.g + (n - 1) * nxl, gseg);
+    if (pend >= 0) load_segs<L, T>(pa.parent + pend * nxl, pseg);
+#pragma unroll
+    for (int jj = 0; jj < L; ++jj) v[padix(base + jj)] = u[jj];
+    __syncthreads();
+    if (pend >= 0) parent_update(pend, pseg);
+    double y[L];
+#pragma unroll
+    for (int jj = 0; jj < L; ++jj) y[jj] = 0.0;
+#pragma unroll
+    for (int e = 0; e < L + W - 1; ++e) {
+      int idx = start + e;
+      idx = idx >= NX ? idx - NX : idx;
+      const double val = v[padix(idx)];
+#pragma unroll
+      for (int t = 0; t < W; ++t) {
+        const int jj = e - t;
+        if (jj >= 0 && jj < L) y[jj] = fma(w[t], val, y[jj]);
+      }
+    }
+    lean_rec<L, K, NW, false>(y, af, tab_f, lmf, qf, [] {});
+    lean_rec<L, K, NW, true>(y, ab, tab_b, lmb, qb, [&] {
+      if (add_g) {
+#pragma unroll
+        for (int q = 0; q < L / 2; ++q) {
+          const int i = 2 * (tid + T * q);
+          v[padix(i)] = gseg[q].x;
+          v[padix(i + 1)] = gseg[q].y;
+        }
+      }
+    });
+    if (add_g) {
+#pragma unroll
+      for (int jj = 0; jj < L; ++jj) u[jj] = y[jj] + v[padix(base + jj)];
+    } else {
+#pragma unroll
+      for (int jj = 0; jj < L; ++jj) u[jj] = y[jj];
+    }
+    pend = add_parent ? n : -1;
+  }
+  if (pend >= 0) {  // the last step's parent update
+    double2 pseg[L / 2];
+    load_segs<L, T>(pa.parent + pend * nxl, pseg);
+#pragma unroll
+    for (int jj = 0; jj < L; ++jj) v[padix(base + jj)] = u[jj];
+    __syncthreads();
+    parent_update(pend, pseg);
+  }
+
+  if (mode == MODE_PASS_A) {
+    store_chunk<L>(pa.cout + (b + 1) * nxl, base, L, u);
+  } else if (mode == MODE_PASS_B) {
+    const double *__restrict__ c1 = pa.cin + (b + 1) * nxl;
+    double ss = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < L; ++jj) {
+      u[jj] -= c1[base + jj];
+      ss = fma(u[jj], u[jj], ss);
+    }
+    store_chunk<L>(pa.r + b * nxl, base, L, u);
+    const double tot = block_sum(ss, red);
+    if (tid == 0) pa.normpart[b] = tot;
+  } else if (mode == MODE_POST_F) {
+    if (b == pa.nint - 1) {
+      load_chunk<L>(pa.cin + pa.nint * nxl, base, L, u);
+      double *row = pa.parent + (pa.nint * m) * nxl;
+      double pv[L];
+      load_chunk<L>(row, base, L, pv);
+#pragma unroll
+      for (int jj = 0; jj < L; ++jj) u[jj] += pv[jj];
+      store_chunk<L>(row, base, L, u);
+    }
+  } else if (mode == MODE_APPLY) {
+    __syncthreads();  // in-place use: every thread has read its input row
+    store_chunk<L>(pa.cout + b * nxl, base, L, u);
+  }
+}
+
+template <int W, int K, int NW>
+hipError_t slc_launch(const LevelDesc *desc, const PassArgs &pa, hipStream_t stream) {
+  constexpr size_t lds = (size_t)lean_lds_offsets(LEAN_L * WAVE * NW, K).total * sizeof(double);
+  hipLaunchKernelGGL((slc_kernel<W, K, NW>), dim3((unsigned)pa.nint), dim3(WAVE * NW), lds, stream, desc, pa);
+  return hipGetLastError();
+}
+
+template <int W, int K>
+hipError_t slc_launch_nw(const LevelDesc *desc, int nw, const PassArgs &pa, hipStream_t stream) {
+  switch (nw) {
+    case 1: return slc_launch<W, K, 1>(desc, pa, stream);
+    case 2: return slc_launch<W, K, 2>(desc, pa, stream);
+    case 4: return slc_launch<W, K, 4>(desc, pa, stream);
+    case 8: return slc_launch<W, K, 8>(desc, pa, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t slc_launch_any(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs &pa,
+                          hipStream_t stream) {
+  const int W = op.sl_l + op.sl_r + 1;
+  const int nw = lay.nx / (WAVE * LEAN_L);
+  if (W == 2 && op.fw.k == 1) return slc_launch_nw<2, 1>(desc, nw, pa, stream);
+  if (W == 4 && op.fw.k == 2) return slc_launch_nw<4, 2>(desc, nw, pa, stream);
+  if (W == 6 && op.fw.k == 3) return slc_launch_nw<6, 3>(desc, nw, pa, stream);
+  return hipErrorInvalidValue;
+}
+
+template <int W, int K>
+hipError_t slc_set_lds(size_t bytes) {
+  hipError_t e;
+  if ((e = hipFuncSetAttribute((const void *)slc_kernel<W, K, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes)))
+    return e;
+  if ((e = hipFuncSetAttribute((const void *)slc_kernel<W, K, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes)))
+    return e;
+  if ((e = hipFuncSetAttribute((const void *)slc_kernel<W, K, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes)))
+    return e;
+  return hipFuncSetAttribute((const void *)slc_kernel<W, K, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+}  // namespace
+
+hipError_t launch_lean(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs &pa,
+                       hipStream_t stream) {
+  return slc_launch_any(desc, op, lay, pa, stream);
+}
+
+hipError_t configure_lean_kernels(size_t bytes) {
+  hipError_t e;
+  if ((e = slc_set_lds<2, 1>(bytes))) return e;
+  if ((e = slc_set_lds<4, 2>(bytes))) return e;
+  return slc_set_lds<6, 3>(bytes);
+}
+
+}  // namespace mgrit

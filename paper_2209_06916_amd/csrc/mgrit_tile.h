@@ -1,0 +1,140 @@
+// Level-0 explicit relaxation with wavefront tiles (included inside
+// namespace mgrit::{anonymous} by the per-width translation units).
+#pragma once
+
+// ---------------------------------------------------------------------------
+// Level-0 explicit relaxation, one wavefront per (CF-interval, spatial tile).
+// Lane l holds the P consecutive points starting at x0 - HL + l P (periodic).
+// Each application of Z = -c L_p reads SL points from the left neighbour lane
+// and SR from the right one; lane 0's left and lane 63's right inputs are
+// stale, which only invalidates points inside the halo.  No LDS, no barriers.
+// ---------------------------------------------------------------------------
+template <int P, int SL, int SR>
+__global__ void __launch_bounds__(256) tile_kernel(const LevelDesc *__restrict__ desc, TileGeom tg, TileArgs ta) {
+  const StepOp &op = desc->op;
+  const int nx = desc->lay.nx;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t item = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (item >= ta.nint * tg.ntiles) return;  // whole wavefront leaves together
+  const int64_t b = item / tg.ntiles;
+  const int tau = (int)(item - b * tg.ntiles);
+  const int x0 = tau * tg.TW;
+  const int tw = min(tg.TW, nx - x0);
+  const int64_t nxl = nx;
+
+  // coefficients -> registers
+  const int ncoef = op.ncoef;
+  double taps[SL + SR + 1];
+#pragma unroll
+  for (int t = 0; t <= SL + SR; ++t) taps[t] = op.taps[t];
+  const double top = op.coef[ncoef - 1];
+
+  // this lane's first global position (periodic) and its local index
+  const int li0 = lane * P;              // local index of point 0 of this lane
+  int g0 = x0 - tg.HL + li0;             // global position, may be outside [0, nx)
+  g0 %= nx;
+  if (g0 < 0) g0 += nx;
+
+  double u[P];
+  {
+    const double *row = ta.cin + b * nxl;
+    int g = g0;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      u[k] = row[g];
+      g = wrap_hi(g + 1, nx);
+    }
+  }
+  // output window of this lane: local indices [HL, HL + tw)
+  const int lo = tg.HL - li0, hi = tg.HL + tw - li0;  // k in [lo, hi) is output
+
+  auto store_out = [&](double *row, const double (&v)[P]) {
+    int g = g0;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      if (k >= lo && k < hi) row[g] = v[k];
+      g = wrap_hi(g + 1, nx);
+    }
+  };
+
+  if (ta.mode == MODE_PASS_A && b == 0) store_out(ta.cout, u);
+  if (ta.mode == MODE_FINAL_F) store_out(ta.out + (b * ta.m) * nxl, u);
+
+  const int nsteps = (ta.mode == MODE_FINAL_F) ? ta.m - 1 : ta.m;
+  for (int j = 1; j <= nsteps; ++j) {
+    double y[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) y[k] = top * u[k];
+    for (int i = ncoef - 2; i >= 0; --i) {
+      double lh[SL > 0 ? SL : 1], rh[SR > 0 ? SR : 1];
+#pragma unroll
+      for (int q = 0; q < SL; ++q) lh[q] = __shfl(y[P - SL + q], (lane - 1) & (WAVE - 1), WAVE);
+#pragma unroll
+      for (int q = 0; q < SR; ++q) rh[q] = __shfl(y[q], (lane + 1) & (WAVE - 1), WAVE);
+      const double ci = op.coef[i];
+      double yn[P];
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        double acc = ci * u[k];
+#pragma unroll
+        for (int t = 0; t <= SL + SR; ++t) {
+          const int src = k + t - SL;
+          const double v = src < 0 ? lh[(src + SL) < 0 ? 0 : (src + SL)]
+                                   : (src >= P ? rh[(src - P) < SR ? (src - P) : 0] : y[src < P ? src : 0]);
+          acc = fma(taps[t], v, acc);
+        }
+        yn[k] = acc;
+      }
+#pragma unroll
+      for (int k = 0; k < P; ++k) y[k] = yn[k];
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) u[k] = y[k];
+    if (ta.mode == MODE_FINAL_F) store_out(ta.out + (b * ta.m + j) * nxl, u);
+  }
+
+  if (ta.mode == MODE_PASS_A) {
+    store_out(ta.cout + (b + 1) * nxl, u);
+  } else if (ta.mode == MODE_PASS_B) {
+    const double *c1 = ta.cin + (b + 1) * nxl;
+    double ss = 0.0;
+    int g = g0;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      if (k >= lo && k < hi) {
+        const double rv = u[k] - c1[g];
+        ta.r[b * nxl + g] = rv;
+        ss = fma(rv, rv, ss);
+      }
+      g = wrap_hi(g + 1, nx);
+    }
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) ss += __shfl_down(ss, d, WAVE);
+    if (lane == 0) ta.normpart[item] = ss;
+  } else if (ta.mode == MODE_FINAL_F && b == ta.nint - 1) {
+    double c[P];
+    const double *row = ta.cin + ta.nint * nxl;
+    int g = g0;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      c[k] = row[g];
+      g = wrap_hi(g + 1, nx);
+    }
+    store_out(ta.out + (ta.nint * ta.m) * nxl, c);
+  }
+}
+
+template <int P>
+hipError_t launch_tiles_p(const LevelDesc *desc, const TileGeom &tg, const TileArgs &ta, hipStream_t stream) {
+  const int64_t items = ta.nint * tg.ntiles;
+  const dim3 grid((unsigned)((items + 3) / 4)), block(256);
+  switch (tg.sl * 4 + tg.sr) {
+    case 1 * 4 + 0: hipLaunchKernelGGL((tile_kernel<P, 1, 0>), grid, block, 0, stream, desc, tg, ta); break;
+    case 2 * 4 + 0: hipLaunchKernelGGL((tile_kernel<P, 2, 0>), grid, block, 0, stream, desc, tg, ta); break;
+    case 2 * 4 + 1: hipLaunchKernelGGL((tile_kernel<P, 2, 1>), grid, block, 0, stream, desc, tg, ta); break;
+    case 3 * 4 + 1: hipLaunchKernelGGL((tile_kernel<P, 3, 1>), grid, block, 0, stream, desc, tg, ta); break;
+    case 3 * 4 + 2: hipLaunchKernelGGL((tile_kernel<P, 3, 2>), grid, block, 0, stream, desc, tg, ta); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
