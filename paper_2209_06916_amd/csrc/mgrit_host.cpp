@@ -540,6 +540,10 @@ struct mgrit_handle {
   int64_t normpart_len = 0;
   double *normsum = nullptr;
   double *normsum_host = nullptr;
+  SolveCtl *ctl = nullptr;       // device iteration state of mgrit_solve
+  SolveCtl *ctl_host = nullptr;  // pinned copy, read once per iteration
+  hipEvent_t ctl_ev = nullptr;
+  const int *guard = nullptr;    // stop flag handed to the passes being queued
   std::string err;
   // profiler
   uint32_t prof_mask = 0;
@@ -674,6 +678,9 @@ void mgrit_destroy(mgrit_handle *h) {
   if (h->normpart) (void)hipFree(h->normpart);
   if (h->normsum) (void)hipFree(h->normsum);
   if (h->normsum_host) (void)hipHostFree(h->normsum_host);
+  if (h->ctl) (void)hipFree(h->ctl);
+  if (h->ctl_host) (void)hipHostFree(h->ctl_host);
+  if (h->ctl_ev) (void)hipEventDestroy(h->ctl_ev);
   for (auto &pe : h->ev_pending) {
     (void)hipEventDestroy(pe.second.first);
     (void)hipEventDestroy(pe.second.second);
@@ -929,7 +936,10 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
   h->normpart_len = std::max<int64_t>(P->nt, 1);
   if (h->lv[0].tiles) h->normpart_len = std::max<int64_t>(h->normpart_len, (P->nt / ms[0]) * h->lv[0].tg.ntiles);
   if (dalloc(&h->normpart, h->normpart_len) != hipSuccess || dalloc(&h->normsum, 1) != hipSuccess ||
-      hipHostMalloc((void **)&h->normsum_host, sizeof(double)) != hipSuccess) {
+      hipHostMalloc((void **)&h->normsum_host, sizeof(double)) != hipSuccess ||
+      hipMalloc((void **)&h->ctl, sizeof(SolveCtl)) != hipSuccess ||
+      hipHostMalloc((void **)&h->ctl_host, sizeof(SolveCtl)) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ctl_ev, hipEventDisableTiming) != hipSuccess) {
     mgrit_destroy(h);
     return bad(MGRIT_ENOMEM, "norm buffers");
   }
@@ -995,6 +1005,7 @@ hipError_t run_pass(mgrit_handle *h, const Level &L, int phase, int mode, int m,
   pa.parent = parent;
   pa.out = out;
   pa.normpart = h->normpart;
+  pa.stop = h->guard;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (h->prof_mask & (1u << phase)) {
     e0 = take_event(h);
@@ -1056,7 +1067,7 @@ mgrit_status vcycle(mgrit_handle *h, int l, const double *g, double *parent) {
   const int64_t nc = L.nt / L.m;
   int cur = 0;
   if (h->opt.nu == 0) {
-    HIPCHK(h, launch_fill(L.c[0], (nc + 1) * (int64_t)nx, 0.0, h->stream));
+    HIPCHK(h, launch_fill(L.c[0], (nc + 1) * (int64_t)nx, 0.0, h->stream, h->guard));
   }
   for (int s = 0; s < h->opt.nu; ++s) {
     HIPCHK(h, run_pass(h, L, MGRIT_PROF_COARSE, MODE_PASS_A, L.m, nc, s == 0 ? nullptr : L.c[cur], L.c[1 - cur], g, nullptr, nullptr,
@@ -1102,40 +1113,47 @@ mgrit_status mgrit_solve(mgrit_handle *h, const double *u0, const double *v_init
   }
   HIPCHK(h, hipMemcpyAsync(L0.c[0], u0, nx * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
 
-  int cur = 0, it = 0;
-  double res0 = NAN, prev = NAN, rho = NAN;
+  // Iteration state lives on the device: solve_ctl_kernel reduces the
+  // residual norm and takes the stopping decision, and the coarse-grid
+  // correction queued behind it skips itself once a stop is recorded.  The
+  // host reads the state while that correction runs, so the GPU never idles
+  // waiting for it; the next iteration is queued only after a "continue".
+  HIPCHK(h, hipMemsetAsync(h->ctl, 0, sizeof(SolveCtl), h->stream));
+  const StopRule rule{h->opt.rtol, h->opt.diverge_factor, h->opt.max_iter};
+  int cur = 0;
+  double prev = NAN;
+  SolveCtl hc{};
+  hc.rho = NAN;
   int hist_len = 0;
-  mgrit_status status = MGRIT_OK;
   for (;;) {
     for (int s = 0; s < h->opt.nu; ++s) {
       HIPCHK(h, run_fine(h, MGRIT_PROF_FINE_RELAX, MODE_PASS_A, L0.c[cur], L0.c[1 - cur], nullptr, nullptr));
       cur = 1 - cur;
     }
     HIPCHK(h, run_fine(h, MGRIT_PROF_FINE_RELAX, MODE_PASS_B, L0.c[cur], nullptr, L0.r, nullptr));
-    hipError_t e;
-    prev = rho;
-    rho = reduce_norm(h, fine_norm_parts(h), e);
-    if (e) return hipfail(h, e, "residual norm");
-    if (stats && stats->res_history && hist_len < stats->res_history_cap) stats->res_history[hist_len] = rho;
+    HIPCHK(h, launch_solve_ctl(h->normpart, fine_norm_parts(h), h->ctl, rule, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->ctl_host, h->ctl, sizeof(SolveCtl), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipEventRecord(h->ctl_ev, h->stream));
+    h->guard = &h->ctl->stop;
+    const mgrit_status st = vcycle(h, 1, L0.r, L0.c[cur]);
+    h->guard = nullptr;
+    if (st != MGRIT_OK) return st;
+    HIPCHK(h, hipEventSynchronize(h->ctl_ev));
+    prev = hc.rho;
+    hc = *h->ctl_host;
+    if (stats && stats->res_history && hist_len < stats->res_history_cap) stats->res_history[hist_len] = hc.rho;
     ++hist_len;
-    if (it == 0) res0 = rho;
-    if (!std::isfinite(rho)) {
-      status = fail(h, MGRIT_EDIVERGED, "non-finite residual");
-      break;
-    }
-    if (rho <= h->opt.rtol * res0) break;
-    if (it >= h->opt.max_iter) {
+    if (hc.stop != STOP_NONE) break;
+  }
+  mgrit_status status = MGRIT_OK;
+  switch (hc.stop) {
+    case STOP_NONFINITE: status = fail(h, MGRIT_EDIVERGED, "non-finite residual"); break;
+    case STOP_MAX_ITER:
       status = MGRIT_ENOTCONVERGED;
       h->err = "max_iter reached";
       break;
-    }
-    if (h->opt.diverge_factor > 0 && rho > h->opt.diverge_factor * res0) {
-      status = fail(h, MGRIT_EDIVERGED, "residual grew past diverge_factor * res0");
-      break;
-    }
-    mgrit_status st = vcycle(h, 1, L0.r, L0.c[cur]);
-    if (st != MGRIT_OK) return st;
-    ++it;
+    case STOP_DIVERGED: status = fail(h, MGRIT_EDIVERGED, "residual grew past diverge_factor * res0"); break;
+    default: break;
   }
   if (u_out) {
     HIPCHK(h, run_fine(h, MGRIT_PROF_FINAL, MODE_FINAL_F, L0.c[cur], nullptr, nullptr, u_out));
@@ -1147,10 +1165,10 @@ mgrit_status mgrit_solve(mgrit_handle *h, const double *u0, const double *v_init
   HIPCHK(h, hipStreamSynchronize(h->stream));
   harvest_events(h);
   if (stats) {
-    stats->iterations = it;
-    stats->res0 = res0;
-    stats->res_final = rho;
-    stats->conv_factor = prev > 0 ? rho / prev : NAN;
+    stats->iterations = hc.it;
+    stats->res0 = hc.res0;
+    stats->res_final = hc.rho;
+    stats->conv_factor = prev > 0 ? hc.rho / prev : NAN;
     stats->res_history_len = std::min(hist_len, std::max(stats->res_history_cap, 0));
     stats->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }

@@ -169,6 +169,24 @@ struct PassArgs {
   double *parent;     // POST_F / SEQ: parent C-point rows to add into
   double *out;        // FINAL_F / SEQ: output rows
   double *normpart;   // PASS_B / RESID: per-workgroup partial sum of squares
+  const int *stop;    // non-NULL: the launch does nothing once *stop != 0
+};
+
+// Iteration state of one solve, kept in device memory: the kernel that
+// reduces the residual norm also takes the stopping decision, so the passes
+// queued behind it (the coarse-grid correction) can skip themselves without
+// the host waiting in between.
+enum StopCode : int { STOP_NONE = 0, STOP_CONVERGED = 1, STOP_MAX_ITER = 2, STOP_NONFINITE = 3, STOP_DIVERGED = 4 };
+struct SolveCtl {
+  double res0;  // ||r_0||
+  double rho;   // the latest ||r_it||
+  int it;       // coarse-grid corrections performed so far
+  int stop;     // StopCode
+};
+struct StopRule {
+  double rtol;
+  double diverge_factor;  // <= 0: no growth test
+  int max_iter;
 };
 
 // Level-0 explicit relaxation with wavefront tiles (temporal blocking): one
@@ -210,7 +228,11 @@ hipError_t launch_reduce(const double *part, int64_t n, double *out, hipStream_t
 // dst rows k = src rows k*stride (k = 0..rows-1), row length nx.
 hipError_t launch_gather_rows(const double *src, int64_t stride, double *dst, int64_t rows, int nx,
                               hipStream_t stream);
-hipError_t launch_fill(double *dst, int64_t n, double value, hipStream_t stream);
+hipError_t launch_fill(double *dst, int64_t n, double value, hipStream_t stream, const int *stop = nullptr);
+// Sum the n norm partials in a fixed order, set ctl->rho = sqrt(sum) and take
+// the stopping decision of iteration ctl->it (ctl zeroed before the first
+// call of a solve).
+hipError_t launch_solve_ctl(const double *part, int64_t n, SolveCtl *ctl, StopRule rule, hipStream_t stream);
 // The lean coarse-step kernel (mgrit_lean.hip) for layouts where
 // lean_slc_applies() holds, and its LDS attribute.
 hipError_t launch_lean(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs &pa,

@@ -24,6 +24,39 @@ __global__ void __launch_bounds__(256) reduce_kernel(const double *__restrict__ 
   if (threadIdx.x == 0) out[0] = red[0];
 }
 
+// Residual norm of one MGRIT iteration and the stopping test (Sec. 2.2: stop
+// once ||r_it|| <= rtol ||r_0||), in the order the solver applies them:
+// non-finite, converged, iteration limit, growth past diverge_factor ||r_0||.
+__global__ void __launch_bounds__(256) solve_ctl_kernel(const double *__restrict__ part, int64_t n,
+                                                         SolveCtl *ctl, StopRule rule) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if (threadIdx.x < d) red[threadIdx.x] += red[threadIdx.x + d];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double rho = sqrt(red[0]);
+  const int it = ctl->it;
+  const double res0 = it == 0 ? rho : ctl->res0;
+  ctl->res0 = res0;
+  ctl->rho = rho;
+  int stop = STOP_NONE;
+  if (!isfinite(rho))
+    stop = STOP_NONFINITE;
+  else if (rho <= rule.rtol * res0)
+    stop = STOP_CONVERGED;
+  else if (it >= rule.max_iter)
+    stop = STOP_MAX_ITER;
+  else if (rule.diverge_factor > 0 && rho > rule.diverge_factor * res0)
+    stop = STOP_DIVERGED;
+  ctl->stop = stop;
+  if (stop == STOP_NONE) ctl->it = it + 1;
+}
+
 __global__ void gather_rows_kernel(const double *__restrict__ src, int64_t stride, double *__restrict__ dst,
                                    int64_t rows, int nx) {
   const int64_t total = rows * (int64_t)nx;
@@ -35,7 +68,8 @@ __global__ void gather_rows_kernel(const double *__restrict__ src, int64_t strid
   }
 }
 
-__global__ void fill_kernel(double *__restrict__ dst, int64_t n, double value) {
+__global__ void fill_kernel(double *__restrict__ dst, int64_t n, double value, const int *stop) {
+  if (stop && *stop) return;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = value;
 }
@@ -90,10 +124,15 @@ hipError_t launch_gather_rows(const double *src, int64_t stride, double *dst, in
   return hipGetLastError();
 }
 
-hipError_t launch_fill(double *dst, int64_t n, double value, hipStream_t stream) {
+hipError_t launch_fill(double *dst, int64_t n, double value, hipStream_t stream, const int *stop) {
   if (n <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
-  hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(256), 0, stream, dst, n, value);
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(256), 0, stream, dst, n, value, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_ctl(const double *part, int64_t n, SolveCtl *ctl, StopRule rule, hipStream_t stream) {
+  hipLaunchKernelGGL(solve_ctl_kernel, dim3(1), dim3(256), 0, stream, part, n, ctl, rule);
   return hipGetLastError();
 }
 

@@ -291,28 +291,15 @@ __global__ void __launch_bounds__(WAVE * NW) slc_kernel(const LevelDesc *__restr
     af[m] = op.fw.a[m];
     ab[m] = op.bw.a[m];
   }
-  for (int i = threadIdx.x; i < RTAB_ALL * KK; i += T) {
-    tab_f[i] = op.fw.tab[i];
-    tab_b[i] = op.bw.tab[i];
-  }
-  __syncthreads();
-
   const int tid = threadIdx.x;
-  const int lane = tid & (WAVE - 1);
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  LaneMats<K, HOIST> lmf, lmb;
-  lmf.init(tab_f, lane & 15, lane, wave);
-  lmb.init(tab_b, (WAVE - 1 - lane) & 15, WAVE - 1 - lane, NW - 1 - wave);
-
   const int base = tid * L;
-  int start = base - (op.sl_K + op.sl_l) % NX;
-  if (start < 0) start += NX;
   const int64_t b = blockIdx.x;
   const int64_t nxl = NX;
   const int m = pa.m;
   const int mode = pa.mode;
   const int nsteps = (mode == MODE_POST_F) ? m - 1 : m;  // PASS_A, PASS_B, SEQ, APPLY: m
   const int64_t row0 = (mode == MODE_SEQ) ? 0 : b;
+  // start vector (loads issued before the table copy so their latencies overlap)
   double u[L];
   if (pa.zero_init) {
 #pragma unroll
@@ -320,6 +307,22 @@ __global__ void __launch_bounds__(WAVE * NW) slc_kernel(const LevelDesc *__restr
   } else {
     load_chunk<L>(pa.cin + row0 * nxl, base, L, u);
   }
+  const bool stopped = pa.stop && *pa.stop;  // the solve has already stopped
+  for (int i = threadIdx.x; i < RTAB_ALL * KK; i += T) {
+    tab_f[i] = op.fw.tab[i];
+    tab_b[i] = op.bw.tab[i];
+  }
+  __syncthreads();
+  if (stopped) return;
+
+  const int lane = tid & (WAVE - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  LaneMats<K, HOIST> lmf, lmb;
+  lmf.init(tab_f, lane & 15, lane, wave);
+  lmb.init(tab_b, (WAVE - 1 - lane) & 15, WAVE - 1 - lane, NW - 1 - wave);
+
+  int start = base - (op.sl_K + op.sl_l) % NX;
+  if (start < 0) start += NX;
   if (mode == MODE_PASS_A && b == 0) store_chunk<L>(pa.cout, base, L, u);
   const bool add_g = pa.g && mode != MODE_APPLY;
   const bool add_parent = mode == MODE_POST_F || (mode == MODE_SEQ && pa.parent);

@@ -454,6 +454,7 @@ __device__ __forceinline__ void run_chain(const PassArgs &pa, int nx, int cnt, d
 
 template <int L, int KIND, int MAXT>
 __global__ void __launch_bounds__(MAXT) step_kernel(const LevelDesc *__restrict__ desc, PassArgs pa) {
+  if (pa.stop && *pa.stop) return;  // the solve has already stopped
   extern __shared__ double smem[];
   const Layout lay = desc->lay;
   const StepOp &op = desc->op;
