@@ -509,6 +509,35 @@ bool choose_tiles(int nx, int m, int depth, int sl, int sr, int Pforce, TileGeom
   return best >= 0;
 }
 
+// Sequential stepping in blocks of T steps through the tile kernel (one
+// launch per block, the halo covering T steps).  Pick (P, T) minimising a
+// model of nt/T dependent launches: a fixed cost per launch (dispatch and
+// drain, about 2.5 us) plus one wavefront's instruction stream (about 5
+// cycles per instruction at 2.4 GHz), the tiles running side by side.
+bool choose_seq_tiles(int nx, int64_t nt, int depth, int sl, int sr, TileGeom &tg, int &T) {
+  static const int Ps[3] = {4, 8, 16};
+  static const int Ts[5] = {2, 4, 8, 16, 32};
+  double best = -1;
+  for (int P : Ps) {
+    for (int Tc : Ts) {
+      const int HL = Tc * depth * sl, HR = Tc * depth * sr;
+      const int avail = WAVE * P - HL - HR;
+      if (avail < 32) continue;
+      const int ntiles = (nx + avail - 1) / avail;
+      const double instr = (double)Tc * depth * (P * (sl + sr + 2) + 2 * (sl + sr));
+      const double rounds = std::ceil(ntiles / 1024.0);  // 256 CUs x 4 SIMDs, one wavefront each
+      const double launch_us = 2.5 + rounds * instr * 5.0 / 2400.0;
+      const double cost = std::ceil((double)nt / Tc) * launch_us;
+      if (best < 0 || cost < best) {
+        best = cost;
+        tg = TileGeom{P, HL, HR, (nx + ntiles - 1) / ntiles, ntiles, sl, sr};
+        T = Tc;
+      }
+    }
+  }
+  return best >= 0;
+}
+
 int env_int(const char *name, int def) {
   const char *v = std::getenv(name);
   return (v && *v) ? std::atoi(v) : def;
@@ -517,6 +546,9 @@ int env_int(const char *name, int def) {
 struct Level {
   bool tiles = false;  // level-0 explicit relaxation through tile_kernel
   TileGeom tg{};
+  bool seq_tiles = false;  // sequential stepping through tile_kernel, seq_T steps per launch
+  TileGeom seq_tg{};
+  int seq_T = 0;
   int64_t nt = 0;
   int m = 0;  // to the next level, 0 on the coarsest
   StepOp op{};
@@ -770,6 +802,8 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
       if (lds_bytes_for(L0.lay, 0) > LDS_LIMIT) L0.lay.dbuf = 0;
       L0.tiles = env_int("MGRIT_NO_TILES", 0) == 0 &&
                  choose_tiles(nx, ms[0], fi.tab.s, fi.l, fi.r, env_int("MGRIT_TILE_P", 0), L0.tg);
+      L0.seq_tiles = env_int("MGRIT_NO_TILES", 0) == 0 &&
+                     choose_seq_tiles(nx, P->nt, fi.tab.s, fi.l, fi.r, L0.seq_tg, L0.seq_T);
       op.kind = OP_POLY_Z;
       op.ncoef = fi.tab.s + 1;
       for (int i = 0; i <= fi.tab.s; ++i) op.coef[i] = (double)fi.beta[i];
@@ -1189,6 +1223,33 @@ mgrit_status mgrit_residual(mgrit_handle *h, const double *u, double *r, double 
 mgrit_status mgrit_sequential(mgrit_handle *h, const double *u0, double *u_out) {
   if (!h || !u0 || !u_out) return MGRIT_EINVAL;
   const Level &L0 = h->lv[0];
+  if (L0.seq_tiles) {
+    // blocks of seq_T steps, each launch reading the row the previous wrote
+    const int64_t nx = h->prob.nx, nt = h->prob.nt;
+    HIPCHK(h, hipMemcpyAsync(u_out, u0, nx * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    for (int64_t k = 0; k < nt; k += L0.seq_T) {
+      TileArgs ta{};
+      ta.mode = MODE_SEQ;
+      ta.m = (int)std::min<int64_t>(L0.seq_T, nt - k);
+      ta.nint = 1;
+      ta.cin = u_out + k * nx;
+      ta.out = u_out + k * nx;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (h->prof_mask & (1u << MGRIT_PROF_SEQUENTIAL)) {
+        e0 = take_event(h);
+        e1 = take_event(h);
+        if (e0 && e1) (void)hipEventRecord(e0, h->stream);
+      }
+      HIPCHK(h, launch_tiles(L0.desc, L0.seq_tg, ta, h->stream));
+      if (e0 && e1) {
+        (void)hipEventRecord(e1, h->stream);
+        h->ev_pending.push_back({MGRIT_PROF_SEQUENTIAL, {e0, e1}});
+      }
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    harvest_events(h);
+    return MGRIT_OK;
+  }
   HIPCHK(h, run_pass(h, L0, MGRIT_PROF_SEQUENTIAL, MODE_SEQ, (int)h->prob.nt, 1, u0, nullptr, nullptr, nullptr, nullptr, u_out, 0));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   harvest_events(h);

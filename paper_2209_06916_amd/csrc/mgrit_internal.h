@@ -203,7 +203,8 @@ struct TileGeom {
 };
 
 struct TileArgs {
-  int mode;           // MODE_PASS_A, MODE_PASS_B or MODE_FINAL_F
+  int mode;           // MODE_PASS_A, MODE_PASS_B, MODE_FINAL_F or MODE_SEQ (one block
+                      // of m sequential steps: nint = 1, cin = out = the block's first row)
   int m;              // steps per interval
   int64_t nint;       // intervals
   const double *cin;  // [nint+1][nx]
@@ -214,6 +215,7 @@ struct TileArgs {
 };
 
 hipError_t launch_tiles(const LevelDesc *desc, const TileGeom &tg, const TileArgs &ta, hipStream_t stream);
+hipError_t launch_tiles_4(const LevelDesc *desc, const TileGeom &tg, const TileArgs &ta, hipStream_t stream);
 hipError_t launch_tiles_8(const LevelDesc *desc, const TileGeom &tg, const TileArgs &ta, hipStream_t stream);
 hipError_t launch_tiles_16(const LevelDesc *desc, const TileGeom &tg, const TileArgs &ta, hipStream_t stream);
 

@@ -104,6 +104,7 @@ hipError_t launch_pass(const LevelDesc *desc, const StepOp &op, const Layout &la
 hipError_t launch_tiles(const LevelDesc *desc, const TileGeom &tg, const TileArgs &ta, hipStream_t stream) {
   if (ta.nint <= 0) return hipSuccess;
   switch (tg.P) {
+    case 4: return launch_tiles_4(desc, tg, ta, stream);
     case 8: return launch_tiles_8(desc, tg, ta, stream);
     case 16: return launch_tiles_16(desc, tg, ta, stream);
     default: return hipErrorInvalidValue;

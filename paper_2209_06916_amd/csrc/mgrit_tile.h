@@ -6,9 +6,42 @@
 // Level-0 explicit relaxation, one wavefront per (CF-interval, spatial tile).
 // Lane l holds the P consecutive points starting at x0 - HL + l P (periodic).
 // Each application of Z = -c L_p reads SL points from the left neighbour lane
-// and SR from the right one; lane 0's left and lane 63's right inputs are
-// stale, which only invalidates points inside the halo.  No LDS, no barriers.
+// and SR from the right one, moved by whole-wavefront DPP shifts; lane 0's
+// left and lane 63's right inputs are zero, which only invalidates points
+// inside the halo.  No LDS, no barriers.
 // ---------------------------------------------------------------------------
+// Whole-wavefront shift of a double by one lane: WAVE_SHR1 (0x138) gives lane
+// l the value of lane l-1, WAVE_SHL1 (0x130) that of lane l+1; the lane
+// without a source reads 0.
+template <int CTRL>
+__device__ __forceinline__ double wave_shift(double v) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(bits & 0xffffffff), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+// x[0..P) = row[g .. g+P) (periodic); 16-byte loads when the run is
+// contiguous and aligned.
+template <int P>
+__device__ __forceinline__ void load_run(const double *__restrict__ row, int g, int nx, double (&x)[P]) {
+  const double *p = row + g;
+  if (g + P <= nx && ((reinterpret_cast<uintptr_t>(p) & 15) == 0)) {
+    const double2 *p2 = reinterpret_cast<const double2 *>(p);
+#pragma unroll
+    for (int k = 0; k < P / 2; ++k) {
+      const double2 t = p2[k];
+      x[2 * k] = t.x;
+      x[2 * k + 1] = t.y;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      x[k] = row[g];
+      g = wrap_hi(g + 1, nx);
+    }
+  }
+}
 template <int P, int SL, int SR>
 __global__ void __launch_bounds__(256) tile_kernel(const LevelDesc *__restrict__ desc, TileGeom tg, TileArgs ta) {
   const StepOp &op = desc->op;
@@ -36,19 +69,19 @@ __global__ void __launch_bounds__(256) tile_kernel(const LevelDesc *__restrict__
   if (g0 < 0) g0 += nx;
 
   double u[P];
-  {
-    const double *row = ta.cin + b * nxl;
-    int g = g0;
-#pragma unroll
-    for (int k = 0; k < P; ++k) {
-      u[k] = row[g];
-      g = wrap_hi(g + 1, nx);
-    }
-  }
+  load_run<P>(ta.cin + b * nxl, g0, nx, u);
   // output window of this lane: local indices [HL, HL + tw)
   const int lo = tg.HL - li0, hi = tg.HL + tw - li0;  // k in [lo, hi) is output
+  const bool whole = lo <= 0 && hi >= P && g0 + P <= nx;  // all P points are output, no wrap
 
   auto store_out = [&](double *row, const double (&v)[P]) {
+    double *p = row + g0;
+    if (whole && ((reinterpret_cast<uintptr_t>(p) & 15) == 0)) {
+      double2 *p2 = reinterpret_cast<double2 *>(p);
+#pragma unroll
+      for (int k = 0; k < P / 2; ++k) p2[k] = make_double2(v[2 * k], v[2 * k + 1]);
+      return;
+    }
     int g = g0;
 #pragma unroll
     for (int k = 0; k < P; ++k) {
@@ -60,7 +93,11 @@ __global__ void __launch_bounds__(256) tile_kernel(const LevelDesc *__restrict__
   if (ta.mode == MODE_PASS_A && b == 0) store_out(ta.cout, u);
   if (ta.mode == MODE_FINAL_F) store_out(ta.out + (b * ta.m) * nxl, u);
 
+  // FINAL_F computes the m-1 F-points (the C-point comes from the iterate);
+  // SEQ advances one block of m steps of sequential time-stepping (nint = 1)
+  // and writes every step.
   const int nsteps = (ta.mode == MODE_FINAL_F) ? ta.m - 1 : ta.m;
+  const bool store_steps = ta.mode == MODE_FINAL_F || ta.mode == MODE_SEQ;
   for (int j = 1; j <= nsteps; ++j) {
     double y[P];
 #pragma unroll
@@ -68,9 +105,9 @@ __global__ void __launch_bounds__(256) tile_kernel(const LevelDesc *__restrict__
     for (int i = ncoef - 2; i >= 0; --i) {
       double lh[SL > 0 ? SL : 1], rh[SR > 0 ? SR : 1];
 #pragma unroll
-      for (int q = 0; q < SL; ++q) lh[q] = __shfl(y[P - SL + q], (lane - 1) & (WAVE - 1), WAVE);
+      for (int q = 0; q < SL; ++q) lh[q] = wave_shift<0x138>(y[P - SL + q]);
 #pragma unroll
-      for (int q = 0; q < SR; ++q) rh[q] = __shfl(y[q], (lane + 1) & (WAVE - 1), WAVE);
+      for (int q = 0; q < SR; ++q) rh[q] = wave_shift<0x130>(y[q]);
       const double ci = op.coef[i];
       double yn[P];
 #pragma unroll
@@ -90,7 +127,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const LevelDesc *__restrict__
     }
 #pragma unroll
     for (int k = 0; k < P; ++k) u[k] = y[k];
-    if (ta.mode == MODE_FINAL_F) store_out(ta.out + (b * ta.m + j) * nxl, u);
+    if (store_steps) store_out(ta.out + (b * ta.m + j) * nxl, u);
   }
 
   if (ta.mode == MODE_PASS_A) {
@@ -113,13 +150,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const LevelDesc *__restrict__
     if (lane == 0) ta.normpart[item] = ss;
   } else if (ta.mode == MODE_FINAL_F && b == ta.nint - 1) {
     double c[P];
-    const double *row = ta.cin + ta.nint * nxl;
-    int g = g0;
-#pragma unroll
-    for (int k = 0; k < P; ++k) {
-      c[k] = row[g];
-      g = wrap_hi(g + 1, nx);
-    }
+    load_run<P>(ta.cin + ta.nint * nxl, g0, nx, c);
     store_out(ta.out + (ta.nint * ta.m) * nxl, c);
   }
 }

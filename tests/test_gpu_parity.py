@@ -155,11 +155,14 @@ def test_lean_and_generic_coarse_kernels_agree(monkeypatch):
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("nx,nt,p,kind,q,c", [(256, 256, 1, "erk", 1, 0.85), (4096, 512, 3, "erk", 3, 0.85),
-                                              (1000, 64, 5, "sdirk", 3, 0.5), (512, 128, 3, "sdirk", 3, 5.0)])
+                                              (1000, 64, 5, "sdirk", 3, 0.5), (512, 128, 3, "sdirk", 3, 5.0),
+                                              (1000, 102, 5, "erk", 5, 0.9), (77, 38, 3, "erk", 3, 1.0),
+                                              (512, 130, 2, "erk", 2, 0.45), (4096, 1000, 4, "erk", 4, 0.9)])
 def test_sequential_and_residual_match_oracle(nx, nt, p, kind, q, c):
     _announce("sequential", nx, nt, p, kind, q, c)
     u0 = inputs.u0_fourier(nx, seed=3)
-    s = mgrit.Solver(mgrit.make_problem(nx, nt, c, p, kind, q), mgrit.make_options(4, coarse="ideal"))
+    m = 4 if nt % 4 == 0 else 2
+    s = mgrit.Solver(mgrit.make_problem(nx, nt, c, p, kind, q), mgrit.make_options(m, coarse="ideal"))
     out = torch.empty((nt + 1, nx), dtype=torch.float64, device=DEV)
     s.sequential(_t(u0), out)
     step = disc.MOLStep(p, kind, q, c)
@@ -327,6 +330,22 @@ def test_tiled_relaxation_matches_oracle(monkeypatch, tile_p, p, q, c, coarse, m
     nx, nt = 300, 128
     s, info, got, fin, ref, rinfo = _solve_both(nx, nt, p, "erk", q, c, ms, coarse=coarse, u0kind="fourier")
     _check_parity(info, got, fin, ref, rinfo, ms[0])
+
+
+def test_tiled_and_slab_sequential_stepping_agree(monkeypatch):
+    """mgrit_sequential through blocks of tile launches and through the
+    one-workgroup step kernel."""
+    _announce("sequential tiles vs slab")
+    nx, nt = 4096, 333
+    u0 = _t(inputs.u0_fourier(nx, 23))
+    outs = []
+    for flag in ("0", "1"):
+        monkeypatch.setenv("MGRIT_NO_TILES", flag)
+        s = mgrit.Solver(mgrit.make_problem(nx, nt, 0.85, 3), mgrit.make_options(3, coarse="ideal"))
+        o = torch.empty((nt + 1, nx), dtype=torch.float64, device=DEV)
+        s.sequential(u0, o)
+        outs.append(_np(o))
+    np.testing.assert_allclose(outs[0], outs[1], rtol=0, atol=1e-13 * np.max(np.abs(outs[1])))
 
 
 def test_tiled_and_slab_relaxation_agree(monkeypatch):
