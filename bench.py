@@ -39,12 +39,13 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_source_hash():
-    """Hash of every library source (kernels, launch shapes, host driver)."""
+    """Hash of the device-code sources (every .hip and .h of the library)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2209_06916_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + b"\0" + fh.read())
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
 
 
@@ -74,34 +75,129 @@ def cpu_baseline(u0, v0):
 
 
 def phase_work(iterations):
-    """Algorithmic (flops, bytes) per solve of each profiled phase.
+    """Algorithmic (flops, bytes, working launches) per solve of each profiled phase.
 
-    Fine relaxation: 2 launches per iteration + 1 (the last pre-relaxation),
-    each nt fine steps of nx points (flops), reading and writing one nx-vector
-    per CF-interval (bytes; F-points stay on chip).  Coarse levels: every
-    application of Psi_l (semi-Lagrangian taps + forward/backward recurrences
-    of order (p+1)/2) reads one right-hand-side vector.  Final: nt - nt/m fine
-    steps, reads the C-points, writes all nt+1 rows."""
+    Rows are nx doubles.  Level 0 (nc0 = nt/m intervals): pass A reads C_k and
+    writes C'_{k+1} (2 nc0 rows), pass B reads C'_k and C'_{k+1} and writes r
+    (3 nc0 rows); F-points never leave the chip; each pass takes nt fine steps.
+    Coarse level l (nt_l points, nc_l intervals): pass A 2 nc_l + nt_l rows (the
+    right-hand side row of every step), pass B 3 nc_l + nt_l, post-F relaxation
+    nc_l C-rows, (m_l - 1) nc_l right-hand sides and a read-modify-write of every
+    parent row (2 nt_l); the coarsest sweep nt_L right-hand sides and 2 nt_L
+    parent rows.  Every Psi application: semi-Lagrangian taps and the forward and
+    backward recurrences of order (p+1)/2.  Final pass: nt - nc0 fine steps,
+    reads the C-points and writes all nt+1 rows."""
+    row = NX * 8
     nc0 = NT // MS[0]
-    fine_launches = 2 * (iterations + 1)
-    fine = (fine_launches * NT * NX * phi_flops_per_dof(), fine_launches * 2 * nc0 * NX * 8, fine_launches)
+    passes = iterations + 1  # pre-relaxation of every iteration and of the last check
+    fine = (2 * passes * NT * NX * phi_flops_per_dof(), passes * (2 + 3) * nc0 * row, 2 * passes)
     k = (P + 1) // 2
     psi_flops = 2 * ((P + 1) + 2 * (2 * k + 1) + 1)
-    apps = 0
-    launches = 0
+    apps = rows = launches = 0
     nt_l = NT
     for lev, m in enumerate(MS):
-        nt_l //= m
+        nt_l //= m  # points of level lev+1
         if lev < len(MS) - 1:
-            m_next = MS[lev + 1]
-            apps += 2 * nt_l + (nt_l - nt_l // m_next)
+            nc = nt_l // MS[lev + 1]
+            apps += 2 * nt_l + (nt_l - nc)
+            rows += (2 * nc + nt_l) + (3 * nc + nt_l) + (nc + (nt_l - nc) + 2 * nt_l)
             launches += 3
         else:
             apps += nt_l
+            rows += nt_l + 2 * nt_l
             launches += 1
-    coarse = (iterations * apps * NX * psi_flops, iterations * apps * NX * 8, iterations * launches)
-    final = ((NT - nc0) * NX * phi_flops_per_dof(), ((NT + 1) + (nc0 + 1)) * NX * 8, 1)
+    coarse = (iterations * apps * NX * psi_flops, iterations * rows * row, iterations * launches)
+    final = ((NT - nc0) * NX * phi_flops_per_dof(), ((NT + 1) + (nc0 + 1)) * row, 1)
     return {"fine_relax": fine, "coarse": coarse, "final": final}
+
+
+PROFILE_COMMANDS = {
+    "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/trace -o run -- "
+             "python3 bench.py --steps 10 --warmup 2 --no-cpu-baseline",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/fetch -o run -- "
+             "python3 bench.py --steps 2 --warmup 1 --traffic-probe",
+    "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/write -o run -- "
+             "python3 bench.py --steps 2 --warmup 1 --traffic-probe",
+}
+DOMINANT_KERNEL = "slc_kernel<4, 2, 4>"
+
+
+def _short(name):
+    name = name.replace("void ", "").replace("mgrit::(anonymous namespace)::", "")
+    return name.split("(")[0]
+
+
+def summarize_profiles(d):
+    """Turn the three rocprofv3 runs under directory d (made by PROFILE_COMMANDS,
+    run from the repository root after `cd /tmp && export TMPDIR=/tmp`) into
+    profiles/kernel_stats_<workload>.txt, profiles/traffic_<workload>.txt and
+    profiles/traffic.json (the counters scaled by what they read for the
+    probe's 1 GiB elementwise copy)."""
+    import csv
+    prof_dir = os.path.join(ROOT, "profiles")
+    rows = list(csv.DictReader(open(os.path.join(d, "trace", "run_kernel_stats.csv"))))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# rocprofv3 kernel statistics -- workload {WORKLOAD}",
+             "# (10 timed + 2 warm-up MGRIT solves, then 4 runs of sequential time-stepping of the same problem)",
+             "# command (repository root on the GPU box, after cd /tmp && export TMPDIR=/tmp):",
+             "#   " + PROFILE_COMMANDS["trace"].replace("<dir>", "gpurun_out/prof"),
+             "#", f"# {'kernel':52s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'share':>7s}"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        lines.append(f"  {_short(r['Name']):52s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
+                     f"{float(r['TotalDurationNs']) / 1e6:10.3f} {100 * float(r['TotalDurationNs']) / tot:6.2f}%")
+    lines += ["#", "# slc_kernel<4, 2, 4>: every coarse-level pass (levels 1-3); tile_kernel<8, 2, 1>: level-0",
+              "# relaxation passes and the final F-relaxation; tile_kernel<4, 2, 1>: sequential time-stepping",
+              "# (blocks of steps); solve_ctl_kernel: residual norm + stopping test."]
+    with open(os.path.join(prof_dir, f"kernel_stats_{WORKLOAD}.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+    def counters(sub, name):
+        per = {}
+        order = []
+        for r in csv.DictReader(open(os.path.join(d, sub, "run_counter_collection.csv"))):
+            if r["Counter_Name"] != name:
+                continue
+            k = _short(r["Kernel_Name"])
+            per.setdefault(k, []).append(float(r["Counter_Value"]))
+            order.append(k)
+        return per, order
+
+    fetch, forder = counters("fetch", "FETCH_SIZE")
+    write, _ = counters("write", "WRITE_SIZE")
+    # the calibration copy is the probe's last dispatch
+    copy_name = forder[-1]
+    copy_kib = COPY_BYTES / 1024
+    fscale = copy_kib / fetch[copy_name][-1]
+    wscale = copy_kib / write[copy_name][-1]
+    lines = [f"# rocprofv3 HBM traffic counters -- workload {WORKLOAD}",
+             "# commands (two separate runs, one counter each; repository root, after cd /tmp && export TMPDIR=/tmp):",
+             "#   " + PROFILE_COMMANDS["fetch"].replace("<dir>", "gpurun_out/prof"),
+             "#   " + PROFILE_COMMANDS["write"].replace("<dir>", "gpurun_out/prof"),
+             f"# calibration: the probe's elementwise copy ({copy_name}) reads and writes {COPY_BYTES >> 20} MiB",
+             f"#   FETCH_SIZE read {fetch[copy_name][-1]:.1f} KiB for {copy_kib:.0f} KiB -> scale {fscale:.4f}",
+             f"#   WRITE_SIZE read {write[copy_name][-1]:.1f} KiB for {copy_kib:.0f} KiB -> scale {wscale:.4f}",
+             "#", f"# {'kernel':40s} {'dispatches':>10s} {'FETCH_KiB/disp':>15s} {'WRITE_KiB/disp':>15s} "
+                  f"{'scaled_MB/disp':>15s}"]
+    result = None
+    for k in fetch:
+        if k == copy_name or k not in write or k.startswith("at::"):
+            continue
+        fk = float(np.mean(fetch[k]))
+        wk = float(np.mean(write[k]))
+        mb = (fk * fscale + wk * wscale) * 1024 / 1e6
+        lines.append(f"  {k:40s} {len(fetch[k]):10d} {fk:15.1f} {wk:15.1f} {mb:15.2f}")
+        if k == DOMINANT_KERNEL:
+            result = dict(fetch_kib=fk, write_kib=wk, bytes=(fk * fscale + wk * wscale) * 1024)
+    with open(os.path.join(prof_dir, f"traffic_{WORKLOAD}.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    if result is not None:
+        with open(os.path.join(prof_dir, "traffic.json"), "w") as fh:
+            json.dump({"workload": WORKLOAD, "phase": "coarse", "kernel": DOMINANT_KERNEL,
+                       "source_hash": kernel_source_hash(), "bytes_per_launch": result["bytes"],
+                       "fetch_scale": fscale, "write_scale": wscale, "fetch_kib_per_dispatch": result["fetch_kib"],
+                       "write_kib_per_dispatch": result["write_kib"],
+                       "source": f"profiles/traffic_{WORKLOAD}.txt"}, fh, indent=1)
+    print("\n".join(lines))
 
 
 def main():
@@ -113,7 +209,12 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for hardware-counter runs: a few solves plus one elementwise copy of "
                          "COPY_BYTES read + COPY_BYTES written (the counter calibration)")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="CPU only: turn the rocprofv3 runs under DIR into the profiles/ summaries")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only (the path is a single-GPU build); "
                                    f"--gpus {args.gpus} is not supported"}))

@@ -514,12 +514,14 @@ bool choose_tiles(int nx, int m, int depth, int sl, int sr, int Pforce, TileGeom
 // model of nt/T dependent launches: a fixed cost per launch (dispatch and
 // drain, about 2.5 us) plus one wavefront's instruction stream (about 5
 // cycles per instruction at 2.4 GHz), the tiles running side by side.
-bool choose_seq_tiles(int nx, int64_t nt, int depth, int sl, int sr, TileGeom &tg, int &T) {
+bool choose_seq_tiles(int nx, int64_t nt, int depth, int sl, int sr, int Pforce, int Tforce, TileGeom &tg, int &T) {
   static const int Ps[3] = {4, 8, 16};
   static const int Ts[5] = {2, 4, 8, 16, 32};
   double best = -1;
   for (int P : Ps) {
+    if (Pforce && P != Pforce) continue;
     for (int Tc : Ts) {
+      if (Tforce && Tc != Tforce) continue;
       const int HL = Tc * depth * sl, HR = Tc * depth * sr;
       const int avail = WAVE * P - HL - HR;
       if (avail < 32) continue;
@@ -803,7 +805,8 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
       L0.tiles = env_int("MGRIT_NO_TILES", 0) == 0 &&
                  choose_tiles(nx, ms[0], fi.tab.s, fi.l, fi.r, env_int("MGRIT_TILE_P", 0), L0.tg);
       L0.seq_tiles = env_int("MGRIT_NO_TILES", 0) == 0 &&
-                     choose_seq_tiles(nx, P->nt, fi.tab.s, fi.l, fi.r, L0.seq_tg, L0.seq_T);
+                     choose_seq_tiles(nx, P->nt, fi.tab.s, fi.l, fi.r, env_int("MGRIT_SEQ_P", 0),
+                                      env_int("MGRIT_SEQ_T", 0), L0.seq_tg, L0.seq_T);
       op.kind = OP_POLY_Z;
       op.ncoef = fi.tab.s + 1;
       for (int i = 0; i <= fi.tab.s; ++i) op.coef[i] = (double)fi.beta[i];
