@@ -4,6 +4,9 @@
 
 __device__ __forceinline__ int padix(int i) { return i + (i >> 4); }
 
+// i + 1 on the periodic mesh, for 0 <= i < nx
+__device__ __forceinline__ int next_periodic(int i, int nx) { return i + 1 == nx ? 0 : i + 1; }
+
 __device__ __forceinline__ int wrap_hi(int i, int nx) {
   while (i >= nx) i -= nx;
   return i;

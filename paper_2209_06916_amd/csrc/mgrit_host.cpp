@@ -575,9 +575,15 @@ struct mgrit_handle {
   double *normsum = nullptr;
   double *normsum_host = nullptr;
   SolveCtl *ctl = nullptr;       // device iteration state of mgrit_solve
-  SolveCtl *ctl_host = nullptr;  // pinned copy, read once per iteration
+  SolveCtl *ctl_host = nullptr;  // pinned coherent copy, read once per iteration
+  SolveCtl *ctl_host_dev = nullptr;  // the same memory as the device addresses it
   hipEvent_t ctl_ev = nullptr;
   const int *guard = nullptr;    // stop flag handed to the passes being queued
+  // persistent coarse V-cycle (one cooperative launch per iteration)
+  bool cv_ok = false;
+  size_t cv_lds = 0;
+  int64_t cv_grid = 0;
+  GridSync *gsync = nullptr;
   std::string err;
   // profiler
   uint32_t prof_mask = 0;
@@ -713,6 +719,7 @@ void mgrit_destroy(mgrit_handle *h) {
   if (h->normsum) (void)hipFree(h->normsum);
   if (h->normsum_host) (void)hipHostFree(h->normsum_host);
   if (h->ctl) (void)hipFree(h->ctl);
+  if (h->gsync) (void)hipFree(h->gsync);
   if (h->ctl_host) (void)hipHostFree(h->ctl_host);
   if (h->ctl_ev) (void)hipEventDestroy(h->ctl_ev);
   for (auto &pe : h->ev_pending) {
@@ -975,10 +982,36 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
   if (dalloc(&h->normpart, h->normpart_len) != hipSuccess || dalloc(&h->normsum, 1) != hipSuccess ||
       hipHostMalloc((void **)&h->normsum_host, sizeof(double)) != hipSuccess ||
       hipMalloc((void **)&h->ctl, sizeof(SolveCtl)) != hipSuccess ||
-      hipHostMalloc((void **)&h->ctl_host, sizeof(SolveCtl)) != hipSuccess ||
+      hipHostMalloc((void **)&h->ctl_host, sizeof(SolveCtl), hipHostMallocMapped | hipHostMallocCoherent) !=
+          hipSuccess ||
+      hipHostGetDevicePointer((void **)&h->ctl_host_dev, h->ctl_host, 0) != hipSuccess ||
       hipEventCreateWithFlags(&h->ctl_ev, hipEventDisableTiming) != hipSuccess) {
     mgrit_destroy(h);
     return bad(MGRIT_ENOMEM, "norm buffers");
+  }
+  // Persistent coarse V-cycle: every coarse level takes the lean kernel, the
+  // tables of all of them fit in LDS beside the vector, and the largest
+  // level's intervals can all be resident at once (cooperative launch).
+  if (nlev >= 2 && env_int("MGRIT_NO_PERSISTENT", 0) == 0) {
+    bool all_lean = true;
+    for (int l = 1; l < nlev; ++l) all_lean = all_lean && lean_slc_applies(h->lv[l].op, h->lv[l].lay);
+    const size_t lds = all_lean ? coarse_vcycle_lds(h->lv[1].op, h->lv[1].lay, nlev - 1) : 0;
+    int64_t grid = 1;
+    int64_t longest = h->lv[nlev - 1].nt;  // steps of the longest phase (the barrier wait bound assumes <= 256)
+    for (int l = 1; l + 1 < nlev; ++l) {
+      grid = std::max<int64_t>(grid, h->lv[l].nt / h->lv[l].m);
+      longest = std::max<int64_t>(longest, h->lv[l].m);
+    }
+    if (lds > 0 && longest <= 256 && grid <= coarse_vcycle_max_grid(h->lv[1].op, h->lv[1].lay, lds)) {
+      if (hipMalloc((void **)&h->gsync, sizeof(GridSync)) != hipSuccess ||
+          hipMemset(h->gsync, 0, sizeof(GridSync)) != hipSuccess) {
+        mgrit_destroy(h);
+        return bad(MGRIT_ENOMEM, "grid barrier state");
+      }
+      h->cv_ok = true;
+      h->cv_lds = lds;
+      h->cv_grid = grid;
+    }
   }
   *out = h;
   return MGRIT_OK;
@@ -1093,28 +1126,94 @@ int64_t fine_norm_parts(const mgrit_handle *h) {
 // Approximate solve of level l >= 1 with rhs g (rows 1..nt_l) and zero initial
 // guess; the result is added into `parent` rows 0..nt_l (the C-points of
 // level l-1).
-mgrit_status vcycle(mgrit_handle *h, int l, const double *g, double *parent) {
+struct PhaseRec {
+  int kind;  // CP_PASS or CP_FILL
+  int level;
+  PassArgs pa;
+};
+
+// The coarse passes of a V-cycle below level l-1, in launch order: level l
+// relaxes (F(CF)^nu, then F and the C-point residual), recurses on its
+// residual, and post-relaxes into its parent's C-points; the last level is
+// solved by sequential stepping (Sec. 2.2).
+void vcycle_plan(mgrit_handle *h, int l, const double *g, double *parent, std::vector<PhaseRec> &out) {
   Level &L = h->lv[l];
   const int nlev = (int)h->lv.size();
   const int nx = (int)h->prob.nx;
+  auto pass = [&](int mode, int m, int64_t nint, const double *cin, double *cout, double *r, double *par,
+                  int zero_init) {
+    PhaseRec p{CP_PASS, l, PassArgs{}};
+    p.pa.mode = mode;
+    p.pa.m = m;
+    p.pa.zero_init = zero_init;
+    p.pa.nint = nint;
+    p.pa.cin = cin;
+    p.pa.cout = cout;
+    p.pa.g = g;
+    p.pa.r = r;
+    p.pa.parent = par;
+    p.pa.normpart = h->normpart;
+    out.push_back(p);
+  };
   if (l == nlev - 1) {
-    HIPCHK(h, run_pass(h, L, MGRIT_PROF_COARSE, MODE_SEQ, (int)L.nt, 1, nullptr, nullptr, g, nullptr, parent, nullptr, 1));
-    return MGRIT_OK;
+    pass(MODE_SEQ, (int)L.nt, 1, nullptr, nullptr, nullptr, parent, 1);
+    return;
   }
   const int64_t nc = L.nt / L.m;
   int cur = 0;
   if (h->opt.nu == 0) {
-    HIPCHK(h, launch_fill(L.c[0], (nc + 1) * (int64_t)nx, 0.0, h->stream, h->guard));
+    PhaseRec f{CP_FILL, l, PassArgs{}};
+    f.pa.cout = L.c[0];
+    f.pa.nint = (nc + 1) * (int64_t)nx;
+    out.push_back(f);
   }
   for (int s = 0; s < h->opt.nu; ++s) {
-    HIPCHK(h, run_pass(h, L, MGRIT_PROF_COARSE, MODE_PASS_A, L.m, nc, s == 0 ? nullptr : L.c[cur], L.c[1 - cur], g, nullptr, nullptr,
-                       nullptr, s == 0));
+    pass(MODE_PASS_A, L.m, nc, s == 0 ? nullptr : L.c[cur], L.c[1 - cur], nullptr, nullptr, s == 0);
     cur = 1 - cur;
   }
-  HIPCHK(h, run_pass(h, L, MGRIT_PROF_COARSE, MODE_PASS_B, L.m, nc, L.c[cur], nullptr, g, L.r, nullptr, nullptr, 0));
-  mgrit_status st = vcycle(h, l + 1, L.r, L.c[cur]);
-  if (st != MGRIT_OK) return st;
-  HIPCHK(h, run_pass(h, L, MGRIT_PROF_COARSE, MODE_POST_F, L.m, nc, L.c[cur], nullptr, g, nullptr, parent, nullptr, 0));
+  pass(MODE_PASS_B, L.m, nc, L.c[cur], nullptr, L.r, nullptr, 0);
+  vcycle_plan(h, l + 1, L.r, L.c[cur], out);
+  pass(MODE_POST_F, L.m, nc, L.c[cur], nullptr, nullptr, parent, 0);
+}
+
+// Queue the coarse-grid correction of one iteration: one persistent launch
+// when it applies, else one launch per pass.
+mgrit_status vcycle(mgrit_handle *h, const double *g, double *parent) {
+  std::vector<PhaseRec> ph;
+  vcycle_plan(h, 1, g, parent, ph);
+  if (h->cv_ok && (int)ph.size() <= MAX_COARSE_PHASES) {
+    CoarsePlan plan{};
+    plan.nphases = (int)ph.size();
+    plan.nlevels = (int)h->lv.size() - 1;
+    for (int l = 1; l < (int)h->lv.size(); ++l) plan.desc[l - 1] = h->lv[l].desc;
+    for (size_t i = 0; i < ph.size(); ++i) plan.ph[i] = CoarsePhase{ph[i].kind, ph[i].level - 1, ph[i].pa};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (h->prof_mask & (1u << MGRIT_PROF_COARSE)) {
+      e0 = take_event(h);
+      e1 = take_event(h);
+      if (e0 && e1) (void)hipEventRecord(e0, h->stream);
+    }
+    const hipError_t e = launch_coarse_vcycle(plan, h->lv[1].op, h->lv[1].lay, h->cv_grid, h->cv_lds, h->gsync,
+                                              h->guard, h->stream);
+    if (e0 && e1) {
+      (void)hipEventRecord(e1, h->stream);
+      h->ev_pending.push_back({MGRIT_PROF_COARSE, {e0, e1}});
+    }
+    if (e == hipSuccess) return MGRIT_OK;
+    // the runtime refused the cooperative launch (for instance when other
+    // work holds the compute units): fall back to one launch per pass
+    (void)hipGetLastError();
+    h->cv_ok = false;
+  }
+  for (const PhaseRec &p : ph) {
+    const Level &L = h->lv[p.level];
+    if (p.kind == CP_FILL) {
+      HIPCHK(h, launch_fill(p.pa.cout, p.pa.nint, 0.0, h->stream, h->guard));
+    } else {
+      HIPCHK(h, run_pass(h, L, MGRIT_PROF_COARSE, p.pa.mode, p.pa.m, p.pa.nint, p.pa.cin, p.pa.cout, p.pa.g, p.pa.r,
+                         p.pa.parent, nullptr, p.pa.zero_init));
+    }
+  }
   return MGRIT_OK;
 }
 
@@ -1168,11 +1267,10 @@ mgrit_status mgrit_solve(mgrit_handle *h, const double *u0, const double *v_init
       cur = 1 - cur;
     }
     HIPCHK(h, run_fine(h, MGRIT_PROF_FINE_RELAX, MODE_PASS_B, L0.c[cur], nullptr, L0.r, nullptr));
-    HIPCHK(h, launch_solve_ctl(h->normpart, fine_norm_parts(h), h->ctl, rule, h->stream));
-    HIPCHK(h, hipMemcpyAsync(h->ctl_host, h->ctl, sizeof(SolveCtl), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, launch_solve_ctl(h->normpart, fine_norm_parts(h), h->ctl, h->ctl_host_dev, h->gsync, rule, h->stream));
     HIPCHK(h, hipEventRecord(h->ctl_ev, h->stream));
     h->guard = &h->ctl->stop;
-    const mgrit_status st = vcycle(h, 1, L0.r, L0.c[cur]);
+    const mgrit_status st = vcycle(h, L0.r, L0.c[cur]);
     h->guard = nullptr;
     if (st != MGRIT_OK) return st;
     HIPCHK(h, hipEventSynchronize(h->ctl_ev));
@@ -1190,6 +1288,12 @@ mgrit_status mgrit_solve(mgrit_handle *h, const double *u0, const double *v_init
       h->err = "max_iter reached";
       break;
     case STOP_DIVERGED: status = fail(h, MGRIT_EDIVERGED, "residual grew past diverge_factor * res0"); break;
+    case STOP_DEVICE:
+      // a persistent launch gave up waiting at a grid barrier: reset the
+      // barrier state so that later solves start clean
+      (void)hipStreamSynchronize(h->stream);
+      (void)hipMemset(h->gsync, 0, sizeof(GridSync));
+      return fail(h, MGRIT_EDEVICE, "coarse-level grid barrier timed out");
     default: break;
   }
   if (u_out) {

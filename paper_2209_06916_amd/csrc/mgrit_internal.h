@@ -176,7 +176,14 @@ struct PassArgs {
 // reduces the residual norm also takes the stopping decision, so the passes
 // queued behind it (the coarse-grid correction) can skip themselves without
 // the host waiting in between.
-enum StopCode : int { STOP_NONE = 0, STOP_CONVERGED = 1, STOP_MAX_ITER = 2, STOP_NONFINITE = 3, STOP_DIVERGED = 4 };
+enum StopCode : int {
+  STOP_NONE = 0,
+  STOP_CONVERGED = 1,
+  STOP_MAX_ITER = 2,
+  STOP_NONFINITE = 3,
+  STOP_DIVERGED = 4,
+  STOP_DEVICE = 5  // a persistent launch gave up at a grid barrier
+};
 struct SolveCtl {
   double res0;  // ||r_0||
   double rho;   // the latest ||r_it||
@@ -233,8 +240,45 @@ hipError_t launch_gather_rows(const double *src, int64_t stride, double *dst, in
 hipError_t launch_fill(double *dst, int64_t n, double value, hipStream_t stream, const int *stop = nullptr);
 // Sum the n norm partials in a fixed order, set ctl->rho = sqrt(sum) and take
 // the stopping decision of iteration ctl->it (ctl zeroed before the first
-// call of a solve).
-hipError_t launch_solve_ctl(const double *part, int64_t n, SolveCtl *ctl, StopRule rule, hipStream_t stream);
+// call of a solve); the new state is also written to ctl_host (pinned host
+// memory) when it is not NULL.
+struct GridSync;
+hipError_t launch_solve_ctl(const double *part, int64_t n, SolveCtl *ctl, SolveCtl *ctl_host, const GridSync *gs,
+                            StopRule rule, hipStream_t stream);
+// The coarse part of one V-cycle (every pass on levels >= 1, in order) as
+// one persistent launch: the workgroups run each phase on the intervals they
+// own and meet at a grid-wide barrier between phases.
+enum CoarsePhaseKind : int { CP_PASS = 0, CP_FILL = 1 };
+constexpr int MAX_COARSE_PHASES = 24;
+constexpr int MAX_COARSE_LEVELS = 15;
+struct CoarsePhase {
+  int kind;     // CP_PASS: PassArgs pa on level `level`; CP_FILL: zero pa.nint doubles at pa.cout
+  int level;    // index into CoarsePlan::desc
+  PassArgs pa;  // pa.stop is not used (the launch checks its stop flag once)
+};
+struct CoarsePlan {
+  int nphases;
+  int nlevels;
+  const LevelDesc *desc[MAX_COARSE_LEVELS];
+  CoarsePhase ph[MAX_COARSE_PHASES];
+};
+// Grid-barrier state in device memory (zeroed at setup): arrivals, the
+// generation counter, and a failure flag set by a workgroup that gave up
+// waiting (the launch then ends early and the solve reports MGRIT_EDEVICE).
+struct GridSync {
+  unsigned count;
+  unsigned gen;
+  int err;
+  int pad;
+};
+// Dynamic LDS bytes of the persistent launch, 0 if it cannot run (the lean
+// kernel does not apply, or LDS or co-residency limits).
+size_t coarse_vcycle_lds(const StepOp &op, const Layout &lay, int nlevels);
+// Largest grid the persistent launch can keep resident (0 on error).
+int coarse_vcycle_max_grid(const StepOp &op, const Layout &lay, size_t lds);
+hipError_t launch_coarse_vcycle(const CoarsePlan &plan, const StepOp &op, const Layout &lay, int64_t grid,
+                                size_t lds, GridSync *gs, const int *stop, hipStream_t stream);
+
 // The lean coarse-step kernel (mgrit_lean.hip) for layouts where
 // lean_slc_applies() holds, and its LDS attribute.
 hipError_t launch_lean(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs &pa,

@@ -28,7 +28,8 @@ __global__ void __launch_bounds__(256) reduce_kernel(const double *__restrict__ 
 // once ||r_it|| <= rtol ||r_0||), in the order the solver applies them:
 // non-finite, converged, iteration limit, growth past diverge_factor ||r_0||.
 __global__ void __launch_bounds__(256) solve_ctl_kernel(const double *__restrict__ part, int64_t n,
-                                                         SolveCtl *ctl, StopRule rule) {
+                                                         SolveCtl *ctl, SolveCtl *ctl_host, const GridSync *gs,
+                                                         StopRule rule) {
   __shared__ double red[256];
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += 256) s += part[i];
@@ -45,7 +46,9 @@ __global__ void __launch_bounds__(256) solve_ctl_kernel(const double *__restrict
   ctl->res0 = res0;
   ctl->rho = rho;
   int stop = STOP_NONE;
-  if (!isfinite(rho))
+  if (gs && __hip_atomic_load(&gs->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+    stop = STOP_DEVICE;
+  else if (!isfinite(rho))
     stop = STOP_NONFINITE;
   else if (rho <= rule.rtol * res0)
     stop = STOP_CONVERGED;
@@ -55,6 +58,7 @@ __global__ void __launch_bounds__(256) solve_ctl_kernel(const double *__restrict
     stop = STOP_DIVERGED;
   ctl->stop = stop;
   if (stop == STOP_NONE) ctl->it = it + 1;
+  if (ctl_host) *ctl_host = *ctl;  // pinned host memory, visible once the kernel has completed
 }
 
 __global__ void gather_rows_kernel(const double *__restrict__ src, int64_t stride, double *__restrict__ dst,
@@ -132,8 +136,9 @@ hipError_t launch_fill(double *dst, int64_t n, double value, hipStream_t stream,
   return hipGetLastError();
 }
 
-hipError_t launch_solve_ctl(const double *part, int64_t n, SolveCtl *ctl, StopRule rule, hipStream_t stream) {
-  hipLaunchKernelGGL(solve_ctl_kernel, dim3(1), dim3(256), 0, stream, part, n, ctl, rule);
+hipError_t launch_solve_ctl(const double *part, int64_t n, SolveCtl *ctl, SolveCtl *ctl_host, const GridSync *gs,
+                            StopRule rule, hipStream_t stream) {
+  hipLaunchKernelGGL(solve_ctl_kernel, dim3(1), dim3(256), 0, stream, part, n, ctl, ctl_host, gs, rule);
   return hipGetLastError();
 }
 

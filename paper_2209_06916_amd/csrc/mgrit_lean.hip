@@ -64,15 +64,18 @@ struct LaneMats {
   double lr_[N], vl_[N], vw_[N];
   const double *tab;
   int lr, vl, vw;
-  __device__ __forceinline__ void init(const double *t, int lr0, int vl0, int vw0) {
+  // t: the LDS copy of the table (read in the loop when not hoisted); src:
+  // the same table in device memory (hoisted values are loaded from there, so
+  // they do not wait for the LDS copy)
+  __device__ __forceinline__ void init(const double *t, const double *src, int lr0, int vl0, int vw0) {
     tab = t;
     lr = lr0;
     vl = vl0;
     vw = vw0;
     if constexpr (HOIST) {
-      ld_mat<K>(t + lr * K * K, lr_);
-      ld_mat<K>(t + vl * K * K, vl_);
-      ld_mat<K>(t + (TAB_HWAVE + vw) * K * K, vw_);
+      ld_mat<K>(src + lr * K * K, lr_);
+      ld_mat<K>(src + vl * K * K, vl_);
+      ld_mat<K>(src + (TAB_HWAVE + vw) * K * K, vw_);
     }
   }
   __device__ __forceinline__ void get(int which, double (&M)[K * K]) const {
@@ -264,22 +267,19 @@ __device__ __forceinline__ void load_segs(const double *__restrict__ row, double
   for (int q = 0; q < L / 2; ++q) seg[q] = r2[threadIdx.x + T * q];
 }
 
-template <int W, int K, int NW>
-__global__ void __launch_bounds__(WAVE * NW) slc_kernel(const LevelDesc *__restrict__ desc, PassArgs pa) {
+// One pass (PassMode) of one CF-interval b with the coarse step of `op`.
+// LDS: v the padded vector (it also stages the right-hand-side row), tab_f /
+// tab_b the scan tables, qf / qb the wavefront totals, red the reduction
+// scratch.  hsrc_f / hsrc_b: where the lane-dependent powers are loaded from.
+// prologue() runs once the first loads are in flight; false ends the pass.
+template <int W, int K, int NW, class Prologue>
+__device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, int64_t b, double *v, double *tab_f,
+                                          double *tab_b, const double *hsrc_f, const double *hsrc_b, double *qf,
+                                          double *qb, double *red, Prologue prologue) {
   constexpr int L = LEAN_L;
   constexpr int T = WAVE * NW;
   constexpr int NX = L * T;
-  constexpr int KK = K * K;
   constexpr bool HOIST = K <= 2;
-  extern __shared__ double smem[];
-  const StepOp &op = desc->op;
-  constexpr LeanLds lo = lean_lds_offsets(NX, K);
-  double *v = smem;  // padded vector; also stages the right-hand-side row
-  double *tab_f = smem + lo.tab_f;
-  double *tab_b = smem + lo.tab_b;
-  double *qf = smem + lo.qf;
-  double *qb = smem + lo.qb;
-  double *red = smem + lo.red;
 
   // interpolation weights with the 1/C of the factorisation folded in
   double w[W], af[K], ab[K];
@@ -293,7 +293,6 @@ __global__ void __launch_bounds__(WAVE * NW) slc_kernel(const LevelDesc *__restr
   }
   const int tid = threadIdx.x;
   const int base = tid * L;
-  const int64_t b = blockIdx.x;
   const int64_t nxl = NX;
   const int m = pa.m;
   const int mode = pa.mode;
@@ -307,19 +306,12 @@ __global__ void __launch_bounds__(WAVE * NW) slc_kernel(const LevelDesc *__restr
   } else {
     load_chunk<L>(pa.cin + row0 * nxl, base, L, u);
   }
-  const bool stopped = pa.stop && *pa.stop;  // the solve has already stopped
-  for (int i = threadIdx.x; i < RTAB_ALL * KK; i += T) {
-    tab_f[i] = op.fw.tab[i];
-    tab_b[i] = op.bw.tab[i];
-  }
-  __syncthreads();
-  if (stopped) return;
-
   const int lane = tid & (WAVE - 1);
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   LaneMats<K, HOIST> lmf, lmb;
-  lmf.init(tab_f, lane & 15, lane, wave);
-  lmb.init(tab_b, (WAVE - 1 - lane) & 15, WAVE - 1 - lane, NW - 1 - wave);
+  lmf.init(tab_f, hsrc_f, lane & 15, lane, wave);
+  lmb.init(tab_b, hsrc_b, (WAVE - 1 - lane) & 15, WAVE - 1 - lane, NW - 1 - wave);
+  if (!prologue()) return;
 
   int start = base - (op.sl_K + op.sl_l) % NX;
   if (start < 0) start += NX;
@@ -352,16 +344,23 @@ __global__ void __launch_bounds__(WAVE * NW) slc_kernel(const LevelDesc *__restr
   // cross-thread reads (gather, parent update) precede the forward
   // recurrence's barrier and the cross-thread writes (right-hand side, in the
   // backward recurrence's hook) follow it.
+  // pseg: the pending parent row's segments; in the last step it is refilled
+  // with what the epilogue needs (the next parent row, or pass B's C'_{k+1})
+  // so that load overlaps the step.
   int64_t pend = -1;  // parent row whose update waits for the next LDS copy
+  double2 pseg[L / 2];
+  if (mode == MODE_PASS_B && nsteps == 0) load_segs<L, T>(pa.cin + (b + 1) * nxl, pseg);
   for (int j = 1; j <= nsteps; ++j) {
     const int64_t n = (mode == MODE_SEQ) ? (int64_t)j : b * m + j;  // level point index
-    double2 gseg[L / 2], pseg[L / 2];
+    double2 gseg[L / 2];
     if (add_g) load_segs<L, T>(pa.g + (n - 1) * nxl, gseg);
     if (pend >= 0) load_segs<L, T>(pa.parent + pend * nxl, pseg);
+    if (mode == MODE_PASS_B && j == nsteps) load_segs<L, T>(pa.cin + (b + 1) * nxl, pseg);
 #pragma unroll
     for (int jj = 0; jj < L; ++jj) v[padix(base + jj)] = u[jj];
     __syncthreads();
     if (pend >= 0) parent_update(pend, pseg);
+    if (add_parent && j == nsteps) load_segs<L, T>(pa.parent + n * nxl, pseg);
     double y[L];
 #pragma unroll
     for (int jj = 0; jj < L; ++jj) y[jj] = 0.0;
@@ -396,9 +395,7 @@ __global__ void __launch_bounds__(WAVE * NW) slc_kernel(const LevelDesc *__restr
     }
     pend = add_parent ? n : -1;
   }
-  if (pend >= 0) {  // the last step's parent update
-    double2 pseg[L / 2];
-    load_segs<L, T>(pa.parent + pend * nxl, pseg);
+  if (pend >= 0) {  // the last step's parent update (row prefetched into pseg)
 #pragma unroll
     for (int jj = 0; jj < L; ++jj) v[padix(base + jj)] = u[jj];
     __syncthreads();
@@ -408,14 +405,20 @@ __global__ void __launch_bounds__(WAVE * NW) slc_kernel(const LevelDesc *__restr
   if (mode == MODE_PASS_A) {
     store_chunk<L>(pa.cout + (b + 1) * nxl, base, L, u);
   } else if (mode == MODE_PASS_B) {
-    const double *__restrict__ c1 = pa.cin + (b + 1) * nxl;
+    // r = u - C'_{k+1} (C'_{k+1} prefetched into pseg), in coalesced segments
+#pragma unroll
+    for (int jj = 0; jj < L; ++jj) v[padix(base + jj)] = u[jj];
+    __syncthreads();
+    double2 *r2 = reinterpret_cast<double2 *>(pa.r + b * nxl);
     double ss = 0.0;
 #pragma unroll
-    for (int jj = 0; jj < L; ++jj) {
-      u[jj] -= c1[base + jj];
-      ss = fma(u[jj], u[jj], ss);
+    for (int q = 0; q < L / 2; ++q) {
+      const int i = 2 * (tid + T * q);
+      const double2 rr = make_double2(v[padix(i)] - pseg[q].x, v[padix(i + 1)] - pseg[q].y);
+      r2[tid + T * q] = rr;
+      ss = fma(rr.x, rr.x, ss);
+      ss = fma(rr.y, rr.y, ss);
     }
-    store_chunk<L>(pa.r + b * nxl, base, L, u);
     const double tot = block_sum(ss, red);
     if (tid == 0) pa.normpart[b] = tot;
   } else if (mode == MODE_POST_F) {
@@ -432,6 +435,127 @@ __global__ void __launch_bounds__(WAVE * NW) slc_kernel(const LevelDesc *__restr
     __syncthreads();  // in-place use: every thread has read its input row
     store_chunk<L>(pa.cout + b * nxl, base, L, u);
   }
+}
+
+template <int W, int K, int NW>
+__global__ void __launch_bounds__(WAVE * NW) slc_kernel(const LevelDesc *__restrict__ desc, PassArgs pa) {
+  extern __shared__ double smem[];
+  constexpr LeanLds lo = lean_lds_offsets(LEAN_L * WAVE * NW, K);
+  const StepOp &op = desc->op;
+  double *tab_f = smem + lo.tab_f;
+  double *tab_b = smem + lo.tab_b;
+  lean_pass<W, K, NW>(op, pa, blockIdx.x, smem, tab_f, tab_b, op.fw.tab, op.bw.tab, smem + lo.qf, smem + lo.qb,
+                      smem + lo.red, [&] {
+                        // Scan tables to LDS.  No barrier here: the first step's
+                        // barrier (after the vector is written to LDS) comes
+                        // before any read of them.
+                        for (int i = threadIdx.x; i < RTAB_ALL * K * K; i += WAVE * NW) {
+                          tab_f[i] = op.fw.tab[i];
+                          tab_b[i] = op.bw.tab[i];
+                        }
+                        return !(pa.stop && *pa.stop);  // the solve has already stopped (uniform)
+                      });
+}
+
+// ---------------------------------------------------------------------------
+// Persistent coarse V-cycle.  The launch is cooperative (every workgroup is
+// resident), so a workgroup may wait for the others.  Each wait is bounded in
+// real time (GRID_WAIT_TICKS of the 100 MHz counter, 0.1 s, far above any
+// phase the host lets through, at most 256 steps): past it, or on seeing
+// another workgroup's failure, a workgroup sets the failure flag and the
+// kernel returns, so the grid always drains.
+// ---------------------------------------------------------------------------
+constexpr unsigned long long GRID_WAIT_TICKS = 10000000ull;
+
+__device__ __forceinline__ bool grid_barrier(GridSync *gs, unsigned &gen, int *ok_lds) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    __threadfence();  // release this workgroup's writes at device scope
+    const unsigned g = gen;
+    if (atomicAdd(&gs->count, 1u) == gridDim.x - 1) {
+      atomicExch(&gs->count, 0u);
+      __threadfence();
+      atomicAdd(&gs->gen, 1u);
+    } else {
+      const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+      for (;;) {
+        if (__hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != g) break;
+        if (__hip_atomic_load(&gs->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+            __builtin_amdgcn_s_memrealtime() - t0 > GRID_WAIT_TICKS) {
+          atomicExch(&gs->err, 1);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __threadfence();  // acquire the other workgroups' writes
+    *ok_lds = ok;
+  }
+  ++gen;
+  __syncthreads();
+  return *ok_lds != 0;
+}
+
+template <int W, int K, int NW>
+__global__ void __launch_bounds__(WAVE * NW) coarse_vcycle_kernel(CoarsePlan plan, GridSync *gs, const int *stop) {
+  extern __shared__ double smem[];
+  __shared__ int ok;
+  constexpr int T = WAVE * NW;
+  constexpr int NX = LEAN_L * T;
+  constexpr int KK = K * K;
+  constexpr int TABSZ = RTAB_ALL * KK;
+  if (stop && *stop) return;  // the solve has already stopped (uniform)
+  if (__hip_atomic_load(&gs->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+  unsigned gen = __hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  double *v = smem;
+  double *tabs = smem + NX + (NX >> 4) + 1;
+  double *qf = tabs + plan.nlevels * 2 * TABSZ;
+  double *qb = qf + (MAXWAVES + 2) * K;
+  double *red = qb + (MAXWAVES + 2) * K;
+  for (int l = 0; l < plan.nlevels; ++l) {
+    const StepOp &op = plan.desc[l]->op;
+    double *tf = tabs + 2 * l * TABSZ;
+    for (int i = threadIdx.x; i < TABSZ; i += T) {
+      tf[i] = op.fw.tab[i];
+      tf[TABSZ + i] = op.bw.tab[i];
+    }
+  }
+  __syncthreads();
+  for (int ph = 0; ph < plan.nphases; ++ph) {
+    const CoarsePhase &P = plan.ph[ph];
+    if (P.kind == CP_FILL) {
+      for (int64_t i = (int64_t)blockIdx.x * T + threadIdx.x; i < P.pa.nint; i += (int64_t)gridDim.x * T)
+        P.pa.cout[i] = 0.0;
+    } else if ((int64_t)blockIdx.x < P.pa.nint) {
+      const StepOp &op = plan.desc[P.level]->op;
+      double *tf = tabs + 2 * P.level * TABSZ;
+      lean_pass<W, K, NW>(op, P.pa, blockIdx.x, v, tf, tf + TABSZ, tf, tf + TABSZ, qf, qb, red,
+                          [] { return true; });
+    }
+    if (ph + 1 < plan.nphases && !grid_barrier(gs, gen, &ok)) return;
+  }
+}
+
+template <int W, int K, int NW>
+hipError_t coarse_vcycle_launch(const CoarsePlan &plan, int64_t grid, size_t lds, GridSync *gs, const int *stop,
+                                hipStream_t stream) {
+  CoarsePlan pl = plan;
+  void *args[3] = {(void *)&pl, (void *)&gs, (void *)&stop};
+  return hipLaunchCooperativeKernel((const void *)coarse_vcycle_kernel<W, K, NW>, dim3((unsigned)grid),
+                                    dim3(WAVE * NW), args, (unsigned)lds, stream);
+}
+
+template <int W, int K, int NW>
+int coarse_vcycle_grid(size_t lds) {
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)coarse_vcycle_kernel<W, K, NW>, WAVE * NW,
+                                                   lds) != hipSuccess)
+    return 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return per_cu * cus;
 }
 
 template <int W, int K, int NW>
@@ -491,5 +615,58 @@ hipError_t configure_lean_kernels(size_t bytes) {
   if ((e = slc_set_lds<4, 2>(bytes))) return e;
   return slc_set_lds<6, 3>(bytes);
 }
+
+size_t coarse_vcycle_lds(const StepOp &op, const Layout &lay, int nlevels) {
+  if (!lean_slc_applies(op, lay) || nlevels < 1 || nlevels > MAX_COARSE_LEVELS) return 0;
+  const int K = op.fw.k;
+  const size_t n = (size_t)lay.nx + (lay.nx >> 4) + 1 + (size_t)nlevels * 2 * RTAB_ALL * K * K +
+                   2 * (MAXWAVES + 2) * K + MAXWAVES;
+  const size_t bytes = n * sizeof(double);
+  return bytes + 256 <= 160 * 1024 ? bytes : 0;  // 256: the kernel's static LDS
+}
+
+// (W, K, NW) of the persistent launch from the operator and the layout.
+#define MGRIT_CV_SWITCH(CALL, FAIL)                                             \
+  do {                                                                          \
+    const int W_ = op.sl_l + op.sl_r + 1;                                       \
+    const int nw_ = lay.nx / (WAVE * LEAN_L);                                   \
+    const int key_ = (W_ * 4 + op.fw.k) * 16 + nw_;                             \
+    switch (key_) {                                                             \
+      case (2 * 4 + 1) * 16 + 1: return CALL(2, 1, 1);                          \
+      case (2 * 4 + 1) * 16 + 2: return CALL(2, 1, 2);                          \
+      case (2 * 4 + 1) * 16 + 4: return CALL(2, 1, 4);                          \
+      case (2 * 4 + 1) * 16 + 8: return CALL(2, 1, 8);                          \
+      case (4 * 4 + 2) * 16 + 1: return CALL(4, 2, 1);                          \
+      case (4 * 4 + 2) * 16 + 2: return CALL(4, 2, 2);                          \
+      case (4 * 4 + 2) * 16 + 4: return CALL(4, 2, 4);                          \
+      case (4 * 4 + 2) * 16 + 8: return CALL(4, 2, 8);                          \
+      case (6 * 4 + 3) * 16 + 1: return CALL(6, 3, 1);                          \
+      case (6 * 4 + 3) * 16 + 2: return CALL(6, 3, 2);                          \
+      case (6 * 4 + 3) * 16 + 4: return CALL(6, 3, 4);                          \
+      case (6 * 4 + 3) * 16 + 8: return CALL(6, 3, 8);                          \
+      default: return FAIL;                                                     \
+    }                                                                           \
+  } while (0)
+
+int coarse_vcycle_max_grid(const StepOp &op, const Layout &lay, size_t lds) {
+  if (!lean_slc_applies(op, lay)) return 0;
+#define MGRIT_CV_GRID(Wv, Kv, NWv)                                                                              \
+  (hipFuncSetAttribute((const void *)coarse_vcycle_kernel<Wv, Kv, NWv>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                       (int)lds) == hipSuccess                                                                  \
+       ? coarse_vcycle_grid<Wv, Kv, NWv>(lds)                                                                   \
+       : 0)
+  MGRIT_CV_SWITCH(MGRIT_CV_GRID, 0);
+#undef MGRIT_CV_GRID
+}
+
+hipError_t launch_coarse_vcycle(const CoarsePlan &plan, const StepOp &op, const Layout &lay, int64_t grid,
+                                size_t lds, GridSync *gs, const int *stop, hipStream_t stream) {
+  if (!lean_slc_applies(op, lay)) return hipErrorInvalidValue;
+#define MGRIT_CV_LAUNCH(Wv, Kv, NWv) coarse_vcycle_launch<Wv, Kv, NWv>(plan, grid, lds, gs, stop, stream)
+  MGRIT_CV_SWITCH(MGRIT_CV_LAUNCH, hipErrorInvalidValue);
+#undef MGRIT_CV_LAUNCH
+}
+
+#undef MGRIT_CV_SWITCH
 
 }  // namespace mgrit

@@ -55,7 +55,7 @@ __device__ __forceinline__ void window_combine(const double *vec, int start, int
         const int j = e - t;
         if (j >= 0 && j < L && t < width) out[j] = fma(w[t], v, out[j]);
       }
-      idx = wrap_hi(idx + 1, nx);
+      idx = next_periodic(idx, nx);
     }
   }
 }

@@ -38,7 +38,7 @@ __device__ __forceinline__ void load_run(const double *__restrict__ row, int g, 
 #pragma unroll
     for (int k = 0; k < P; ++k) {
       x[k] = row[g];
-      g = wrap_hi(g + 1, nx);
+      g = next_periodic(g, nx);
     }
   }
 }
@@ -55,11 +55,15 @@ __global__ void __launch_bounds__(256) tile_kernel(const LevelDesc *__restrict__
   const int tw = min(tg.TW, nx - x0);
   const int64_t nxl = nx;
 
-  // coefficients -> registers
+  // coefficients -> registers (the Horner loop below is unrolled over the
+  // largest stage count with uniform guards, so no stage reloads them)
   const int ncoef = op.ncoef;
   double taps[SL + SR + 1];
 #pragma unroll
   for (int t = 0; t <= SL + SR; ++t) taps[t] = op.taps[t];
+  double cf[MAXCOEF];
+#pragma unroll
+  for (int i = 0; i < MAXCOEF; ++i) cf[i] = op.coef[i];
   const double top = op.coef[ncoef - 1];
 
   // this lane's first global position (periodic) and its local index
@@ -86,7 +90,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const LevelDesc *__restrict__
 #pragma unroll
     for (int k = 0; k < P; ++k) {
       if (k >= lo && k < hi) row[g] = v[k];
-      g = wrap_hi(g + 1, nx);
+      g = next_periodic(g, nx);
     }
   };
 
@@ -102,13 +106,15 @@ __global__ void __launch_bounds__(256) tile_kernel(const LevelDesc *__restrict__
     double y[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) y[k] = top * u[k];
-    for (int i = ncoef - 2; i >= 0; --i) {
+#pragma unroll
+    for (int i = MAXCOEF - 2; i >= 0; --i) {
+      if (i > ncoef - 2) continue;  // uniform
       double lh[SL > 0 ? SL : 1], rh[SR > 0 ? SR : 1];
 #pragma unroll
       for (int q = 0; q < SL; ++q) lh[q] = wave_shift<0x138>(y[P - SL + q]);
 #pragma unroll
       for (int q = 0; q < SR; ++q) rh[q] = wave_shift<0x130>(y[q]);
-      const double ci = op.coef[i];
+      const double ci = cf[i];
       double yn[P];
 #pragma unroll
       for (int k = 0; k < P; ++k) {
@@ -143,7 +149,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const LevelDesc *__restrict__
         ta.r[b * nxl + g] = rv;
         ss = fma(rv, rv, ss);
       }
-      g = wrap_hi(g + 1, nx);
+      g = next_periodic(g, nx);
     }
 #pragma unroll
     for (int d = WAVE / 2; d > 0; d >>= 1) ss += __shfl_down(ss, d, WAVE);

@@ -150,6 +150,28 @@ def test_lean_and_generic_coarse_kernels_agree(monkeypatch):
     np.testing.assert_allclose(outs[0][1], outs[1][1], rtol=0, atol=1e-13 * np.max(np.abs(outs[1][1])))
 
 
+@pytest.mark.parametrize("nu,ms,nx,p", [(1, [8, 8, 8], 4096, 3), (0, [4, 4], 1024, 1), (2, [4, 2, 2], 2048, 5)])
+def test_persistent_and_per_pass_coarse_cycles_agree(monkeypatch, nu, ms, nx, p):
+    """The coarse part of each V-cycle as one cooperative launch with grid
+    barriers and as one launch per pass: same passes, same arithmetic, so the
+    same bits."""
+    _announce("persistent vs per-pass", nu, ms, nx, p)
+    nt = int(np.prod(ms)) * 8
+    c = {1: 0.85, 3: 1.2, 5: 0.9}[p]
+    u0 = inputs.u0_fourier(nx, 41)
+    v0 = _t(inputs.initial_iterate(nt, nx, u0, 41))
+    outs = []
+    for flag in ("0", "1"):
+        monkeypatch.setenv("MGRIT_NO_PERSISTENT", flag)
+        s = mgrit.Solver(mgrit.make_problem(nx, nt, c, p), mgrit.make_options(ms, max_levels=len(ms) + 1, nu=nu))
+        o = torch.empty((nt + 1, nx), dtype=torch.float64, device=DEV)
+        info = s.solve(_t(u0), v0, u_out=o)
+        outs.append((info["iterations"], info["res_history"], _np(o)))
+    assert outs[0][0] == outs[1][0]
+    assert outs[0][1] == outs[1][1]
+    np.testing.assert_array_equal(outs[0][2], outs[1][2])
+
+
 # --------------------------------------------------------------------------
 # sequential stepping and the space-time residual
 # --------------------------------------------------------------------------
