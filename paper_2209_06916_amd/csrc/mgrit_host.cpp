@@ -1002,7 +1002,8 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
       grid = std::max<int64_t>(grid, h->lv[l].nt / h->lv[l].m);
       longest = std::max<int64_t>(longest, h->lv[l].m);
     }
-    if (lds > 0 && longest <= 256 && grid <= coarse_vcycle_max_grid(h->lv[1].op, h->lv[1].lay, lds)) {
+    if (lds > 0 && longest <= 256 && grid <= MAX_PERSISTENT_GRID &&
+        grid <= coarse_vcycle_max_grid(h->lv[1].op, h->lv[1].lay, lds)) {
       if (hipMalloc((void **)&h->gsync, sizeof(GridSync)) != hipSuccess ||
           hipMemset(h->gsync, 0, sizeof(GridSync)) != hipSuccess) {
         mgrit_destroy(h);
@@ -1200,8 +1201,7 @@ mgrit_status vcycle(mgrit_handle *h, const double *g, double *parent) {
       h->ev_pending.push_back({MGRIT_PROF_COARSE, {e0, e1}});
     }
     if (e == hipSuccess) return MGRIT_OK;
-    // the runtime refused the cooperative launch (for instance when other
-    // work holds the compute units): fall back to one launch per pass
+    // the launch was refused: fall back to one launch per pass
     (void)hipGetLastError();
     h->cv_ok = false;
   }

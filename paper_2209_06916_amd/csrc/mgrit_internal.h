@@ -262,14 +262,16 @@ struct CoarsePlan {
   const LevelDesc *desc[MAX_COARSE_LEVELS];
   CoarsePhase ph[MAX_COARSE_PHASES];
 };
-// Grid-barrier state in device memory (zeroed at setup): arrivals, the
-// generation counter, and a failure flag set by a workgroup that gave up
-// waiting (the launch then ends early and the solve reports MGRIT_EDEVICE).
+// Grid-barrier state in device memory (zeroed at setup): the generation
+// released by workgroup 0, a failure flag set by a workgroup that gave up
+// waiting (the launch then ends early and the solve reports MGRIT_EDEVICE),
+// and one arrival word per workgroup.
+constexpr int MAX_PERSISTENT_GRID = 1024;
 struct GridSync {
-  unsigned count;
-  unsigned gen;
+  unsigned rel;
   int err;
-  int pad;
+  unsigned pad[30];  // rel and err on their own 128-byte line
+  unsigned arrive[MAX_PERSISTENT_GRID];
 };
 // Dynamic LDS bytes of the persistent launch, 0 if it cannot run (the lean
 // kernel does not apply, or LDS or co-residency limits).

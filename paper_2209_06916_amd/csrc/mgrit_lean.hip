@@ -458,42 +458,67 @@ __global__ void __launch_bounds__(WAVE * NW) slc_kernel(const LevelDesc *__restr
 }
 
 // ---------------------------------------------------------------------------
-// Persistent coarse V-cycle.  The launch is cooperative (every workgroup is
-// resident), so a workgroup may wait for the others.  Each wait is bounded in
-// real time (GRID_WAIT_TICKS of the 100 MHz counter, 0.1 s, far above any
-// phase the host lets through, at most 256 steps): past it, or on seeing
-// another workgroup's failure, a workgroup sets the failure flag and the
-// kernel returns, so the grid always drains.
+// Persistent coarse V-cycle.  Every workgroup of the launch is resident (the
+// host checks the grid against the occupancy limit, and the launch follows
+// the previous kernel on the stream), so a workgroup may wait for the others.
+// Each wait is bounded in real time (GRID_WAIT_TICKS of the 100 MHz counter,
+// 0.1 s, far above any phase the host lets through, at most 256 steps): past
+// it, or on seeing another workgroup's failure, a workgroup sets the failure
+// flag and the kernel returns, so the grid always drains.
 // ---------------------------------------------------------------------------
 constexpr unsigned long long GRID_WAIT_TICKS = 10000000ull;
 
+__device__ __forceinline__ bool wait_expired(unsigned long long t0, const GridSync *gs) {
+  return __builtin_amdgcn_s_memrealtime() - t0 > GRID_WAIT_TICKS ||
+         __hip_atomic_load(&gs->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+// Grid barrier: every workgroup publishes its arrival in its own word, the
+// first wavefront of workgroup 0 polls all of them and releases the new
+// generation, everyone waits for that release.  Every thread's global writes
+// are released at device scope before its workgroup arrives (the workgroup
+// barrier alone does not wait for them), and acquired after the release.
 __device__ __forceinline__ bool grid_barrier(GridSync *gs, unsigned &gen, int *ok_lds) {
+  __threadfence();
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int ok = 1;
-    __threadfence();  // release this workgroup's writes at device scope
-    const unsigned g = gen;
-    if (atomicAdd(&gs->count, 1u) == gridDim.x - 1) {
-      atomicExch(&gs->count, 0u);
+  const unsigned target = gen + 1;
+  int ok = 1;
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&gs->arrive[blockIdx.x], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (blockIdx.x == 0 && threadIdx.x < WAVE) {
+    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+    for (;;) {
+      bool done = true;
+      for (unsigned b = threadIdx.x; b < gridDim.x; b += WAVE)
+        done = done && __hip_atomic_load(&gs->arrive[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == target;
+      if (__all(done)) break;
+      if (wait_expired(t0, gs)) {
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (threadIdx.x == 0 && ok) {
       __threadfence();
-      atomicAdd(&gs->gen, 1u);
-    } else {
+      __hip_atomic_store(&gs->rel, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  if (threadIdx.x == 0) {
+    if (ok) {
       const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
-      for (;;) {
-        if (__hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != g) break;
-        if (__hip_atomic_load(&gs->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-            __builtin_amdgcn_s_memrealtime() - t0 > GRID_WAIT_TICKS) {
-          atomicExch(&gs->err, 1);
+      while (__hip_atomic_load(&gs->rel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target) {
+        if (wait_expired(t0, gs)) {
           ok = 0;
           break;
         }
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(1);
       }
     }
-    __threadfence();  // acquire the other workgroups' writes
+    if (!ok) atomicExch(&gs->err, 1);
+    __threadfence();
     *ok_lds = ok;
   }
-  ++gen;
+  gen = target;
   __syncthreads();
   return *ok_lds != 0;
 }
@@ -508,7 +533,7 @@ __global__ void __launch_bounds__(WAVE * NW) coarse_vcycle_kernel(CoarsePlan pla
   constexpr int TABSZ = RTAB_ALL * KK;
   if (stop && *stop) return;  // the solve has already stopped (uniform)
   if (__hip_atomic_load(&gs->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
-  unsigned gen = __hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned gen = __hip_atomic_load(&gs->rel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   double *v = smem;
   double *tabs = smem + NX + (NX >> 4) + 1;
   double *qf = tabs + plan.nlevels * 2 * TABSZ;
@@ -541,10 +566,9 @@ __global__ void __launch_bounds__(WAVE * NW) coarse_vcycle_kernel(CoarsePlan pla
 template <int W, int K, int NW>
 hipError_t coarse_vcycle_launch(const CoarsePlan &plan, int64_t grid, size_t lds, GridSync *gs, const int *stop,
                                 hipStream_t stream) {
-  CoarsePlan pl = plan;
-  void *args[3] = {(void *)&pl, (void *)&gs, (void *)&stop};
-  return hipLaunchCooperativeKernel((const void *)coarse_vcycle_kernel<W, K, NW>, dim3((unsigned)grid),
-                                    dim3(WAVE * NW), args, (unsigned)lds, stream);
+  hipLaunchKernelGGL((coarse_vcycle_kernel<W, K, NW>), dim3((unsigned)grid), dim3(WAVE * NW), lds, stream, plan, gs,
+                     stop);
+  return hipGetLastError();
 }
 
 template <int W, int K, int NW>
