@@ -347,13 +347,14 @@ __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, 
   // pseg: the pending parent row's segments; in the last step it is refilled
   // with what the epilogue needs (the next parent row, or pass B's C'_{k+1})
   // so that load overlaps the step.
+  // gseg: the right-hand-side row of the coming step, loaded a whole step
+  // ahead (right after the previous row is consumed) so its latency is hidden.
   int64_t pend = -1;  // parent row whose update waits for the next LDS copy
-  double2 pseg[L / 2];
+  double2 pseg[L / 2], gseg[L / 2];
   if (mode == MODE_PASS_B && nsteps == 0) load_segs<L, T>(pa.cin + (b + 1) * nxl, pseg);
+  if (add_g && nsteps >= 1) load_segs<L, T>(pa.g + ((mode == MODE_SEQ) ? 0 : b * m) * nxl, gseg);
   for (int j = 1; j <= nsteps; ++j) {
     const int64_t n = (mode == MODE_SEQ) ? (int64_t)j : b * m + j;  // level point index
-    double2 gseg[L / 2];
-    if (add_g) load_segs<L, T>(pa.g + (n - 1) * nxl, gseg);
     if (pend >= 0) load_segs<L, T>(pa.parent + pend * nxl, pseg);
     if (mode == MODE_PASS_B && j == nsteps) load_segs<L, T>(pa.cin + (b + 1) * nxl, pseg);
 #pragma unroll
@@ -377,13 +378,14 @@ __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, 
     }
     lean_rec<L, K, NW, false>(y, af, tab_f, lmf, qf, [] {});
     lean_rec<L, K, NW, true>(y, ab, tab_b, lmb, qb, [&] {
-      if (add_g) {
+      if (add_g) {  // g_n -> v in chunk order, then fetch the next step's row
 #pragma unroll
         for (int q = 0; q < L / 2; ++q) {
           const int i = 2 * (tid + T * q);
           v[padix(i)] = gseg[q].x;
           v[padix(i + 1)] = gseg[q].y;
         }
+        if (j < nsteps) load_segs<L, T>(pa.g + n * nxl, gseg);
       }
     });
     if (add_g) {
