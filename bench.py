@@ -145,9 +145,10 @@ def summarize_profiles(d):
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
         lines.append(f"  {_short(r['Name']):52s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
                      f"{float(r['TotalDurationNs']) / 1e6:10.3f} {100 * float(r['TotalDurationNs']) / tot:6.2f}%")
-    lines += ["#", "# slc_kernel<4, 2, 4>: every coarse-level pass (levels 1-3); tile_kernel<8, 2, 1>: level-0",
-              "# relaxation passes and the final F-relaxation; tile_kernel<4, 2, 1>: sequential time-stepping",
-              "# (blocks of steps); solve_ctl_kernel: residual norm + stopping test."]
+    lines += ["#", "# coarse_vcycle_kernel<4, 2, 4>: every coarse-level pass of one V-cycle (levels 1-3) in one launch",
+              "# (the last launch of each solve returns at once); tile_kernel<8, 2, 1>: level-0 relaxation passes",
+              "# and the final F-relaxation; tile_kernel<4, 2, 1>: sequential time-stepping (blocks of 16 steps);",
+              "# solve_ctl_kernel: residual norm + stopping test."]
     with open(os.path.join(prof_dir, f"kernel_stats_{WORKLOAD}.txt"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
