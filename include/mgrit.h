@@ -59,7 +59,11 @@ typedef enum {
   /* Psi = Phi^m, the ideal coarse operator (Sec. 2.2); two levels only        */
   MGRIT_CG_IDEAL = 1,
   /* Psi_l = S_p^(Delta_l) with phi = 0 (uncorrected semi-Lagrangian)          */
-  MGRIT_CG_SL_PLAIN = 2
+  MGRIT_CG_SL_PLAIN = 2,
+  /* Psi_l = the fine Runge-Kutta + upwind step at the level's step Delta_l
+     (rediscretisation; Sec. 5, the comparison of Fig. 2 and Theorem 1).
+     Explicit schemes must stay below their CFL limit at c * m_0 * ... * m_{l-1}. */
+  MGRIT_CG_REDISC = 3
 } mgrit_cg_kind;
 
 /* The paper's problem statement (Sec. 2.1, 4.1-4.3). */
@@ -134,7 +138,8 @@ typedef struct mgrit_handle mgrit_handle;
  * them, and allocate the per-level device workspace (owned by the handle).
  * Returns MGRIT_EINVAL for nt % m[0] != 0, nx outside 1..MGRIT_MAX_NX, even p
  * with a semi-Lagrangian coarse operator, or an unsupported (kind, order);
- * MGRIT_EUNSTABLE for ERK above its CFL limit.  *out is NULL on failure. */
+ * MGRIT_EUNSTABLE for ERK above its CFL limit (on the fine level, or on a
+ * rediscretised coarse level).  *out is NULL on failure. */
 mgrit_status mgrit_setup(const mgrit_problem *problem, const mgrit_options *options,
                          void *hip_stream, mgrit_handle **out);
 

@@ -33,8 +33,10 @@ class Hierarchy:
     """Time-steppers and sizes of every level.
 
     ``coarse`` selects the coarse operator: "sl_corrected" (the paper's
-    eq. MOL-SL-corrected-multilevel), "sl_plain" (phi = 0) or "ideal"
-    (Psi = Phi^m; only meaningful for two levels).
+    eq. MOL-SL-corrected-multilevel), "sl_plain" (phi = 0), "ideal"
+    (Psi = Phi^m; only meaningful for two levels) or "redisc" (the fine
+    Runge-Kutta + upwind step taken with the level's step, i.e. at CFL number
+    c m_0 ... m_{l-1}: the rediscretisation of Sec. 5 and Theorem 1).
     """
 
     def __init__(self, nx, nt, p, kind, q, c, ms, coarse="sl_corrected"):
@@ -53,6 +55,11 @@ class Hierarchy:
             if len(self.ms) != 1:
                 raise ValueError("ideal coarse operator only for two levels")
             self.steps.append(disc.RepeatedStep(fine, self.ms[0]))
+        elif coarse == "redisc":
+            prod = 1
+            for m in self.ms:
+                prod *= m
+                self.steps.append(disc.MOLStep(p, kind, q, self.c * prod))
         else:
             self.coeffs = disc.correction_coefficients(p, kind, q, c, self.ms)
             for rec in self.coeffs:

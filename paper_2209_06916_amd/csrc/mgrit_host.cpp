@@ -684,6 +684,73 @@ bool erk_stable(const FineInfo &fi, double c) {
   return true;
 }
 
+// One Runge-Kutta step of the upwind semi-discretisation at CFL c
+// (eq. MOL_M_def), as a Horner form: ERK R(z) in z = -c L_p (OP_POLY_Z);
+// SDIRK R as a polynomial in w = (I + gamma c L_p)^{-1} (OP_POLY_W), every
+// stage solving with the same periodic banded matrix.
+bool build_mol_step(const FineInfo &fi, int rk_kind, double c, int nx, int Lpref, StepOp &op, Layout &lay,
+                    std::vector<double> &tabs, std::vector<size_t> &offs, std::string &err) {
+  op = StepOp{};
+  op.repeat = 1;
+  if (rk_kind == MGRIT_ERK) {
+    lay = choose_layout(nx, Lpref);
+    lay.dbuf = 1;
+    if (lds_bytes_for(lay, 0) > LDS_LIMIT) lay.dbuf = 0;
+    op.kind = OP_POLY_Z;
+    op.ncoef = fi.tab.s + 1;
+    for (int i = 0; i <= fi.tab.s; ++i) op.coef[i] = (double)fi.beta[i];
+    op.st_l = fi.l;
+    op.st_r = fi.r;
+    for (int j = 0; j <= fi.l + fi.r; ++j) op.taps[j] = -c * fi.w[j];
+    return true;
+  }
+  // R(z) = P(z) / (1 - g z)^s as a polynomial in w = 1/(1 - g z):
+  // z = (w - 1)/(g w)  =>  R = sum_n P_n g^-n (w - 1)^n w^(s-n).
+  lay = choose_layout(nx, Lpref);
+  const int s = fi.tab.s;
+  const ld g = fi.tab.gamma;
+  std::vector<ld> beta = rk_series(fi.tab, s);
+  std::vector<ld> Q(s + 1, 0), Pc(s + 1, 0), coefw(s + 1, 0);
+  for (int n = 0; n <= s; ++n) {
+    ld bin = 1;
+    for (int i = 0; i < n; ++i) bin = bin * (s - i) / (i + 1);
+    Q[n] = bin * std::pow(-g, (ld)n);
+  }
+  for (int n = 0; n <= s; ++n)
+    for (int j = 0; j <= n; ++j) Pc[n] += beta[j] * Q[n - j];
+  for (int n = 0; n <= s; ++n) {
+    ld bin = 1;
+    for (int k = 0; k <= n; ++k) {
+      coefw[k + s - n] += Pc[n] * std::pow(g, (ld)-n) * bin * (((n - k) % 2) ? -1 : 1);
+      bin = bin * (n - k) / (k + 1);
+    }
+  }
+  op.kind = OP_POLY_W;
+  op.ncoef = s + 1;
+  for (int i = 0; i <= s; ++i) op.coef[i] = (double)coefw[i];
+  std::map<int, ld> taps;
+  taps[0] += 1;
+  for (int j = -fi.l; j <= fi.r; ++j) taps[j] += g * c * fi.w[j + fi.l];
+  if (!attach_solve(op, taps, lay, tabs, offs, err)) {
+    err = "SDIRK stage operator: " + err;
+    return false;
+  }
+  // self-check of the w-polynomial against R(z)
+  for (double zr : {-0.3, -2.0, -7.5}) {
+    const std::complex<double> z(zr, 0.7);
+    const std::complex<double> w = 1.0 / (1.0 - (double)g * z);
+    std::complex<double> acc = 0;
+    for (int i = s; i >= 0; --i) acc = acc * w + (double)coefw[i];
+    const std::complex<double> ref = rk_R(fi.tab, z);
+    if (std::abs(acc - ref) > 1e-11 * (1 + std::abs(ref))) {
+      err = "internal: SDIRK rational form check failed";
+      return false;
+    }
+  }
+  return true;
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -748,8 +815,9 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
   if (O->nu < 0 || O->nu > 8) return bad(MGRIT_EINVAL, "nu must be in 0..8");
   if (O->max_iter < 0) return bad(MGRIT_EINVAL, "max_iter must be >= 0");
   if (!(O->rtol >= 0)) return bad(MGRIT_EINVAL, "rtol must be >= 0");
-  if (O->cg_kind < 0 || O->cg_kind > 2) return bad(MGRIT_EINVAL, "unknown coarse operator");
-  if (O->cg_kind != MGRIT_CG_IDEAL && P->upwind_order % 2 == 0)
+  if (O->cg_kind < 0 || O->cg_kind > 3) return bad(MGRIT_EINVAL, "unknown coarse operator");
+  const bool sl_coarse = O->cg_kind == MGRIT_CG_SL_CORRECTED || O->cg_kind == MGRIT_CG_SL_PLAIN;
+  if (sl_coarse && P->upwind_order % 2 == 0)
     return bad(MGRIT_EINVAL, "semi-Lagrangian coarse operators need odd upwind order");
   if (O->cg_kind == MGRIT_CG_IDEAL && O->max_levels != 2) return bad(MGRIT_EINVAL, "ideal coarse operator: two levels only");
 
@@ -760,9 +828,7 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
   const double c = P->cfl;
   const int p = P->upwind_order, q = P->rk_order;
   if (P->rk_kind == MGRIT_ERK && !erk_stable(fi, c)) return bad(MGRIT_EUNSTABLE, "CFL number above the stability limit of the explicit scheme");
-  if (P->rk_kind == MGRIT_SDIRK && q != p && (q % 2 == 0) && O->cg_kind != MGRIT_CG_IDEAL)
-    return bad(MGRIT_EINVAL, "mixed orders need an odd Runge-Kutta order for the correction");
-  if (P->rk_kind == MGRIT_ERK && q != p && (q % 2 == 0) && O->cg_kind != MGRIT_CG_IDEAL)
+  if (q != p && (q % 2 == 0) && sl_coarse)
     return bad(MGRIT_EINVAL, "mixed orders need an odd Runge-Kutta order for the correction");
 
   // level hierarchy
@@ -806,64 +872,16 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
     op = StepOp{};
     op.repeat = 1;
     if (P->rk_kind == MGRIT_ERK) {
-      L0.lay = choose_layout(nx, Lfine);
-      L0.lay.dbuf = 1;
-      if (lds_bytes_for(L0.lay, 0) > LDS_LIMIT) L0.lay.dbuf = 0;
       L0.tiles = env_int("MGRIT_NO_TILES", 0) == 0 &&
                  choose_tiles(nx, ms[0], fi.tab.s, fi.l, fi.r, env_int("MGRIT_TILE_P", 0), L0.tg);
       L0.seq_tiles = env_int("MGRIT_NO_TILES", 0) == 0 &&
                      choose_seq_tiles(nx, P->nt, fi.tab.s, fi.l, fi.r, env_int("MGRIT_SEQ_P", 0),
                                       env_int("MGRIT_SEQ_T", 0), L0.seq_tg, L0.seq_T);
-      op.kind = OP_POLY_Z;
-      op.ncoef = fi.tab.s + 1;
-      for (int i = 0; i <= fi.tab.s; ++i) op.coef[i] = (double)fi.beta[i];
-      op.st_l = fi.l;
-      op.st_r = fi.r;
-      for (int j = 0; j <= fi.l + fi.r; ++j) op.taps[j] = -c * fi.w[j];
-    } else {
-      // R(z) = P(z) / (1 - g z)^s as a polynomial in w = 1/(1 - g z):
-      // z = (w - 1)/(g w)  =>  R = sum_n P_n g^-n (w - 1)^n w^(s-n).
-      L0.lay = choose_layout(nx, Lcoarse);
-      const int s = fi.tab.s;
-      const ld g = fi.tab.gamma;
-      std::vector<ld> beta = rk_series(fi.tab, s);
-      std::vector<ld> Q(s + 1, 0), Pc(s + 1, 0), coefw(s + 1, 0);
-      for (int n = 0; n <= s; ++n) {
-        ld bin = 1;
-        for (int i = 0; i < n; ++i) bin = bin * (s - i) / (i + 1);
-        Q[n] = bin * std::pow(-g, (ld)n);
-      }
-      for (int n = 0; n <= s; ++n)
-        for (int j = 0; j <= n; ++j) Pc[n] += beta[j] * Q[n - j];
-      for (int n = 0; n <= s; ++n) {
-        ld bin = 1;
-        for (int k = 0; k <= n; ++k) {
-          coefw[k + s - n] += Pc[n] * std::pow(g, (ld)-n) * bin * (((n - k) % 2) ? -1 : 1);
-          bin = bin * (n - k) / (k + 1);
-        }
-      }
-      op.kind = OP_POLY_W;
-      op.ncoef = s + 1;
-      for (int i = 0; i <= s; ++i) op.coef[i] = (double)coefw[i];
-      std::map<int, ld> taps;
-      taps[0] += 1;
-      for (int j = -fi.l; j <= fi.r; ++j) taps[j] += g * c * fi.w[j + fi.l];
-      if (!attach_solve(op, taps, L0.lay, tabs[0], offs[0], err)) {
-        mgrit_destroy(h);
-        return bad(MGRIT_EINVAL, "SDIRK stage operator: " + err);
-      }
-      // self-check of the w-polynomial against R(z)
-      for (double zr : {-0.3, -2.0, -7.5}) {
-        const std::complex<double> z(zr, 0.7);
-        const std::complex<double> w = 1.0 / (1.0 - (double)g * z);
-        std::complex<double> acc = 0;
-        for (int i = s; i >= 0; --i) acc = acc * w + (double)coefw[i];
-        const std::complex<double> ref = rk_R(fi.tab, z);
-        if (std::abs(acc - ref) > 1e-11 * (1 + std::abs(ref))) {
-          mgrit_destroy(h);
-          return bad(MGRIT_EINVAL, "internal: SDIRK rational form check failed");
-        }
-      }
+    }
+    if (!build_mol_step(fi, P->rk_kind, c, nx, P->rk_kind == MGRIT_ERK ? Lfine : Lcoarse, op, L0.lay, tabs[0],
+                        offs[0], err)) {
+      mgrit_destroy(h);
+      return bad(MGRIT_EINVAL, err);
     }
   }
 
@@ -883,6 +901,20 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
         Lv.lay = h->lv[0].lay;
         tabs[l] = tabs[0];
         offs[l] = offs[0];
+        continue;
+      }
+      if (O->cg_kind == MGRIT_CG_REDISC) {
+        // the fine scheme rediscretised with the level's step (Sec. 5, Theorem 1)
+        const double cl = (double)((ld)c * prod);
+        if (P->rk_kind == MGRIT_ERK && !erk_stable(fi, cl)) {
+          mgrit_destroy(h);
+          return bad(MGRIT_EUNSTABLE, "rediscretised explicit coarse step above its CFL limit");
+        }
+        Lv.shift = cl;
+        if (!build_mol_step(fi, P->rk_kind, cl, nx, Lcoarse, Lv.op, Lv.lay, tabs[l], offs[l], err)) {
+          mgrit_destroy(h);
+          return bad(MGRIT_EINVAL, "coarse operator: " + err);
+        }
         continue;
       }
       const ld shift = (ld)c * prod;
@@ -1413,7 +1445,7 @@ mgrit_status mgrit_lfa_rho(const mgrit_problem *P, const mgrit_options *O, doubl
   if (O->cg_kind == MGRIT_CG_SL_PLAIN) phi_p = phi_q = 0;
   int sl_l = 0, sl_r = 0;
   std::vector<double> slw;
-  if (O->cg_kind != MGRIT_CG_IDEAL) sl_weights(p, eps, sl_l, sl_r, slw);
+  if (O->cg_kind == MGRIT_CG_SL_CORRECTED || O->cg_kind == MGRIT_CG_SL_PLAIN) sl_weights(p, eps, sl_l, sl_r, slw);
   const int N = 1 << 11;
   std::vector<std::pair<double, double>> oms;  // (|omega|, omega)
   for (int k = 0; k < N; ++k) {
@@ -1429,6 +1461,8 @@ mgrit_status mgrit_lfa_rho(const mgrit_problem *P, const mgrit_options *O, doubl
     const std::complex<double> lamm = std::pow(lam, m);
     if (O->cg_kind == MGRIT_CG_IDEAL) {
       mu = lamm;
+    } else if (O->cg_kind == MGRIT_CG_REDISC) {
+      mu = rk_R(fi.tab, -(c * m) * upwind_symbol(fi, om));
     } else {
       std::complex<double> S = 0;
       for (int j = -sl_l; j <= sl_r; ++j) S += slw[j + sl_l] * std::polar(1.0, (double)(j - K) * om);

@@ -18,7 +18,7 @@ MAX_NX = 16384
 
 OK, ENOTCONVERGED, EINVAL, EUNSTABLE, ENOMEM, EDEVICE, EDIVERGED = 0, 1, -1, -2, -3, -4, -5
 ERK, SDIRK = 0, 1
-CG_SL_CORRECTED, CG_IDEAL, CG_SL_PLAIN = 0, 1, 2
+CG_SL_CORRECTED, CG_IDEAL, CG_SL_PLAIN, CG_REDISC = 0, 1, 2, 3
 
 
 class MgritError(RuntimeError):
@@ -115,7 +115,7 @@ def make_options(m, max_levels=2, min_coarse_nt=0, nu=1, coarse="sl_corrected", 
         o.m[i] = v
     o.min_coarse_nt = min_coarse_nt
     o.nu = nu
-    o.cg_kind = {"sl_corrected": CG_SL_CORRECTED, "ideal": CG_IDEAL, "sl_plain": CG_SL_PLAIN}[coarse]
+    o.cg_kind = {"sl_corrected": CG_SL_CORRECTED, "ideal": CG_IDEAL, "sl_plain": CG_SL_PLAIN, "redisc": CG_REDISC}[coarse]
     o.rtol = rtol
     o.max_iter = max_iter
     o.diverge_factor = diverge_factor

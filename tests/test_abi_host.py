@@ -44,6 +44,7 @@ def _setup_status(problem, options):
     (dict(nx=64, nt=32, cfl=0.5, p=3, kind="sdirk", q=4), dict(m=4), mgrit.EINVAL),  # no SDIRK4 tableau
     (dict(nx=64, nt=32, cfl=0.5, p=1), dict(m=1), mgrit.EINVAL),          # m must be >= 2
     (dict(nx=64, nt=32, cfl=0.5, p=1), dict(m=4, max_levels=3, coarse="ideal"), mgrit.EINVAL),
+    (dict(nx=64, nt=32, cfl=0.5, p=3), dict(m=4, coarse="redisc"), mgrit.EUNSTABLE),  # ERK3+U3 at 4 c > c_max
 ])
 def test_setup_rejects_invalid_problems(kw, opt, expected):
     st, msg = _setup_status(mgrit.make_problem(**kw), mgrit.make_options(**opt))
@@ -55,7 +56,8 @@ def test_setup_rejects_invalid_problems(kw, opt, expected):
     (1, "erk", 1, 0.85, 4, "sl_corrected"), (3, "erk", 3, 1.2, 8, "sl_corrected"),
     (5, "erk", 5, 0.9, 4, "sl_corrected"), (3, "sdirk", 3, 5.0, 4, "sl_corrected"),
     (1, "sdirk", 1, 2.0, 16, "sl_corrected"), (5, "sdirk", 3, 0.5, 16, "sl_corrected"),
-    (1, "erk", 1, 0.5, 4, "sl_plain"),
+    (1, "erk", 1, 0.5, 4, "sl_plain"), (3, "sdirk", 3, 5.0, 8, "redisc"), (1, "sdirk", 1, 1.0, 4, "redisc"),
+    (2, "erk", 2, 0.2, 2, "redisc"), (4, "sdirk", 2, 1.5, 4, "redisc"),
 ])
 def test_host_lfa_helper_matches_oracle(p, kind, q, c, m, coarse):
     prob = mgrit.make_problem(256, 256, c, p, kind, q)
@@ -75,3 +77,14 @@ def test_erk_stability_boundary_matches_table2_reading():
         bad, _ = _setup_status(mgrit.make_problem(64, 32, cm * (1 + 1e-4), p), mgrit.make_options(4, coarse="ideal"))
         assert ok != mgrit.EUNSTABLE and ok != mgrit.EINVAL
         assert bad == mgrit.EUNSTABLE
+
+
+def test_rediscretised_coarse_levels_accept_stable_explicit_steps():
+    """ERK3+U3 at c = 0.4 with m = 2, 2: coarse CFL 0.8 and 1.6 stay below
+    c_max = 1.62589, so setup succeeds; a third factor of 2 (3.2) does not."""
+    ok, msg = _setup_status(mgrit.make_problem(64, 64, 0.4, 3), mgrit.make_options([2, 2], max_levels=3,
+                                                                                 coarse="redisc"))
+    assert ok not in (mgrit.EUNSTABLE, mgrit.EINVAL), msg  # OK on a GPU, EDEVICE without one
+    bad, _ = _setup_status(mgrit.make_problem(64, 64, 0.4, 3), mgrit.make_options([2, 2, 2], max_levels=4,
+                                                                                coarse="redisc"))
+    assert bad == mgrit.EUNSTABLE

@@ -210,7 +210,8 @@ def _solve_both(nx, nt, p, kind, q, c, ms, coarse="sl_corrected", nu=1, u0kind="
                 rtol=1e-10, max_iter=30):
     u0 = inputs.u0_sin4(nx) if u0kind == "sin4" else inputs.u0_fourier(nx, seed)
     v0 = inputs.initial_iterate(nt, nx, u0, seed)
-    opts = mgrit.make_options(ms, max_levels=len(ms) + 1, nu=nu, coarse=coarse, rtol=rtol, max_iter=max_iter)
+    opts = mgrit.make_options(ms, max_levels=len(ms) + 1, nu=nu, coarse=coarse, rtol=rtol, max_iter=max_iter,
+                              diverge_factor=0.0)
     s = mgrit.Solver(mgrit.make_problem(nx, nt, c, p, kind, q), opts)
     out = torch.empty((nt + 1, nx), dtype=torch.float64, device=DEV)
     fin = torch.empty((nx,), dtype=torch.float64, device=DEV)
@@ -249,6 +250,30 @@ def test_full_solve_matches_oracle(case):
     _announce("solve", case)
     s, info, got, fin, ref, rinfo = _solve_both(case["nx"], case["nt"], case["p"], case["kind"], case["q"],
                                                 case["c"], case["ms"])
+    _check_parity(info, got, fin, ref, rinfo, case["ms"][0])
+
+
+@pytest.mark.parametrize("case", [
+    dict(nx=64, nt=256, p=1, kind="sdirk", q=1, c=1.0, ms=[4], max_iter=60),
+    dict(nx=96, nt=128, p=3, kind="sdirk", q=3, c=2.0, ms=[4, 4], max_iter=60),
+    dict(nx=128, nt=64, p=3, kind="erk", q=3, c=0.4, ms=[2, 2], max_iter=30),
+    dict(nx=64, nt=256, p=3, kind="sdirk", q=3, c=5.0, ms=[8], max_iter=6),  # diverging (LFA 2.4)
+])
+def test_rediscretised_coarse_operator_matches_oracle(case):
+    """Coarse levels take the fine scheme at the level's step (Sec. 5): same
+    iterates and residual histories as the oracle, also where the iteration
+    diverges (there the last residual is ~1e3 times the first, so the
+    history is compared relative to each entry)."""
+    _announce("redisc", case)
+    s, info, got, fin, ref, rinfo = _solve_both(case["nx"], case["nt"], case["p"], case["kind"], case["q"],
+                                                case["c"], case["ms"], coarse="redisc", u0kind="fourier",
+                                                max_iter=case["max_iter"])
+    if case["max_iter"] == 6:
+        assert info["status"] == mgrit.ENOTCONVERGED and info["iterations"] == 6 == rinfo["iterations"]
+        np.testing.assert_allclose(info["res_history"], rinfo["res_history"], rtol=1e-8)
+        per_c = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        assert np.max(per_c) <= 1e-10
+        return
     _check_parity(info, got, fin, ref, rinfo, case["ms"][0])
 
 

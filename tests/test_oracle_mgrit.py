@@ -212,3 +212,55 @@ def test_theorem1_lower_bound(p, c, m):
     bound = lfa.rho_check(p, disc.e_fd_closed_form(p), erk, erk, c, m)
     rho = lfa.rho_for(p, "sdirk", p, c, m, coarse="redisc", n=1 << 14, drop=0)
     assert rho >= 0.97 * bound
+
+
+# --------------------------------------------------------------------------
+# rediscretised coarse operator (Sec. 5, Theorem 1)
+# --------------------------------------------------------------------------
+
+def test_finite_step_exactness_with_rediscretised_coarse_operator():
+    """Exactness after N_c / 2 FCF iterations holds for any coarse operator,
+    the rediscretised SDIRK1+U1 step included (N_c = 16)."""
+    nx, nt, m = 16, 64, 4
+    u0, v = _problem(nx, nt, seed=5)
+    H = mgrit.Hierarchy(nx, nt, 1, "sdirk", 1, 2.0, [m], coarse="redisc")
+    u, info = mgrit.solve(H, u0, v, rtol=1e-13, max_iter=40, nu=1)
+    hist = np.array(info["res_history"])
+    assert hist[8] < 1e-13 * hist[0]
+    seq = mgrit.sequential(H.steps[0], u0, nt)
+    np.testing.assert_allclose(u, seq, atol=1e-12)
+
+
+@pytest.mark.parametrize("p,q,c,m", [(1, 1, 1.0, 4), (3, 3, 5.0, 4)])
+def test_lfa_bounds_measured_convergence_rediscretised(p, q, c, m):
+    """eq. (rho-asym) with mu the rediscretised coarse step bounds the
+    measured two-level factor; the coarse step is the fine SDIRK step at
+    CFL m c (its symbol is checked against the Butcher evaluation)."""
+    nx, nt = 128, 512
+    u0, v = _problem(nx, nt)
+    H = mgrit.Hierarchy(nx, nt, p, "sdirk", q, c, [m], coarse="redisc")
+    om = lfa.omega_samples(64, 0)
+    np.testing.assert_allclose(H.steps[1].symbol(om), disc.MOLStep(p, "sdirk", q, m * c).symbol(om), rtol=0,
+                               atol=1e-14)
+    _, info = mgrit.solve(H, u0, v, rtol=1e-10, max_iter=30)
+    rho = lfa.rho_for(p, "sdirk", q, c, m, coarse="redisc")
+    assert 0.0 < info["conv_factor"] <= 1.1 * rho
+
+
+def test_rediscretisation_converges_slower_than_the_corrected_sl_operator():
+    """The paper's motivation (Sec. 5-6): for SDIRK3+U3 at c = 5 the LFA factor
+    of the rediscretised coarse operator is far above that of the corrected
+    semi-Lagrangian operator, and the measured two-level iteration counts
+    follow."""
+    p, c, m = 3, 5.0, 8
+    rho_r = lfa.rho_for(p, "sdirk", p, c, m, coarse="redisc")
+    rho_s = lfa.rho_for(p, "sdirk", p, c, m, coarse="sl_corrected")
+    assert rho_r > 2 * rho_s
+    nx, nt = 64, 256
+    u0, v = _problem(nx, nt)
+    its = {}
+    for coarse in ("redisc", "sl_corrected"):
+        H = mgrit.Hierarchy(nx, nt, p, "sdirk", p, c, [m], coarse=coarse)
+        _, info = mgrit.solve(H, u0, v, rtol=1e-10, max_iter=30)
+        its[coarse] = info["iterations"]
+    assert its["redisc"] > its["sl_corrected"]
