@@ -201,6 +201,54 @@ def summarize_profiles(d):
     print("\n".join(lines))
 
 
+def serve_bench(n, seed):
+    """Config 5: n independent 1D solves (nx, nt in 256..8192, ERK1/3/5 with
+    the matching upwind order, CFL U(0.5, 0.9), m in {4, 8, 16}, multilevel
+    down to <= 8 coarse steps, seeded 16-mode Fourier u0, zero initial
+    iterate).  Throughput with one solve in flight and with up to 16 in
+    flight (all requests queued at once), then latency under Poisson
+    arrivals at 0.8x the single-stream capacity."""
+    from paper_2209_06916_amd import serve
+    reqs = serve.synthetic_stream(n, seed=seed, rate_hz=0)
+    dof = sum(r.nx * r.nt for r in reqs)
+    serve.Server(max_inflight=16).run(reqs[:8], realtime=False)  # warm-up (kernels, allocator)
+    t = time.perf_counter()
+    one = serve.Server(max_inflight=1).run(reqs, realtime=False)
+    t_one = time.perf_counter() - t
+    t = time.perf_counter()
+    many = serve.Server(max_inflight=16).run(reqs, realtime=False)
+    t_many = time.perf_counter() - t
+    by1 = {r.tag: r for r in one}
+    same = all(np.array_equal(by1[r.tag].u_final, r.u_final) for r in many)
+    rate = 0.8 * n / t_one
+    arrivals = serve.synthetic_stream(n, seed=seed, rate_hz=rate)
+    t = time.perf_counter()
+    live = serve.Server(max_inflight=16).run(arrivals, realtime=True)
+    t_live = time.perf_counter() - t
+    lat = np.array([r.latency for r in live]) * 1e3
+    line = {
+        "metric": "served MGRIT solves: space-time DOF/s and p50/p99 request latency",
+        "value": dof / t_many,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"served-advection1d-{n}-requests", "requests": n, "sizes": "nx, nt in 256..8192",
+                   "schemes": "ERK1/3/5 + U1/3/5", "cfl": "U(0.5, 0.9)", "m": [4, 8, 16], "max_inflight": 16},
+        "dof_per_s_one_in_flight": dof / t_one,
+        "dof_per_s_16_in_flight": dof / t_many,
+        "concurrency_speedup": t_one / t_many,
+        "same_results_alone_and_in_mix": bool(same),
+        "all_converged": all(r.status == 0 for r in many),
+        "poisson_rate_hz": rate,
+        "poisson_dof_per_s": dof / t_live,
+        "latency_ms_p50": float(np.percentile(lat, 50)),
+        "latency_ms_p99": float(np.percentile(lat, 99)),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,6 +258,8 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for hardware-counter runs: a few solves plus one elementwise copy of "
                          "COPY_BYTES read + COPY_BYTES written (the counter calibration)")
+    ap.add_argument("--serve", type=int, metavar="N", default=0,
+                    help="the request-loop benchmark (N independent solves) instead of the single-solve one")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="CPU only: turn the rocprofv3 runs under DIR into the profiles/ summaries")
     args = ap.parse_args()
@@ -223,6 +273,9 @@ def main():
 
     import torch
     from paper_2209_06916_amd import inputs, mgrit
+    if args.serve:
+        serve_bench(args.serve, seed=1005)
+        return
 
     dev = torch.device("cuda:0")
     u0 = inputs.u0_fourier(NX, SEED)

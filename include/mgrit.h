@@ -90,6 +90,11 @@ typedef struct {
   int32_t max_iter;      /* upper bound on coarse-grid corrections           */
   double diverge_factor; /* ||r_it|| > diverge_factor ||r_0|| => EDIVERGED;
                             <= 0 disables the check                          */
+  int32_t coarse_launch; /* 0: the coarse part of each V-cycle as one
+                            persistent launch when it applies (it assumes its
+                            workgroups are the only persistent ones resident);
+                            1: one launch per pass (for handles that run
+                            concurrently on several streams)                 */
 } mgrit_options;
 
 typedef struct {
@@ -156,6 +161,25 @@ mgrit_status mgrit_setup(const mgrit_problem *problem, const mgrit_options *opti
  * hold the last iterate), MGRIT_EDIVERGED on a non-finite or growing residual. */
 mgrit_status mgrit_solve(mgrit_handle *h, const double *u0_dev, const double *v_init_dev,
                          double *u_out_dev, double *u_final_dev, mgrit_stats *stats);
+
+/* The same solve in steps, for request loops that keep several solves in
+ * flight (one handle and one stream each).  mgrit_solve_start queues the
+ * start and the first iteration; mgrit_solve_advance never blocks: once the
+ * last queued iteration's stopping test has run it queues the next iteration,
+ * or the outputs and sets *done = 1; mgrit_solve_finish waits for the solve to
+ * end (driving it if needed), fills stats and returns the status mgrit_solve
+ * would have returned.  Arguments as for mgrit_solve; the device buffers must
+ * stay valid until mgrit_solve_finish returns.  One solve at a time per handle
+ * (MGRIT_EINVAL otherwise).  mgrit_solve is start + finish. */
+mgrit_status mgrit_solve_start(mgrit_handle *h, const double *u0_dev, const double *v_init_dev, double *u_out_dev,
+                               double *u_final_dev);
+mgrit_status mgrit_solve_advance(mgrit_handle *h, int32_t *done);
+mgrit_status mgrit_solve_finish(mgrit_handle *h, mgrit_stats *stats);
+
+/* Host-only: device memory (bytes) the handle of (problem, options) allocates
+ * (C-point and residual arrays of every level, norm partials, tables); the
+ * caller's own buffers (u0, v_init, outputs) are not included. */
+mgrit_status mgrit_workspace_bytes(const mgrit_problem *problem, const mgrit_options *options, uint64_t *bytes);
 
 /* Space-time residual of an arbitrary iterate u_dev [nt+1][nx] of the fine
  * system: r_n = Phi u_{n-1} - u_n, n = 1..nt, one fine step per time point,

@@ -540,6 +540,39 @@ bool choose_seq_tiles(int nx, int64_t nt, int depth, int sl, int sr, int Pforce,
   return best >= 0;
 }
 
+// Level sizes (Sec. 2.2): nt_0 = nt, nt_{l+1} = nt_l / m_l while the level
+// has more than min_coarse_nt steps and m_l divides it; a zero m[l] repeats
+// the previous factor.
+bool level_hierarchy(const mgrit_problem &P, const mgrit_options &O, std::vector<int64_t> &nts, std::vector<int> &ms,
+                     std::string &err) {
+  nts.assign(1, P.nt);
+  ms.clear();
+  int mprev = 0;
+  for (int l = 0; l < O.max_levels - 1; ++l) {
+    const int m = O.m[l] > 0 ? O.m[l] : mprev;
+    if (m < 2) {
+      if (l == 0) {
+        err = "m[0] must be >= 2";
+        return false;
+      }
+      break;
+    }
+    mprev = m;
+    const int64_t cur = nts.back();
+    if (l > 0 && cur <= O.min_coarse_nt) break;
+    if (cur % m != 0) {
+      if (l == 0) {
+        err = "nt must be divisible by m[0]";
+        return false;
+      }
+      break;
+    }
+    ms.push_back(m);
+    nts.push_back(cur / m);
+  }
+  return true;
+}
+
 int env_int(const char *name, int def) {
   const char *v = std::getenv(name);
   return (v && *v) ? std::atoi(v) : def;
@@ -585,6 +618,17 @@ struct mgrit_handle {
   int64_t cv_grid = 0;
   GridSync *gsync = nullptr;
   std::string err;
+  // the solve in progress (mgrit_solve_start .. mgrit_solve_finish)
+  struct {
+    bool active = false, finished = false;
+    double *u_out = nullptr, *u_final = nullptr;
+    int cur = 0;
+    double prev = NAN;
+    SolveCtl hc{};
+    std::vector<double> hist;
+    mgrit_status status = MGRIT_OK;
+    std::chrono::steady_clock::time_point t0;
+  } ss;
   // profiler
   uint32_t prof_mask = 0;
   std::vector<hipEvent_t> ev_free;
@@ -816,6 +860,7 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
   if (O->max_iter < 0) return bad(MGRIT_EINVAL, "max_iter must be >= 0");
   if (!(O->rtol >= 0)) return bad(MGRIT_EINVAL, "rtol must be >= 0");
   if (O->cg_kind < 0 || O->cg_kind > 3) return bad(MGRIT_EINVAL, "unknown coarse operator");
+  if (O->coarse_launch < 0 || O->coarse_launch > 1) return bad(MGRIT_EINVAL, "coarse_launch must be 0 or 1");
   const bool sl_coarse = O->cg_kind == MGRIT_CG_SL_CORRECTED || O->cg_kind == MGRIT_CG_SL_PLAIN;
   if (sl_coarse && P->upwind_order % 2 == 0)
     return bad(MGRIT_EINVAL, "semi-Lagrangian coarse operators need odd upwind order");
@@ -832,25 +877,9 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
     return bad(MGRIT_EINVAL, "mixed orders need an odd Runge-Kutta order for the correction");
 
   // level hierarchy
-  std::vector<int64_t> nts{P->nt};
+  std::vector<int64_t> nts;
   std::vector<int> ms;
-  int mprev = 0;
-  for (int l = 0; l < O->max_levels - 1; ++l) {
-    int m = O->m[l] > 0 ? O->m[l] : mprev;
-    if (m < 2) {
-      if (l == 0) return bad(MGRIT_EINVAL, "m[0] must be >= 2");
-      break;
-    }
-    mprev = m;
-    const int64_t cur = nts.back();
-    if (l > 0 && cur <= O->min_coarse_nt) break;
-    if (cur % m != 0) {
-      if (l == 0) return bad(MGRIT_EINVAL, "nt must be divisible by m[0]");
-      break;
-    }
-    ms.push_back(m);
-    nts.push_back(cur / m);
-  }
+  if (!level_hierarchy(*P, *O, nts, ms, err)) return bad(MGRIT_EINVAL, err);
   const int nlev = (int)nts.size();
 
   mgrit_handle *h = new mgrit_handle();
@@ -1024,7 +1053,7 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
   // Persistent coarse V-cycle: every coarse level takes the lean kernel, the
   // tables of all of them fit in LDS beside the vector, and the largest
   // level's intervals can all be resident at once (cooperative launch).
-  if (nlev >= 2 && env_int("MGRIT_NO_PERSISTENT", 0) == 0) {
+  if (nlev >= 2 && O->coarse_launch == 0 && env_int("MGRIT_NO_PERSISTENT", 0) == 0) {
     bool all_lean = true;
     for (int l = 1; l < nlev; ++l) all_lean = all_lean && lean_slc_applies(h->lv[l].op, h->lv[l].lay);
     const size_t lds = all_lean ? coarse_vcycle_lds(h->lv[1].op, h->lv[1].lay, nlev - 1) : 0;
@@ -1249,6 +1278,63 @@ mgrit_status vcycle(mgrit_handle *h, const double *g, double *parent) {
   return MGRIT_OK;
 }
 
+// One MGRIT iteration of the solve in progress: level-0 relaxation (F(CF)^nu
+// then F and the C-point residual), the norm and stopping test on the
+// device (its state also lands in pinned host memory, with an event behind
+// it), and the coarse-grid correction, queued before the decision is known
+// and skipping itself once a stop is recorded.
+mgrit_status queue_iteration(mgrit_handle *h) {
+  auto &ss = h->ss;
+  Level &L0 = h->lv[0];
+  const StopRule rule{h->opt.rtol, h->opt.diverge_factor, h->opt.max_iter};
+  for (int s = 0; s < h->opt.nu; ++s) {
+    HIPCHK(h, run_fine(h, MGRIT_PROF_FINE_RELAX, MODE_PASS_A, L0.c[ss.cur], L0.c[1 - ss.cur], nullptr, nullptr));
+    ss.cur = 1 - ss.cur;
+  }
+  HIPCHK(h, run_fine(h, MGRIT_PROF_FINE_RELAX, MODE_PASS_B, L0.c[ss.cur], nullptr, L0.r, nullptr));
+  HIPCHK(h, launch_solve_ctl(h->normpart, fine_norm_parts(h), h->ctl, h->ctl_host_dev, h->gsync, rule, h->stream));
+  HIPCHK(h, hipEventRecord(h->ctl_ev, h->stream));
+  h->guard = &h->ctl->stop;
+  const mgrit_status st = vcycle(h, L0.r, L0.c[ss.cur]);
+  h->guard = nullptr;
+  return st;
+}
+
+// Read the stopping decision of the last queued iteration (its event has
+// completed); on a stop, queue the outputs and mark the solve finished.
+mgrit_status take_decision(mgrit_handle *h) {
+  auto &ss = h->ss;
+  Level &L0 = h->lv[0];
+  const int nx = (int)h->prob.nx;
+  const int64_t nc = L0.nt / L0.m;
+  ss.prev = ss.hc.rho;
+  ss.hc = *h->ctl_host;
+  ss.hist.push_back(ss.hc.rho);
+  if (ss.hc.stop == STOP_NONE) return MGRIT_OK;
+  ss.finished = true;
+  switch (ss.hc.stop) {
+    case STOP_NONFINITE: ss.status = fail(h, MGRIT_EDIVERGED, "non-finite residual"); break;
+    case STOP_MAX_ITER:
+      ss.status = MGRIT_ENOTCONVERGED;
+      h->err = "max_iter reached";
+      break;
+    case STOP_DIVERGED: ss.status = fail(h, MGRIT_EDIVERGED, "residual grew past diverge_factor * res0"); break;
+    case STOP_DEVICE:
+      // a persistent launch gave up waiting at a grid barrier: reset the
+      // barrier state so that later solves start clean; no outputs
+      (void)hipStreamSynchronize(h->stream);
+      (void)hipMemset(h->gsync, 0, sizeof(GridSync));
+      ss.status = fail(h, MGRIT_EDEVICE, "coarse-level grid barrier timed out");
+      return MGRIT_OK;
+    default: break;
+  }
+  if (ss.u_out) HIPCHK(h, run_fine(h, MGRIT_PROF_FINAL, MODE_FINAL_F, L0.c[ss.cur], nullptr, nullptr, ss.u_out));
+  if (ss.u_final)
+    HIPCHK(h, hipMemcpyAsync(ss.u_final, L0.c[ss.cur] + nc * (int64_t)nx, nx * sizeof(double),
+                             hipMemcpyDeviceToDevice, h->stream));
+  return MGRIT_OK;
+}
+
 double reduce_norm(mgrit_handle *h, int64_t n, hipError_t &e) {
   e = launch_reduce(h->normpart, n, h->normsum, h->stream);
   if (e) return NAN;
@@ -1264,88 +1350,110 @@ double reduce_norm(mgrit_handle *h, int64_t n, hipError_t &e) {
 
 extern "C" {
 
-mgrit_status mgrit_solve(mgrit_handle *h, const double *u0, const double *v_init, double *u_out, double *u_final,
-                         mgrit_stats *stats) {
+mgrit_status mgrit_solve_start(mgrit_handle *h, const double *u0, const double *v_init, double *u_out,
+                               double *u_final) {
   if (!h) return MGRIT_EINVAL;
   if (!u0) return fail(h, MGRIT_EINVAL, "u0 is required");
-  const auto t0 = std::chrono::steady_clock::now();
+  if (h->ss.active) return fail(h, MGRIT_EINVAL, "a solve is already in progress on this handle");
+  auto &ss = h->ss;
+  ss = {};
+  ss.t0 = std::chrono::steady_clock::now();
+  ss.u_out = u_out;
+  ss.u_final = u_final;
+  ss.hc.rho = NAN;
   Level &L0 = h->lv[0];
   const int nx = (int)h->prob.nx;
   const int64_t nc = L0.nt / L0.m;
-  const int m0 = L0.m;
   // initial C-points
   if (v_init) {
-    HIPCHK(h, launch_gather_rows(v_init, m0, L0.c[0], nc + 1, nx, h->stream));
+    HIPCHK(h, launch_gather_rows(v_init, L0.m, L0.c[0], nc + 1, nx, h->stream));
   } else {
     HIPCHK(h, launch_fill(L0.c[0], (nc + 1) * (int64_t)nx, 0.0, h->stream));
   }
   HIPCHK(h, hipMemcpyAsync(L0.c[0], u0, nx * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
-
-  // Iteration state lives on the device: solve_ctl_kernel reduces the
-  // residual norm and takes the stopping decision, and the coarse-grid
-  // correction queued behind it skips itself once a stop is recorded.  The
-  // host reads the state while that correction runs, so the GPU never idles
-  // waiting for it; the next iteration is queued only after a "continue".
   HIPCHK(h, hipMemsetAsync(h->ctl, 0, sizeof(SolveCtl), h->stream));
-  const StopRule rule{h->opt.rtol, h->opt.diverge_factor, h->opt.max_iter};
-  int cur = 0;
-  double prev = NAN;
-  SolveCtl hc{};
-  hc.rho = NAN;
-  int hist_len = 0;
-  for (;;) {
-    for (int s = 0; s < h->opt.nu; ++s) {
-      HIPCHK(h, run_fine(h, MGRIT_PROF_FINE_RELAX, MODE_PASS_A, L0.c[cur], L0.c[1 - cur], nullptr, nullptr));
-      cur = 1 - cur;
-    }
-    HIPCHK(h, run_fine(h, MGRIT_PROF_FINE_RELAX, MODE_PASS_B, L0.c[cur], nullptr, L0.r, nullptr));
-    HIPCHK(h, launch_solve_ctl(h->normpart, fine_norm_parts(h), h->ctl, h->ctl_host_dev, h->gsync, rule, h->stream));
-    HIPCHK(h, hipEventRecord(h->ctl_ev, h->stream));
-    h->guard = &h->ctl->stop;
-    const mgrit_status st = vcycle(h, L0.r, L0.c[cur]);
-    h->guard = nullptr;
-    if (st != MGRIT_OK) return st;
+  ss.active = true;
+  const mgrit_status st = queue_iteration(h);
+  if (st != MGRIT_OK) ss.active = false;
+  return st;
+}
+
+mgrit_status mgrit_solve_advance(mgrit_handle *h, int32_t *done) {
+  if (!h || !done) return MGRIT_EINVAL;
+  auto &ss = h->ss;
+  if (!ss.active) return fail(h, MGRIT_EINVAL, "no solve in progress");
+  *done = 0;
+  if (ss.finished) {
+    *done = 1;
+    return MGRIT_OK;
+  }
+  const hipError_t q = hipEventQuery(h->ctl_ev);
+  if (q == hipErrorNotReady) return MGRIT_OK;
+  if (q != hipSuccess) return hipfail(h, q, "stopping-test event");
+  const mgrit_status st = take_decision(h);
+  if (st != MGRIT_OK) return st;
+  if (ss.finished) {
+    *done = 1;
+    return MGRIT_OK;
+  }
+  return queue_iteration(h);
+}
+
+mgrit_status mgrit_solve_finish(mgrit_handle *h, mgrit_stats *stats) {
+  if (!h) return MGRIT_EINVAL;
+  auto &ss = h->ss;
+  if (!ss.active) return fail(h, MGRIT_EINVAL, "no solve in progress");
+  while (!ss.finished) {
     HIPCHK(h, hipEventSynchronize(h->ctl_ev));
-    prev = hc.rho;
-    hc = *h->ctl_host;
-    if (stats && stats->res_history && hist_len < stats->res_history_cap) stats->res_history[hist_len] = hc.rho;
-    ++hist_len;
-    if (hc.stop != STOP_NONE) break;
-  }
-  mgrit_status status = MGRIT_OK;
-  switch (hc.stop) {
-    case STOP_NONFINITE: status = fail(h, MGRIT_EDIVERGED, "non-finite residual"); break;
-    case STOP_MAX_ITER:
-      status = MGRIT_ENOTCONVERGED;
-      h->err = "max_iter reached";
-      break;
-    case STOP_DIVERGED: status = fail(h, MGRIT_EDIVERGED, "residual grew past diverge_factor * res0"); break;
-    case STOP_DEVICE:
-      // a persistent launch gave up waiting at a grid barrier: reset the
-      // barrier state so that later solves start clean
+    int32_t done = 0;
+    const mgrit_status st = mgrit_solve_advance(h, &done);
+    if (st != MGRIT_OK) {
       (void)hipStreamSynchronize(h->stream);
-      (void)hipMemset(h->gsync, 0, sizeof(GridSync));
-      return fail(h, MGRIT_EDEVICE, "coarse-level grid barrier timed out");
-    default: break;
+      ss.active = false;
+      return st;
+    }
   }
-  if (u_out) {
-    HIPCHK(h, run_fine(h, MGRIT_PROF_FINAL, MODE_FINAL_F, L0.c[cur], nullptr, nullptr, u_out));
-  }
-  if (u_final) {
-    HIPCHK(h, hipMemcpyAsync(u_final, L0.c[cur] + nc * (int64_t)nx, nx * sizeof(double), hipMemcpyDeviceToDevice,
-                             h->stream));
-  }
+  ss.active = false;
   HIPCHK(h, hipStreamSynchronize(h->stream));
   harvest_events(h);
   if (stats) {
+    const auto &hc = ss.hc;
     stats->iterations = hc.it;
     stats->res0 = hc.res0;
     stats->res_final = hc.rho;
-    stats->conv_factor = prev > 0 ? hc.rho / prev : NAN;
-    stats->res_history_len = std::min(hist_len, std::max(stats->res_history_cap, 0));
-    stats->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    stats->conv_factor = ss.prev > 0 ? hc.rho / ss.prev : NAN;
+    const int len = (int)ss.hist.size();
+    if (stats->res_history)
+      for (int i = 0; i < std::min(len, stats->res_history_cap); ++i) stats->res_history[i] = ss.hist[i];
+    stats->res_history_len = std::min(len, std::max(stats->res_history_cap, 0));
+    stats->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - ss.t0).count();
   }
-  return status;
+  return ss.status;
+}
+
+mgrit_status mgrit_solve(mgrit_handle *h, const double *u0, const double *v_init, double *u_out, double *u_final,
+                         mgrit_stats *stats) {
+  const mgrit_status st = mgrit_solve_start(h, u0, v_init, u_out, u_final);
+  if (st != MGRIT_OK) return st;
+  return mgrit_solve_finish(h, stats);
+}
+
+mgrit_status mgrit_workspace_bytes(const mgrit_problem *P, const mgrit_options *O, uint64_t *bytes) {
+  if (!P || !O || !bytes) return MGRIT_EINVAL;
+  std::vector<int64_t> nts;
+  std::vector<int> ms;
+  std::string err;
+  if (P->nx < 1 || P->nt < 1 || O->max_levels < 2 || O->max_levels > MGRIT_MAX_LEVELS ||
+      !level_hierarchy(*P, *O, nts, ms, err))
+    return MGRIT_EINVAL;
+  uint64_t n = 0;
+  for (size_t l = 0; l + 1 < nts.size(); ++l) {
+    const uint64_t nc = (uint64_t)(nts[l] / ms[l]);
+    n += (2 * (nc + 1) + nc) * (uint64_t)P->nx;  // two C-point arrays and the residual
+  }
+  n += (uint64_t)std::max<int64_t>(P->nt, 1) * 64;  // norm partials (bound)
+  *bytes = n * sizeof(double) + (uint64_t)nts.size() * (2 * RTAB_ALL * KMAX * KMAX * sizeof(double) + 4096);
+  return MGRIT_OK;
 }
 
 mgrit_status mgrit_residual(mgrit_handle *h, const double *u, double *r, double *norm2) {

@@ -36,7 +36,8 @@ class Problem(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("max_levels", ctypes.c_int32), ("m", ctypes.c_int32 * (MAX_LEVELS - 1)),
                 ("min_coarse_nt", ctypes.c_int32), ("nu", ctypes.c_int32), ("cg_kind", ctypes.c_int32),
-                ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("diverge_factor", ctypes.c_double)]
+                ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("diverge_factor", ctypes.c_double),
+                ("coarse_launch", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -59,7 +60,8 @@ class Profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64 * len(PROF_PHASES)), ("total_ms", ctypes.c_double * len(PROF_PHASES))]
 
 
-EXPORTED = ["mgrit_setup", "mgrit_solve", "mgrit_residual", "mgrit_sequential", "mgrit_apply_step",
+EXPORTED = ["mgrit_setup", "mgrit_solve", "mgrit_solve_start", "mgrit_solve_advance", "mgrit_solve_finish",
+            "mgrit_workspace_bytes", "mgrit_residual", "mgrit_sequential", "mgrit_apply_step",
             "mgrit_num_levels", "mgrit_level_info", "mgrit_lfa_rho", "mgrit_profile_enable",
             "mgrit_profile_read", "mgrit_status_string", "mgrit_last_error", "mgrit_destroy"]
 
@@ -79,6 +81,11 @@ def lib():
         vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
         L.mgrit_setup.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options), vp, ctypes.POINTER(vp)]
         L.mgrit_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(Stats)]
+        L.mgrit_solve_start.argtypes = [vp, vp, vp, vp, vp]
+        L.mgrit_solve_advance.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+        L.mgrit_solve_finish.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.mgrit_workspace_bytes.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options),
+                                            ctypes.POINTER(ctypes.c_uint64)]
         L.mgrit_residual.argtypes = [vp, vp, vp, dp]
         L.mgrit_sequential.argtypes = [vp, vp, vp]
         L.mgrit_apply_step.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_int64, ctypes.c_int32]
@@ -94,7 +101,8 @@ def lib():
         L.mgrit_last_error.restype = ctypes.c_char_p
         L.mgrit_destroy.argtypes = [vp]
         L.mgrit_destroy.restype = None
-        for name in ("mgrit_setup", "mgrit_solve", "mgrit_residual", "mgrit_sequential", "mgrit_apply_step",
+        for name in ("mgrit_setup", "mgrit_solve", "mgrit_solve_start", "mgrit_solve_advance", "mgrit_solve_finish",
+                     "mgrit_workspace_bytes", "mgrit_residual", "mgrit_sequential", "mgrit_apply_step",
                      "mgrit_level_info", "mgrit_lfa_rho", "mgrit_profile_enable", "mgrit_profile_read"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -107,7 +115,7 @@ def make_problem(nx, nt, cfl, p, kind="erk", q=None, velocity=1.0, x_lo=-1.0, x_
 
 
 def make_options(m, max_levels=2, min_coarse_nt=0, nu=1, coarse="sl_corrected", rtol=1e-10, max_iter=30,
-                 diverge_factor=1e8):
+                 diverge_factor=1e8, coarse_launch=0):
     o = Options()
     o.max_levels = max_levels
     ms = list(m) if isinstance(m, (list, tuple)) else [m]
@@ -119,7 +127,17 @@ def make_options(m, max_levels=2, min_coarse_nt=0, nu=1, coarse="sl_corrected", 
     o.rtol = rtol
     o.max_iter = max_iter
     o.diverge_factor = diverge_factor
+    o.coarse_launch = coarse_launch
     return o
+
+
+def workspace_bytes(problem, options):
+    """Device memory a handle of (problem, options) allocates (host-only query)."""
+    n = ctypes.c_uint64()
+    st = lib().mgrit_workspace_bytes(ctypes.byref(problem), ctypes.byref(options), ctypes.byref(n))
+    if st != OK:
+        raise MgritError(st, "workspace_bytes")
+    return n.value
 
 
 def lfa_rho(problem, options):
@@ -190,6 +208,30 @@ class Solver:
         stats.res_history_cap = history_cap
         st = lib().mgrit_solve(self.h, _ptr(u0, (nx,)), _ptr(v_init, (nt + 1, nx)), _ptr(u_out, (nt + 1, nx)),
                                _ptr(u_final, (nx,)), ctypes.byref(stats))
+        self._check(st, allow)
+        return dict(status=st, iterations=stats.iterations, res0=stats.res0, res_final=stats.res_final,
+                    conv_factor=stats.conv_factor, res_history=list(hist[:stats.res_history_len]),
+                    t_solve_s=stats.t_solve_s)
+
+    # the same solve in steps (mgrit_solve_start / _advance / _finish)
+    def solve_start(self, u0, v_init=None, u_out=None, u_final=None):
+        nx, nt = self.nx, self.nt
+        self._keep = (u0, v_init, u_out, u_final)  # the device buffers must outlive the solve
+        self._check(lib().mgrit_solve_start(self.h, _ptr(u0, (nx,)), _ptr(v_init, (nt + 1, nx)),
+                                            _ptr(u_out, (nt + 1, nx)), _ptr(u_final, (nx,))))
+
+    def solve_advance(self):
+        done = ctypes.c_int32()
+        self._check(lib().mgrit_solve_advance(self.h, ctypes.byref(done)))
+        return bool(done.value)
+
+    def solve_finish(self, history_cap=128, allow=(OK, ENOTCONVERGED)):
+        hist = (ctypes.c_double * history_cap)()
+        stats = Stats()
+        stats.res_history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+        stats.res_history_cap = history_cap
+        st = lib().mgrit_solve_finish(self.h, ctypes.byref(stats))
+        self._keep = None
         self._check(st, allow)
         return dict(status=st, iterations=stats.iterations, res0=stats.res0, res_final=stats.res_final,
                     conv_factor=stats.conv_factor, res_history=list(hist[:stats.res_history_len]),

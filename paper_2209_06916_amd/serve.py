@@ -1,0 +1,157 @@
+"""Request loop that keeps many independent advection solves in flight on one GPU.
+
+Each request is one MGRIT solve (its own problem, options and initial data,
+zero initial iterate).  Requests are admitted in arrival order while the
+device memory of the in-flight ones (the handle's workspace, u0 and the
+final-time row) stays within a budget.  Every admitted request gets its own
+handle and HIP stream and is advanced one MGRIT iteration at a time
+(mgrit_solve_advance never blocks), so the kernels of all in-flight solves
+overlap on the GPU and a request that finishes makes room for the next one
+at once (continuous batching).  The coarse levels of a single solve occupy
+only a few compute units, which is what concurrency recovers.
+
+Handles of finished requests are destroyed only when nothing is in flight:
+freeing device memory synchronises the device.  Every step of every solve
+runs in the HIP library; this module only schedules.
+"""
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import mgrit
+
+
+@dataclass
+class Request:
+    """One solve: u_t + u_x = 0 on [-1, 1) with the given mesh, scheme and MGRIT options."""
+    nx: int
+    nt: int
+    p: int
+    c: float
+    m: int
+    u0: np.ndarray
+    kind: str = "erk"
+    q: int = None
+    min_coarse_nt: int = 8
+    max_levels: int = 16
+    arrival: float = 0.0  # seconds after the start of the run
+    tag: object = None
+
+    def problem(self):
+        return mgrit.make_problem(self.nx, self.nt, self.c, self.p, self.kind, self.q)
+
+    def options(self):
+        return mgrit.make_options([self.m], max_levels=self.max_levels, min_coarse_nt=self.min_coarse_nt,
+                                  coarse_launch=1)
+
+
+@dataclass
+class Result:
+    tag: object
+    status: int
+    iterations: int
+    u_final: np.ndarray
+    t_arrival: float
+    t_admit: float
+    t_done: float
+    dof: int = 0
+    res_history: list = field(default_factory=list)
+
+    @property
+    def latency(self):
+        return self.t_done - self.t_arrival
+
+
+class Server:
+    """Continuous-batching request loop.
+
+    budget_bytes bounds the device memory of the requests in flight;
+    max_inflight bounds their number (one HIP stream each)."""
+
+    def __init__(self, budget_bytes=64 << 30, max_inflight=16, device="cuda:0"):
+        self.budget = int(budget_bytes)
+        self.max_inflight = int(max_inflight)
+        self.device = torch.device(device)
+
+    @staticmethod
+    def footprint(req):
+        return mgrit.workspace_bytes(req.problem(), req.options()) + 2 * req.nx * 8
+
+    def run(self, requests, realtime=True):
+        """Serve `requests` (arrival times honoured when realtime); returns one
+        Result per request, in completion order."""
+        pending = sorted(requests, key=lambda r: r.arrival)
+        for r in pending:
+            if self.footprint(r) > self.budget:
+                raise ValueError(f"request {r.tag} needs more than the whole budget")
+        active, results, graveyard = [], [], []
+        used = 0
+        t0 = time.perf_counter()
+        while pending or active:
+            now = time.perf_counter() - t0
+            # admit in arrival order while memory and slots allow
+            while pending and len(active) < self.max_inflight and (not realtime or pending[0].arrival <= now):
+                req = pending[0]
+                need = self.footprint(req)
+                if used + need > self.budget:
+                    break
+                pending.pop(0)
+                stream = torch.cuda.Stream(device=self.device)
+                with torch.cuda.stream(stream):
+                    u0 = torch.from_numpy(np.ascontiguousarray(req.u0, dtype=np.float64)).to(self.device,
+                                                                                            non_blocking=False)
+                    ufin = torch.empty(req.nx, dtype=torch.float64, device=self.device)
+                solver = mgrit.Solver(req.problem(), req.options(), stream=stream)
+                solver.solve_start(u0, None, None, ufin)
+                used += need
+                active.append(dict(req=req, solver=solver, stream=stream, u0=u0, ufin=ufin, need=need,
+                                   t_admit=time.perf_counter() - t0))
+            # advance every in-flight solve by at most one iteration
+            progressed = False
+            for a in list(active):
+                if a["solver"].solve_advance():
+                    info = a["solver"].solve_finish()
+                    a["stream"].synchronize()
+                    req = a["req"]
+                    results.append(Result(tag=req.tag, status=info["status"], iterations=info["iterations"],
+                                          u_final=a["ufin"].cpu().numpy(), t_arrival=req.arrival,
+                                          t_admit=a["t_admit"], t_done=time.perf_counter() - t0,
+                                          dof=req.nx * req.nt, res_history=info["res_history"]))
+                    used -= a["need"]
+                    active.remove(a)
+                    graveyard.append(a)
+                    progressed = True
+            if not active and graveyard:
+                for a in graveyard:
+                    a["solver"].close()
+                graveyard.clear()
+            if not progressed and not active and pending and realtime:
+                time.sleep(min(1e-3, max(0.0, pending[0].arrival - (time.perf_counter() - t0))))
+        for a in graveyard:
+            a["solver"].close()
+        return results
+
+
+def synthetic_stream(n, seed, rate_hz, sizes=(256, 512, 1024, 2048, 4096, 8192), orders=(1, 3, 5), ms=(4, 8, 16),
+                     cfl=(0.5, 0.9)):
+    """Seeded request mix: nx, nt drawn from `sizes`, upwind order p from
+    `orders` with ERKp, CFL uniform in `cfl`, coarsening factor from `ms`,
+    u0 a seeded 16-mode Fourier sum, Poisson arrivals at `rate_hz`."""
+    from . import inputs
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    reqs = []
+    for i in range(n):
+        nx = int(rng.choice(sizes))
+        nt = int(rng.choice(sizes))
+        p = int(rng.choice(orders))
+        c = float(rng.uniform(*cfl))
+        m = int(rng.choice(ms))
+        while nt % m:
+            m //= 2
+        t += rng.exponential(1.0 / rate_hz) if rate_hz > 0 else 0.0
+        reqs.append(Request(nx=nx, nt=nt, p=p, c=c, m=m, u0=inputs.u0_fourier(nx, seed * 100003 + i), arrival=t,
+                            tag=i))
+    return reqs
