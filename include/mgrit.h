@@ -148,6 +148,18 @@ typedef struct mgrit_handle mgrit_handle;
 mgrit_status mgrit_setup(const mgrit_problem *problem, const mgrit_options *options,
                          void *hip_stream, mgrit_handle **out);
 
+/* As mgrit_setup, with the handle's device workspace carved from the
+ * caller's buffer instead of allocated: workspace_dev must be 256-byte
+ * aligned and hold workspace_bytes >= mgrit_workspace_bytes(problem, options)
+ * bytes; it stays owned by the caller, must stay valid until mgrit_destroy,
+ * and must not be used by anything else meanwhile.  The tables are uploaded
+ * on hip_stream.  MGRIT_EINVAL for a null, misaligned or too small
+ * workspace; otherwise as mgrit_setup.  Neither this call nor mgrit_destroy
+ * frees device memory, so neither waits for other work on the device: the
+ * form for request loops that keep many solves in flight. */
+mgrit_status mgrit_setup_ws(const mgrit_problem *problem, const mgrit_options *options, void *hip_stream,
+                            void *workspace_dev, uint64_t workspace_bytes, mgrit_handle **out);
+
 /* Solve the one-step system u_{n+1} = Phi u_n, u_0 = u0 (eq. one-step-general)
  * with MGRIT.
  *   u0_dev      [nx], required.
@@ -176,9 +188,10 @@ mgrit_status mgrit_solve_start(mgrit_handle *h, const double *u0_dev, const doub
 mgrit_status mgrit_solve_advance(mgrit_handle *h, int32_t *done);
 mgrit_status mgrit_solve_finish(mgrit_handle *h, mgrit_stats *stats);
 
-/* Host-only: device memory (bytes) the handle of (problem, options) allocates
- * (C-point and residual arrays of every level, norm partials, tables); the
- * caller's own buffers (u0, v_init, outputs) are not included. */
+/* Host-only: an upper bound on the device memory (bytes) the handle of
+ * (problem, options) allocates, in one piece, at mgrit_setup (C-point and
+ * residual arrays of every level, norm partials, tables); the caller's own
+ * buffers (u0, v_init, outputs) are not included. */
 mgrit_status mgrit_workspace_bytes(const mgrit_problem *problem, const mgrit_options *options, uint64_t *bytes);
 
 /* Space-time residual of an arbitrary iterate u_dev [nt+1][nx] of the fine

@@ -11,7 +11,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -301,24 +303,36 @@ std::vector<cld> poly_roots(const std::vector<ld> &c) {
       p = p * z + mon[i];
     }
   };
+  // |p(z)| at or below this bound is rounding noise of the Horner evaluation
+  auto noise = [&](cld z) {
+    const ld az = std::abs(z);
+    ld s = std::fabs(std::abs(mon[n])), t = 1;
+    for (int i = n - 1; i >= 0; --i) s = s * az + std::abs(mon[i]), t = t * az + 1;
+    return 8 * (ld)std::numeric_limits<ld>::epsilon() * (s + t) * (2 * n + 1);
+  };
   const ld rad = std::pow(std::abs(mon[0]) + 1e-300L, 1.0L / n);
   std::vector<cld> z(n);
+  std::vector<char> done(n, 0);
   for (int k = 0; k < n; ++k) z[k] = std::polar(rad * (1 + 0.1L * k), (ld)(2 * M_PI * k / n + 0.4));
   for (int it = 0; it < 500; ++it) {
-    ld maxstep = 0;
+    int live = 0;
     for (int k = 0; k < n; ++k) {
+      if (done[k]) continue;
       cld p, dp;
       eval(z[k], p, dp);
-      if (p == cld(0)) continue;
+      if (std::abs(p) <= noise(z[k])) {
+        done[k] = 1;
+        continue;
+      }
+      ++live;
       const cld ratio = p / dp;
       cld sum = 0;
       for (int j = 0; j < n; ++j)
         if (j != k) sum += 1.0L / (z[k] - z[j]);
       const cld step = ratio / (1.0L - ratio * sum);
       z[k] -= step;
-      maxstep = std::max(maxstep, std::abs(step) / (1 + std::abs(z[k])));
     }
-    if (maxstep < 1e-19L) break;
+    if (live == 0) break;
   }
   for (int k = 0; k < n; ++k)  // Newton polish
     for (int it = 0; it < 3; ++it) {
@@ -617,6 +631,10 @@ struct mgrit_handle {
   size_t cv_lds = 0;
   int64_t cv_grid = 0;
   GridSync *gsync = nullptr;
+  char *arena = nullptr;       // every device buffer of the handle
+  size_t arena_bytes = 0;
+  bool owns_arena = false;     // false: the caller's workspace (mgrit_setup_ws)
+  char *host_arena = nullptr;  // pinned words: normsum_host, ctl_host
   std::string err;
   // the solve in progress (mgrit_solve_start .. mgrit_solve_finish)
   struct {
@@ -654,6 +672,42 @@ mgrit_status hipfail(mgrit_handle *h, hipError_t e, const char *where) {
   } while (0)
 
 thread_local std::string g_setup_error;
+
+// Pinned, mapped, coherent host memory in 256-byte slots, one per handle.
+// Blocks are taken from the runtime 64 KiB at a time and kept for the life
+// of the process, so creating and destroying handles never frees pinned
+// memory (which would synchronise the device).
+std::mutex g_pinned_mu;
+std::vector<std::pair<char *, char *>> g_pinned_free;  // (host, device) addresses
+std::map<char *, char *> g_pinned_dev;                 // host slot -> device address
+
+bool pinned_slot_take(char *&host, char *&dev) {
+  std::lock_guard<std::mutex> lk(g_pinned_mu);
+  if (g_pinned_free.empty()) {
+    const size_t block = 64 << 10;
+    char *hb = nullptr, *db = nullptr;
+    if (hipHostMalloc((void **)&hb, block, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) return false;
+    if (hipHostGetDevicePointer((void **)&db, hb, 0) != hipSuccess) return false;
+    for (size_t o = block; o > 0; o -= 256) g_pinned_free.push_back({hb + o - 256, db + o - 256});
+  }
+  host = g_pinned_free.back().first;
+  dev = g_pinned_free.back().second;
+  g_pinned_free.pop_back();
+  g_pinned_dev[host] = dev;
+  std::memset(host, 0, 256);
+  return true;
+}
+
+void pinned_slot_give(char *host) {
+  std::lock_guard<std::mutex> lk(g_pinned_mu);
+  auto it = g_pinned_dev.find(host);
+  if (it == g_pinned_dev.end()) return;
+  g_pinned_free.push_back({host, it->second});
+  g_pinned_dev.erase(it);
+}
+
+mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *stream, void *ws, uint64_t ws_bytes,
+                        mgrit_handle **out);
 
 // Build the StepOp of a solve-free or solve-carrying operator.
 bool attach_solve(StepOp &op, const std::map<int, ld> &taps, const Layout &lay, std::vector<double> &tabs,
@@ -719,11 +773,48 @@ std::complex<double> upwind_symbol(const FineInfo &fi, double om) {
 }
 
 // ERK stability: max over omega of |R(-c Lhat(omega))| <= 1 (Sec. 4.3, Table 2).
+// R is the degree-s polynomial sum_j beta_j z^j of an explicit tableau, so
+// each sample is one sincos, a few complex multiply-adds for the symbol and
+// a Horner pass, written on real pairs.
 bool erk_stable(const FineInfo &fi, double c) {
   const int N = 16384;
+  const int s = fi.tab.s;
+  const std::vector<ld> beta = rk_series(fi.tab, s);
+  const int nt = fi.l + fi.r + 1;
+  // e^{i om_k} by rotation from an exact value every 64 samples
+  const double cd = std::cos(M_PI / N), sd = std::sin(M_PI / N);
+  double c1 = 1, s1 = 0;
   for (int k = 1; k <= N; ++k) {
-    const double om = M_PI * k / N;
-    if (std::abs(rk_R(fi.tab, -c * upwind_symbol(fi, om))) > 1 + 1e-10) return false;
+    if (k % 64 == 0) {
+      c1 = std::cos(M_PI * k / N);
+      s1 = std::sin(M_PI * k / N);
+    } else {
+      const double nr = c1 * cd - s1 * sd;
+      s1 = c1 * sd + s1 * cd;
+      c1 = nr;
+    }
+    // z = -c sum_j w_j e^{i j om}, j = -l..r, starting from e^{-i l om}
+    double er = 1, ei = 0;
+    for (int j = 0; j < fi.l; ++j) {
+      const double nr = er * c1 + ei * s1;
+      ei = ei * c1 - er * s1;
+      er = nr;
+    }
+    double zr = 0, zi = 0;
+    for (int t = 0; t < nt; ++t) {
+      zr -= c * fi.w[t] * er;
+      zi -= c * fi.w[t] * ei;
+      const double nr = er * c1 - ei * s1;
+      ei = er * s1 + ei * c1;
+      er = nr;
+    }
+    double ar = (double)beta[s], ai = 0;
+    for (int j = s - 1; j >= 0; --j) {
+      const double nr = ar * zr - ai * zi + (double)beta[j];
+      ai = ar * zi + ai * zr;
+      ar = nr;
+    }
+    if (std::sqrt(ar * ar + ai * ai) > 1 + 1e-10) return false;
   }
   return true;
 }
@@ -819,19 +910,8 @@ const char *mgrit_last_error(const mgrit_handle *h) {
 
 void mgrit_destroy(mgrit_handle *h) {
   if (!h) return;
-  for (auto &L : h->lv) {
-    if (L.tabs) (void)hipFree(L.tabs);
-    if (L.desc) (void)hipFree(L.desc);
-    for (int i = 0; i < 2; ++i)
-      if (L.c[i]) (void)hipFree(L.c[i]);
-    if (L.r) (void)hipFree(L.r);
-  }
-  if (h->normpart) (void)hipFree(h->normpart);
-  if (h->normsum) (void)hipFree(h->normsum);
-  if (h->normsum_host) (void)hipHostFree(h->normsum_host);
-  if (h->ctl) (void)hipFree(h->ctl);
-  if (h->gsync) (void)hipFree(h->gsync);
-  if (h->ctl_host) (void)hipHostFree(h->ctl_host);
+  if (h->arena && h->owns_arena) (void)hipFree(h->arena);
+  if (h->host_arena) pinned_slot_give(h->host_arena);
   if (h->ctl_ev) (void)hipEventDestroy(h->ctl_ev);
   for (auto &pe : h->ev_pending) {
     (void)hipEventDestroy(pe.second.first);
@@ -842,6 +922,25 @@ void mgrit_destroy(mgrit_handle *h) {
 }
 
 mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *stream, mgrit_handle **out) {
+  return setup_impl(P, O, stream, nullptr, 0, out);
+}
+
+mgrit_status mgrit_setup_ws(const mgrit_problem *P, const mgrit_options *O, void *stream, void *workspace,
+                            uint64_t workspace_bytes, mgrit_handle **out) {
+  if (!workspace) {
+    g_setup_error = "workspace is required";
+    if (out) *out = nullptr;
+    return MGRIT_EINVAL;
+  }
+  return setup_impl(P, O, stream, workspace, workspace_bytes, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *stream, void *ws, uint64_t ws_bytes,
+                        mgrit_handle **out) {
   g_setup_error.clear();
   if (out) *out = nullptr;
   if (!P || !O || !out) {
@@ -990,69 +1089,15 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
     }
   }
 
-  // ---- device data
-  auto dalloc = [&](double **p, size_t n) -> hipError_t { return hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(double)); };
   // Every layout chosen above needs at most LDS_LIMIT bytes; the attribute is
   // per kernel and process-wide, so it is always raised to that limit.
   if (hipError_t e = configure_kernels(LDS_LIMIT)) {
     mgrit_destroy(h);
     return bad(MGRIT_EDEVICE, std::string("configure: ") + hipGetErrorString(e));
   }
-  for (int l = 0; l < nlev; ++l) {
-    Level &Lv = h->lv[l];
-    if (!tabs[l].empty()) {
-      if (dalloc(&Lv.tabs, tabs[l].size()) != hipSuccess) {
-        mgrit_destroy(h);
-        return bad(MGRIT_ENOMEM, "tables");
-      }
-      if (hipMemcpy(Lv.tabs, tabs[l].data(), tabs[l].size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
-        mgrit_destroy(h);
-        return bad(MGRIT_EDEVICE, "table upload");
-      }
-    }
-    if (offs[l].size() == 2) {
-      Lv.op.fw.tab = offs[l][0] == (size_t)-1 ? nullptr : Lv.tabs + offs[l][0];
-      Lv.op.bw.tab = offs[l][1] == (size_t)-1 ? nullptr : Lv.tabs + offs[l][1];
-    }
-    {
-      LevelDesc hd{Lv.op, Lv.lay};
-      if (hipMalloc((void **)&Lv.desc, sizeof(LevelDesc)) != hipSuccess) {
-        mgrit_destroy(h);
-        return bad(MGRIT_ENOMEM, "level descriptor");
-      }
-      if (hipMemcpy(Lv.desc, &hd, sizeof(LevelDesc), hipMemcpyHostToDevice) != hipSuccess) {
-        mgrit_destroy(h);
-        return bad(MGRIT_EDEVICE, "descriptor upload");
-      }
-    }
-    if (l < nlev - 1) {
-      const int64_t nc = Lv.nt / Lv.m;
-      for (int i = 0; i < 2; ++i)
-        if (dalloc(&Lv.c[i], (size_t)(nc + 1) * nx) != hipSuccess) {
-          mgrit_destroy(h);
-          return bad(MGRIT_ENOMEM, "C-point arrays");
-        }
-      if (dalloc(&Lv.r, (size_t)nc * nx) != hipSuccess) {
-        mgrit_destroy(h);
-        return bad(MGRIT_ENOMEM, "residual arrays");
-      }
-    }
-  }
-  h->normpart_len = std::max<int64_t>(P->nt, 1);
-  if (h->lv[0].tiles) h->normpart_len = std::max<int64_t>(h->normpart_len, (P->nt / ms[0]) * h->lv[0].tg.ntiles);
-  if (dalloc(&h->normpart, h->normpart_len) != hipSuccess || dalloc(&h->normsum, 1) != hipSuccess ||
-      hipHostMalloc((void **)&h->normsum_host, sizeof(double)) != hipSuccess ||
-      hipMalloc((void **)&h->ctl, sizeof(SolveCtl)) != hipSuccess ||
-      hipHostMalloc((void **)&h->ctl_host, sizeof(SolveCtl), hipHostMallocMapped | hipHostMallocCoherent) !=
-          hipSuccess ||
-      hipHostGetDevicePointer((void **)&h->ctl_host_dev, h->ctl_host, 0) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ctl_ev, hipEventDisableTiming) != hipSuccess) {
-    mgrit_destroy(h);
-    return bad(MGRIT_ENOMEM, "norm buffers");
-  }
   // Persistent coarse V-cycle: every coarse level takes the lean kernel, the
   // tables of all of them fit in LDS beside the vector, and the largest
-  // level's intervals can all be resident at once (cooperative launch).
+  // level's intervals can all be resident at once.
   if (nlev >= 2 && O->coarse_launch == 0 && env_int("MGRIT_NO_PERSISTENT", 0) == 0) {
     bool all_lean = true;
     for (int l = 1; l < nlev; ++l) all_lean = all_lean && lean_slc_applies(h->lv[l].op, h->lv[l].lay);
@@ -1065,19 +1110,107 @@ mgrit_status mgrit_setup(const mgrit_problem *P, const mgrit_options *O, void *s
     }
     if (lds > 0 && longest <= 256 && grid <= MAX_PERSISTENT_GRID &&
         grid <= coarse_vcycle_max_grid(h->lv[1].op, h->lv[1].lay, lds)) {
-      if (hipMalloc((void **)&h->gsync, sizeof(GridSync)) != hipSuccess ||
-          hipMemset(h->gsync, 0, sizeof(GridSync)) != hipSuccess) {
-        mgrit_destroy(h);
-        return bad(MGRIT_ENOMEM, "grid barrier state");
-      }
       h->cv_ok = true;
       h->cv_lds = lds;
       h->cv_grid = grid;
     }
   }
+
+  // ---- device data: one allocation carved into 256-byte aligned pieces.
+  // Its head (scan tables, level descriptors, grid-barrier state) is
+  // uploaded in one copy; the iterate, residual and norm buffers follow.
+  auto al = [](size_t bytes) { return (bytes + 255) & ~(size_t)255; };
+  const size_t none = (size_t)-1;
+  std::vector<size_t> o_tab(nlev, none), o_desc(nlev, none), o_c0(nlev, none), o_c1(nlev, none), o_r(nlev, none);
+  size_t off = 0;
+  for (int l = 0; l < nlev; ++l)
+    if (!tabs[l].empty()) o_tab[l] = off, off += al(tabs[l].size() * sizeof(double));
+  for (int l = 0; l < nlev; ++l) o_desc[l] = off, off += al(sizeof(LevelDesc));
+  size_t o_gs = none;
+  if (h->cv_ok) o_gs = off, off += al(sizeof(GridSync));
+  const size_t head = off;
+  for (int l = 0; l + 1 < nlev; ++l) {
+    const size_t rows = (size_t)(h->lv[l].nt / h->lv[l].m);
+    o_c0[l] = off, off += al((rows + 1) * nx * sizeof(double));
+    o_c1[l] = off, off += al((rows + 1) * nx * sizeof(double));
+    o_r[l] = off, off += al(std::max<size_t>(rows * nx, 1) * sizeof(double));
+  }
+  h->normpart_len = std::max<int64_t>(P->nt, 1);
+  if (h->lv[0].tiles) h->normpart_len = std::max<int64_t>(h->normpart_len, (P->nt / ms[0]) * h->lv[0].tg.ntiles);
+  const size_t o_np = off;
+  off += al(h->normpart_len * sizeof(double));
+  const size_t o_ns = off;
+  off += al(sizeof(double));
+  const size_t o_ctl = off;
+  off += al(sizeof(SolveCtl));
+  if (ws) {
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) {
+      mgrit_destroy(h);
+      return bad(MGRIT_EINVAL, "workspace must be 256-byte aligned");
+    }
+    if (ws_bytes < off) {
+      mgrit_destroy(h);
+      return bad(MGRIT_EINVAL, "workspace too small: " + std::to_string(off) + " bytes needed");
+    }
+    h->arena = (char *)ws;
+    h->owns_arena = false;
+  } else {
+    if (hipMalloc((void **)&h->arena, off) != hipSuccess) {
+      mgrit_destroy(h);
+      return bad(MGRIT_ENOMEM, "device workspace");
+    }
+    h->owns_arena = true;
+  }
+  h->arena_bytes = off;
+  char *base = h->arena;
+  std::vector<char> up(head, 0);
+  for (int l = 0; l < nlev; ++l) {
+    Level &Lv = h->lv[l];
+    if (o_tab[l] != none) {
+      Lv.tabs = (double *)(base + o_tab[l]);
+      std::memcpy(up.data() + o_tab[l], tabs[l].data(), tabs[l].size() * sizeof(double));
+    }
+    if (offs[l].size() == 2) {
+      Lv.op.fw.tab = offs[l][0] == none ? nullptr : Lv.tabs + offs[l][0];
+      Lv.op.bw.tab = offs[l][1] == none ? nullptr : Lv.tabs + offs[l][1];
+    }
+    Lv.desc = (LevelDesc *)(base + o_desc[l]);
+    const LevelDesc hd{Lv.op, Lv.lay};
+    std::memcpy(up.data() + o_desc[l], &hd, sizeof(LevelDesc));
+    if (o_c0[l] != none) {
+      Lv.c[0] = (double *)(base + o_c0[l]);
+      Lv.c[1] = (double *)(base + o_c1[l]);
+      Lv.r = (double *)(base + o_r[l]);
+    }
+  }
+  if (o_gs != none) h->gsync = (GridSync *)(base + o_gs);  // zero from the upload
+  h->normpart = (double *)(base + o_np);
+  h->normsum = (double *)(base + o_ns);
+  h->ctl = (SolveCtl *)(base + o_ctl);
+  // on the handle's stream, where all of its work goes; the source is
+  // pageable, so the call returns once it has been staged
+  if (hipMemcpyAsync(base, up.data(), head, hipMemcpyHostToDevice, h->stream) != hipSuccess) {
+    mgrit_destroy(h);
+    return bad(MGRIT_EDEVICE, "table upload");
+  }
+  // pinned host words: the norm read back by mgrit_residual and the mapped,
+  // coherent copy of the iteration state
+  char *slot_dev = nullptr;
+  if (!pinned_slot_take(h->host_arena, slot_dev) ||
+      hipEventCreateWithFlags(&h->ctl_ev, hipEventDisableTiming) != hipSuccess) {
+    mgrit_destroy(h);
+    return bad(MGRIT_ENOMEM, "pinned host words");
+  }
+  h->normsum_host = (double *)h->host_arena;
+  h->ctl_host = (SolveCtl *)(h->host_arena + 128);
+  h->ctl_host_dev = (SolveCtl *)(slot_dev + 128);
   *out = h;
   return MGRIT_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int32_t mgrit_num_levels(const mgrit_handle *h) { return h ? (int32_t)h->lv.size() : 0; }
 
@@ -1452,7 +1585,11 @@ mgrit_status mgrit_workspace_bytes(const mgrit_problem *P, const mgrit_options *
     n += (2 * (nc + 1) + nc) * (uint64_t)P->nx;  // two C-point arrays and the residual
   }
   n += (uint64_t)std::max<int64_t>(P->nt, 1) * 64;  // norm partials (bound)
-  *bytes = n * sizeof(double) + (uint64_t)nts.size() * (2 * RTAB_ALL * KMAX * KMAX * sizeof(double) + 4096);
+  // per level: scan tables, descriptor and the alignment of five pieces;
+  // once: the grid-barrier state and the alignment of the norm pieces
+  *bytes = n * sizeof(double) +
+           (uint64_t)nts.size() * (2 * RTAB_ALL * KMAX * KMAX * sizeof(double) + sizeof(LevelDesc) + 5 * 256) +
+           sizeof(GridSync) + 4 * 256 + sizeof(SolveCtl);
   return MGRIT_OK;
 }
 

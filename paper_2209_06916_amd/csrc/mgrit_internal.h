@@ -190,6 +190,7 @@ struct SolveCtl {
   int it;       // coarse-grid corrections performed so far
   int stop;     // StopCode
 };
+static_assert(sizeof(SolveCtl) <= 128, "the pinned host words hold SolveCtl in 128 bytes");
 struct StopRule {
   double rtol;
   double diverge_factor;  // <= 0: no growth test

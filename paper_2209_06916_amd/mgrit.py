@@ -60,7 +60,7 @@ class Profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64 * len(PROF_PHASES)), ("total_ms", ctypes.c_double * len(PROF_PHASES))]
 
 
-EXPORTED = ["mgrit_setup", "mgrit_solve", "mgrit_solve_start", "mgrit_solve_advance", "mgrit_solve_finish",
+EXPORTED = ["mgrit_setup", "mgrit_setup_ws", "mgrit_solve", "mgrit_solve_start", "mgrit_solve_advance", "mgrit_solve_finish",
             "mgrit_workspace_bytes", "mgrit_residual", "mgrit_sequential", "mgrit_apply_step",
             "mgrit_num_levels", "mgrit_level_info", "mgrit_lfa_rho", "mgrit_profile_enable",
             "mgrit_profile_read", "mgrit_status_string", "mgrit_last_error", "mgrit_destroy"]
@@ -80,6 +80,8 @@ def lib():
         L = ctypes.CDLL(_LIB_PATH)
         vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
         L.mgrit_setup.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options), vp, ctypes.POINTER(vp)]
+        L.mgrit_setup_ws.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options), vp, vp, ctypes.c_uint64,
+                                     ctypes.POINTER(vp)]
         L.mgrit_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(Stats)]
         L.mgrit_solve_start.argtypes = [vp, vp, vp, vp, vp]
         L.mgrit_solve_advance.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
@@ -101,7 +103,7 @@ def lib():
         L.mgrit_last_error.restype = ctypes.c_char_p
         L.mgrit_destroy.argtypes = [vp]
         L.mgrit_destroy.restype = None
-        for name in ("mgrit_setup", "mgrit_solve", "mgrit_solve_start", "mgrit_solve_advance", "mgrit_solve_finish",
+        for name in ("mgrit_setup", "mgrit_setup_ws", "mgrit_solve", "mgrit_solve_start", "mgrit_solve_advance", "mgrit_solve_finish",
                      "mgrit_workspace_bytes", "mgrit_residual", "mgrit_sequential", "mgrit_apply_step",
                      "mgrit_level_info", "mgrit_lfa_rho", "mgrit_profile_enable", "mgrit_profile_read"):
             getattr(L, name).restype = ctypes.c_int
@@ -161,14 +163,23 @@ def _ptr(t, shape=None):
 class Solver:
     """One mgrit_handle: a problem + options set up on the current device."""
 
-    def __init__(self, problem, options, stream=None):
+    def __init__(self, problem, options, stream=None, workspace=None):
+        """workspace: None (the handle allocates its own device memory) or a
+        device tensor of at least workspace_bytes(problem, options) bytes,
+        256-byte aligned, that the handle uses until close()."""
         self.problem, self.options = problem, options
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
         h = ctypes.c_void_p()
-        st = lib().mgrit_setup(ctypes.byref(problem), ctypes.byref(options), ctypes.c_void_p(stream.cuda_stream),
-                               ctypes.byref(h))
+        sp = ctypes.c_void_p(stream.cuda_stream)
+        if workspace is None:
+            st = lib().mgrit_setup(ctypes.byref(problem), ctypes.byref(options), sp, ctypes.byref(h))
+        else:
+            nbytes = workspace.numel() * workspace.element_size()
+            st = lib().mgrit_setup_ws(ctypes.byref(problem), ctypes.byref(options), sp,
+                                      ctypes.c_void_p(workspace.data_ptr()), nbytes, ctypes.byref(h))
+        self.workspace = workspace
         if st != OK:
             raise MgritError(st, lib().mgrit_last_error(None).decode())
         self.h = h
@@ -183,6 +194,7 @@ class Solver:
         if getattr(self, "h", None):
             lib().mgrit_destroy(self.h)
             self.h = None
+        self.workspace = None
 
     def __del__(self):
         try:

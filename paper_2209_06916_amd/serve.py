@@ -10,9 +10,10 @@ overlap on the GPU and a request that finishes makes room for the next one
 at once (continuous batching).  The coarse levels of a single solve occupy
 only a few compute units, which is what concurrency recovers.
 
-Handles of finished requests are destroyed only when nothing is in flight:
-freeing device memory synchronises the device.  Every step of every solve
-runs in the HIP library; this module only schedules.
+A handle's device workspace is a tensor from PyTorch's caching allocator,
+handed to mgrit_setup_ws, so admitting and retiring requests never calls
+hipMalloc or hipFree (hipFree would wait for every solve in flight).  Every
+step of every solve runs in the HIP library; this module only schedules.
 """
 import time
 from dataclasses import dataclass, field
@@ -74,10 +75,15 @@ class Server:
         self.budget = int(budget_bytes)
         self.max_inflight = int(max_inflight)
         self.device = torch.device(device)
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(self.max_inflight)]
+
+    @staticmethod
+    def workspace(req):
+        return mgrit.workspace_bytes(req.problem(), req.options())
 
     @staticmethod
     def footprint(req):
-        return mgrit.workspace_bytes(req.problem(), req.options()) + 2 * req.nx * 8
+        return Server.workspace(req) + 2 * req.nx * 8
 
     def run(self, requests, realtime=True):
         """Serve `requests` (arrival times honoured when realtime); returns one
@@ -86,7 +92,8 @@ class Server:
         for r in pending:
             if self.footprint(r) > self.budget:
                 raise ValueError(f"request {r.tag} needs more than the whole budget")
-        active, results, graveyard = [], [], []
+        active, results = [], []
+        free_streams = list(self.streams)
         used = 0
         t0 = time.perf_counter()
         while pending or active:
@@ -98,12 +105,13 @@ class Server:
                 if used + need > self.budget:
                     break
                 pending.pop(0)
-                stream = torch.cuda.Stream(device=self.device)
+                stream = free_streams.pop()
                 with torch.cuda.stream(stream):
                     u0 = torch.from_numpy(np.ascontiguousarray(req.u0, dtype=np.float64)).to(self.device,
                                                                                             non_blocking=False)
                     ufin = torch.empty(req.nx, dtype=torch.float64, device=self.device)
-                solver = mgrit.Solver(req.problem(), req.options(), stream=stream)
+                    ws = torch.empty(self.workspace(req), dtype=torch.uint8, device=self.device)
+                solver = mgrit.Solver(req.problem(), req.options(), stream=stream, workspace=ws)
                 solver.solve_start(u0, None, None, ufin)
                 used += need
                 active.append(dict(req=req, solver=solver, stream=stream, u0=u0, ufin=ufin, need=need,
@@ -119,18 +127,15 @@ class Server:
                                           u_final=a["ufin"].cpu().numpy(), t_arrival=req.arrival,
                                           t_admit=a["t_admit"], t_done=time.perf_counter() - t0,
                                           dof=req.nx * req.nt, res_history=info["res_history"]))
+                    # the stream is idle: the workspace goes back to the
+                    # caching allocator for the next request on any stream
+                    a["solver"].close()
                     used -= a["need"]
                     active.remove(a)
-                    graveyard.append(a)
+                    free_streams.append(a["stream"])
                     progressed = True
-            if not active and graveyard:
-                for a in graveyard:
-                    a["solver"].close()
-                graveyard.clear()
             if not progressed and not active and pending and realtime:
                 time.sleep(min(1e-3, max(0.0, pending[0].arrival - (time.perf_counter() - t0))))
-        for a in graveyard:
-            a["solver"].close()
         return results
 
 

@@ -88,3 +88,27 @@ def test_rediscretised_coarse_levels_accept_stable_explicit_steps():
     bad, _ = _setup_status(mgrit.make_problem(64, 64, 0.4, 3), mgrit.make_options([2, 2, 2], max_levels=4,
                                                                                 coarse="redisc"))
     assert bad == mgrit.EUNSTABLE
+
+
+def test_caller_workspace_setup_requires_a_workspace():
+    import ctypes
+    h = ctypes.c_void_p()
+    st = mgrit.lib().mgrit_setup_ws(ctypes.byref(mgrit.make_problem(64, 32, 0.5, 1)),
+                                    ctypes.byref(mgrit.make_options(4)), None, None, 1 << 20, ctypes.byref(h))
+    assert st == mgrit.EINVAL and not h.value
+    assert "workspace" in mgrit.lib().mgrit_last_error(None).decode()
+
+
+def test_workspace_bound_grows_with_the_hierarchy():
+    """The bound covers three nx-row arrays per coarse interval of every
+    non-coarsest level (two C-point copies and the residual)."""
+    pr = mgrit.make_problem(1024, 4096, 0.8, 3)
+    for ms in ([8], [4], [16]):
+        op = mgrit.make_options(ms, max_levels=16, min_coarse_nt=8)
+        b = mgrit.workspace_bytes(pr, op)
+        rows, nt = 0, 4096
+        m = ms[0]
+        while nt // m >= 8 and nt % m == 0:
+            rows += 3 * (nt // m) + 2
+            nt //= m
+        assert b >= rows * 1024 * 8

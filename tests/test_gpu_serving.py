@@ -72,3 +72,39 @@ def test_memory_budget_serialises_admission():
         t0 = tight[t].t_admit
         live = sum(fp[u] for u in tight if tight[u].t_admit <= t0 < tight[u].t_done)
         assert live <= one
+
+
+def test_caller_workspace_gives_the_same_solve():
+    """mgrit_setup_ws carves the handle's buffers from a caller tensor; the
+    solve is bitwise the one of a handle that allocates its own."""
+    _announce("setup_ws vs setup")
+    for nx, nt, p, m in [(1024, 512, 3, 8), (512, 768, 5, 4), (4096, 256, 1, 16)]:
+        pr = mgrit.make_problem(nx, nt, 0.8, p, "erk")
+        op = mgrit.make_options([m], max_levels=16, min_coarse_nt=8)
+        u0 = torch.from_numpy(inputs.u0_fourier(nx, nx + nt)).cuda()
+        outs = []
+        for use_ws in (False, True):
+            ws = torch.empty(mgrit.workspace_bytes(pr, op), dtype=torch.uint8, device="cuda") if use_ws else None
+            s = mgrit.Solver(pr, op, workspace=ws)
+            uf = torch.empty(nx, dtype=torch.float64, device="cuda")
+            info = s.solve(u0, u_final=uf)
+            torch.cuda.synchronize()
+            outs.append((info["iterations"], uf.cpu().numpy()))
+            s.close()
+        assert outs[0][0] == outs[1][0]
+        np.testing.assert_array_equal(outs[0][1], outs[1][1])
+
+
+def test_caller_workspace_is_checked():
+    _announce("setup_ws checks")
+    pr = mgrit.make_problem(1024, 512, 0.8, 3, "erk")
+    op = mgrit.make_options([8], max_levels=16, min_coarse_nt=8)
+    need = mgrit.workspace_bytes(pr, op)
+    small = torch.empty(4096, dtype=torch.uint8, device="cuda")
+    with pytest.raises(mgrit.MgritError) as e:
+        mgrit.Solver(pr, op, workspace=small)
+    assert e.value.status == mgrit.EINVAL
+    big = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    with pytest.raises(mgrit.MgritError) as e:
+        mgrit.Solver(pr, op, workspace=big[1:])  # misaligned view
+    assert e.value.status == mgrit.EINVAL
