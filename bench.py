@@ -235,7 +235,8 @@ def serve_bench(n, seed):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"served-advection1d-{n}-requests", "requests": n, "sizes": "nx, nt in 256..8192",
-                   "schemes": "ERK1/3/5 + U1/3/5", "cfl": "U(0.5, 0.9)", "m": [4, 8, 16], "max_inflight": 16},
+                   "schemes": "ERK1/3/5 + U1/3/5", "cfl": "U(0.5, 0.9)", "m": [4, 8, 16], "max_inflight": 16,
+                   "setup_threads": 8},
         "dof_per_s_one_in_flight": dof / t_one,
         "dof_per_s_16_in_flight": dof / t_many,
         "concurrency_speedup": t_one / t_many,

@@ -773,50 +773,44 @@ std::complex<double> upwind_symbol(const FineInfo &fi, double om) {
 }
 
 // ERK stability: max over omega of |R(-c Lhat(omega))| <= 1 (Sec. 4.3, Table 2).
-// R is the degree-s polynomial sum_j beta_j z^j of an explicit tableau, so
-// each sample is one sincos, a few complex multiply-adds for the symbol and
-// a Horner pass, written on real pairs.
+// R is the degree-s polynomial sum_j beta_j z^j of an explicit tableau.  The
+// samples om_k = pi k / N take the phasors e^{i j om_k} from one table of
+// e^{i pi n / N}, n < 2N (built once), so each sample is a few complex
+// multiply-adds, written on real pairs.
 bool erk_stable(const FineInfo &fi, double c) {
-  const int N = 16384;
+  constexpr int N = 16384;
+  static const std::vector<double> ph = [] {
+    std::vector<double> t(4 * N);
+    for (int n = 0; n < 2 * N; ++n) {
+      t[2 * n] = std::cos(M_PI * n / N);
+      t[2 * n + 1] = std::sin(M_PI * n / N);
+    }
+    return t;
+  }();
   const int s = fi.tab.s;
-  const std::vector<ld> beta = rk_series(fi.tab, s);
+  const std::vector<ld> beta_l = rk_series(fi.tab, s);
+  double beta[16];
+  for (int j = 0; j <= s; ++j) beta[j] = (double)beta_l[j];
   const int nt = fi.l + fi.r + 1;
-  // e^{i om_k} by rotation from an exact value every 64 samples
-  const double cd = std::cos(M_PI / N), sd = std::sin(M_PI / N);
-  double c1 = 1, s1 = 0;
+  double cw[16];
+  for (int t = 0; t < nt; ++t) cw[t] = -c * fi.w[t];
+  bool ok = true;
   for (int k = 1; k <= N; ++k) {
-    if (k % 64 == 0) {
-      c1 = std::cos(M_PI * k / N);
-      s1 = std::sin(M_PI * k / N);
-    } else {
-      const double nr = c1 * cd - s1 * sd;
-      s1 = c1 * sd + s1 * cd;
-      c1 = nr;
-    }
-    // z = -c sum_j w_j e^{i j om}, j = -l..r, starting from e^{-i l om}
-    double er = 1, ei = 0;
-    for (int j = 0; j < fi.l; ++j) {
-      const double nr = er * c1 + ei * s1;
-      ei = ei * c1 - er * s1;
-      er = nr;
-    }
     double zr = 0, zi = 0;
     for (int t = 0; t < nt; ++t) {
-      zr -= c * fi.w[t] * er;
-      zi -= c * fi.w[t] * ei;
-      const double nr = er * c1 - ei * s1;
-      ei = er * s1 + ei * c1;
-      er = nr;
+      const int n = ((t - fi.l) * k) & (2 * N - 1);  // phase index of e^{i (t - l) om_k} (2N = 2^15)
+      zr += cw[t] * ph[2 * n];
+      zi += cw[t] * ph[2 * n + 1];
     }
-    double ar = (double)beta[s], ai = 0;
+    double ar = beta[s], ai = 0;
     for (int j = s - 1; j >= 0; --j) {
-      const double nr = ar * zr - ai * zi + (double)beta[j];
+      const double nr = ar * zr - ai * zi + beta[j];
       ai = ar * zi + ai * zr;
       ar = nr;
     }
-    if (std::sqrt(ar * ar + ai * ai) > 1 + 1e-10) return false;
+    ok &= ar * ar + ai * ai <= (1 + 1e-10) * (1 + 1e-10);
   }
-  return true;
+  return ok;
 }
 
 // One Runge-Kutta step of the upwind semi-discretisation at CFL c

@@ -105,10 +105,16 @@ struct LevelDesc {
   Layout lay;
 };
 
-// The lean coarse-step kernel: 16 points per lane, NW full wavefronts
-// (nx = 1024 NW, NW = 1, 2, 4 or 8; at 16 wavefronts the 128-register
-// budget of a 1024-thread workgroup would spill).
-constexpr int LEAN_L = 16;
+// The lean coarse-step kernel: L points per lane and NW full wavefronts,
+// nx = 64 L NW, for L = 16 with NW = 1, 2, 4, 8 (nx = 1024 ... 8192) and for
+// L = 4 or 8 with one wavefront (nx = 256, 512).  At 16 wavefronts the
+// 128-register budget of a 1024-thread workgroup would spill.
+constexpr __host__ __device__ inline bool lean_shape(int L, int nw) {
+  return (L == 16 && (nw == 1 || nw == 2 || nw == 4 || nw == 8)) || ((L == 4 || L == 8) && nw == 1);
+}
+constexpr __host__ __device__ inline int lean_key(int W, int K, int L, int nw) {
+  return ((W * 4 + K) * 32 + L) * 16 + nw;
+}
 
 // LDS layout of the lean coarse-step kernel (in doubles): one padded vector,
 // the forward and backward tables, the two wavefront-total arrays, and the
@@ -140,9 +146,9 @@ constexpr __host__ __device__ inline LeanLds lean_lds_offsets(int nx, int K) {
 // for 16-point chunks that cover nx exactly.
 inline bool lean_slc_applies(const StepOp &op, const Layout &lay) {
   const int W = op.sl_l + op.sl_r + 1;
-  const int nw = lay.nx / (WAVE * LEAN_L);
-  return op.kind == OP_SLC && op.has_solve && op.repeat == 1 && !lay.ragged && lay.L == LEAN_L &&
-         lay.A == lay.T && lay.nx == nw * WAVE * LEAN_L && (nw == 1 || nw == 2 || nw == 4 || nw == 8) &&
+  const int nw = lay.L > 0 ? lay.nx / (WAVE * lay.L) : 0;
+  return op.kind == OP_SLC && op.has_solve && op.repeat == 1 && !lay.ragged && lay.A == lay.T &&
+         lay.nx == nw * WAVE * lay.L && lean_shape(lay.L, nw) &&
          op.fw.k == op.bw.k && op.fw.k >= 1 && W == 2 * op.fw.k &&
          lean_lds_offsets(lay.nx, op.fw.k).total * sizeof(double) <= 160 * 1024;
 }

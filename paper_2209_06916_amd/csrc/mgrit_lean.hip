@@ -1,6 +1,7 @@
 // gfx950 kernel for the coarse-level time step of MGRIT (Sec. 2.2 with the
 // corrected semi-Lagrangian operator, eqs. MOL-SL-corrected and
-// MOL-SL-corrected-multilevel) on vectors of 1024 NW points, NW = 1, 2, 4, 8.
+// MOL-SL-corrected-multilevel) on vectors of 64 L NW points: L = 16 with
+// NW = 1, 2, 4, 8 wavefronts, and one wavefront with L = 4 or 8.
 #include "mgrit_internal.h"
 
 namespace mgrit {
@@ -11,7 +12,7 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // Coarse time step Psi = T^{-1} S (eq. MOL-SL-corrected-multilevel) for
-// nx = 1024 NW: 16 points per lane, NW full wavefronts, W interpolation taps,
+// nx = 64 L NW: L points per lane, NW full wavefronts, W interpolation taps,
 // order-K forward and backward recurrences.  Per step: one barrier after the
 // vector is written to LDS, one per recurrence.  After a recurrence's
 // wavefront totals are published, every wavefront folds them and the
@@ -272,11 +273,10 @@ __device__ __forceinline__ void load_segs(const double *__restrict__ row, double
 // tab_b the scan tables, qf / qb the wavefront totals, red the reduction
 // scratch.  hsrc_f / hsrc_b: where the lane-dependent powers are loaded from.
 // prologue() runs once the first loads are in flight; false ends the pass.
-template <int W, int K, int NW, class Prologue>
+template <int W, int K, int L, int NW, class Prologue>
 __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, int64_t b, double *v, double *tab_f,
                                           double *tab_b, const double *hsrc_f, const double *hsrc_b, double *qf,
                                           double *qb, double *red, Prologue prologue) {
-  constexpr int L = LEAN_L;
   constexpr int T = WAVE * NW;
   constexpr int NX = L * T;
   constexpr bool HOIST = K <= 2;
@@ -439,14 +439,14 @@ __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, 
   }
 }
 
-template <int W, int K, int NW>
+template <int W, int K, int L, int NW>
 __global__ void __launch_bounds__(WAVE * NW) slc_kernel(const LevelDesc *__restrict__ desc, PassArgs pa) {
   extern __shared__ double smem[];
-  constexpr LeanLds lo = lean_lds_offsets(LEAN_L * WAVE * NW, K);
+  constexpr LeanLds lo = lean_lds_offsets(L * WAVE * NW, K);
   const StepOp &op = desc->op;
   double *tab_f = smem + lo.tab_f;
   double *tab_b = smem + lo.tab_b;
-  lean_pass<W, K, NW>(op, pa, blockIdx.x, smem, tab_f, tab_b, op.fw.tab, op.bw.tab, smem + lo.qf, smem + lo.qb,
+  lean_pass<W, K, L, NW>(op, pa, blockIdx.x, smem, tab_f, tab_b, op.fw.tab, op.bw.tab, smem + lo.qf, smem + lo.qb,
                       smem + lo.red, [&] {
                         // Scan tables to LDS.  No barrier here: the first step's
                         // barrier (after the vector is written to LDS) comes
@@ -525,12 +525,12 @@ __device__ __forceinline__ bool grid_barrier(GridSync *gs, unsigned &gen, int *o
   return *ok_lds != 0;
 }
 
-template <int W, int K, int NW>
+template <int W, int K, int L, int NW>
 __global__ void __launch_bounds__(WAVE * NW) coarse_vcycle_kernel(CoarsePlan plan, GridSync *gs, const int *stop) {
   extern __shared__ double smem[];
   __shared__ int ok;
   constexpr int T = WAVE * NW;
-  constexpr int NX = LEAN_L * T;
+  constexpr int NX = L * T;
   constexpr int KK = K * K;
   constexpr int TABSZ = RTAB_ALL * KK;
   if (stop && *stop) return;  // the solve has already stopped (uniform)
@@ -558,25 +558,25 @@ __global__ void __launch_bounds__(WAVE * NW) coarse_vcycle_kernel(CoarsePlan pla
     } else if ((int64_t)blockIdx.x < P.pa.nint) {
       const StepOp &op = plan.desc[P.level]->op;
       double *tf = tabs + 2 * P.level * TABSZ;
-      lean_pass<W, K, NW>(op, P.pa, blockIdx.x, v, tf, tf + TABSZ, tf, tf + TABSZ, qf, qb, red,
+      lean_pass<W, K, L, NW>(op, P.pa, blockIdx.x, v, tf, tf + TABSZ, tf, tf + TABSZ, qf, qb, red,
                           [] { return true; });
     }
     if (ph + 1 < plan.nphases && !grid_barrier(gs, gen, &ok)) return;
   }
 }
 
-template <int W, int K, int NW>
+template <int W, int K, int L, int NW>
 hipError_t coarse_vcycle_launch(const CoarsePlan &plan, int64_t grid, size_t lds, GridSync *gs, const int *stop,
                                 hipStream_t stream) {
-  hipLaunchKernelGGL((coarse_vcycle_kernel<W, K, NW>), dim3((unsigned)grid), dim3(WAVE * NW), lds, stream, plan, gs,
+  hipLaunchKernelGGL((coarse_vcycle_kernel<W, K, L, NW>), dim3((unsigned)grid), dim3(WAVE * NW), lds, stream, plan, gs,
                      stop);
   return hipGetLastError();
 }
 
-template <int W, int K, int NW>
+template <int W, int K, int L, int NW>
 int coarse_vcycle_grid(size_t lds) {
   int per_cu = 0, dev = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)coarse_vcycle_kernel<W, K, NW>, WAVE * NW,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)coarse_vcycle_kernel<W, K, L, NW>, WAVE * NW,
                                                    lds) != hipSuccess)
     return 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -584,48 +584,42 @@ int coarse_vcycle_grid(size_t lds) {
   return per_cu * cus;
 }
 
-template <int W, int K, int NW>
+template <int W, int K, int L, int NW>
 hipError_t slc_launch(const LevelDesc *desc, const PassArgs &pa, hipStream_t stream) {
-  constexpr size_t lds = (size_t)lean_lds_offsets(LEAN_L * WAVE * NW, K).total * sizeof(double);
-  hipLaunchKernelGGL((slc_kernel<W, K, NW>), dim3((unsigned)pa.nint), dim3(WAVE * NW), lds, stream, desc, pa);
+  constexpr size_t lds = (size_t)lean_lds_offsets(L * WAVE * NW, K).total * sizeof(double);
+  hipLaunchKernelGGL((slc_kernel<W, K, L, NW>), dim3((unsigned)pa.nint), dim3(WAVE * NW), lds, stream, desc, pa);
   return hipGetLastError();
 }
 
-template <int W, int K>
-hipError_t slc_launch_nw(const LevelDesc *desc, int nw, const PassArgs &pa, hipStream_t stream) {
-  switch (nw) {
-    case 1: return slc_launch<W, K, 1>(desc, pa, stream);
-    case 2: return slc_launch<W, K, 2>(desc, pa, stream);
-    case 4: return slc_launch<W, K, 4>(desc, pa, stream);
-    case 8: return slc_launch<W, K, 8>(desc, pa, stream);
-    default: return hipErrorInvalidValue;
-  }
-}
+// The (L, NW) shapes: nx = 64 L NW.
+#define MGRIT_LEAN_SHAPES(X, W, K) X(W, K, 16, 1) X(W, K, 16, 2) X(W, K, 16, 4) X(W, K, 16, 8) X(W, K, 8, 1) X(W, K, 4, 1)
 
 hipError_t slc_launch_any(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs &pa,
                           hipStream_t stream) {
   const int W = op.sl_l + op.sl_r + 1;
-  const int nw = lay.nx / (WAVE * LEAN_L);
-  if (W == 2 && op.fw.k == 1) return slc_launch_nw<2, 1>(desc, nw, pa, stream);
-  if (W == 4 && op.fw.k == 2) return slc_launch_nw<4, 2>(desc, nw, pa, stream);
-  if (W == 6 && op.fw.k == 3) return slc_launch_nw<6, 3>(desc, nw, pa, stream);
-  return hipErrorInvalidValue;
+  const int key = lean_key(W, op.fw.k, lay.L, lay.nx / (WAVE * lay.L));
+#define MGRIT_SLC_CASE(Wv, Kv, Lv, NWv) \
+  case lean_key(Wv, Kv, Lv, NWv): return slc_launch<Wv, Kv, Lv, NWv>(desc, pa, stream);
+  switch (key) {
+    MGRIT_LEAN_SHAPES(MGRIT_SLC_CASE, 2, 1)
+    MGRIT_LEAN_SHAPES(MGRIT_SLC_CASE, 4, 2)
+    MGRIT_LEAN_SHAPES(MGRIT_SLC_CASE, 6, 3)
+    default: return hipErrorInvalidValue;
+  }
+#undef MGRIT_SLC_CASE
 }
 
-template <int W, int K>
 hipError_t slc_set_lds(size_t bytes) {
-  hipError_t e;
-  if ((e = hipFuncSetAttribute((const void *)slc_kernel<W, K, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)bytes)))
-    return e;
-  if ((e = hipFuncSetAttribute((const void *)slc_kernel<W, K, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)bytes)))
-    return e;
-  if ((e = hipFuncSetAttribute((const void *)slc_kernel<W, K, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)bytes)))
-    return e;
-  return hipFuncSetAttribute((const void *)slc_kernel<W, K, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)bytes);
+  hipError_t e = hipSuccess;
+#define MGRIT_SLC_LDS(Wv, Kv, Lv, NWv)                                                                           \
+  if (e == hipSuccess)                                                                                          \
+    e = hipFuncSetAttribute((const void *)slc_kernel<Wv, Kv, Lv, NWv>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                            (int)bytes);
+  MGRIT_LEAN_SHAPES(MGRIT_SLC_LDS, 2, 1)
+  MGRIT_LEAN_SHAPES(MGRIT_SLC_LDS, 4, 2)
+  MGRIT_LEAN_SHAPES(MGRIT_SLC_LDS, 6, 3)
+#undef MGRIT_SLC_LDS
+  return e;
 }
 
 }  // namespace
@@ -635,12 +629,7 @@ hipError_t launch_lean(const LevelDesc *desc, const StepOp &op, const Layout &la
   return slc_launch_any(desc, op, lay, pa, stream);
 }
 
-hipError_t configure_lean_kernels(size_t bytes) {
-  hipError_t e;
-  if ((e = slc_set_lds<2, 1>(bytes))) return e;
-  if ((e = slc_set_lds<4, 2>(bytes))) return e;
-  return slc_set_lds<6, 3>(bytes);
-}
+hipError_t configure_lean_kernels(size_t bytes) { return slc_set_lds(bytes); }
 
 size_t coarse_vcycle_lds(const StepOp &op, const Layout &lay, int nlevels) {
   if (!lean_slc_applies(op, lay) || nlevels < 1 || nlevels > MAX_COARSE_LEVELS) return 0;
@@ -651,36 +640,25 @@ size_t coarse_vcycle_lds(const StepOp &op, const Layout &lay, int nlevels) {
   return bytes + 256 <= 160 * 1024 ? bytes : 0;  // 256: the kernel's static LDS
 }
 
-// (W, K, NW) of the persistent launch from the operator and the layout.
-#define MGRIT_CV_SWITCH(CALL, FAIL)                                             \
-  do {                                                                          \
-    const int W_ = op.sl_l + op.sl_r + 1;                                       \
-    const int nw_ = lay.nx / (WAVE * LEAN_L);                                   \
-    const int key_ = (W_ * 4 + op.fw.k) * 16 + nw_;                             \
-    switch (key_) {                                                             \
-      case (2 * 4 + 1) * 16 + 1: return CALL(2, 1, 1);                          \
-      case (2 * 4 + 1) * 16 + 2: return CALL(2, 1, 2);                          \
-      case (2 * 4 + 1) * 16 + 4: return CALL(2, 1, 4);                          \
-      case (2 * 4 + 1) * 16 + 8: return CALL(2, 1, 8);                          \
-      case (4 * 4 + 2) * 16 + 1: return CALL(4, 2, 1);                          \
-      case (4 * 4 + 2) * 16 + 2: return CALL(4, 2, 2);                          \
-      case (4 * 4 + 2) * 16 + 4: return CALL(4, 2, 4);                          \
-      case (4 * 4 + 2) * 16 + 8: return CALL(4, 2, 8);                          \
-      case (6 * 4 + 3) * 16 + 1: return CALL(6, 3, 1);                          \
-      case (6 * 4 + 3) * 16 + 2: return CALL(6, 3, 2);                          \
-      case (6 * 4 + 3) * 16 + 4: return CALL(6, 3, 4);                          \
-      case (6 * 4 + 3) * 16 + 8: return CALL(6, 3, 8);                          \
-      default: return FAIL;                                                     \
-    }                                                                           \
+// (W, K, L, NW) of the persistent launch from the operator and the layout.
+#define MGRIT_CV_SWITCH(CASE, FAIL)                                                 \
+  do {                                                                              \
+    switch (lean_key(op.sl_l + op.sl_r + 1, op.fw.k, lay.L, lay.nx / (WAVE * lay.L))) { \
+      MGRIT_LEAN_SHAPES(CASE, 2, 1)                                                 \
+      MGRIT_LEAN_SHAPES(CASE, 4, 2)                                                 \
+      MGRIT_LEAN_SHAPES(CASE, 6, 3)                                                 \
+      default: return FAIL;                                                         \
+    }                                                                               \
   } while (0)
 
 int coarse_vcycle_max_grid(const StepOp &op, const Layout &lay, size_t lds) {
   if (!lean_slc_applies(op, lay)) return 0;
-#define MGRIT_CV_GRID(Wv, Kv, NWv)                                                                              \
-  (hipFuncSetAttribute((const void *)coarse_vcycle_kernel<Wv, Kv, NWv>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                       (int)lds) == hipSuccess                                                                  \
-       ? coarse_vcycle_grid<Wv, Kv, NWv>(lds)                                                                   \
-       : 0)
+#define MGRIT_CV_GRID(Wv, Kv, Lv, NWv)                                                                    \
+  case lean_key(Wv, Kv, Lv, NWv):                                                                         \
+    return hipFuncSetAttribute((const void *)coarse_vcycle_kernel<Wv, Kv, Lv, NWv>,                       \
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess        \
+               ? coarse_vcycle_grid<Wv, Kv, Lv, NWv>(lds)                                                 \
+               : 0;
   MGRIT_CV_SWITCH(MGRIT_CV_GRID, 0);
 #undef MGRIT_CV_GRID
 }
@@ -688,11 +666,13 @@ int coarse_vcycle_max_grid(const StepOp &op, const Layout &lay, size_t lds) {
 hipError_t launch_coarse_vcycle(const CoarsePlan &plan, const StepOp &op, const Layout &lay, int64_t grid,
                                 size_t lds, GridSync *gs, const int *stop, hipStream_t stream) {
   if (!lean_slc_applies(op, lay)) return hipErrorInvalidValue;
-#define MGRIT_CV_LAUNCH(Wv, Kv, NWv) coarse_vcycle_launch<Wv, Kv, NWv>(plan, grid, lds, gs, stop, stream)
+#define MGRIT_CV_LAUNCH(Wv, Kv, Lv, NWv) \
+  case lean_key(Wv, Kv, Lv, NWv): return coarse_vcycle_launch<Wv, Kv, Lv, NWv>(plan, grid, lds, gs, stop, stream);
   MGRIT_CV_SWITCH(MGRIT_CV_LAUNCH, hipErrorInvalidValue);
 #undef MGRIT_CV_LAUNCH
 }
 
 #undef MGRIT_CV_SWITCH
+#undef MGRIT_LEAN_SHAPES
 
 }  // namespace mgrit

@@ -16,6 +16,7 @@ hipMalloc or hipFree (hipFree would wait for every solve in flight).  Every
 step of every solve runs in the HIP library; this module only schedules.
 """
 import time
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -69,11 +70,14 @@ class Server:
     """Continuous-batching request loop.
 
     budget_bytes bounds the device memory of the requests in flight;
-    max_inflight bounds their number (one HIP stream each)."""
+    max_inflight bounds their number (one HIP stream each); setup_threads
+    host threads run mgrit_setup_ws (ctypes releases the interpreter lock
+    for the call, so setups overlap each other and the launch loop)."""
 
-    def __init__(self, budget_bytes=64 << 30, max_inflight=16, device="cuda:0"):
+    def __init__(self, budget_bytes=64 << 30, max_inflight=16, device="cuda:0", setup_threads=8):
         self.budget = int(budget_bytes)
         self.max_inflight = int(max_inflight)
+        self.setup_threads = int(setup_threads)
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(self.max_inflight)]
 
@@ -85,58 +89,97 @@ class Server:
     def footprint(req):
         return Server.workspace(req) + 2 * req.nx * 8
 
+    def _setup(self, req, stream, ws):
+        with torch.cuda.device(self.device):
+            return mgrit.Solver(req.problem(), req.options(), stream=stream, workspace=ws)
+
     def run(self, requests, realtime=True):
         """Serve `requests` (arrival times honoured when realtime); returns one
-        Result per request, in completion order."""
+        Result per request, in completion order.  A request that fails (at
+        setup or in the solve) gets a Result with its status and no u_final;
+        the others are not affected."""
         pending = sorted(requests, key=lambda r: r.arrival)
         for r in pending:
             if self.footprint(r) > self.budget:
                 raise ValueError(f"request {r.tag} needs more than the whole budget")
-        active, results = [], []
+        preparing, active, results = [], [], []
         free_streams = list(self.streams)
         used = 0
         t0 = time.perf_counter()
-        while pending or active:
-            now = time.perf_counter() - t0
-            # admit in arrival order while memory and slots allow
-            while pending and len(active) < self.max_inflight and (not realtime or pending[0].arrival <= now):
-                req = pending[0]
-                need = self.footprint(req)
-                if used + need > self.budget:
-                    break
-                pending.pop(0)
-                stream = free_streams.pop()
-                with torch.cuda.stream(stream):
-                    u0 = torch.from_numpy(np.ascontiguousarray(req.u0, dtype=np.float64)).to(self.device,
-                                                                                            non_blocking=False)
-                    ufin = torch.empty(req.nx, dtype=torch.float64, device=self.device)
-                    ws = torch.empty(self.workspace(req), dtype=torch.uint8, device=self.device)
-                solver = mgrit.Solver(req.problem(), req.options(), stream=stream, workspace=ws)
-                solver.solve_start(u0, None, None, ufin)
-                used += need
-                active.append(dict(req=req, solver=solver, stream=stream, u0=u0, ufin=ufin, need=need,
-                                   t_admit=time.perf_counter() - t0))
-            # advance every in-flight solve by at most one iteration
-            progressed = False
-            for a in list(active):
-                if a["solver"].solve_advance():
-                    info = a["solver"].solve_finish()
-                    a["stream"].synchronize()
-                    req = a["req"]
-                    results.append(Result(tag=req.tag, status=info["status"], iterations=info["iterations"],
-                                          u_final=a["ufin"].cpu().numpy(), t_arrival=req.arrival,
-                                          t_admit=a["t_admit"], t_done=time.perf_counter() - t0,
-                                          dof=req.nx * req.nt, res_history=info["res_history"]))
-                    # the stream is idle: the workspace goes back to the
-                    # caching allocator for the next request on any stream
-                    a["solver"].close()
-                    used -= a["need"]
-                    active.remove(a)
-                    free_streams.append(a["stream"])
+
+        def retire(a, status, iterations=0, hist=(), u_final=None):
+            nonlocal used
+            req = a["req"]
+            results.append(Result(tag=req.tag, status=status, iterations=iterations, u_final=u_final,
+                                  t_arrival=req.arrival, t_admit=a["t_admit"], t_done=time.perf_counter() - t0,
+                                  dof=req.nx * req.nt, res_history=list(hist)))
+            if a.get("solver") is not None:
+                a["solver"].close()  # the stream is idle: the workspace returns to the caching allocator
+            used -= a["need"]
+            free_streams.append(a["stream"])
+
+        with ThreadPoolExecutor(max_workers=self.setup_threads) as pool:
+            while pending or preparing or active:
+                now = time.perf_counter() - t0
+                progressed = False
+                # admit in arrival order while memory and slots allow; the
+                # host-side setup runs on the pool
+                while pending and len(active) + len(preparing) < self.max_inflight and \
+                        (not realtime or pending[0].arrival <= now):
+                    req = pending[0]
+                    need = self.footprint(req)
+                    if used + need > self.budget:
+                        break
+                    pending.pop(0)
+                    used += need
+                    stream = free_streams.pop()
+                    with torch.cuda.stream(stream):
+                        host = torch.from_numpy(np.ascontiguousarray(req.u0, dtype=np.float64)).pin_memory()
+                        u0 = host.to(self.device, non_blocking=True)
+                        ufin = torch.empty(req.nx, dtype=torch.float64, device=self.device)
+                        ws = torch.empty(self.workspace(req), dtype=torch.uint8, device=self.device)
+                    fut = pool.submit(self._setup, req, stream, ws)
+                    preparing.append(dict(req=req, fut=fut, stream=stream, u0=u0, ufin=ufin, need=need,
+                                          t_admit=time.perf_counter() - t0))
                     progressed = True
-            if not progressed and not active and pending and realtime:
-                time.sleep(min(1e-3, max(0.0, pending[0].arrival - (time.perf_counter() - t0))))
+                # start the solves whose setup has finished
+                for a in [a for a in preparing if a["fut"].done()]:
+                    preparing.remove(a)
+                    progressed = True
+                    try:
+                        a["solver"] = a["fut"].result()
+                        a["solver"].solve_start(a["u0"], None, None, a["ufin"])
+                    except mgrit.MgritError as e:
+                        a["stream"].synchronize()
+                        retire(a, e.status)
+                        continue
+                    active.append(a)
+                # advance every in-flight solve by at most one iteration
+                for a in list(active):
+                    try:
+                        done = a["solver"].solve_advance()
+                        if done:
+                            info = a["solver"].solve_finish(allow=_ANY_STATUS)
+                    except mgrit.MgritError as e:
+                        done, info = True, dict(status=e.status, iterations=0, res_history=[])
+                    if not done:
+                        continue
+                    a["stream"].synchronize()
+                    ok = info["status"] in (mgrit.OK, mgrit.ENOTCONVERGED)
+                    active.remove(a)
+                    retire(a, info["status"], info["iterations"], info["res_history"],
+                           a["ufin"].cpu().numpy() if ok else None)
+                    progressed = True
+                if not progressed:
+                    if realtime and not active and not preparing and pending:
+                        time.sleep(min(1e-3, max(0.0, pending[0].arrival - (time.perf_counter() - t0))))
+                    else:
+                        time.sleep(0)  # let the setup threads take the interpreter
         return results
+
+
+_ANY_STATUS = (mgrit.OK, mgrit.ENOTCONVERGED, mgrit.EINVAL, mgrit.EUNSTABLE, mgrit.ENOMEM, mgrit.EDEVICE,
+               mgrit.EDIVERGED)
 
 
 def synthetic_stream(n, seed, rate_hz, sizes=(256, 512, 1024, 2048, 4096, 8192), orders=(1, 3, 5), ms=(4, 8, 16),

@@ -95,9 +95,10 @@ def test_coarse_steps_match_oracle(nx, p, kind, q, c, ms):
         assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref)) * max(1.0, abs(rec["phi_p"])), lev
 
 
-# the lean coarse-step kernel: 16 points per lane, nx = 1024 NW, NW = 1, 2, 4, 8,
-# for the three (taps, recurrence order) pairs p = 1, 3, 5
-LEAN_CASES = [(nx, p) for nx in (1024, 2048, 4096, 8192) for p in (1, 3, 5)]
+# the lean coarse-step kernel: 16 points per lane with nx = 1024 NW, NW = 1,
+# 2, 4, 8, and one wavefront of 8 or 4 points per lane (nx = 512, 256), for
+# the three (taps, recurrence order) pairs p = 1, 3, 5
+LEAN_CASES = [(nx, p) for nx in (256, 512, 1024, 2048, 4096, 8192) for p in (1, 3, 5)]
 
 
 @pytest.mark.parametrize("nx,p", LEAN_CASES)
@@ -124,6 +125,9 @@ def test_lean_coarse_steps_match_oracle(nx, p):
     dict(nx=2048, nt=128, p=5, kind="erk", q=5, c=0.9, ms=[4, 8]),
     dict(nx=1024, nt=128, p=3, kind="sdirk", q=3, c=5.0, ms=[4, 4]),
     dict(nx=8192, nt=64, p=3, kind="erk", q=3, c=0.85, ms=[4, 4]),
+    dict(nx=256, nt=512, p=3, kind="erk", q=3, c=0.7, ms=[4, 4, 4]),
+    dict(nx=512, nt=256, p=5, kind="erk", q=5, c=0.9, ms=[8, 4]),
+    dict(nx=512, nt=128, p=1, kind="sdirk", q=1, c=2.0, ms=[4, 4]),
 ])
 def test_lean_full_solve_matches_oracle(case):
     _announce("lean solve", case)
@@ -132,15 +136,17 @@ def test_lean_full_solve_matches_oracle(case):
     _check_parity(info, got, fin, ref, rinfo, case["ms"][0])
 
 
-def test_lean_and_generic_coarse_kernels_agree(monkeypatch):
-    """Chunks of 8 points select the generic step kernel on the coarse levels,
-    chunks of 16 the lean one; both solve the same system."""
-    _announce("lean vs generic")
-    nx, nt = 4096, 512
+@pytest.mark.parametrize("nx,generic_l", [(4096, "8"), (512, "4"), (256, "2")])
+def test_lean_and_generic_coarse_kernels_agree(monkeypatch, nx, generic_l):
+    """A chunk length outside the lean shapes selects the generic step kernel
+    on the coarse levels, the default one the lean kernel; both solve the
+    same system."""
+    _announce("lean vs generic", nx, generic_l)
+    nt = 512
     u0 = inputs.u0_fourier(nx, 31)
     v0 = _t(inputs.initial_iterate(nt, nx, u0, 31))
     outs = []
-    for lc in ("16", "8"):
+    for lc in ("16", generic_l):
         monkeypatch.setenv("MGRIT_L_COARSE", lc)
         s = mgrit.Solver(mgrit.make_problem(nx, nt, 0.85, 3), mgrit.make_options([8, 8, 8], max_levels=4))
         o = torch.empty((nt + 1, nx), dtype=torch.float64, device=DEV)
@@ -150,7 +156,8 @@ def test_lean_and_generic_coarse_kernels_agree(monkeypatch):
     np.testing.assert_allclose(outs[0][1], outs[1][1], rtol=0, atol=1e-13 * np.max(np.abs(outs[1][1])))
 
 
-@pytest.mark.parametrize("nu,ms,nx,p", [(1, [8, 8, 8], 4096, 3), (0, [4, 4], 1024, 1), (2, [4, 2, 2], 2048, 5)])
+@pytest.mark.parametrize("nu,ms,nx,p", [(1, [8, 8, 8], 4096, 3), (0, [4, 4], 1024, 1), (2, [4, 2, 2], 2048, 5),
+                                        (1, [4, 4, 4], 512, 3), (1, [8, 4], 256, 5)])
 def test_persistent_and_per_pass_coarse_cycles_agree(monkeypatch, nu, ms, nx, p):
     """The coarse part of each V-cycle as one cooperative launch with grid
     barriers and as one launch per pass: same passes, same arithmetic, so the

@@ -108,3 +108,17 @@ def test_caller_workspace_is_checked():
     with pytest.raises(mgrit.MgritError) as e:
         mgrit.Solver(pr, op, workspace=big[1:])  # misaligned view
     assert e.value.status == mgrit.EINVAL
+
+
+def test_a_failing_request_does_not_affect_the_others():
+    """ERK1+U1 at CFL 1.2 is above its stability limit: that request ends with
+    MGRIT_EUNSTABLE and no result; the rest are served as when alone."""
+    _announce("serving failure isolation")
+    reqs = _mix()[:4]
+    bad = serve.Request(nx=512, nt=256, p=1, c=1.2, m=4, u0=inputs.u0_fourier(512, 9), tag="unstable")
+    got = _by_tag(serve.Server(max_inflight=4).run(reqs + [bad], realtime=False))
+    assert got["unstable"].status == mgrit.EUNSTABLE and got["unstable"].u_final is None
+    alone = _by_tag(serve.Server(max_inflight=1).run(reqs, realtime=False))
+    for r in reqs:
+        assert got[r.tag].status == mgrit.OK
+        np.testing.assert_array_equal(got[r.tag].u_final, alone[r.tag].u_final)
