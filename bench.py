@@ -118,8 +118,11 @@ PROFILE_COMMANDS = {
              "python3 bench.py --steps 2 --warmup 1 --traffic-probe",
     "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/write -o run -- "
              "python3 bench.py --steps 2 --warmup 1 --traffic-probe",
+    "serve": "rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/serve -o run -- "
+             "python3 bench.py --serve 512",
 }
-DOMINANT_KERNEL = "coarse_vcycle_kernel<4, 2, 4>"
+SERVE_WORKLOAD = "served-advection1d-512-requests"
+DOMINANT_KERNEL = "coarse_vcycle_kernel<4, 2, 16, 4>"
 
 
 def _short(name):
@@ -145,12 +148,30 @@ def summarize_profiles(d):
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
         lines.append(f"  {_short(r['Name']):52s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
                      f"{float(r['TotalDurationNs']) / 1e6:10.3f} {100 * float(r['TotalDurationNs']) / tot:6.2f}%")
-    lines += ["#", "# coarse_vcycle_kernel<4, 2, 4>: every coarse-level pass of one V-cycle (levels 1-3) in one launch",
+    lines += ["#", "# coarse_vcycle_kernel<4, 2, 16, 4>: every coarse-level pass of one V-cycle (levels 1-3) in one launch",
               "# (the last launch of each solve returns at once); tile_kernel<8, 2, 1>: level-0 relaxation passes",
               "# and the final F-relaxation; tile_kernel<4, 2, 1>: sequential time-stepping (blocks of 16 steps);",
               "# solve_ctl_kernel: residual norm + stopping test."]
     with open(os.path.join(prof_dir, f"kernel_stats_{WORKLOAD}.txt"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
+
+    serve_csv = os.path.join(d, "serve", "run_kernel_stats.csv")
+    if os.path.exists(serve_csv):
+        rows = list(csv.DictReader(open(serve_csv)))
+        tot = sum(float(r["TotalDurationNs"]) for r in rows)
+        lines = [f"# rocprofv3 kernel statistics -- workload {SERVE_WORKLOAD}",
+                 "# (bench.py --serve 512: 8 warm-up requests, then the 512-request stream served with 1 and with 16",
+                 "# solves in flight, then with Poisson arrivals; the profiler slows the host loop, so the rates it",
+                 "# prints are lower than without it)",
+                 "# command (repository root on the GPU box, after cd /tmp && export TMPDIR=/tmp):",
+                 "#   " + PROFILE_COMMANDS["serve"].replace("<dir>", "gpurun_out/prof"),
+                 f"# total kernel time {tot / 1e6:.1f} ms over {sum(int(r['Calls']) for r in rows)} launches",
+                 "#", f"# {'kernel':52s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'share':>7s}"]
+        for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:25]:
+            lines.append(f"  {_short(r['Name']):52s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
+                         f"{float(r['TotalDurationNs']) / 1e6:10.3f} {100 * float(r['TotalDurationNs']) / tot:6.2f}%")
+        with open(os.path.join(prof_dir, f"kernel_stats_{SERVE_WORKLOAD}.txt"), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
 
     def counters(sub, name):
         per = {}
@@ -349,7 +370,7 @@ def main():
     flops = flops_s / launches
     bytes_ = bytes_s / launches
     kernel = {"fine_relax": "tile_kernel<8, 2, 1>: level-0 F/C relaxation and C-point residual",
-              "coarse": "coarse_vcycle_kernel<4, 2, 4>: every coarse-level pass of a V-cycle in one cooperative "
+              "coarse": "coarse_vcycle_kernel<4, 2, 16, 4>: every coarse-level pass of a V-cycle in one cooperative "
                         "launch (SL step + periodic banded solve)",
               "final": "tile_kernel<8, 2, 1>: final F-relaxation writing the space-time solution"}[dom]
     ai = flops / bytes_
