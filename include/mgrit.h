@@ -95,7 +95,24 @@ typedef struct {
                             workgroups are the only persistent ones resident);
                             1: one launch per pass (for handles that run
                             concurrently on several streams)                 */
+  int32_t precision;     /* mgrit_precision                                   */
+  double inner_rtol;     /* MGRIT_PREC_MIXED: each inner solve stops once its
+                            C-point residual falls by this factor (> 0)      */
+  int32_t inner_max_iter; /* MGRIT_PREC_MIXED: cap on each inner solve's
+                            iterations (>= 1)                                 */
 } mgrit_options;
+
+/* Arithmetic of mgrit_solve.
+ * MGRIT_PREC_FP64: the whole solve in float64.
+ * MGRIT_PREC_MIXED: iterative refinement.  The outer loop runs in float64 on
+ *   the device: the full space-time residual r = g - A u (one fine step per
+ *   time point, all in parallel), its norm and the convergence test, and the
+ *   update u += e.  Between them, MGRIT solves A e = r in float32 (every
+ *   level's relaxation, residual and coarse solve; zero initial guess) until
+ *   its C-point residual falls by inner_rtol.  res0 / res_final / the history
+ *   are then norms of the full space-time residual, iterations counts outer
+ *   iterations and inner_iterations the float32 MGRIT iterations. */
+typedef enum { MGRIT_PREC_FP64 = 0, MGRIT_PREC_MIXED = 1 } mgrit_precision;
 
 typedef struct {
   int32_t iterations;   /* coarse-grid corrections performed                 */
@@ -106,6 +123,8 @@ typedef struct {
   int32_t res_history_cap;
   int32_t res_history_len; /* entries written (iterations + 1, capped)       */
   double t_solve_s;     /* host wall time of the solve call                  */
+  int32_t inner_iterations; /* MGRIT_PREC_MIXED: float32 MGRIT iterations, all
+                               outer iterations together (0 otherwise)       */
 } mgrit_stats;
 
 typedef struct {
@@ -170,7 +189,10 @@ mgrit_status mgrit_setup_ws(const mgrit_problem *problem, const mgrit_options *o
  *   u_final_dev [nx] receives row nt of the final iterate, or NULL.
  *   stats       optional.
  * Returns MGRIT_OK on convergence, MGRIT_ENOTCONVERGED at max_iter (outputs
- * hold the last iterate), MGRIT_EDIVERGED on a non-finite or growing residual. */
+ * hold the last iterate), MGRIT_EDIVERGED on a non-finite or growing residual.
+ * With MGRIT_PREC_MIXED the iterate is the whole space-time array: v_init
+ * (every row, row 0 replaced by u0) or zero, kept in u_out_dev when given
+ * (else in the handle's workspace); max_iter bounds the outer iterations. */
 mgrit_status mgrit_solve(mgrit_handle *h, const double *u0_dev, const double *v_init_dev,
                          double *u_out_dev, double *u_final_dev, mgrit_stats *stats);
 
@@ -182,7 +204,8 @@ mgrit_status mgrit_solve(mgrit_handle *h, const double *u0_dev, const double *v_
  * end (driving it if needed), fills stats and returns the status mgrit_solve
  * would have returned.  Arguments as for mgrit_solve; the device buffers must
  * stay valid until mgrit_solve_finish returns.  One solve at a time per handle
- * (MGRIT_EINVAL otherwise).  mgrit_solve is start + finish. */
+ * (MGRIT_EINVAL otherwise).  mgrit_solve is start + finish.  Float64 handles
+ * only: MGRIT_EINVAL for MGRIT_PREC_MIXED. */
 mgrit_status mgrit_solve_start(mgrit_handle *h, const double *u0_dev, const double *v_init_dev, double *u_out_dev,
                                double *u_final_dev);
 mgrit_status mgrit_solve_advance(mgrit_handle *h, int32_t *done);

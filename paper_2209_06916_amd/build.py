@@ -12,7 +12,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libmgrit.so")
 CSRC = os.path.join(PKG, "csrc")
-SOURCES = [os.path.join(CSRC, f) for f in ("mgrit_step_poly_z.hip", "mgrit_step_poly_w.hip", "mgrit_step_slc.hip", "mgrit_lean.hip",
+SOURCES = [os.path.join(CSRC, f) for f in ("mgrit_step_poly_z.hip", "mgrit_step_poly_w.hip", "mgrit_step_slc.hip",
+                                           "mgrit_step32_poly_z.hip", "mgrit_step32_poly_w.hip", "mgrit_step32_slc.hip",
+                                           "mgrit_lean.hip",
                                            "mgrit_tile4.hip", "mgrit_tile8.hip", "mgrit_tile16.hip",
                                            "mgrit_kernels.hip", "mgrit_host.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

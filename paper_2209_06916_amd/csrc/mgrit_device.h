@@ -17,19 +17,19 @@ __device__ __forceinline__ int wrap_lo(int i, int nx) {
   return i;
 }
 
-template <int L>
-__device__ __forceinline__ void load_chunk(const double *__restrict__ row, int base, int cnt, double (&x)[L]) {
+template <int L, class T>
+__device__ __forceinline__ void load_chunk(const T *__restrict__ row, int base, int cnt, T (&x)[L]) {
   if (cnt == L) {
 #pragma unroll
     for (int j = 0; j < L; ++j) x[j] = row[base + j];
   } else {
 #pragma unroll
-    for (int j = 0; j < L; ++j) x[j] = (j < cnt) ? row[base + j] : 0.0;
+    for (int j = 0; j < L; ++j) x[j] = (j < cnt) ? row[base + j] : T(0);
   }
 }
 
-template <int L>
-__device__ __forceinline__ void store_chunk(double *__restrict__ row, int base, int cnt, const double (&x)[L]) {
+template <int L, class T>
+__device__ __forceinline__ void store_chunk(T *__restrict__ row, int base, int cnt, const T (&x)[L]) {
   if (cnt == L) {
 #pragma unroll
     for (int j = 0; j < L; ++j) row[base + j] = x[j];
@@ -40,8 +40,8 @@ __device__ __forceinline__ void store_chunk(double *__restrict__ row, int base, 
   }
 }
 
-template <int L>
-__device__ __forceinline__ void chunk_to_lds(double *vec, int base, int cnt, const double (&x)[L]) {
+template <int L, class T>
+__device__ __forceinline__ void chunk_to_lds(T *vec, int base, int cnt, const T (&x)[L]) {
   if (cnt == L) {
 #pragma unroll
     for (int j = 0; j < L; ++j) vec[padix(base + j)] = x[j];

@@ -608,6 +608,11 @@ struct Level {
   LevelDesc *desc = nullptr;  // device copy of (op, lay)
   double *c[2] = {nullptr, nullptr};
   double *r = nullptr;
+  // float32 copies for the inner solves of mixed precision
+  float *tabs32 = nullptr;
+  LevelDesc *desc32 = nullptr;  // (op, lay) with the tables' float32 copy
+  float *c32[2] = {nullptr, nullptr};
+  float *r32 = nullptr;
 };
 
 }  // namespace
@@ -631,6 +636,10 @@ struct mgrit_handle {
   size_t cv_lds = 0;
   int64_t cv_grid = 0;
   GridSync *gsync = nullptr;
+  // mixed precision: the inner right-hand side and solution (float32), the
+  // outer residual and, when the caller keeps no u_out, the outer iterate
+  float *g32 = nullptr, *e32 = nullptr;
+  double *r64 = nullptr, *u64 = nullptr;
   char *arena = nullptr;       // every device buffer of the handle
   size_t arena_bytes = 0;
   bool owns_arena = false;     // false: the caller's workspace (mgrit_setup_ws)
@@ -954,6 +963,11 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
   if (!(O->rtol >= 0)) return bad(MGRIT_EINVAL, "rtol must be >= 0");
   if (O->cg_kind < 0 || O->cg_kind > 3) return bad(MGRIT_EINVAL, "unknown coarse operator");
   if (O->coarse_launch < 0 || O->coarse_launch > 1) return bad(MGRIT_EINVAL, "coarse_launch must be 0 or 1");
+  if (O->precision != MGRIT_PREC_FP64 && O->precision != MGRIT_PREC_MIXED) return bad(MGRIT_EINVAL, "unknown precision");
+  if (O->precision == MGRIT_PREC_MIXED && !(O->inner_rtol > 0 && O->inner_rtol < 1))
+    return bad(MGRIT_EINVAL, "mixed precision needs 0 < inner_rtol < 1");
+  if (O->precision == MGRIT_PREC_MIXED && O->inner_max_iter < 1)
+    return bad(MGRIT_EINVAL, "mixed precision needs inner_max_iter >= 1");
   const bool sl_coarse = O->cg_kind == MGRIT_CG_SL_CORRECTED || O->cg_kind == MGRIT_CG_SL_PLAIN;
   if (sl_coarse && P->upwind_order % 2 == 0)
     return bad(MGRIT_EINVAL, "semi-Lagrangian coarse operators need odd upwind order");
@@ -1120,6 +1134,13 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
   for (int l = 0; l < nlev; ++l)
     if (!tabs[l].empty()) o_tab[l] = off, off += al(tabs[l].size() * sizeof(double));
   for (int l = 0; l < nlev; ++l) o_desc[l] = off, off += al(sizeof(LevelDesc));
+  const bool mixed = O->precision == MGRIT_PREC_MIXED;
+  std::vector<size_t> o_tab32(nlev, none), o_desc32(nlev, none);
+  if (mixed) {
+    for (int l = 0; l < nlev; ++l)
+      if (!tabs[l].empty()) o_tab32[l] = off, off += al(tabs[l].size() * sizeof(float));
+    for (int l = 0; l < nlev; ++l) o_desc32[l] = off, off += al(sizeof(LevelDesc));
+  }
   size_t o_gs = none;
   if (h->cv_ok) o_gs = off, off += al(sizeof(GridSync));
   const size_t head = off;
@@ -1128,6 +1149,21 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
     o_c0[l] = off, off += al((rows + 1) * nx * sizeof(double));
     o_c1[l] = off, off += al((rows + 1) * nx * sizeof(double));
     o_r[l] = off, off += al(std::max<size_t>(rows * nx, 1) * sizeof(double));
+  }
+  std::vector<size_t> o_c32a(nlev, none), o_c32b(nlev, none), o_r32(nlev, none);
+  size_t o_g32 = none, o_e32 = none, o_r64 = none, o_u64 = none;
+  if (mixed) {
+    for (int l = 0; l + 1 < nlev; ++l) {
+      const size_t rows = (size_t)(h->lv[l].nt / h->lv[l].m);
+      o_c32a[l] = off, off += al((rows + 1) * nx * sizeof(float));
+      o_c32b[l] = off, off += al((rows + 1) * nx * sizeof(float));
+      o_r32[l] = off, off += al(std::max<size_t>(rows * nx, 1) * sizeof(float));
+    }
+    const size_t pts = (size_t)P->nt * nx;
+    o_g32 = off, off += al(pts * sizeof(float));
+    o_e32 = off, off += al((pts + nx) * sizeof(float));
+    o_r64 = off, off += al(pts * sizeof(double));
+    o_u64 = off, off += al((pts + nx) * sizeof(double));
   }
   h->normpart_len = std::max<int64_t>(P->nt, 1);
   if (h->lv[0].tiles) h->normpart_len = std::max<int64_t>(h->normpart_len, (P->nt / ms[0]) * h->lv[0].tg.ntiles);
@@ -1176,6 +1212,31 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
       Lv.c[1] = (double *)(base + o_c1[l]);
       Lv.r = (double *)(base + o_r[l]);
     }
+    if (mixed) {
+      LevelDesc hd32{Lv.op, Lv.lay};
+      if (o_tab32[l] != none) {
+        Lv.tabs32 = (float *)(base + o_tab32[l]);
+        float *dst = (float *)(up.data() + o_tab32[l]);
+        for (size_t i = 0; i < tabs[l].size(); ++i) dst[i] = (float)tabs[l][i];
+      }
+      if (offs[l].size() == 2) {
+        hd32.op.fw.tab = offs[l][0] == none ? nullptr : Lv.tabs32 + offs[l][0];
+        hd32.op.bw.tab = offs[l][1] == none ? nullptr : Lv.tabs32 + offs[l][1];
+      }
+      Lv.desc32 = (LevelDesc *)(base + o_desc32[l]);
+      std::memcpy(up.data() + o_desc32[l], &hd32, sizeof(LevelDesc));
+      if (o_c32a[l] != none) {
+        Lv.c32[0] = (float *)(base + o_c32a[l]);
+        Lv.c32[1] = (float *)(base + o_c32b[l]);
+        Lv.r32 = (float *)(base + o_r32[l]);
+      }
+    }
+  }
+  if (mixed) {
+    h->g32 = (float *)(base + o_g32);
+    h->e32 = (float *)(base + o_e32);
+    h->r64 = (double *)(base + o_r64);
+    h->u64 = (double *)(base + o_u64);
   }
   if (o_gs != none) h->gsync = (GridSync *)(base + o_gs);  // zero from the upload
   h->normpart = (double *)(base + o_np);
@@ -1473,6 +1534,179 @@ double reduce_norm(mgrit_handle *h, int64_t n, hipError_t &e) {
   return std::sqrt(*h->normsum_host);
 }
 
+// ---------------------------------------------------------------------------
+// Mixed precision: float32 MGRIT on the correction equation A e = r inside a
+// float64 refinement loop (see mgrit_precision).
+// ---------------------------------------------------------------------------
+hipError_t run_pass32(mgrit_handle *h, const Level &L, int phase, int mode, int m, int64_t nint, const float *cin,
+                      float *cout, const float *g, float *r, float *parent, float *out, int zero_init) {
+  PassArgs32 pa{};
+  pa.mode = mode;
+  pa.m = m;
+  pa.zero_init = zero_init;
+  pa.nint = nint;
+  pa.cin = cin;
+  pa.cout = cout;
+  pa.g = g;
+  pa.r = r;
+  pa.parent = parent;
+  pa.out = out;
+  pa.normpart = h->normpart;
+  pa.stop = h->guard;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->prof_mask & (1u << phase)) {
+    e0 = take_event(h);
+    e1 = take_event(h);
+    if (e0 && e1) (void)hipEventRecord(e0, h->stream);
+  }
+  hipError_t err = launch_pass32(L.desc32, L.op, L.lay, pa, h->stream);
+  if (e0 && e1) {
+    (void)hipEventRecord(e1, h->stream);
+    h->ev_pending.push_back({phase, {e0, e1}});
+  }
+  return err;
+}
+
+// The float32 coarse-grid correction below level l-1: the passes of
+// vcycle_plan, one launch each.
+mgrit_status vcycle32(mgrit_handle *h, int l, const float *g, float *parent) {
+  Level &L = h->lv[l];
+  const int nlev = (int)h->lv.size();
+  const int nx = (int)h->prob.nx;
+  const int ph = MGRIT_PROF_COARSE;
+  if (l == nlev - 1) {
+    HIPCHK(h, run_pass32(h, L, ph, MODE_SEQ, (int)L.nt, 1, nullptr, nullptr, g, nullptr, parent, nullptr, 1));
+    return MGRIT_OK;
+  }
+  const int64_t nc = L.nt / L.m;
+  int cur = 0;
+  if (h->opt.nu == 0) HIPCHK(h, launch_fill32(L.c32[0], (nc + 1) * (int64_t)nx, h->stream, h->guard));
+  for (int s = 0; s < h->opt.nu; ++s) {
+    HIPCHK(h, run_pass32(h, L, ph, MODE_PASS_A, L.m, nc, s == 0 ? nullptr : L.c32[cur], L.c32[1 - cur], g, nullptr,
+                         nullptr, nullptr, s == 0));
+    cur = 1 - cur;
+  }
+  HIPCHK(h, run_pass32(h, L, ph, MODE_PASS_B, L.m, nc, L.c32[cur], nullptr, g, L.r32, nullptr, nullptr, 0));
+  const mgrit_status st = vcycle32(h, l + 1, L.r32, L.c32[cur]);
+  if (st != MGRIT_OK) return st;
+  HIPCHK(h, run_pass32(h, L, ph, MODE_POST_F, L.m, nc, L.c32[cur], nullptr, g, nullptr, parent, nullptr, 0));
+  return MGRIT_OK;
+}
+
+// Float32 MGRIT for A e = g32 (rows 1..nt), e_0 = 0, zero initial iterate,
+// until the C-point residual falls by inner_rtol (or inner_max_iter); every
+// row of e lands in e32.  Returns the iterations performed in *iters.
+mgrit_status inner_solve(mgrit_handle *h, int *iters, int *stop) {
+  Level &L0 = h->lv[0];
+  const int nx = (int)h->prob.nx;
+  const int64_t nc = L0.nt / L0.m;
+  const StopRule rule{h->opt.inner_rtol, h->opt.diverge_factor, h->opt.inner_max_iter};
+  int cur = 0;
+  HIPCHK(h, launch_fill32(L0.c32[0], (nc + 1) * (int64_t)nx, h->stream));
+  HIPCHK(h, hipMemsetAsync(h->ctl, 0, sizeof(SolveCtl), h->stream));
+  for (;;) {
+    for (int s = 0; s < h->opt.nu; ++s) {
+      HIPCHK(h, run_pass32(h, L0, MGRIT_PROF_FINE_RELAX, MODE_PASS_A, L0.m, nc, L0.c32[cur], L0.c32[1 - cur], h->g32,
+                           nullptr, nullptr, nullptr, 0));
+      cur = 1 - cur;
+    }
+    HIPCHK(h, run_pass32(h, L0, MGRIT_PROF_FINE_RELAX, MODE_PASS_B, L0.m, nc, L0.c32[cur], nullptr, h->g32, L0.r32,
+                         nullptr, nullptr, 0));
+    HIPCHK(h, launch_solve_ctl(h->normpart, nc, h->ctl, h->ctl_host_dev, nullptr, rule, h->stream));
+    HIPCHK(h, hipEventRecord(h->ctl_ev, h->stream));
+    // the correction is queued before the decision is known and skips
+    // itself once the stop flag is set
+    h->guard = &h->ctl->stop;
+    const mgrit_status st = vcycle32(h, 1, L0.r32, L0.c32[cur]);
+    h->guard = nullptr;
+    if (st != MGRIT_OK) return st;
+    HIPCHK(h, hipEventSynchronize(h->ctl_ev));
+    const SolveCtl hc = *h->ctl_host;
+    if (hc.stop != STOP_NONE) {
+      *iters = hc.it;
+      *stop = hc.stop;
+      break;
+    }
+  }
+  HIPCHK(h, run_pass32(h, L0, MGRIT_PROF_FINAL, MODE_FINAL_F, L0.m, nc, L0.c32[cur], nullptr, h->g32, nullptr, nullptr,
+                       h->e32, 0));
+  return MGRIT_OK;
+}
+
+mgrit_status mp_solve(mgrit_handle *h, const double *u0, const double *v_init, double *u_out, double *u_final,
+                      mgrit_stats *stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int nx = (int)h->prob.nx;
+  const int64_t nt = h->prob.nt;
+  const int64_t pts = nt * nx;
+  const Level &L0 = h->lv[0];
+  double *U = u_out ? u_out : h->u64;
+  // outer iterate: v_init (or zero) with row 0 = u0
+  if (v_init && v_init != U) {
+    HIPCHK(h, hipMemcpyAsync(U, v_init, (pts + nx) * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  } else if (!v_init) {
+    HIPCHK(h, launch_fill(U, pts + nx, 0.0, h->stream));
+  }
+  HIPCHK(h, hipMemcpyAsync(U, u0, nx * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  std::vector<double> hist;
+  double res0 = NAN, rho = NAN, prev = NAN;
+  int outer = 0, inner_total = 0;
+  mgrit_status status = MGRIT_OK;
+  for (;;) {
+    // float64: r = g - A u at every time point, and its norm
+    HIPCHK(h, run_pass(h, L0, MGRIT_PROF_RESIDUAL, MODE_RESID, 1, nt, U, nullptr, nullptr, h->r64, nullptr, nullptr,
+                       0));
+    hipError_t e;
+    prev = rho;
+    rho = reduce_norm(h, nt, e);
+    if (e) return hipfail(h, e, "outer residual norm");
+    hist.push_back(rho);
+    if (outer == 0) res0 = rho;
+    if (!std::isfinite(rho)) {
+      status = fail(h, MGRIT_EDIVERGED, "non-finite residual");
+      break;
+    }
+    if (rho <= h->opt.rtol * res0) break;
+    if (outer >= h->opt.max_iter) {
+      status = MGRIT_ENOTCONVERGED;
+      h->err = "max_iter reached";
+      break;
+    }
+    if (h->opt.diverge_factor > 0 && rho > h->opt.diverge_factor * res0) {
+      status = fail(h, MGRIT_EDIVERGED, "residual grew past diverge_factor * res0");
+      break;
+    }
+    // float32: A e = r, then u += e in float64
+    HIPCHK(h, launch_round32(h->r64, h->g32, pts, h->stream));
+    int iters = 0, stop = 0;
+    const mgrit_status st = inner_solve(h, &iters, &stop);
+    if (st != MGRIT_OK) return st;
+    inner_total += iters;
+    if (stop == STOP_NONFINITE || stop == STOP_DIVERGED) {
+      status = fail(h, MGRIT_EDIVERGED, "the float32 inner solve diverged");
+      break;
+    }
+    HIPCHK(h, launch_add32(U, h->e32, pts + nx, h->stream));
+    ++outer;
+  }
+  if (u_final) HIPCHK(h, hipMemcpyAsync(u_final, U + pts, nx * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  harvest_events(h);
+  if (stats) {
+    stats->iterations = outer;
+    stats->inner_iterations = inner_total;
+    stats->res0 = res0;
+    stats->res_final = rho;
+    stats->conv_factor = prev > 0 ? rho / prev : NAN;
+    const int len = (int)hist.size();
+    if (stats->res_history)
+      for (int i = 0; i < std::min(len, stats->res_history_cap); ++i) stats->res_history[i] = hist[i];
+    stats->res_history_len = std::min(len, std::max(stats->res_history_cap, 0));
+    stats->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return status;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1482,6 +1716,8 @@ mgrit_status mgrit_solve_start(mgrit_handle *h, const double *u0, const double *
   if (!h) return MGRIT_EINVAL;
   if (!u0) return fail(h, MGRIT_EINVAL, "u0 is required");
   if (h->ss.active) return fail(h, MGRIT_EINVAL, "a solve is already in progress on this handle");
+  if (h->opt.precision != MGRIT_PREC_FP64)
+    return fail(h, MGRIT_EINVAL, "the incremental solve runs float64 handles only");
   auto &ss = h->ss;
   ss = {};
   ss.t0 = std::chrono::steady_clock::now();
@@ -1546,6 +1782,7 @@ mgrit_status mgrit_solve_finish(mgrit_handle *h, mgrit_stats *stats) {
   if (stats) {
     const auto &hc = ss.hc;
     stats->iterations = hc.it;
+    stats->inner_iterations = 0;
     stats->res0 = hc.res0;
     stats->res_final = hc.rho;
     stats->conv_factor = ss.prev > 0 ? hc.rho / ss.prev : NAN;
@@ -1560,6 +1797,11 @@ mgrit_status mgrit_solve_finish(mgrit_handle *h, mgrit_stats *stats) {
 
 mgrit_status mgrit_solve(mgrit_handle *h, const double *u0, const double *v_init, double *u_out, double *u_final,
                          mgrit_stats *stats) {
+  if (h && h->opt.precision == MGRIT_PREC_MIXED) {
+    if (!u0) return fail(h, MGRIT_EINVAL, "u0 is required");
+    if (h->ss.active) return fail(h, MGRIT_EINVAL, "a solve is already in progress on this handle");
+    return mp_solve(h, u0, v_init, u_out, u_final, stats);
+  }
   const mgrit_status st = mgrit_solve_start(h, u0, v_init, u_out, u_final);
   if (st != MGRIT_OK) return st;
   return mgrit_solve_finish(h, stats);
@@ -1584,6 +1826,19 @@ mgrit_status mgrit_workspace_bytes(const mgrit_problem *P, const mgrit_options *
   *bytes = n * sizeof(double) +
            (uint64_t)nts.size() * (2 * RTAB_ALL * KMAX * KMAX * sizeof(double) + sizeof(LevelDesc) + 5 * 256) +
            sizeof(GridSync) + 4 * 256 + sizeof(SolveCtl);
+  if (O->precision == MGRIT_PREC_MIXED) {
+    // float32 copies of the level arrays and tables, the inner right-hand
+    // side and solution (float32), the outer residual and iterate (float64)
+    uint64_t n32 = 0;
+    for (size_t l = 0; l + 1 < nts.size(); ++l) {
+      const uint64_t nc = (uint64_t)(nts[l] / ms[l]);
+      n32 += (2 * (nc + 1) + nc) * (uint64_t)P->nx;
+    }
+    const uint64_t pts = (uint64_t)P->nt * (uint64_t)P->nx;
+    *bytes += n32 * sizeof(float) + (2 * pts + P->nx) * sizeof(float) + (2 * pts + P->nx) * sizeof(double) +
+              (uint64_t)nts.size() * (2 * RTAB_ALL * KMAX * KMAX * sizeof(float) + sizeof(LevelDesc) + 5 * 256) +
+              4 * 256;
+  }
   return MGRIT_OK;
 }
 

@@ -41,7 +41,7 @@ constexpr int RTAB_ALL = RTAB + MAXWAVES;
 struct Recurrence {
   int k;
   double a[KMAX];
-  const double *tab;
+  const void *tab;  // the tables in the precision of the kernels that read them
 };
 
 struct StepOp {
@@ -163,20 +163,23 @@ enum PassMode : int {
   MODE_RESID = 6     // one step per time point: space-time residual
 };
 
-struct PassArgs {
+template <class T>
+struct PassArgsT {
   int mode;
   int m;              // steps per interval (MODE_SEQ: total steps; APPLY: nsteps)
   int zero_init;      // start every interval from 0 instead of cin
   int64_t nint;       // intervals / vectors / time points = gridDim.x
-  const double *cin;  // [nint+1][nx] C-points (APPLY/RESID: [nint(+1)][nx])
-  double *cout;       // PASS_A: [nint+1][nx]; APPLY: [nint][nx]
-  const double *g;    // right-hand side rows, g[n-1] for level point n; NULL = 0
-  double *r;          // PASS_B: [nint][nx] residual; RESID: [nint][nx] or NULL
-  double *parent;     // POST_F / SEQ: parent C-point rows to add into
-  double *out;        // FINAL_F / SEQ: output rows
+  const T *cin;       // [nint+1][nx] C-points (APPLY/RESID: [nint(+1)][nx])
+  T *cout;            // PASS_A: [nint+1][nx]; APPLY: [nint][nx]
+  const T *g;         // right-hand side rows, g[n-1] for level point n; NULL = 0
+  T *r;               // PASS_B: [nint][nx] residual; RESID: [nint][nx] or NULL
+  T *parent;          // POST_F / SEQ: parent C-point rows to add into
+  T *out;             // FINAL_F / SEQ: output rows
   double *normpart;   // PASS_B / RESID: per-workgroup partial sum of squares
   const int *stop;    // non-NULL: the launch does nothing once *stop != 0
 };
+using PassArgs = PassArgsT<double>;   // every kernel
+using PassArgs32 = PassArgsT<float>;  // the generic step kernel in FP32 (inner solves of mixed precision)
 
 // Iteration state of one solve, kept in device memory: the kernel that
 // reduces the residual norm also takes the stopping decision, so the passes
@@ -245,6 +248,14 @@ hipError_t launch_reduce(const double *part, int64_t n, double *out, hipStream_t
 hipError_t launch_gather_rows(const double *src, int64_t stride, double *dst, int64_t rows, int nx,
                               hipStream_t stream);
 hipError_t launch_fill(double *dst, int64_t n, double value, hipStream_t stream, const int *stop = nullptr);
+// Float32 passes of the generic step kernel (mixed precision).
+hipError_t launch_pass32(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs32 &pa,
+                         hipStream_t stream);
+hipError_t launch_fill32(float *dst, int64_t n, hipStream_t stream, const int *stop = nullptr);
+// dst[i] = (float) src[i]
+hipError_t launch_round32(const double *src, float *dst, int64_t n, hipStream_t stream);
+// u[i] += (double) e[i]
+hipError_t launch_add32(double *u, const float *e, int64_t n, hipStream_t stream);
 // Sum the n norm partials in a fixed order, set ctl->rho = sqrt(sum) and take
 // the stopping decision of iteration ctl->it (ctl zeroed before the first
 // call of a solve); the new state is also written to ctl_host (pinned host
@@ -301,6 +312,16 @@ hipError_t launch_step_poly_w(const LevelDesc *desc, const Layout &lay, const Pa
 hipError_t launch_step_slc(const LevelDesc *desc, const Layout &lay, const PassArgs &pa, size_t lds,
                            hipStream_t stream);
 hipError_t configure_step_poly_z(size_t bytes);
+// Float32 instances (mgrit_step32_*.hip); the level descriptor's tables are float32.
+hipError_t launch_step32_poly_z(const LevelDesc *desc, const Layout &lay, const PassArgs32 &pa, size_t lds,
+                                hipStream_t stream);
+hipError_t launch_step32_poly_w(const LevelDesc *desc, const Layout &lay, const PassArgs32 &pa, size_t lds,
+                                hipStream_t stream);
+hipError_t launch_step32_slc(const LevelDesc *desc, const Layout &lay, const PassArgs32 &pa, size_t lds,
+                             hipStream_t stream);
+hipError_t configure_step32_poly_z(size_t bytes);
+hipError_t configure_step32_poly_w(size_t bytes);
+hipError_t configure_step32_slc(size_t bytes);
 hipError_t configure_step_poly_w(size_t bytes);
 hipError_t configure_step_slc(size_t bytes);
 // Allow the step kernels to use up to `bytes` of dynamic LDS.

@@ -78,6 +78,24 @@ __global__ void fill_kernel(double *__restrict__ dst, int64_t n, double value, c
     dst[i] = value;
 }
 
+__global__ void fill32_kernel(float *__restrict__ dst, int64_t n, const int *stop) {
+  if (stop && *stop) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = 0.0f;
+}
+
+__global__ void round32_kernel(const double *__restrict__ src, float *__restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
+__global__ void add32_kernel(double *__restrict__ u, const float *__restrict__ e, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    u[i] += (double)e[i];
+}
+
+unsigned grid_for(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 65536); }
+
 }  // namespace
 
 size_t lds_bytes_for(const Layout &lay, int has_solve) {
@@ -89,7 +107,40 @@ hipError_t configure_kernels(size_t bytes) {
   if ((e = configure_lean_kernels(bytes))) return e;
   if ((e = configure_step_poly_z(bytes))) return e;
   if ((e = configure_step_poly_w(bytes))) return e;
-  return configure_step_slc(bytes);
+  if ((e = configure_step_slc(bytes))) return e;
+  if ((e = configure_step32_poly_z(bytes))) return e;
+  if ((e = configure_step32_poly_w(bytes))) return e;
+  return configure_step32_slc(bytes);
+}
+
+hipError_t launch_pass32(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs32 &pa,
+                         hipStream_t stream) {
+  if (pa.nint <= 0) return hipSuccess;
+  const size_t lds = lds_bytes_for(lay, op.has_solve);
+  switch (op.kind) {
+    case OP_POLY_Z: return launch_step32_poly_z(desc, lay, pa, lds, stream);
+    case OP_POLY_W: return launch_step32_poly_w(desc, lay, pa, lds, stream);
+    case OP_SLC: return launch_step32_slc(desc, lay, pa, lds, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fill32(float *dst, int64_t n, hipStream_t stream, const int *stop) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill32_kernel, dim3(grid_for(n)), dim3(256), 0, stream, dst, n, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_round32(const double *src, float *dst, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(round32_kernel, dim3(grid_for(n)), dim3(256), 0, stream, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_add32(double *u, const float *e, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(add32_kernel, dim3(grid_for(n)), dim3(256), 0, stream, u, e, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_pass(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs &pa,

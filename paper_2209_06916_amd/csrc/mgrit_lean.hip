@@ -446,14 +446,15 @@ __global__ void __launch_bounds__(WAVE * NW) slc_kernel(const LevelDesc *__restr
   const StepOp &op = desc->op;
   double *tab_f = smem + lo.tab_f;
   double *tab_b = smem + lo.tab_b;
-  lean_pass<W, K, L, NW>(op, pa, blockIdx.x, smem, tab_f, tab_b, op.fw.tab, op.bw.tab, smem + lo.qf, smem + lo.qb,
+  const double *gtab_f = static_cast<const double *>(op.fw.tab), *gtab_b = static_cast<const double *>(op.bw.tab);
+  lean_pass<W, K, L, NW>(op, pa, blockIdx.x, smem, tab_f, tab_b, gtab_f, gtab_b, smem + lo.qf, smem + lo.qb,
                       smem + lo.red, [&] {
                         // Scan tables to LDS.  No barrier here: the first step's
                         // barrier (after the vector is written to LDS) comes
                         // before any read of them.
                         for (int i = threadIdx.x; i < RTAB_ALL * K * K; i += WAVE * NW) {
-                          tab_f[i] = op.fw.tab[i];
-                          tab_b[i] = op.bw.tab[i];
+                          tab_f[i] = gtab_f[i];
+                          tab_b[i] = gtab_b[i];
                         }
                         return !(pa.stop && *pa.stop);  // the solve has already stopped (uniform)
                       });
@@ -545,8 +546,8 @@ __global__ void __launch_bounds__(WAVE * NW) coarse_vcycle_kernel(CoarsePlan pla
     const StepOp &op = plan.desc[l]->op;
     double *tf = tabs + 2 * l * TABSZ;
     for (int i = threadIdx.x; i < TABSZ; i += T) {
-      tf[i] = op.fw.tab[i];
-      tf[TABSZ + i] = op.bw.tab[i];
+      tf[i] = static_cast<const double *>(op.fw.tab)[i];
+      tf[TABSZ + i] = static_cast<const double *>(op.bw.tab)[i];
     }
   }
   __syncthreads();

@@ -12,9 +12,9 @@ namespace {
 
 hipError_t launch_step_poly_w(const LevelDesc *desc, const Layout &lay, const PassArgs &pa, size_t lds,
                          hipStream_t stream) {
-  return launch_kind<OP_POLY_W>(desc, lay, pa, lds, stream);
+  return launch_kind<OP_POLY_W, double>(desc, lay, pa, lds, stream);
 }
 
-hipError_t configure_step_poly_w(size_t bytes) { return set_lds_all<OP_POLY_W>(bytes); }
+hipError_t configure_step_poly_w(size_t bytes) { return set_lds_all<OP_POLY_W, double>(bytes); }
 
 }  // namespace mgrit

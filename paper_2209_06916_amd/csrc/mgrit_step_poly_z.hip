@@ -12,9 +12,9 @@ namespace {
 
 hipError_t launch_step_poly_z(const LevelDesc *desc, const Layout &lay, const PassArgs &pa, size_t lds,
                          hipStream_t stream) {
-  return launch_kind<OP_POLY_Z>(desc, lay, pa, lds, stream);
+  return launch_kind<OP_POLY_Z, double>(desc, lay, pa, lds, stream);
 }
 
-hipError_t configure_step_poly_z(size_t bytes) { return set_lds_all<OP_POLY_Z>(bytes); }
+hipError_t configure_step_poly_z(size_t bytes) { return set_lds_all<OP_POLY_Z, double>(bytes); }
 
 }  // namespace mgrit

@@ -12,9 +12,9 @@ namespace {
 
 hipError_t launch_step_slc(const LevelDesc *desc, const Layout &lay, const PassArgs &pa, size_t lds,
                          hipStream_t stream) {
-  return launch_kind<OP_SLC>(desc, lay, pa, lds, stream);
+  return launch_kind<OP_SLC, double>(desc, lay, pa, lds, stream);
 }
 
-hipError_t configure_step_slc(size_t bytes) { return set_lds_all<OP_SLC>(bytes); }
+hipError_t configure_step_slc(size_t bytes) { return set_lds_all<OP_SLC, double>(bytes); }
 
 }  // namespace mgrit

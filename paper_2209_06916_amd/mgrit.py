@@ -19,6 +19,7 @@ MAX_NX = 16384
 OK, ENOTCONVERGED, EINVAL, EUNSTABLE, ENOMEM, EDEVICE, EDIVERGED = 0, 1, -1, -2, -3, -4, -5
 ERK, SDIRK = 0, 1
 CG_SL_CORRECTED, CG_IDEAL, CG_SL_PLAIN, CG_REDISC = 0, 1, 2, 3
+PREC_FP64, PREC_MIXED = 0, 1
 
 
 class MgritError(RuntimeError):
@@ -37,14 +38,15 @@ class Options(ctypes.Structure):
     _fields_ = [("max_levels", ctypes.c_int32), ("m", ctypes.c_int32 * (MAX_LEVELS - 1)),
                 ("min_coarse_nt", ctypes.c_int32), ("nu", ctypes.c_int32), ("cg_kind", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("diverge_factor", ctypes.c_double),
-                ("coarse_launch", ctypes.c_int32)]
+                ("coarse_launch", ctypes.c_int32), ("precision", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
+                ("inner_max_iter", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("res0", ctypes.c_double), ("res_final", ctypes.c_double),
                 ("conv_factor", ctypes.c_double), ("res_history", ctypes.POINTER(ctypes.c_double)),
                 ("res_history_cap", ctypes.c_int32), ("res_history_len", ctypes.c_int32),
-                ("t_solve_s", ctypes.c_double)]
+                ("t_solve_s", ctypes.c_double), ("inner_iterations", ctypes.c_int32)]
 
 
 class LevelDesc(ctypes.Structure):
@@ -117,7 +119,7 @@ def make_problem(nx, nt, cfl, p, kind="erk", q=None, velocity=1.0, x_lo=-1.0, x_
 
 
 def make_options(m, max_levels=2, min_coarse_nt=0, nu=1, coarse="sl_corrected", rtol=1e-10, max_iter=30,
-                 diverge_factor=1e8, coarse_launch=0):
+                 diverge_factor=1e8, coarse_launch=0, precision="fp64", inner_rtol=1e-5, inner_max_iter=30):
     o = Options()
     o.max_levels = max_levels
     ms = list(m) if isinstance(m, (list, tuple)) else [m]
@@ -130,6 +132,9 @@ def make_options(m, max_levels=2, min_coarse_nt=0, nu=1, coarse="sl_corrected", 
     o.max_iter = max_iter
     o.diverge_factor = diverge_factor
     o.coarse_launch = coarse_launch
+    o.precision = {"fp64": PREC_FP64, "mixed": PREC_MIXED}[precision]
+    o.inner_rtol = inner_rtol
+    o.inner_max_iter = inner_max_iter
     return o
 
 
@@ -223,7 +228,7 @@ class Solver:
         self._check(st, allow)
         return dict(status=st, iterations=stats.iterations, res0=stats.res0, res_final=stats.res_final,
                     conv_factor=stats.conv_factor, res_history=list(hist[:stats.res_history_len]),
-                    t_solve_s=stats.t_solve_s)
+                    t_solve_s=stats.t_solve_s, inner_iterations=stats.inner_iterations)
 
     # the same solve in steps (mgrit_solve_start / _advance / _finish)
     def solve_start(self, u0, v_init=None, u_out=None, u_final=None):
@@ -247,7 +252,7 @@ class Solver:
         self._check(st, allow)
         return dict(status=st, iterations=stats.iterations, res0=stats.res0, res_final=stats.res_final,
                     conv_factor=stats.conv_factor, res_history=list(hist[:stats.res_history_len]),
-                    t_solve_s=stats.t_solve_s)
+                    t_solve_s=stats.t_solve_s, inner_iterations=stats.inner_iterations)
 
     def residual(self, u, r=None):
         n = ctypes.c_double()

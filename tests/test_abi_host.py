@@ -112,3 +112,18 @@ def test_workspace_bound_grows_with_the_hierarchy():
             rows += 3 * (nt // m) + 2
             nt //= m
         assert b >= rows * 1024 * 8
+
+
+@pytest.mark.parametrize("opt", [dict(precision="mixed", inner_rtol=0.0), dict(precision="mixed", inner_rtol=1.5),
+                                 dict(precision="mixed", inner_max_iter=0)])
+def test_setup_rejects_bad_mixed_precision_options(opt):
+    st, msg = _setup_status(mgrit.make_problem(64, 32, 0.5, 1), mgrit.make_options(4, **opt))
+    assert st == mgrit.EINVAL and "inner" in msg
+
+
+def test_mixed_precision_workspace_holds_the_space_time_arrays():
+    pr = mgrit.make_problem(1024, 512, 0.8, 3)
+    fp64 = mgrit.workspace_bytes(pr, mgrit.make_options([8], max_levels=3))
+    mixed = mgrit.workspace_bytes(pr, mgrit.make_options([8], max_levels=3, precision="mixed"))
+    # outer iterate and residual (float64), inner right-hand side and solution (float32)
+    assert mixed - fp64 >= (2 * 513 * 1024 - 1024) * (8 + 4)
