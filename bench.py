@@ -271,6 +271,63 @@ def serve_bench(n, seed):
     print(json.dumps(line), flush=True)
 
 
+def precision_bench(steps):
+    """Float64 MGRIT against mixed precision (float32 inner MGRIT in float64
+    refinement) on config 2 (nx = nt = 4096, ERK3 + U3, c = 0.85, m = 8,
+    4 levels) and config 3 (nx = nt = 16384, SDIRK3 + U5, c = 0.5, m = 16,
+    levels 16384 -> 1024 -> 64 -> 4), from the seeded U[0,1) initial
+    iterate.  Float64 MGRIT stops at a C-point residual of 1e-10 of its
+    first one (the bench's criterion); mixed precision measures the full
+    space-time residual, whose first value also carries the random
+    F-points, so it stops at 1e-12 of it, which gives the same solution
+    error.  Each result's error is taken against sequential time-stepping
+    on the GPU (mgrit_sequential, the exact solution of the one-step system
+    up to rounding).  A last, untimed solve of each records the GPU time of
+    its phases with the library's event profiler."""
+    import torch
+    from paper_2209_06916_amd import inputs, mgrit
+    dev = torch.device("cuda:0")
+    cases = [("advection1d-4096x4096-erk3u3-vcycle-m8", 4096, 4096, 3, "erk", 3, 0.85, [8, 8, 8], 1002),
+             ("advection1d-16384x16384-sdirk3u5-vcycle-m16", 16384, 16384, 5, "sdirk", 3, 0.5, [16, 16, 16], 1003)]
+    for name, nx, nt, p, kind, q, c, ms, seed in cases:
+        u0 = inputs.u0_fourier(nx, seed)
+        v0 = torch.from_numpy(inputs.initial_iterate(nt, nx, u0, seed)).to(dev)
+        u0_d = torch.from_numpy(u0).to(dev)
+        prob = mgrit.make_problem(nx, nt, c, p, kind, q)
+        out = torch.empty((nt + 1, nx), dtype=torch.float64, device=dev)
+        ref = torch.empty((nt + 1, nx), dtype=torch.float64, device=dev)
+        line = {"workload": name, "dof": nx * nt, "steps": steps}
+        seq = mgrit.Solver(prob, mgrit.make_options(ms, max_levels=len(ms) + 1))
+        seq.sequential(u0_d, ref)
+        torch.cuda.synchronize()
+        ref_norm = torch.linalg.vector_norm(ref).item()
+        for prec in ("fp64", "mixed"):
+            s = mgrit.Solver(prob, mgrit.make_options(ms, max_levels=len(ms) + 1,
+                                                      rtol=1e-10 if prec == "fp64" else 1e-12, max_iter=30,
+                                                      precision=prec))
+            info = s.solve(u0_d, v0, u_out=out)  # warm-up
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(steps):
+                info = s.solve(u0_d, v0, u_out=out)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t) / steps
+            err = torch.linalg.vector_norm(out - ref).item() / ref_norm
+            s.profile_enable(mgrit.PROF_PHASES)
+            s.solve(u0_d, v0, u_out=out)
+            prof = s.profile_read()
+            line[prec] = {"ms_per_solve": 1e3 * wall, "dof_per_s": nx * nt / wall, "status": info["status"],
+                          "iterations": info["iterations"], "inner_iterations": info["inner_iterations"],
+                          "rel_l2_error_vs_sequential": err,
+                          "phase_ms": {k: round(v["total_ms"], 3) for k, v in prof.items() if v["launches"]}}
+            s.close()
+        line["mixed_speedup"] = line["fp64"]["ms_per_solve"] / line["mixed"]["ms_per_solve"]
+        print(json.dumps(line), flush=True)
+        seq.close()
+        del out, ref, v0
+        torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -282,6 +339,8 @@ def main():
                          "COPY_BYTES read + COPY_BYTES written (the counter calibration)")
     ap.add_argument("--serve", type=int, metavar="N", default=0,
                     help="the request-loop benchmark (N independent solves) instead of the single-solve one")
+    ap.add_argument("--precision", action="store_true",
+                    help="float64 against mixed-precision MGRIT on configs 2 and 3 instead of the single-solve bench")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="CPU only: turn the rocprofv3 runs under DIR into the profiles/ summaries")
     args = ap.parse_args()
@@ -297,6 +356,9 @@ def main():
     from paper_2209_06916_amd import inputs, mgrit
     if args.serve:
         serve_bench(args.serve, seed=1005)
+        return
+    if args.precision:
+        precision_bench(max(1, min(args.steps, 5)))
         return
 
     dev = torch.device("cuda:0")

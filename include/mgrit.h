@@ -109,7 +109,8 @@ typedef struct {
  *   time point, all in parallel), its norm and the convergence test, and the
  *   update u += e.  Between them, MGRIT solves A e = r in float32 (every
  *   level's relaxation, residual and coarse solve; zero initial guess) until
- *   its C-point residual falls by inner_rtol.  res0 / res_final / the history
+ *   its C-point residual falls by inner_rtol, or stalls at float32 rounding
+ *   (an iteration that gains less than a factor 2), or inner_max_iter.  res0 / res_final / the history
  *   are then norms of the full space-time residual, iterations counts outer
  *   iterations and inner_iterations the float32 MGRIT iterations. */
 typedef enum { MGRIT_PREC_FP64 = 0, MGRIT_PREC_MIXED = 1 } mgrit_precision;

@@ -1474,7 +1474,7 @@ mgrit_status vcycle(mgrit_handle *h, const double *g, double *parent) {
 mgrit_status queue_iteration(mgrit_handle *h) {
   auto &ss = h->ss;
   Level &L0 = h->lv[0];
-  const StopRule rule{h->opt.rtol, h->opt.diverge_factor, h->opt.max_iter};
+  const StopRule rule{h->opt.rtol, h->opt.diverge_factor, h->opt.max_iter, 0.0};
   for (int s = 0; s < h->opt.nu; ++s) {
     HIPCHK(h, run_fine(h, MGRIT_PROF_FINE_RELAX, MODE_PASS_A, L0.c[ss.cur], L0.c[1 - ss.cur], nullptr, nullptr));
     ss.cur = 1 - ss.cur;
@@ -1600,7 +1600,9 @@ mgrit_status inner_solve(mgrit_handle *h, int *iters, int *stop) {
   Level &L0 = h->lv[0];
   const int nx = (int)h->prob.nx;
   const int64_t nc = L0.nt / L0.m;
-  const StopRule rule{h->opt.inner_rtol, h->opt.diverge_factor, h->opt.inner_max_iter};
+  // a float32 residual cannot fall much below float32 rounding of the
+  // iterate: an iteration that gains less than a factor 2 ends the solve
+  const StopRule rule{h->opt.inner_rtol, h->opt.diverge_factor, h->opt.inner_max_iter, 0.5};
   int cur = 0;
   HIPCHK(h, launch_fill32(L0.c32[0], (nc + 1) * (int64_t)nx, h->stream));
   HIPCHK(h, hipMemsetAsync(h->ctl, 0, sizeof(SolveCtl), h->stream));

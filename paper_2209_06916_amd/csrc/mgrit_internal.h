@@ -191,7 +191,8 @@ enum StopCode : int {
   STOP_MAX_ITER = 2,
   STOP_NONFINITE = 3,
   STOP_DIVERGED = 4,
-  STOP_DEVICE = 5  // a persistent launch gave up at a grid barrier
+  STOP_DEVICE = 5,  // a persistent launch gave up at a grid barrier
+  STOP_STALLED = 6  // the residual fell by less than StopRule::stall in one iteration
 };
 struct SolveCtl {
   double res0;  // ||r_0||
@@ -204,6 +205,7 @@ struct StopRule {
   double rtol;
   double diverge_factor;  // <= 0: no growth test
   int max_iter;
+  double stall;           // > 0: stop once ||r_it|| > stall ||r_{it-1}|| (float32 inner solves)
 };
 
 // Level-0 explicit relaxation with wavefront tiles (temporal blocking): one

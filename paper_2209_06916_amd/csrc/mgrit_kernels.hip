@@ -26,7 +26,8 @@ __global__ void __launch_bounds__(256) reduce_kernel(const double *__restrict__ 
 
 // Residual norm of one MGRIT iteration and the stopping test (Sec. 2.2: stop
 // once ||r_it|| <= rtol ||r_0||), in the order the solver applies them:
-// non-finite, converged, iteration limit, growth past diverge_factor ||r_0||.
+// non-finite, converged, stalled (inner float32 solves only), iteration
+// limit, growth past diverge_factor ||r_0||.
 __global__ void __launch_bounds__(256) solve_ctl_kernel(const double *__restrict__ part, int64_t n,
                                                          SolveCtl *ctl, SolveCtl *ctl_host, const GridSync *gs,
                                                          StopRule rule) {
@@ -42,6 +43,7 @@ __global__ void __launch_bounds__(256) solve_ctl_kernel(const double *__restrict
   if (threadIdx.x != 0) return;
   const double rho = sqrt(red[0]);
   const int it = ctl->it;
+  const double prev = ctl->rho;
   const double res0 = it == 0 ? rho : ctl->res0;
   ctl->res0 = res0;
   ctl->rho = rho;
@@ -52,6 +54,8 @@ __global__ void __launch_bounds__(256) solve_ctl_kernel(const double *__restrict
     stop = STOP_NONFINITE;
   else if (rho <= rule.rtol * res0)
     stop = STOP_CONVERGED;
+  else if (rule.stall > 0 && it >= 1 && rho > rule.stall * prev)
+    stop = STOP_STALLED;
   else if (it >= rule.max_iter)
     stop = STOP_MAX_ITER;
   else if (rule.diverge_factor > 0 && rho > rule.diverge_factor * res0)
