@@ -17,7 +17,8 @@ Schedule (identical on the GPU side):
   coarse level (V-cycle, recursive): start from v = 0, same pre-relaxation and
     residual, recurse, correct the C-points, then post F-relaxation.
 The reported iteration count is the number of coarse-grid corrections done.
-Arrays hold every time point of a level ([nt+1, nx]); F-relaxation advances all
+Arrays hold every time point of a level ([nt+1, nx], or [nt+1, ny, nx] for
+the 2D hierarchy of oracle.advection2d); F-relaxation advances all
 CF-intervals at once (they are independent by definition).
 """
 import numpy as np
@@ -41,6 +42,7 @@ class Hierarchy:
 
     def __init__(self, nx, nt, p, kind, q, c, ms, coarse="sl_corrected"):
         self.nx, self.nt = nx, nt
+        self.space = (nx,)  # shape of one time point's vector
         self.p, self.kind, self.q, self.c = p, kind, q, float(c)
         self.ms = list(ms)
         self.nts = [nt]
@@ -93,8 +95,9 @@ def coarsening_schedule(nt, m, min_coarse_nt, max_levels=32):
 # ---------------------------------------------------------------------------
 
 def sequential(step, u0, nt):
-    """u_{n+1} = Phi u_n, n = 0..nt-1; returns [nt+1, nx]."""
-    u = np.empty((nt + 1, len(u0)))
+    """u_{n+1} = Phi u_n, n = 0..nt-1; returns [nt+1, nx] ([nt+1, ny, nx] in 2D)."""
+    u0 = np.asarray(u0, dtype=float)
+    u = np.empty((nt + 1,) + u0.shape)
     u[0] = u0
     for n in range(nt):
         u[n + 1] = step(u[n])
@@ -149,7 +152,7 @@ def vcycle(H, lev, g, nu):
     Returns the full level iterate [nt_lev+1, nx]."""
     nt = H.nts[lev]
     step = H.steps[lev]
-    v = np.zeros((nt + 1, H.nx))
+    v = np.zeros((nt + 1,) + H.space)
     if lev == H.nlevels - 1:
         for n in range(1, nt + 1):
             v[n] = step(v[n - 1]) + g[n]
@@ -157,7 +160,7 @@ def vcycle(H, lev, g, nu):
     m = H.ms[lev]
     _pre_relax(v, g, step, m, nu)
     r = c_residual(v, g, step, m)
-    gc = np.zeros((nt // m + 1, H.nx))
+    gc = np.zeros((nt // m + 1,) + H.space)
     gc[1:] = r
     e = vcycle(H, lev + 1, gc, nu)
     v[0::m] += e
@@ -192,7 +195,7 @@ def solve(H, u0, v_init, rtol=1e-10, max_iter=30, nu=1, record=False):
             raise FloatingPointError("MGRIT diverged (non-finite residual)")
         if rho <= rtol * hist[0] or it == max_iter:
             break
-        gc = np.zeros((nt // m + 1, H.nx))
+        gc = np.zeros((nt // m + 1,) + H.space)
         gc[1:] = r
         e = vcycle(H, 1, gc, nu)
         v[0::m] += e
