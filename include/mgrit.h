@@ -257,6 +257,57 @@ const char *mgrit_status_string(mgrit_status s);
 const char *mgrit_last_error(const mgrit_handle *h);
 void mgrit_destroy(mgrit_handle *h);
 
+/* ------------------------------------------------------------------------
+ * 2D extension: u_t + a_x u_x + a_y u_y = 0 on a periodic rectangle.  The
+ * paper is one-dimensional; this follows one reading of it:
+ *  - fine step: one explicit Runge-Kutta step (ERK1..5) of the
+ *    dimension-split semi-discretisation -(c_x L_p^(x) + c_y L_p^(y)), the 1D
+ *    upwind stencil of Sec. 4.1 along each axis, c_x = a_x dt / h_x,
+ *    c_y = a_y dt / h_y;
+ *  - coarse step on level l: the 1D corrected semi-Lagrangian step of eq.
+ *    (MOL-SL-corrected-multilevel) along x with the coefficients of the 1D
+ *    problem at CFL c_x, then the same along y for c_y (a tensor-product
+ *    semi-Lagrangian step and one periodic banded solve per grid line in
+ *    each direction);
+ *  - MGRIT as in the 1D solver (Sec. 2.2): F(CF)^nu relaxation, C-point
+ *    residual, V-cycle, sequential coarsest level, float64 throughout.
+ * Space-time arrays are [nt+1][ny][nx] float64, x contiguous.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  double velocity_x, velocity_y; /* a_x, a_y > 0                              */
+  double x_lo, x_hi, y_lo, y_hi; /* periodic rectangle                        */
+  int64_t nx, ny;                /* points per axis, 1 <= n <= MGRIT_MAX_NX   */
+  int64_t nt;                    /* time steps                                */
+  double dt;                     /* time step > 0                             */
+  int32_t upwind_order;          /* p in {1, 3, 5} (the coarse step needs odd p) */
+  int32_t rk_order;              /* ERK order q in 1..5                       */
+} mgrit2d_problem;
+
+typedef struct mgrit2d_handle mgrit2d_handle;
+
+/* Validate, build the hierarchy from options (max_levels, m, min_coarse_nt,
+ * nu, rtol, max_iter, diverge_factor; cg_kind must be
+ * MGRIT_CG_SL_CORRECTED and precision MGRIT_PREC_FP64, else MGRIT_EINVAL),
+ * factorise the x- and y-line operators of every coarse level and allocate
+ * the workspace (owned by the handle).  MGRIT_EUNSTABLE when the fine step's
+ * amplification factor exceeds 1 on a 256 x 256 grid of frequencies. */
+mgrit_status mgrit2d_setup(const mgrit2d_problem *problem, const mgrit_options *options, void *hip_stream,
+                           mgrit2d_handle **out);
+/* MGRIT solve; arguments and statuses as mgrit_solve, with [ny][nx] slabs:
+ * u0_dev [ny][nx]; v_init_dev [nt+1][ny][nx] or NULL (zero; only C-points
+ * are read); u_out_dev [nt+1][ny][nx] or NULL; u_final_dev [ny][nx] or NULL. */
+mgrit_status mgrit2d_solve(mgrit2d_handle *h, const double *u0_dev, const double *v_init_dev, double *u_out_dev,
+                           double *u_final_dev, mgrit_stats *stats);
+/* Sequential time-stepping of the fine step: u_out_dev [nt+1][ny][nx]. */
+mgrit_status mgrit2d_sequential(mgrit2d_handle *h, const double *u0_dev, double *u_out_dev);
+/* count slabs: v_out = step_level(v_in) (level 0 = fine; v_in and v_out may
+ * not overlap). */
+mgrit_status mgrit2d_apply_step(mgrit2d_handle *h, int32_t level, const double *v_in_dev, double *v_out_dev,
+                                int64_t count);
+int32_t mgrit2d_num_levels(const mgrit2d_handle *h);
+const char *mgrit2d_last_error(const mgrit2d_handle *h);
+void mgrit2d_destroy(mgrit2d_handle *h);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,7 +16,7 @@ SOURCES = [os.path.join(CSRC, f) for f in ("mgrit_step_poly_z.hip", "mgrit_step_
                                            "mgrit_step32_poly_z.hip", "mgrit_step32_poly_w.hip", "mgrit_step32_slc.hip",
                                            "mgrit_lean.hip",
                                            "mgrit_tile4.hip", "mgrit_tile8.hip", "mgrit_tile16.hip",
-                                           "mgrit_kernels.hip", "mgrit_host.cpp")]
+                                           "mgrit_kernels.hip", "mgrit_2d.hip", "mgrit_host.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 BUILD_DIR = os.path.join(PKG, "_build")
 

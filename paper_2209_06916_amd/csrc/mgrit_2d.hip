@@ -1,0 +1,198 @@
+// gfx950 kernels of the 2D extension (dimension-split reading): the fused
+// explicit Runge-Kutta step on 2D tiles, the batched slab transpose that
+// lets the 1D coarse-step kernels run along y, and small batched slab
+// operations.  Slabs are [ny][nx] float64, x contiguous; a batch of nb slabs
+// has a stride (in elements) between consecutive slabs.
+#include "mgrit_internal.h"
+
+namespace mgrit {
+
+namespace {
+
+constexpr int TX = 64, TY = 16;  // output tile of one workgroup (256 threads)
+
+__device__ __forceinline__ int wrap(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+// One explicit Runge-Kutta step Phi = R(Z), Z = -(c_x L_p^(x) + c_y L_p^(y)),
+// as the Horner form y <- coef[i] u + Z y, on one TX x TY output tile of one
+// slab.  The tile and a halo of s*l (left/below) and s*r (right/above)
+// points on each axis sit in LDS; every stencil application shrinks the
+// valid region by the stencil extent, so after the s applications exactly
+// the output tile is valid.  dst = Phi(src) (+ g).
+__global__ void __launch_bounds__(256) step2d_kernel(Step2dArgs a) {
+  extern __shared__ double lds[];
+  const int nx = a.nx, ny = a.ny;
+  const int s = a.ncoef - 1;  // stencil applications
+  const int hl = s * a.sl, hr = s * a.sr;
+  const int wx = TX + hl + hr, wy = TY + hl + hr;
+  const int area = wx * wy;
+  double *u = lds, *y0 = lds + area, *y1 = lds + 2 * area;
+  const int tiles_x = (nx + TX - 1) / TX, tiles_y = (ny + TY - 1) / TY;
+  const int64_t item = blockIdx.x;
+  const int64_t b = item / ((int64_t)tiles_x * tiles_y);
+  const int t = (int)(item - b * tiles_x * tiles_y);
+  const int x0 = (t % tiles_x) * TX - hl, y0g = (t / tiles_x) * TY - hl;
+  const double *src = a.src + b * a.src_stride;
+  const double top = a.coef[a.ncoef - 1];
+  for (int i = threadIdx.x; i < area; i += 256) {
+    const int lx = i % wx, ly = i / wx;
+    const double v = src[(int64_t)wrap(y0g + ly, ny) * nx + wrap(x0 + lx, nx)];
+    u[i] = v;
+    y0[i] = top * v;
+  }
+  __syncthreads();
+  const int nt_ = a.sl + a.sr + 1;
+  double *yin = y0, *yout = y1;
+  for (int k = 1; k <= s; ++k) {
+    const double ci = a.coef[a.ncoef - 1 - k];
+    // valid after this application: [k*sl, w - k*sr) on both axes
+    const int lo = k * a.sl, hx = wx - k * a.sr, hy = wy - k * a.sr;
+    const int cw = hx - lo, ch = hy - lo;
+    for (int i = threadIdx.x; i < cw * ch; i += 256) {
+      const int lx = lo + i % cw, ly = lo + i / cw;
+      double acc = ci * u[ly * wx + lx];
+      for (int tt = 0; tt < nt_; ++tt) {
+        const int d = tt - a.sl;
+        acc = fma(a.tx[tt], yin[ly * wx + lx + d], acc);
+        acc = fma(a.ty[tt], yin[(ly + d) * wx + lx], acc);
+      }
+      yout[ly * wx + lx] = acc;
+    }
+    __syncthreads();
+    double *tmp = yin;
+    yin = yout;
+    yout = tmp;
+  }
+  double *dst = a.dst + b * a.dst_stride;
+  const double *g = a.g ? a.g + b * a.g_stride : nullptr;
+  for (int i = threadIdx.x; i < TX * TY; i += 256) {
+    const int ox = i % TX, oy = i / TX;
+    const int gx = x0 + hl + ox, gy = y0g + hl + oy;
+    if (gx >= nx || gy >= ny) continue;
+    const int64_t o = (int64_t)gy * nx + gx;
+    double v = yin[(oy + hl) * wx + ox + hl];
+    if (g) v += g[o];
+    dst[o] = v;
+  }
+}
+
+// dst slab b = transpose of src slab b ([rows][cols] -> [cols][rows]),
+// plus g slab b (already in the destination layout) when given.
+__global__ void __launch_bounds__(256) transpose_kernel(const double *__restrict__ src, int64_t src_stride,
+                                                         double *__restrict__ dst, int64_t dst_stride,
+                                                         const double *__restrict__ g, int64_t g_stride, int rows,
+                                                         int cols) {
+  __shared__ double tile[32][33];
+  const int tiles_c = (cols + 31) / 32, tiles_r = (rows + 31) / 32;
+  const int64_t item = blockIdx.x;
+  const int64_t b = item / ((int64_t)tiles_c * tiles_r);
+  const int t = (int)(item - b * tiles_c * tiles_r);
+  const int c0 = (t % tiles_c) * 32, r0 = (t / tiles_c) * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const double *s = src + b * src_stride;
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k, c = c0 + tx;
+    if (r < rows && c < cols) tile[k][tx] = s[(int64_t)r * cols + c];
+  }
+  __syncthreads();
+  double *d = dst + b * dst_stride;
+  const double *gg = g ? g + b * g_stride : nullptr;
+  for (int k = ty; k < 32; k += 8) {
+    const int c = c0 + k, r = r0 + tx;  // destination row c, column r
+    if (r < rows && c < cols) {
+      const int64_t o = (int64_t)c * rows + r;
+      double v = tile[tx][k];
+      if (gg) v += gg[o];
+      d[o] = v;
+    }
+  }
+}
+
+// dst slab b (+)= src slab b, n points per slab
+__global__ void __launch_bounds__(256) slab_axpy_kernel(double *__restrict__ dst, int64_t dst_stride,
+                                                         const double *__restrict__ src, int64_t src_stride,
+                                                         int64_t nb, int64_t n, int accumulate) {
+  const int64_t total = nb * n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = i / n, j = i - b * n;
+    const double v = src[b * src_stride + j];
+    double *p = dst + b * dst_stride + j;
+    *p = accumulate ? *p + v : v;
+  }
+}
+
+// r slab b = a slab b - c slab b; part[b * blocks_per_slab + k] = sum of
+// squares over block k of slab b (fixed order: deterministic)
+__global__ void __launch_bounds__(256) slab_resid_kernel(const double *__restrict__ a, const double *__restrict__ c,
+                                                          double *__restrict__ r, int64_t n, int blocks_per_slab,
+                                                          double *__restrict__ part) {
+  __shared__ double red[256];
+  const int64_t b = blockIdx.x / blocks_per_slab;
+  const int k = (int)(blockIdx.x - b * blocks_per_slab);
+  const int64_t chunk = (n + blocks_per_slab - 1) / blocks_per_slab;
+  const int64_t j0 = k * chunk, j1 = min(n, j0 + chunk);
+  double ss = 0.0;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) {
+    const double v = a[b * n + j] - c[b * n + j];
+    if (r) r[b * n + j] = v;
+    ss = fma(v, v, ss);
+  }
+  red[threadIdx.x] = ss;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if (threadIdx.x < d) red[threadIdx.x] += red[threadIdx.x + d];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+unsigned blocks_for(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 65536); }
+
+}  // namespace
+
+size_t step2d_lds_bytes(int ncoef, int sl, int sr) {
+  const int s = ncoef - 1;
+  return (size_t)3 * (TX + s * (sl + sr)) * (TY + s * (sl + sr)) * sizeof(double);
+}
+
+hipError_t configure_2d_kernels(size_t bytes) {
+  return hipFuncSetAttribute((const void *)step2d_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_step2d(const Step2dArgs &a, hipStream_t stream) {
+  if (a.nb <= 0) return hipSuccess;
+  const int64_t tiles = (int64_t)((a.nx + TX - 1) / TX) * ((a.ny + TY - 1) / TY);
+  const size_t lds = step2d_lds_bytes(a.ncoef, a.sl, a.sr);
+  hipLaunchKernelGGL(step2d_kernel, dim3((unsigned)(tiles * a.nb)), dim3(256), lds, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(const double *src, int64_t src_stride, double *dst, int64_t dst_stride, const double *g,
+                            int64_t g_stride, int64_t nb, int rows, int cols, hipStream_t stream) {
+  if (nb <= 0) return hipSuccess;
+  const int64_t tiles = (int64_t)((cols + 31) / 32) * ((rows + 31) / 32);
+  hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)(tiles * nb)), dim3(256), 0, stream, src, src_stride, dst,
+                     dst_stride, g, g_stride, rows, cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_slab_axpy(double *dst, int64_t dst_stride, const double *src, int64_t src_stride, int64_t nb,
+                            int64_t n, bool accumulate, hipStream_t stream) {
+  if (nb <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(slab_axpy_kernel, dim3(blocks_for(nb * n)), dim3(256), 0, stream, dst, dst_stride, src,
+                     src_stride, nb, n, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_slab_resid(const double *a, const double *c, double *r, int64_t nb, int64_t n, int blocks_per_slab,
+                             double *part, hipStream_t stream) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(slab_resid_kernel, dim3((unsigned)(nb * blocks_per_slab)), dim3(256), 0, stream, a, c, r, n,
+                     blocks_per_slab, part);
+  return hipGetLastError();
+}
+
+}  // namespace mgrit

@@ -822,6 +822,74 @@ bool erk_stable(const FineInfo &fi, double c) {
   return ok;
 }
 
+// The corrected semi-Lagrangian coarse step of every coarse level
+// (eqs. MOL-SL-corrected, MOL-SL-corrected-multilevel) for the 1D problem at
+// CFL c on n points: level l (1-based) steps by m_1...m_l fine steps, its
+// shift is c m_1...m_l, and phi follows the recursion over the levels
+// (phi_q carries the Runge-Kutta term separately when q != p).  plain: phi = 0.
+struct SlLevel {
+  double shift = 0, eps = 0, phi_p = 0, phi_q = 0;
+  int64_t K = 0;
+  StepOp op{};
+  Layout lay{};
+  std::vector<double> tabs;
+  std::vector<size_t> offs;
+};
+
+bool sl_chain(const FineInfo &fi, int p, int q, double c, const std::vector<int> &ms, int n, int Lcoarse, bool plain,
+              std::vector<SlLevel> &out, std::string &err) {
+  const int sgn = ((p + 1) % 2) ? -1 : 1;  // (-1)^{p+1}
+  ld prod = 1, phi_p = 0, phi_q = 0, eps_prev = 0;
+  out.assign(ms.size(), SlLevel{});
+  for (size_t i = 0; i < ms.size(); ++i) {
+    SlLevel &Lv = out[i];
+    const int mcur = ms[i];
+    prod *= mcur;
+    const ld shift = (ld)c * prod;
+    const ld Kf = std::floor(shift);
+    const ld eps = shift - Kf;
+    if (i == 0) {
+      if (q == p) {
+        phi_p = mcur * ((ld)c * fi.efd + std::pow(-(ld)c, (ld)(p + 1)) * fi.erk) + sgn * f_poly(p, eps);
+        phi_q = 0;
+      } else {
+        phi_p = mcur * (ld)c * fi.efd + sgn * f_poly(p, eps);
+        phi_q = mcur * std::pow(-(ld)c, (ld)(q + 1)) * fi.erk;
+      }
+    } else {
+      phi_p = sgn * (-mcur * f_poly(p, eps_prev) + f_poly(p, eps)) + mcur * phi_p;
+      phi_q = mcur * phi_q;
+    }
+    eps_prev = eps;
+    Lv.shift = (double)shift;
+    Lv.K = (int64_t)Kf;
+    Lv.eps = (double)eps;
+    Lv.phi_p = plain ? 0.0 : (double)phi_p;
+    Lv.phi_q = plain ? 0.0 : (double)phi_q;
+    StepOp &op = Lv.op;
+    op = StepOp{};
+    op.kind = OP_SLC;
+    op.repeat = 1;
+    std::vector<double> slw;
+    sl_weights(p, eps, op.sl_l, op.sl_r, slw);
+    for (size_t j = 0; j < slw.size(); ++j) op.slw[j] = slw[j];
+    op.sl_K = (int)(((int64_t)Kf) % n);
+    std::map<int, ld> taps;
+    taps[0] += 1;
+    for (auto &kv : dmat(p + 1)) taps[kv.first] -= (ld)Lv.phi_p * kv.second;
+    if (Lv.phi_q != 0)
+      for (auto &kv : dmat(q + 1)) taps[kv.first] -= (ld)Lv.phi_q * kv.second;
+    Lv.lay = choose_layout(n, Lcoarse);
+    Lv.lay.dbuf = 1;
+    if (lds_bytes_for(Lv.lay, 1) > LDS_LIMIT) Lv.lay.dbuf = 0;
+    if (!attach_solve(op, taps, Lv.lay, Lv.tabs, Lv.offs, err)) {
+      err = "coarse operator: " + err;
+      return false;
+    }
+  }
+  return true;
+}
+
 // One Runge-Kutta step of the upwind semi-discretisation at CFL c
 // (eq. MOL_M_def), as a Horner form: ERK R(z) in z = -c L_p (OP_POLY_Z);
 // SDIRK R as a polynomial in w = (I + gamma c L_p)^{-1} (OP_POLY_W), every
@@ -1022,9 +1090,30 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
   }
 
   // ---- coarse operators (eqs. MOL-SL-corrected, MOL-SL-corrected-multilevel)
-  {
-    const int sgn = ((p + 1) % 2) ? -1 : 1;  // (-1)^{p+1}
-    ld prod = 1, phi_p = 0, phi_q = 0, eps_prev = 0;
+  if (O->cg_kind == MGRIT_CG_SL_CORRECTED || O->cg_kind == MGRIT_CG_SL_PLAIN) {
+    std::vector<SlLevel> chain;
+    if (!sl_chain(fi, p, q, c, std::vector<int>(ms.begin(), ms.begin() + (nlev - 1)), nx, Lcoarse,
+                  O->cg_kind == MGRIT_CG_SL_PLAIN, chain, err)) {
+      mgrit_destroy(h);
+      return bad(MGRIT_EINVAL, err);
+    }
+    for (int l = 1; l < nlev; ++l) {
+      Level &Lv = h->lv[l];
+      SlLevel &S = chain[l - 1];
+      Lv.nt = nts[l];
+      Lv.m = (l < nlev - 1) ? ms[l] : 0;
+      Lv.shift = S.shift;
+      Lv.K = S.K;
+      Lv.eps = S.eps;
+      Lv.phi_p = S.phi_p;
+      Lv.phi_q = S.phi_q;
+      Lv.op = S.op;
+      Lv.lay = S.lay;
+      tabs[l] = std::move(S.tabs);
+      offs[l] = std::move(S.offs);
+    }
+  } else {
+    ld prod = 1;
     for (int l = 1; l < nlev; ++l) {
       Level &Lv = h->lv[l];
       Lv.nt = nts[l];
@@ -1039,58 +1128,15 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
         offs[l] = offs[0];
         continue;
       }
-      if (O->cg_kind == MGRIT_CG_REDISC) {
-        // the fine scheme rediscretised with the level's step (Sec. 5, Theorem 1)
-        const double cl = (double)((ld)c * prod);
-        if (P->rk_kind == MGRIT_ERK && !erk_stable(fi, cl)) {
-          mgrit_destroy(h);
-          return bad(MGRIT_EUNSTABLE, "rediscretised explicit coarse step above its CFL limit");
-        }
-        Lv.shift = cl;
-        if (!build_mol_step(fi, P->rk_kind, cl, nx, Lcoarse, Lv.op, Lv.lay, tabs[l], offs[l], err)) {
-          mgrit_destroy(h);
-          return bad(MGRIT_EINVAL, "coarse operator: " + err);
-        }
-        continue;
+      // MGRIT_CG_REDISC: the fine scheme rediscretised with the level's step
+      // (Sec. 5, Theorem 1)
+      const double cl = (double)((ld)c * prod);
+      if (P->rk_kind == MGRIT_ERK && !erk_stable(fi, cl)) {
+        mgrit_destroy(h);
+        return bad(MGRIT_EUNSTABLE, "rediscretised explicit coarse step above its CFL limit");
       }
-      const ld shift = (ld)c * prod;
-      const ld Kf = std::floor(shift);
-      const ld eps = shift - Kf;
-      if (l == 1) {
-        if (q == p) {
-          phi_p = mcur * ((ld)c * fi.efd + std::pow(-(ld)c, (ld)(p + 1)) * fi.erk) + sgn * f_poly(p, eps);
-          phi_q = 0;
-        } else {
-          phi_p = mcur * (ld)c * fi.efd + sgn * f_poly(p, eps);
-          phi_q = mcur * std::pow(-(ld)c, (ld)(q + 1)) * fi.erk;
-        }
-      } else {
-        phi_p = sgn * (-mcur * f_poly(p, eps_prev) + f_poly(p, eps)) + mcur * phi_p;
-        phi_q = mcur * phi_q;
-      }
-      eps_prev = eps;
-      Lv.shift = (double)shift;
-      Lv.K = (int64_t)Kf;
-      Lv.eps = (double)eps;
-      Lv.phi_p = O->cg_kind == MGRIT_CG_SL_PLAIN ? 0.0 : (double)phi_p;
-      Lv.phi_q = O->cg_kind == MGRIT_CG_SL_PLAIN ? 0.0 : (double)phi_q;
-      StepOp &op = Lv.op;
-      op = StepOp{};
-      op.kind = OP_SLC;
-      op.repeat = 1;
-      std::vector<double> slw;
-      sl_weights(p, eps, op.sl_l, op.sl_r, slw);
-      for (size_t j = 0; j < slw.size(); ++j) op.slw[j] = slw[j];
-      op.sl_K = (int)(((int64_t)Kf) % nx);
-      std::map<int, ld> taps;
-      taps[0] += 1;
-      for (auto &kv : dmat(p + 1)) taps[kv.first] -= (ld)Lv.phi_p * kv.second;
-      if (Lv.phi_q != 0)
-        for (auto &kv : dmat(q + 1)) taps[kv.first] -= (ld)Lv.phi_q * kv.second;
-      Lv.lay = choose_layout(nx, Lcoarse);
-      Lv.lay.dbuf = 1;
-      if (lds_bytes_for(Lv.lay, 1) > LDS_LIMIT) Lv.lay.dbuf = 0;
-      if (!attach_solve(op, taps, Lv.lay, tabs[l], offs[l], err)) {
+      Lv.shift = cl;
+      if (!build_mol_step(fi, P->rk_kind, cl, nx, Lcoarse, Lv.op, Lv.lay, tabs[l], offs[l], err)) {
         mgrit_destroy(h);
         return bad(MGRIT_EINVAL, "coarse operator: " + err);
       }
@@ -1971,6 +2017,464 @@ mgrit_status mgrit_lfa_rho(const mgrit_problem *P, const mgrit_options *O, doubl
   }
   *rho = best;
   return MGRIT_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// 2D extension (dimension-split reading; see mgrit.h)
+// ===========================================================================
+namespace {
+
+struct Line1D {  // a 1D coarse step applied along one axis of every slab
+  StepOp op{};
+  Layout lay{};
+  LevelDesc *desc = nullptr;
+};
+
+struct Level2 {
+  int64_t nt = 0;
+  int m = 0;         // to the next level, 0 on the coarsest
+  Line1D x, y;       // levels >= 1
+  double *c[2] = {nullptr, nullptr};  // C-points, nc + 1 slabs
+  double *r = nullptr;                // C-point residual, nc slabs
+};
+
+}  // namespace
+
+struct mgrit2d_handle {
+  mgrit2d_problem prob{};
+  mgrit_options opt{};
+  hipStream_t stream = nullptr;
+  std::vector<Level2> lv;
+  Step2dArgs fine{};  // fine-step constants (pointers set per launch)
+  int64_t cap = 0;    // slabs the work buffers hold
+  double *w[2] = {nullptr, nullptr}, *t1 = nullptr, *t2 = nullptr;
+  double *zero = nullptr;  // one zero slab
+  double *normpart = nullptr, *normsum = nullptr, *normsum_host = nullptr;
+  int64_t normpart_len = 0;
+  char *arena = nullptr;
+  std::string err;
+};
+
+namespace {
+
+constexpr int RESID_BLOCKS = 64;  // partial sums per slab of the C-point residual
+
+mgrit_status fail2(mgrit2d_handle *h, mgrit_status s, const std::string &msg) {
+  h->err = msg;
+  return s;
+}
+
+#define HIPCHK2(h, expr)                                                                   \
+  do {                                                                                     \
+    const hipError_t e2_ = (expr);                                                         \
+    if (e2_ != hipSuccess) return fail2((h), MGRIT_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e2_)); \
+  } while (0)
+
+int64_t slab(const mgrit2d_handle *h) { return h->prob.nx * h->prob.ny; }
+
+// dst = Phi_l(src) (+ g) on nb contiguous slabs (g: slab b at g + b g_stride)
+hipError_t apply2d(mgrit2d_handle *h, int l, const double *src, double *dst, int64_t nb, const double *g,
+                   int64_t g_stride) {
+  const int nx = (int)h->prob.nx, ny = (int)h->prob.ny;
+  const int64_t S = slab(h);
+  if (l == 0) {
+    Step2dArgs a = h->fine;
+    a.src = src;
+    a.src_stride = S;
+    a.dst = dst;
+    a.dst_stride = S;
+    a.g = g;
+    a.g_stride = g_stride;
+    a.nb = nb;
+    return launch_step2d(a, h->stream);
+  }
+  const Level2 &L = h->lv[l];
+  // along x: every row of every slab is one 1D vector
+  PassArgs pa{};
+  pa.mode = MODE_APPLY;
+  pa.m = 1;
+  pa.nint = nb * ny;
+  pa.cin = src;
+  pa.cout = h->t1;
+  if (hipError_t e = launch_pass(L.x.desc, L.x.op, L.x.lay, pa, h->stream)) return e;
+  if (hipError_t e = launch_transpose(h->t1, S, h->t2, S, nullptr, 0, nb, ny, nx, h->stream)) return e;
+  // along y: the rows of the transposed slabs, in place
+  pa.nint = nb * nx;
+  pa.cin = h->t2;
+  pa.cout = h->t2;
+  if (hipError_t e = launch_pass(L.y.desc, L.y.op, L.y.lay, pa, h->stream)) return e;
+  return launch_transpose(h->t2, S, dst, S, g, g_stride, nb, nx, ny, h->stream);
+}
+
+// One relaxation pass (PassMode) of level l over all its CF-intervals at
+// once: the intervals' vectors advance together, one step per launch group.
+mgrit_status relax2d(mgrit2d_handle *h, int l, int mode, const double *cin, double *cout, const double *g, double *r,
+                     double *parent, double *out) {
+  const Level2 &L = h->lv[l];
+  const int64_t S = slab(h);
+  const int m = L.m;
+  const int64_t nc = L.nt / m;
+  const int nsteps = (mode == MODE_POST_F || mode == MODE_FINAL_F) ? m - 1 : m;
+  if (mode == MODE_POST_F) HIPCHK2(h, launch_slab_axpy(parent, m * S, cin, S, nc, S, true, h->stream));
+  if (mode == MODE_FINAL_F) HIPCHK2(h, launch_slab_axpy(out, m * S, cin, S, nc, S, false, h->stream));
+  const double *src = cin;
+  for (int j = 1; j <= nsteps; ++j) {
+    double *dst = h->w[j & 1];
+    HIPCHK2(h, apply2d(h, l, src, dst, nc, g ? g + (j - 1) * S : nullptr, m * S));
+    if (mode == MODE_POST_F) HIPCHK2(h, launch_slab_axpy(parent + j * S, m * S, dst, S, nc, S, true, h->stream));
+    if (mode == MODE_FINAL_F) HIPCHK2(h, launch_slab_axpy(out + j * S, m * S, dst, S, nc, S, false, h->stream));
+    src = dst;
+  }
+  if (mode == MODE_PASS_A) {
+    if (cout != cin) HIPCHK2(h, launch_slab_axpy(cout, S, cin, S, 1, S, false, h->stream));
+    HIPCHK2(h, launch_slab_axpy(cout + S, S, src, S, nc, S, false, h->stream));
+  } else if (mode == MODE_PASS_B) {
+    HIPCHK2(h, launch_slab_resid(src, cin + S, r, nc, S, RESID_BLOCKS, h->normpart, h->stream));
+  } else if (mode == MODE_POST_F) {
+    HIPCHK2(h, launch_slab_axpy(parent + nc * m * S, S, cin + nc * S, S, 1, S, true, h->stream));
+  } else if (mode == MODE_FINAL_F) {
+    HIPCHK2(h, launch_slab_axpy(out + nc * m * S, S, cin + nc * S, S, 1, S, false, h->stream));
+  }
+  return MGRIT_OK;
+}
+
+// Coarse-grid correction below level l-1 (Sec. 2.2, V-cycle): relax level l
+// from zero with right-hand side g, recurse on its residual, post-relax into
+// the parent's C-points; the last level is solved by sequential stepping.
+mgrit_status vcycle2d(mgrit2d_handle *h, int l, const double *g, double *parent) {
+  Level2 &L = h->lv[l];
+  const int64_t S = slab(h);
+  const int nlev = (int)h->lv.size();
+  if (l == nlev - 1) {
+    const double *src = h->zero;
+    for (int64_t j = 1; j <= L.nt; ++j) {
+      double *dst = h->w[j & 1];
+      HIPCHK2(h, apply2d(h, l, src, dst, 1, g + (j - 1) * S, S));
+      HIPCHK2(h, launch_slab_axpy(parent + j * S, S, dst, S, 1, S, true, h->stream));
+      src = dst;
+    }
+    return MGRIT_OK;
+  }
+  const int64_t nc = L.nt / L.m;
+  int cur = 0;
+  HIPCHK2(h, launch_fill(L.c[0], (nc + 1) * S, 0.0, h->stream));
+  for (int s = 0; s < h->opt.nu; ++s) {
+    const mgrit_status st = relax2d(h, l, MODE_PASS_A, L.c[cur], L.c[1 - cur], g, nullptr, nullptr, nullptr);
+    if (st != MGRIT_OK) return st;
+    cur = 1 - cur;
+  }
+  mgrit_status st = relax2d(h, l, MODE_PASS_B, L.c[cur], nullptr, g, L.r, nullptr, nullptr);
+  if (st != MGRIT_OK) return st;
+  st = vcycle2d(h, l + 1, L.r, L.c[cur]);
+  if (st != MGRIT_OK) return st;
+  return relax2d(h, l, MODE_POST_F, L.c[cur], nullptr, g, nullptr, parent, nullptr);
+}
+
+bool build_line(const SlLevel &S, Line1D &ln, std::vector<double> &tabs_all, std::vector<std::pair<Line1D *, size_t>> &fix,
+                std::vector<size_t> &offs) {
+  ln.op = S.op;
+  ln.lay = S.lay;
+  const size_t base = tabs_all.size();
+  tabs_all.insert(tabs_all.end(), S.tabs.begin(), S.tabs.end());
+  fix.push_back({&ln, base});
+  offs = S.offs;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+mgrit_status mgrit2d_setup(const mgrit2d_problem *P, const mgrit_options *O, void *stream, mgrit2d_handle **out) {
+  g_setup_error.clear();
+  if (out) *out = nullptr;
+  auto bad = [&](mgrit_status s, const std::string &m) {
+    g_setup_error = m;
+    return s;
+  };
+  if (!P || !O || !out) return bad(MGRIT_EINVAL, "null argument");
+  if (!(P->velocity_x > 0) || !(P->velocity_y > 0) || !(P->x_hi > P->x_lo) || !(P->y_hi > P->y_lo) || !(P->dt > 0))
+    return bad(MGRIT_EINVAL, "need a_x, a_y > 0, a non-empty rectangle and dt > 0");
+  if (P->nx < 1 || P->nx > MGRIT_MAX_NX || P->ny < 1 || P->ny > MGRIT_MAX_NX)
+    return bad(MGRIT_EINVAL, "nx and ny must be in 1..16384");
+  if (P->nt < 1) return bad(MGRIT_EINVAL, "nt must be >= 1");
+  if (P->upwind_order != 1 && P->upwind_order != 3 && P->upwind_order != 5)
+    return bad(MGRIT_EINVAL, "the 2D coarse step needs odd upwind order 1, 3 or 5");
+  if (O->max_levels < 2 || O->max_levels > MGRIT_MAX_LEVELS) return bad(MGRIT_EINVAL, "max_levels must be in 2..16");
+  if (O->nu < 0 || O->nu > 8) return bad(MGRIT_EINVAL, "nu must be in 0..8");
+  if (O->max_iter < 0 || !(O->rtol >= 0)) return bad(MGRIT_EINVAL, "need max_iter >= 0 and rtol >= 0");
+  if (O->cg_kind != MGRIT_CG_SL_CORRECTED) return bad(MGRIT_EINVAL, "2D: corrected semi-Lagrangian coarse step only");
+  if (O->precision != MGRIT_PREC_FP64) return bad(MGRIT_EINVAL, "2D: float64 only");
+  mgrit_problem p1{};
+  p1.velocity = 1;
+  p1.x_lo = 0;
+  p1.x_hi = 1;
+  p1.nx = P->nx;
+  p1.nt = P->nt;
+  p1.cfl = 1;
+  p1.upwind_order = P->upwind_order;
+  p1.rk_kind = MGRIT_ERK;
+  p1.rk_order = P->rk_order;
+  FineInfo fi;
+  std::string err;
+  mgrit_status st = fine_info(p1, fi, err);
+  if (st != MGRIT_OK) return bad(st, err);
+  std::vector<int64_t> nts;
+  std::vector<int> ms;
+  if (!level_hierarchy(p1, *O, nts, ms, err)) return bad(MGRIT_EINVAL, err);
+  const int nlev = (int)nts.size();
+  const int p = P->upwind_order, q = P->rk_order;
+  const double cx = P->velocity_x * P->dt / ((P->x_hi - P->x_lo) / (double)P->nx);
+  const double cy = P->velocity_y * P->dt / ((P->y_hi - P->y_lo) / (double)P->ny);
+  // stability of the fine step: |R(-(c_x Lhat(w_x) + c_y Lhat(w_y)))| <= 1
+  {
+    const int N = 256;
+    const std::vector<ld> beta = rk_series(fi.tab, fi.tab.s);
+    std::vector<std::complex<double>> lx(N), ly(N);
+    for (int k = 0; k < N; ++k) {
+      const double om = -M_PI + 2 * M_PI * k / N;
+      lx[k] = cx * upwind_symbol(fi, om);
+      ly[k] = cy * upwind_symbol(fi, om);
+    }
+    for (int i = 0; i < N; ++i)
+      for (int k = 0; k < N; ++k) {
+        const std::complex<double> z = -(lx[i] + ly[k]);
+        std::complex<double> acc = (double)beta[fi.tab.s];
+        for (int j = fi.tab.s - 1; j >= 0; --j) acc = acc * z + (double)beta[j];
+        if (std::abs(acc) > 1 + 1e-10) return bad(MGRIT_EUNSTABLE, "2D explicit step above its stability limit");
+      }
+  }
+  std::vector<SlLevel> chx, chy;
+  const std::vector<int> mc(ms.begin(), ms.begin() + (nlev - 1));
+  if (!sl_chain(fi, p, q, cx, mc, (int)P->nx, 16, false, chx, err) ||
+      !sl_chain(fi, p, q, cy, mc, (int)P->ny, 16, false, chy, err))
+    return bad(MGRIT_EINVAL, err);
+
+  auto *h = new mgrit2d_handle();
+  h->prob = *P;
+  h->opt = *O;
+  h->stream = (hipStream_t)stream;
+  h->lv.resize(nlev);
+  for (int l = 0; l < nlev; ++l) {
+    h->lv[l].nt = nts[l];
+    h->lv[l].m = l < nlev - 1 ? ms[l] : 0;
+  }
+  // fine step constants: Horner coefficients of R and the two stencils
+  Step2dArgs &f = h->fine;
+  f.nx = (int)P->nx;
+  f.ny = (int)P->ny;
+  f.ncoef = fi.tab.s + 1;
+  for (int i = 0; i <= fi.tab.s; ++i) f.coef[i] = (double)fi.beta[i];
+  f.sl = fi.l;
+  f.sr = fi.r;
+  for (int j = 0; j <= fi.l + fi.r; ++j) {
+    f.tx[j] = -cx * fi.w[j];
+    f.ty[j] = -cy * fi.w[j];
+  }
+  const size_t lds = step2d_lds_bytes(f.ncoef, f.sl, f.sr);
+  if (lds > LDS_LIMIT) {
+    mgrit2d_destroy(h);
+    return bad(MGRIT_EINVAL, "2D fine step: halo too wide for LDS");
+  }
+  if (configure_kernels(LDS_LIMIT) != hipSuccess || configure_2d_kernels(LDS_LIMIT) != hipSuccess) {
+    mgrit2d_destroy(h);
+    return bad(MGRIT_EDEVICE, "configure");
+  }
+  // device memory: tables and descriptors (uploaded), then the arrays
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  std::vector<double> tabs;
+  std::vector<std::pair<Line1D *, size_t>> fix;
+  std::vector<std::vector<size_t>> offs(2 * nlev);
+  for (int l = 1; l < nlev; ++l) {
+    build_line(chx[l - 1], h->lv[l].x, tabs, fix, offs[2 * l]);
+    build_line(chy[l - 1], h->lv[l].y, tabs, fix, offs[2 * l + 1]);
+  }
+  const int64_t S = P->nx * P->ny;
+  const int64_t nc0 = nts[0] / ms[0];
+  h->cap = std::max<int64_t>(nc0, 1);
+  size_t off = 0;
+  const size_t o_tabs = off;
+  off += al(std::max<size_t>(tabs.size(), 1) * sizeof(double));
+  const size_t o_desc = off;
+  off += al(2 * nlev * sizeof(LevelDesc));
+  const size_t head = off;
+  std::vector<size_t> o_c0(nlev), o_c1(nlev), o_r(nlev);
+  for (int l = 0; l + 1 < nlev; ++l) {
+    const int64_t nc = nts[l] / ms[l];
+    o_c0[l] = off, off += al((nc + 1) * S * sizeof(double));
+    o_c1[l] = off, off += al((nc + 1) * S * sizeof(double));
+    o_r[l] = off, off += al(nc * S * sizeof(double));
+  }
+  const size_t o_w0 = off;
+  off += al(h->cap * S * sizeof(double));
+  const size_t o_w1 = off;
+  off += al(h->cap * S * sizeof(double));
+  const size_t o_t1 = off;
+  off += al(h->cap * S * sizeof(double));
+  const size_t o_t2 = off;
+  off += al(h->cap * S * sizeof(double));
+  const size_t o_zero = off;
+  off += al(S * sizeof(double));
+  h->normpart_len = h->cap * RESID_BLOCKS;
+  const size_t o_np = off;
+  off += al(h->normpart_len * sizeof(double));
+  const size_t o_ns = off;
+  off += al(sizeof(double));
+  if (hipMalloc((void **)&h->arena, off) != hipSuccess) {
+    mgrit2d_destroy(h);
+    return bad(MGRIT_ENOMEM, "device workspace");
+  }
+  char *base = h->arena;
+  double *dtabs = (double *)(base + o_tabs);
+  std::vector<char> up(head, 0);
+  std::memcpy(up.data() + o_tabs, tabs.data(), tabs.size() * sizeof(double));
+  int di = 0;
+  for (int l = 1; l < nlev; ++l)
+    for (int ax = 0; ax < 2; ++ax) {
+      Line1D &ln = ax == 0 ? h->lv[l].x : h->lv[l].y;
+      size_t tb = 0;
+      for (auto &fx : fix)
+        if (fx.first == &ln) tb = fx.second;
+      const std::vector<size_t> &of = offs[2 * l + ax];
+      if (of.size() == 2) {
+        ln.op.fw.tab = of[0] == (size_t)-1 ? nullptr : dtabs + tb + of[0];
+        ln.op.bw.tab = of[1] == (size_t)-1 ? nullptr : dtabs + tb + of[1];
+      }
+      ln.desc = (LevelDesc *)(base + o_desc) + di;
+      const LevelDesc hd{ln.op, ln.lay};
+      std::memcpy(up.data() + o_desc + di * sizeof(LevelDesc), &hd, sizeof(LevelDesc));
+      ++di;
+    }
+  for (int l = 0; l + 1 < nlev; ++l) {
+    h->lv[l].c[0] = (double *)(base + o_c0[l]);
+    h->lv[l].c[1] = (double *)(base + o_c1[l]);
+    h->lv[l].r = (double *)(base + o_r[l]);
+  }
+  h->w[0] = (double *)(base + o_w0);
+  h->w[1] = (double *)(base + o_w1);
+  h->t1 = (double *)(base + o_t1);
+  h->t2 = (double *)(base + o_t2);
+  h->zero = (double *)(base + o_zero);
+  h->normpart = (double *)(base + o_np);
+  h->normsum = (double *)(base + o_ns);
+  if (hipMemcpyAsync(base, up.data(), head, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+      launch_fill(h->zero, S, 0.0, h->stream) != hipSuccess ||
+      hipHostMalloc((void **)&h->normsum_host, sizeof(double)) != hipSuccess) {
+    mgrit2d_destroy(h);
+    return bad(MGRIT_EDEVICE, "upload");
+  }
+  *out = h;
+  return MGRIT_OK;
+}
+
+mgrit_status mgrit2d_solve(mgrit2d_handle *h, const double *u0, const double *v_init, double *u_out, double *u_final,
+                           mgrit_stats *stats) {
+  if (!h) return MGRIT_EINVAL;
+  if (!u0) return fail2(h, MGRIT_EINVAL, "u0 is required");
+  const auto t0 = std::chrono::steady_clock::now();
+  Level2 &L0 = h->lv[0];
+  const int64_t S = slab(h);
+  const int m = L0.m;
+  const int64_t nc = L0.nt / m;
+  int cur = 0;
+  if (v_init) {
+    HIPCHK2(h, launch_slab_axpy(L0.c[0], S, v_init, m * S, nc + 1, S, false, h->stream));
+  } else {
+    HIPCHK2(h, launch_fill(L0.c[0], (nc + 1) * S, 0.0, h->stream));
+  }
+  HIPCHK2(h, hipMemcpyAsync(L0.c[0], u0, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  std::vector<double> hist;
+  double res0 = NAN, rho = NAN, prev = NAN;
+  int it = 0;
+  mgrit_status status = MGRIT_OK;
+  for (;;) {
+    for (int s = 0; s < h->opt.nu; ++s) {
+      const mgrit_status st = relax2d(h, 0, MODE_PASS_A, L0.c[cur], L0.c[1 - cur], nullptr, nullptr, nullptr, nullptr);
+      if (st != MGRIT_OK) return st;
+      cur = 1 - cur;
+    }
+    mgrit_status st = relax2d(h, 0, MODE_PASS_B, L0.c[cur], nullptr, nullptr, L0.r, nullptr, nullptr);
+    if (st != MGRIT_OK) return st;
+    HIPCHK2(h, launch_reduce(h->normpart, nc * RESID_BLOCKS, h->normsum, h->stream));
+    HIPCHK2(h, hipMemcpyAsync(h->normsum_host, h->normsum, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK2(h, hipStreamSynchronize(h->stream));
+    prev = rho;
+    rho = std::sqrt(*h->normsum_host);
+    hist.push_back(rho);
+    if (it == 0) res0 = rho;
+    if (!std::isfinite(rho)) {
+      status = fail2(h, MGRIT_EDIVERGED, "non-finite residual");
+      break;
+    }
+    if (rho <= h->opt.rtol * res0) break;
+    if (it >= h->opt.max_iter) {
+      status = MGRIT_ENOTCONVERGED;
+      h->err = "max_iter reached";
+      break;
+    }
+    if (h->opt.diverge_factor > 0 && rho > h->opt.diverge_factor * res0) {
+      status = fail2(h, MGRIT_EDIVERGED, "residual grew past diverge_factor * res0");
+      break;
+    }
+    st = vcycle2d(h, 1, L0.r, L0.c[cur]);
+    if (st != MGRIT_OK) return st;
+    ++it;
+  }
+  if (status == MGRIT_OK || status == MGRIT_ENOTCONVERGED) {
+    if (u_out) {
+      const mgrit_status st = relax2d(h, 0, MODE_FINAL_F, L0.c[cur], nullptr, nullptr, nullptr, nullptr, u_out);
+      if (st != MGRIT_OK) return st;
+    }
+    if (u_final)
+      HIPCHK2(h, hipMemcpyAsync(u_final, L0.c[cur] + nc * S, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  }
+  HIPCHK2(h, hipStreamSynchronize(h->stream));
+  if (stats) {
+    stats->iterations = it;
+    stats->inner_iterations = 0;
+    stats->res0 = res0;
+    stats->res_final = rho;
+    stats->conv_factor = prev > 0 ? rho / prev : NAN;
+    const int len = (int)hist.size();
+    if (stats->res_history)
+      for (int i = 0; i < std::min(len, stats->res_history_cap); ++i) stats->res_history[i] = hist[i];
+    stats->res_history_len = std::min(len, std::max(stats->res_history_cap, 0));
+    stats->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return status;
+}
+
+mgrit_status mgrit2d_sequential(mgrit2d_handle *h, const double *u0, double *u_out) {
+  if (!h || !u0 || !u_out) return MGRIT_EINVAL;
+  const int64_t S = slab(h);
+  HIPCHK2(h, hipMemcpyAsync(u_out, u0, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  for (int64_t n = 1; n <= h->prob.nt; ++n) HIPCHK2(h, apply2d(h, 0, u_out + (n - 1) * S, u_out + n * S, 1, nullptr, 0));
+  HIPCHK2(h, hipStreamSynchronize(h->stream));
+  return MGRIT_OK;
+}
+
+mgrit_status mgrit2d_apply_step(mgrit2d_handle *h, int32_t level, const double *v_in, double *v_out, int64_t count) {
+  if (!h || !v_in || !v_out || level < 0 || level >= (int32_t)h->lv.size() || count < 0) return MGRIT_EINVAL;
+  const int64_t S = slab(h);
+  for (int64_t b = 0; b < count; b += h->cap) {
+    const int64_t nb = std::min<int64_t>(h->cap, count - b);
+    HIPCHK2(h, apply2d(h, level, v_in + b * S, v_out + b * S, nb, nullptr, 0));
+  }
+  HIPCHK2(h, hipStreamSynchronize(h->stream));
+  return MGRIT_OK;
+}
+
+int32_t mgrit2d_num_levels(const mgrit2d_handle *h) { return h ? (int32_t)h->lv.size() : 0; }
+
+const char *mgrit2d_last_error(const mgrit2d_handle *h) { return h ? h->err.c_str() : g_setup_error.c_str(); }
+
+void mgrit2d_destroy(mgrit2d_handle *h) {
+  if (!h) return;
+  if (h->arena) (void)hipFree(h->arena);
+  if (h->normsum_host) (void)hipHostFree(h->normsum_host);
+  delete h;
 }
 
 }  // extern "C"

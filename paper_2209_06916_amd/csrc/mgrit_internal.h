@@ -238,6 +238,38 @@ hipError_t launch_tiles_4(const LevelDesc *desc, const TileGeom &tg, const TileA
 hipError_t launch_tiles_8(const LevelDesc *desc, const TileGeom &tg, const TileArgs &ta, hipStream_t stream);
 hipError_t launch_tiles_16(const LevelDesc *desc, const TileGeom &tg, const TileArgs &ta, hipStream_t stream);
 
+// 2D extension (mgrit_2d.hip).  One explicit Runge-Kutta step of the
+// dimension-split operator on a batch of nb [ny][nx] slabs: dst = Phi(src)
+// (+ g).  The Horner coefficients and the x / y stencil taps (-c_x w,
+// -c_y w, offsets -sl..sr) are passed by value.
+struct Step2dArgs {
+  const double *src;
+  int64_t src_stride;
+  double *dst;
+  int64_t dst_stride;
+  const double *g;  // NULL: no right-hand side
+  int64_t g_stride;
+  int64_t nb;
+  int nx, ny;
+  int ncoef;
+  double coef[MAXCOEF];
+  int sl, sr;
+  double tx[MAXTAPS], ty[MAXTAPS];
+};
+size_t step2d_lds_bytes(int ncoef, int sl, int sr);
+hipError_t configure_2d_kernels(size_t bytes);
+hipError_t launch_step2d(const Step2dArgs &a, hipStream_t stream);
+// dst slab b = transpose(src slab b) (+ g slab b), src slabs [rows][cols]
+hipError_t launch_transpose(const double *src, int64_t src_stride, double *dst, int64_t dst_stride, const double *g,
+                            int64_t g_stride, int64_t nb, int rows, int cols, hipStream_t stream);
+// dst slab b = (dst slab b +) src slab b, n points per slab
+hipError_t launch_slab_axpy(double *dst, int64_t dst_stride, const double *src, int64_t src_stride, int64_t nb,
+                            int64_t n, bool accumulate, hipStream_t stream);
+// r = a - c over nb contiguous slabs of n points (r may be NULL); part gets
+// blocks_per_slab partial sums of squares per slab
+hipError_t launch_slab_resid(const double *a, const double *c, double *r, int64_t nb, int64_t n, int blocks_per_slab,
+                             double *part, hipStream_t stream);
+
 // Launch the step kernel for one pass (mgrit_kernels.hip).  lds_bytes is
 // computed by the launcher.  Returns the HIP error of the launch.
 // `desc` is the device copy of (op, lay); op.kind and lay are read on the host

@@ -10,6 +10,9 @@ Recipes (the paper's experiments are synthetic, Sec. 5.3 and Sec. 6.3):
   (period 2, so periodic on [-1, 1)).
 * ``initial_iterate``: uniformly random U[0, 1) at every space-time point
   except t = 0, where it equals u0.
+* ``u0_bumps_2d``: 2D, a sum of `count` Gaussian bumps exp(-d^2 / (2 w^2)) of
+  amplitude 1 with centres U[-1, 1)^2 and d the minimum-image periodic
+  distance on [-1, 1)^2.
 """
 import numpy as np
 
@@ -39,3 +42,17 @@ def initial_iterate(nt, nx, u0, seed):
     v = rng.random((nt + 1, nx))
     v[0] = u0
     return v
+
+
+def u0_bumps_2d(nx, ny, count, width, seed, lo=-1.0, hi=1.0):
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(lo, hi, size=(count, 2))
+    L = hi - lo
+    x = mesh(nx, lo, hi)[None, :]
+    y = mesh(ny, lo, hi)[:, None]
+    out = np.zeros((ny, nx))
+    for cx, cy in centres:
+        dx = (x - cx + L / 2) % L - L / 2
+        dy = (y - cy + L / 2) % L - L / 2
+        out += np.exp(-(dx * dx + dy * dy) / (2.0 * width * width))
+    return out

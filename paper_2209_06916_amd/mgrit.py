@@ -49,6 +49,13 @@ class Stats(ctypes.Structure):
                 ("t_solve_s", ctypes.c_double), ("inner_iterations", ctypes.c_int32)]
 
 
+class Problem2D(ctypes.Structure):
+    _fields_ = [("velocity_x", ctypes.c_double), ("velocity_y", ctypes.c_double), ("x_lo", ctypes.c_double),
+                ("x_hi", ctypes.c_double), ("y_lo", ctypes.c_double), ("y_hi", ctypes.c_double),
+                ("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nt", ctypes.c_int64), ("dt", ctypes.c_double),
+                ("upwind_order", ctypes.c_int32), ("rk_order", ctypes.c_int32)]
+
+
 class LevelDesc(ctypes.Structure):
     _fields_ = [("nt", ctypes.c_int64), ("m", ctypes.c_int32), ("shift", ctypes.c_double),
                 ("K", ctypes.c_int64), ("eps", ctypes.c_double), ("phi_p", ctypes.c_double),
@@ -65,7 +72,9 @@ class Profile(ctypes.Structure):
 EXPORTED = ["mgrit_setup", "mgrit_setup_ws", "mgrit_solve", "mgrit_solve_start", "mgrit_solve_advance", "mgrit_solve_finish",
             "mgrit_workspace_bytes", "mgrit_residual", "mgrit_sequential", "mgrit_apply_step",
             "mgrit_num_levels", "mgrit_level_info", "mgrit_lfa_rho", "mgrit_profile_enable",
-            "mgrit_profile_read", "mgrit_status_string", "mgrit_last_error", "mgrit_destroy"]
+            "mgrit_profile_read", "mgrit_status_string", "mgrit_last_error", "mgrit_destroy",
+            "mgrit2d_setup", "mgrit2d_solve", "mgrit2d_sequential", "mgrit2d_apply_step", "mgrit2d_num_levels",
+            "mgrit2d_last_error", "mgrit2d_destroy"]
 
 
 def library_path():
@@ -105,6 +114,18 @@ def lib():
         L.mgrit_last_error.restype = ctypes.c_char_p
         L.mgrit_destroy.argtypes = [vp]
         L.mgrit_destroy.restype = None
+        L.mgrit2d_setup.argtypes = [ctypes.POINTER(Problem2D), ctypes.POINTER(Options), vp, ctypes.POINTER(vp)]
+        L.mgrit2d_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(Stats)]
+        L.mgrit2d_sequential.argtypes = [vp, vp, vp]
+        L.mgrit2d_apply_step.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_int64]
+        L.mgrit2d_num_levels.argtypes = [vp]
+        L.mgrit2d_num_levels.restype = ctypes.c_int32
+        L.mgrit2d_last_error.argtypes = [vp]
+        L.mgrit2d_last_error.restype = ctypes.c_char_p
+        L.mgrit2d_destroy.argtypes = [vp]
+        L.mgrit2d_destroy.restype = None
+        for name in ("mgrit2d_setup", "mgrit2d_solve", "mgrit2d_sequential", "mgrit2d_apply_step"):
+            getattr(L, name).restype = ctypes.c_int
         for name in ("mgrit_setup", "mgrit_setup_ws", "mgrit_solve", "mgrit_solve_start", "mgrit_solve_advance", "mgrit_solve_finish",
                      "mgrit_workspace_bytes", "mgrit_residual", "mgrit_sequential", "mgrit_apply_step",
                      "mgrit_level_info", "mgrit_lfa_rho", "mgrit_profile_enable", "mgrit_profile_read"):
@@ -278,3 +299,77 @@ class Solver:
         count = v_in.shape[0]
         self._check(lib().mgrit_apply_step(self.h, level, _ptr(v_in, (count, self.nx)),
                                            _ptr(v_out, (count, self.nx)), count, nsteps))
+
+
+def make_problem_2d(nx, ny, nt, dt_over_h, p, q=None, ax=0.85, ay=1.0, lo=-1.0, hi=1.0):
+    """u_t + a_x u_x + a_y u_y = 0 on [lo, hi)^2 with nx x ny points and
+    dt = dt_over_h * h, h the smaller of the two mesh widths; ERKq (q
+    defaults to p) + Up."""
+    pr = Problem2D()
+    pr.velocity_x, pr.velocity_y = ax, ay
+    pr.x_lo, pr.x_hi, pr.y_lo, pr.y_hi = lo, hi, lo, hi
+    pr.nx, pr.ny, pr.nt = nx, ny, nt
+    pr.dt = dt_over_h * (hi - lo) / max(nx, ny)
+    pr.upwind_order = p
+    pr.rk_order = p if q is None else q
+    return pr
+
+
+class Solver2D:
+    """One mgrit2d_handle (the dimension-split 2D extension)."""
+
+    def __init__(self, problem, options, stream=None):
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.problem, self.options = problem, options
+        h = ctypes.c_void_p()
+        st = lib().mgrit2d_setup(ctypes.byref(problem), ctypes.byref(options), ctypes.c_void_p(stream.cuda_stream),
+                                 ctypes.byref(h))
+        if st != OK:
+            raise MgritError(st, lib().mgrit2d_last_error(None).decode())
+        self.h = h
+        self.nx, self.ny, self.nt = problem.nx, problem.ny, problem.nt
+
+    def _check(self, st, allow=(OK,)):
+        if st not in allow:
+            raise MgritError(st, lib().mgrit2d_last_error(self.h).decode())
+        return st
+
+    @property
+    def num_levels(self):
+        return lib().mgrit2d_num_levels(self.h)
+
+    def solve(self, u0, v_init=None, u_out=None, u_final=None, history_cap=128, allow=(OK, ENOTCONVERGED)):
+        sl = (self.ny, self.nx)
+        hist = (ctypes.c_double * history_cap)()
+        stats = Stats()
+        stats.res_history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+        stats.res_history_cap = history_cap
+        st = lib().mgrit2d_solve(self.h, _ptr(u0, sl), _ptr(v_init, (self.nt + 1,) + sl),
+                                 _ptr(u_out, (self.nt + 1,) + sl), _ptr(u_final, sl), ctypes.byref(stats))
+        self._check(st, allow)
+        return dict(status=st, iterations=stats.iterations, res0=stats.res0, res_final=stats.res_final,
+                    conv_factor=stats.conv_factor, res_history=list(hist[:stats.res_history_len]),
+                    t_solve_s=stats.t_solve_s)
+
+    def sequential(self, u0, u_out):
+        sl = (self.ny, self.nx)
+        self._check(lib().mgrit2d_sequential(self.h, _ptr(u0, sl), _ptr(u_out, (self.nt + 1,) + sl)))
+
+    def apply_step(self, level, v_in, v_out):
+        count = v_in.shape[0]
+        sl = (self.ny, self.nx)
+        self._check(lib().mgrit2d_apply_step(self.h, level, _ptr(v_in, (count,) + sl), _ptr(v_out, (count,) + sl),
+                                             count))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mgrit2d_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

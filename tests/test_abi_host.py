@@ -4,6 +4,7 @@ device, and its host-only LFA helper agrees with the oracle's LFA."""
 import os
 import re
 
+import numpy as np
 import pytest
 
 from oracle import discretization as disc
@@ -15,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared_functions():
     text = open(os.path.join(ROOT, "include", "mgrit.h")).read()
-    return sorted(set(re.findall(r"\b(mgrit_[a-z_0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(mgrit(?:2d)?_[a-z_0-9]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -127,3 +128,43 @@ def test_mixed_precision_workspace_holds_the_space_time_arrays():
     mixed = mgrit.workspace_bytes(pr, mgrit.make_options([8], max_levels=3, precision="mixed"))
     # outer iterate and residual (float64), inner right-hand side and solution (float32)
     assert mixed - fp64 >= (2 * 513 * 1024 - 1024) * (8 + 4)
+
+
+def _setup2d_status(pr, opts):
+    import ctypes
+    h = ctypes.c_void_p()
+    st = mgrit.lib().mgrit2d_setup(ctypes.byref(pr), ctypes.byref(opts), None, ctypes.byref(h))
+    if h.value:
+        mgrit.lib().mgrit2d_destroy(h)
+    return st, mgrit.lib().mgrit2d_last_error(None).decode()
+
+
+def test_2d_setup_validation():
+    ok, msg = _setup2d_status(mgrit.make_problem_2d(64, 64, 16, 0.5, 3), mgrit.make_options([4]))
+    assert ok not in (mgrit.EINVAL, mgrit.EUNSTABLE), msg  # OK on a GPU, EDEVICE without one
+    # dt = h with a = (0.85, 1.0): ERK3 + U3 is unstable in 2D (c = (0.85, 1.0))
+    st, _ = _setup2d_status(mgrit.make_problem_2d(64, 64, 16, 1.0, 3), mgrit.make_options([4]))
+    assert st == mgrit.EUNSTABLE
+    st, _ = _setup2d_status(mgrit.make_problem_2d(64, 64, 16, 0.5, 2), mgrit.make_options([4]))
+    assert st == mgrit.EINVAL
+    st, _ = _setup2d_status(mgrit.make_problem_2d(64, 64, 16, 0.5, 3), mgrit.make_options([4], precision="mixed"))
+    assert st == mgrit.EINVAL
+
+
+def test_2d_stability_limit_matches_the_oracle_symbol():
+    """The setup's scan agrees with the oracle's 2D symbol on both sides of
+    the limit along dt (a = (0.85, 1.0), ERK3 + U3)."""
+    from oracle import advection2d as a2
+    om = -np.pi + 2 * np.pi * np.arange(256) / 256
+    wx, wy = np.meshgrid(om, om)
+
+    def stable(r):
+        return np.max(np.abs(a2.MOLStep2D(3, 3, 0.85 * r, 1.0 * r).symbol(wx, wy))) <= 1 + 1e-10
+
+    lo, hi = 0.5, 1.0
+    for _ in range(20):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if stable(mid) else (lo, mid)
+    below, _ = _setup2d_status(mgrit.make_problem_2d(64, 64, 16, lo * 0.999, 3), mgrit.make_options([4]))
+    above, _ = _setup2d_status(mgrit.make_problem_2d(64, 64, 16, hi * 1.001, 3), mgrit.make_options([4]))
+    assert below != mgrit.EUNSTABLE and above == mgrit.EUNSTABLE
