@@ -328,6 +328,52 @@ def precision_bench(steps):
         torch.cuda.empty_cache()
 
 
+def twod_bench(steps):
+    """Config 4: u_t + a.grad u = 0 on [-1, 1)^2, a = (0.85, 1.0),
+    nx = ny = nt = 1024, dt = h/2 (c = (0.425, 0.5)), ERK3 + U3, m = 8,
+    3 levels (1024 -> 128 -> 16), u0 = 8 seeded Gaussian bumps of width
+    0.1, seeded U[0,1) initial iterate, relative C-point residual 1e-10;
+    against sequential time-stepping of the same fine step on the GPU."""
+    import torch
+    from paper_2209_06916_amd import inputs, mgrit
+    dev = torch.device("cuda:0")
+    n, nt, ms, seed = 1024, 1024, [8, 8], 1004
+    u0 = inputs.u0_bumps_2d(n, n, 8, 0.1, seed)
+    rng = np.random.default_rng(seed)
+    v0 = torch.empty((nt + 1, n, n), dtype=torch.float64, device=dev)
+    for k in range(0, nt + 1, 64):  # seeded U[0,1) rows, drawn in blocks
+        rows = min(64, nt + 1 - k)
+        v0[k:k + rows] = torch.from_numpy(rng.random((rows, n, n))).to(dev)
+    u0_d = torch.from_numpy(u0).to(dev)
+    v0[0] = u0_d
+    pr = mgrit.make_problem_2d(n, n, nt, 0.5, 3)
+    s = mgrit.Solver2D(pr, mgrit.make_options(ms, max_levels=3, rtol=1e-10, max_iter=30))
+    out = torch.empty((nt + 1, n, n), dtype=torch.float64, device=dev)
+    info = s.solve(u0_d, v0, u_out=out)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        info = s.solve(u0_d, v0, u_out=out)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t) / steps
+    del v0
+    ref = torch.empty_like(out)
+    s.sequential(u0_d, ref)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        s.sequential(u0_d, ref)
+    torch.cuda.synchronize()
+    seq = (time.perf_counter() - t) / steps
+    err = (torch.linalg.vector_norm(out - ref) / torch.linalg.vector_norm(ref)).item()
+    dof = n * n * nt
+    print(json.dumps({"workload": "advection2d-1024x1024x1024-erk3u3-vcycle-m8", "dof": dof, "steps": steps,
+                      "mgrit_ms": 1e3 * wall, "mgrit_dof_per_s": dof / wall, "iterations": info["iterations"],
+                      "res_history": info["res_history"], "sequential_ms": 1e3 * seq,
+                      "sequential_dof_per_s": dof / seq, "mgrit_vs_sequential": seq / wall,
+                      "rel_l2_error_vs_sequential": err}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -339,6 +385,8 @@ def main():
                          "COPY_BYTES read + COPY_BYTES written (the counter calibration)")
     ap.add_argument("--serve", type=int, metavar="N", default=0,
                     help="the request-loop benchmark (N independent solves) instead of the single-solve one")
+    ap.add_argument("--twod", action="store_true",
+                    help="the 2D extension (config 4) against 2D sequential stepping instead of the single-solve bench")
     ap.add_argument("--precision", action="store_true",
                     help="float64 against mixed-precision MGRIT on configs 2 and 3 instead of the single-solve bench")
     ap.add_argument("--summarize-profiles", metavar="DIR",
@@ -359,6 +407,9 @@ def main():
         return
     if args.precision:
         precision_bench(max(1, min(args.steps, 5)))
+        return
+    if args.twod:
+        twod_bench(max(1, min(args.steps, 5)))
         return
 
     dev = torch.device("cuda:0")

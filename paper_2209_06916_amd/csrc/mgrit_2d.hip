@@ -37,29 +37,65 @@ __global__ void __launch_bounds__(256) step2d_kernel(Step2dArgs a) {
   const int x0 = (t % tiles_x) * TX - hl, y0g = (t / tiles_x) * TY - hl;
   const double *src = a.src + b * a.src_stride;
   const double top = a.coef[a.ncoef - 1];
-  for (int i = threadIdx.x; i < area; i += 256) {
-    const int lx = i % wx, ly = i / wx;
-    const double v = src[(int64_t)wrap(y0g + ly, ny) * nx + wrap(x0 + lx, nx)];
-    u[i] = v;
-    y0[i] = top * v;
+  // Every loop below walks a w x h region in row-major order, 256 points
+  // apart: each thread keeps its (x, y) and advances it by (256 mod w,
+  // 256 div w) with one carry, so no lane idles and nothing divides.
+  const int tid = threadIdx.x;
+  {
+    int lx = tid % wx, ly = tid / wx;
+    const int dx = 256 % wx, dy = 256 / wx;
+    for (; ly < wy;) {
+      int gy = y0g + ly;
+      while (gy < 0) gy += ny;
+      while (gy >= ny) gy -= ny;
+      int gx = x0 + lx;
+      while (gx < 0) gx += nx;
+      while (gx >= nx) gx -= nx;
+      const double v = src[(int64_t)gy * nx + gx];
+      u[ly * wx + lx] = v;
+      y0[ly * wx + lx] = top * v;
+      lx += dx;
+      ly += dy;
+      if (lx >= wx) {
+        lx -= wx;
+        ++ly;
+      }
+    }
   }
   __syncthreads();
   const int nt_ = a.sl + a.sr + 1;
+  double tapx[MAXTAPS], tapy[MAXTAPS];
+#pragma unroll
+  for (int k = 0; k < MAXTAPS; ++k) {
+    tapx[k] = a.tx[k];
+    tapy[k] = a.ty[k];
+  }
   double *yin = y0, *yout = y1;
   for (int k = 1; k <= s; ++k) {
     const double ci = a.coef[a.ncoef - 1 - k];
     // valid after this application: [k*sl, w - k*sr) on both axes
     const int lo = k * a.sl, hx = wx - k * a.sr, hy = wy - k * a.sr;
     const int cw = hx - lo, ch = hy - lo;
-    for (int i = threadIdx.x; i < cw * ch; i += 256) {
-      const int lx = lo + i % cw, ly = lo + i / cw;
-      double acc = ci * u[ly * wx + lx];
-      for (int tt = 0; tt < nt_; ++tt) {
-        const int d = tt - a.sl;
-        acc = fma(a.tx[tt], yin[ly * wx + lx + d], acc);
-        acc = fma(a.ty[tt], yin[(ly + d) * wx + lx], acc);
+    int lx = tid % cw, ly = tid / cw;
+    const int dx = 256 % cw, dy = 256 / cw;
+    for (; ly < ch;) {
+      const int c = (ly + lo) * wx + lx + lo;
+      double acc = ci * u[c];
+#pragma unroll
+      for (int tt = 0; tt < MAXTAPS; ++tt) {
+        if (tt < nt_) {
+          const int d = tt - a.sl;
+          acc = fma(tapx[tt], yin[c + d], acc);
+          acc = fma(tapy[tt], yin[c + d * wx], acc);
+        }
       }
-      yout[ly * wx + lx] = acc;
+      yout[c] = acc;
+      lx += dx;
+      ly += dy;
+      if (lx >= cw) {
+        lx -= cw;
+        ++ly;
+      }
     }
     __syncthreads();
     double *tmp = yin;
@@ -68,9 +104,10 @@ __global__ void __launch_bounds__(256) step2d_kernel(Step2dArgs a) {
   }
   double *dst = a.dst + b * a.dst_stride;
   const double *g = a.g ? a.g + b * a.g_stride : nullptr;
-  for (int i = threadIdx.x; i < TX * TY; i += 256) {
-    const int ox = i % TX, oy = i / TX;
-    const int gx = x0 + hl + ox, gy = y0g + hl + oy;
+  for (int i = tid; i < TX * TY; i += 256) {
+    const int ox = i & (TX - 1), oy = i / TX;  // TX is a power of two
+    const int gy = y0g + hl + oy;
+    const int gx = x0 + hl + ox;
     if (gx >= nx || gy >= ny) continue;
     const int64_t o = (int64_t)gy * nx + gx;
     double v = yin[(oy + hl) * wx + ox + hl];
