@@ -106,11 +106,11 @@ struct LevelDesc {
 };
 
 // The lean coarse-step kernel: L points per lane and NW full wavefronts,
-// nx = 64 L NW, for L = 16 with NW = 1, 2, 4, 8 (nx = 1024 ... 8192) and for
-// L = 4 or 8 with one wavefront (nx = 256, 512).  At 16 wavefronts the
+// nx = 64 L NW, for L = 16 or 8 with NW = 1, 2, 4, 8 (nx = 512 ... 8192) and
+// for L = 4 with one wavefront (nx = 256).  At 16 wavefronts the
 // 128-register budget of a 1024-thread workgroup would spill.
 constexpr __host__ __device__ inline bool lean_shape(int L, int nw) {
-  return (L == 16 && (nw == 1 || nw == 2 || nw == 4 || nw == 8)) || ((L == 4 || L == 8) && nw == 1);
+  return ((L == 16 || L == 8) && (nw == 1 || nw == 2 || nw == 4 || nw == 8)) || (L == 4 && nw == 1);
 }
 constexpr __host__ __device__ inline int lean_key(int W, int K, int L, int nw) {
   return ((W * 4 + K) * 32 + L) * 16 + nw;

@@ -593,7 +593,9 @@ hipError_t slc_launch(const LevelDesc *desc, const PassArgs &pa, hipStream_t str
 }
 
 // The (L, NW) shapes: nx = 64 L NW.
-#define MGRIT_LEAN_SHAPES(X, W, K) X(W, K, 16, 1) X(W, K, 16, 2) X(W, K, 16, 4) X(W, K, 16, 8) X(W, K, 8, 1) X(W, K, 4, 1)
+#define MGRIT_LEAN_SHAPES(X, W, K)                                                                 \
+  X(W, K, 16, 1) X(W, K, 16, 2) X(W, K, 16, 4) X(W, K, 16, 8) X(W, K, 8, 1) X(W, K, 8, 2) X(W, K, 8, 4) \
+  X(W, K, 8, 8) X(W, K, 4, 1)
 
 hipError_t slc_launch_any(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs &pa,
                           hipStream_t stream) {

@@ -136,7 +136,31 @@ def test_lean_full_solve_matches_oracle(case):
     _check_parity(info, got, fin, ref, rinfo, case["ms"][0])
 
 
-@pytest.mark.parametrize("nx,generic_l", [(4096, "8"), (512, "4"), (256, "2")])
+@pytest.mark.parametrize("nx,p", [(1024, 3), (2048, 5), (4096, 1), (4096, 3)])
+def test_lean_eight_point_shapes_match_oracle(monkeypatch, nx, p):
+    """Chunks of 8 points on 2, 4 and 8 wavefronts (MGRIT_L_COARSE=8): single
+    coarse steps and a full V-cycle solve against the oracle."""
+    _announce("lean L=8", nx, p)
+    monkeypatch.setenv("MGRIT_L_COARSE", "8")
+    c = {1: 0.85, 3: 1.2, 5: 0.9}[p]
+    ms = [8, 8]
+    s = mgrit.Solver(mgrit.make_problem(nx, 2 * 64, c, p), mgrit.make_options(ms, max_levels=3))
+    recs = disc.correction_coefficients(p, "erk", p, c, ms)
+    v = np.random.default_rng(nx + 13 * p).standard_normal((3, nx))
+    for lev, rec in enumerate(recs, start=1):
+        out = torch.empty((3, nx), dtype=torch.float64, device=DEV)
+        s.apply_step(lev, _t(v), out, 5)
+        psi = disc.CorrectedSLStep(p, p, rec["shift"], rec["phi_p"], rec["phi_q"])
+        ref = v
+        for _ in range(5):
+            ref = psi(ref)
+        got = _np(out)
+        assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref)) * max(1.0, abs(rec["phi_p"])), lev
+    s2, info, got, fin, ref, rinfo = _solve_both(nx, 256, p, "erk", p, c, [4, 4, 4], u0kind="fourier")
+    _check_parity(info, got, fin, ref, rinfo, 4)
+
+
+@pytest.mark.parametrize("nx,generic_l", [(4096, "4"), (512, "2"), (256, "2")])
 def test_lean_and_generic_coarse_kernels_agree(monkeypatch, nx, generic_l):
     """A chunk length outside the lean shapes selects the generic step kernel
     on the coarse levels, the default one the lean kernel; both solve the
