@@ -483,7 +483,7 @@ def main():
     flops = flops_s / launches
     bytes_ = bytes_s / launches
     kernel = {"fine_relax": "tile_kernel<8, 2, 1>: level-0 F/C relaxation and C-point residual",
-              "coarse": "coarse_vcycle_kernel<4, 2, 16, 4>: every coarse-level pass of a V-cycle in one cooperative "
+              "coarse": "coarse_vcycle_kernel<4, 2, 16, 4>: every coarse-level pass of a V-cycle in one persistent "
                         "launch (SL step + periodic banded solve)",
               "final": "tile_kernel<8, 2, 1>: final F-relaxation writing the space-time solution"}[dom]
     ai = flops / bytes_
