@@ -255,6 +255,8 @@ mgrit_status mgrit_profile_read(mgrit_handle *h, mgrit_profile *out, int32_t res
 
 const char *mgrit_status_string(mgrit_status s);
 const char *mgrit_last_error(const mgrit_handle *h);
+/* Waits for the work queued on the handle's stream, then releases the handle
+ * (its own workspace with hipFree; a caller's workspace stays the caller's). */
 void mgrit_destroy(mgrit_handle *h);
 
 /* ------------------------------------------------------------------------

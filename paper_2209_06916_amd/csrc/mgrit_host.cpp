@@ -981,6 +981,10 @@ const char *mgrit_last_error(const mgrit_handle *h) {
 
 void mgrit_destroy(mgrit_handle *h) {
   if (!h) return;
+  // work still queued on the handle's stream may write its workspace and
+  // its pinned words (an abandoned incremental solve): wait for it before
+  // either is reused
+  if (h->arena) (void)hipStreamSynchronize(h->stream);
   if (h->arena && h->owns_arena) (void)hipFree(h->arena);
   if (h->host_arena) pinned_slot_give(h->host_arena);
   if (h->ctl_ev) (void)hipEventDestroy(h->ctl_ev);
@@ -2472,6 +2476,7 @@ const char *mgrit2d_last_error(const mgrit2d_handle *h) { return h ? h->err.c_st
 
 void mgrit2d_destroy(mgrit2d_handle *h) {
   if (!h) return;
+  if (h->arena) (void)hipStreamSynchronize(h->stream);
   if (h->arena) (void)hipFree(h->arena);
   if (h->normsum_host) (void)hipHostFree(h->normsum_host);
   delete h;
