@@ -227,24 +227,29 @@ def serve_bench(n, seed):
     the matching upwind order, CFL U(0.5, 0.9), m in {4, 8, 16}, multilevel
     down to <= 8 coarse steps, seeded 16-mode Fourier u0, zero initial
     iterate).  Throughput with one solve in flight and with up to 16 in
-    flight (all requests queued at once), then latency under Poisson
-    arrivals at 0.8x the single-stream capacity."""
+    flight (all requests queued at once; one host thread per request in
+    flight, and the single-thread polling loop for comparison), then latency
+    under Poisson arrivals at 0.8x the single-stream capacity."""
     from paper_2209_06916_amd import serve
     reqs = serve.synthetic_stream(n, seed=seed, rate_hz=0)
     dof = sum(r.nx * r.nt for r in reqs)
-    serve.Server(max_inflight=16).run(reqs[:8], realtime=False)  # warm-up (kernels, allocator)
+    serve.ThreadedServer(max_inflight=16).run(reqs[:16], realtime=False)  # warm-up (kernels, allocator)
+    serve.Server(max_inflight=16).run(reqs[:16], realtime=False)
     t = time.perf_counter()
     one = serve.Server(max_inflight=1).run(reqs, realtime=False)
     t_one = time.perf_counter() - t
     t = time.perf_counter()
-    many = serve.Server(max_inflight=16).run(reqs, realtime=False)
+    many = serve.ThreadedServer(max_inflight=16).run(reqs, realtime=False)
     t_many = time.perf_counter() - t
+    t = time.perf_counter()
+    serve.Server(max_inflight=16).run(reqs, realtime=False)
+    t_loop = time.perf_counter() - t
     by1 = {r.tag: r for r in one}
     same = all(np.array_equal(by1[r.tag].u_final, r.u_final) for r in many)
     rate = 0.8 * n / t_one
     arrivals = serve.synthetic_stream(n, seed=seed, rate_hz=rate)
     t = time.perf_counter()
-    live = serve.Server(max_inflight=16).run(arrivals, realtime=True)
+    live = serve.ThreadedServer(max_inflight=16).run(arrivals, realtime=True)
     t_live = time.perf_counter() - t
     lat = np.array([r.latency for r in live]) * 1e3
     line = {
@@ -257,9 +262,10 @@ def serve_bench(n, seed):
         "data": "synthetic",
         "config": {"workload": f"served-advection1d-{n}-requests", "requests": n, "sizes": "nx, nt in 256..8192",
                    "schemes": "ERK1/3/5 + U1/3/5", "cfl": "U(0.5, 0.9)", "m": [4, 8, 16], "max_inflight": 16,
-                   "setup_threads": 8},
+                   "server": "one host thread per request in flight"},
         "dof_per_s_one_in_flight": dof / t_one,
         "dof_per_s_16_in_flight": dof / t_many,
+        "dof_per_s_16_in_flight_polling_loop": dof / t_loop,
         "concurrency_speedup": t_one / t_many,
         "same_results_alone_and_in_mix": bool(same),
         "all_converged": all(r.status == 0 for r in many),

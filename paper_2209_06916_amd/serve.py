@@ -203,3 +203,77 @@ def synthetic_stream(n, seed, rate_hz, sizes=(256, 512, 1024, 2048, 4096, 8192),
         reqs.append(Request(nx=nx, nt=nt, p=p, c=c, m=m, u0=inputs.u0_fourier(nx, seed * 100003 + i), arrival=t,
                             tag=i))
     return reqs
+
+
+class ThreadedServer(Server):
+    """The same admission rules, with one host thread per request in flight:
+    each thread sets up its handle, runs the whole solve with one blocking
+    mgrit_solve call on its own stream (ctypes drops the interpreter lock
+    for the call) and retires it.  Launch work is spread over the threads
+    instead of one polling loop."""
+
+    def run(self, requests, realtime=True):
+        import threading
+        pending = sorted(requests, key=lambda r: r.arrival)
+        for r in pending:
+            if self.footprint(r) > self.budget:
+                raise ValueError(f"request {r.tag} needs more than the whole budget")
+        cv = threading.Condition()
+        state = dict(used=0, active=0)
+        free_streams = list(self.streams)
+        results = []
+        t0 = time.perf_counter()
+
+        def work(req, need, stream, t_admit):
+            status, iters, hist, u_final = mgrit.EDEVICE, 0, [], None
+            try:
+                with torch.cuda.device(self.device), torch.cuda.stream(stream):
+                    host = torch.from_numpy(np.ascontiguousarray(req.u0, dtype=np.float64)).pin_memory()
+                    u0 = host.to(self.device, non_blocking=True)
+                    ufin = torch.empty(req.nx, dtype=torch.float64, device=self.device)
+                    ws = torch.empty(self.workspace(req), dtype=torch.uint8, device=self.device)
+                    solver = None
+                    try:
+                        solver = mgrit.Solver(req.problem(), req.options(), stream=stream, workspace=ws)
+                        info = solver.solve(u0, u_final=ufin, allow=_ANY_STATUS)
+                        status, iters, hist = info["status"], info["iterations"], info["res_history"]
+                        if status in (mgrit.OK, mgrit.ENOTCONVERGED):
+                            u_final = ufin.cpu().numpy()
+                    except mgrit.MgritError as e:
+                        status = e.status
+                    finally:
+                        stream.synchronize()
+                        if solver is not None:
+                            solver.close()
+            finally:
+                with cv:
+                    results.append(Result(tag=req.tag, status=status, iterations=iters, u_final=u_final,
+                                          t_arrival=req.arrival, t_admit=t_admit, t_done=time.perf_counter() - t0,
+                                          dof=req.nx * req.nt, res_history=list(hist)))
+                    state["used"] -= need
+                    state["active"] -= 1
+                    free_streams.append(stream)
+                    cv.notify_all()
+
+        threads = []
+        with cv:
+            while pending:
+                req = pending[0]
+                need = self.footprint(req)
+                now = time.perf_counter() - t0
+                if realtime and req.arrival > now:
+                    cv.wait(timeout=req.arrival - now)
+                    continue
+                if state["active"] >= self.max_inflight or state["used"] + need > self.budget:
+                    cv.wait()
+                    continue
+                pending.pop(0)
+                state["used"] += need
+                state["active"] += 1
+                stream = free_streams.pop()
+                th = threading.Thread(target=work, args=(req, need, stream, time.perf_counter() - t0), daemon=True)
+                th.start()
+                threads.append(th)
+        for th in threads:
+            th.join()
+        return results

@@ -122,3 +122,23 @@ def test_a_failing_request_does_not_affect_the_others():
     for r in reqs:
         assert got[r.tag].status == mgrit.OK
         np.testing.assert_array_equal(got[r.tag].u_final, alone[r.tag].u_final)
+
+
+def test_threaded_server_gives_the_same_results_and_respects_the_budget():
+    _announce("threaded server")
+    reqs = _mix()
+    alone = _by_tag(serve.Server(max_inflight=1).run(reqs, realtime=False))
+    thr = _by_tag(serve.ThreadedServer(max_inflight=len(reqs)).run(reqs, realtime=False))
+    for tag in alone:
+        assert thr[tag].status == mgrit.OK and thr[tag].iterations == alone[tag].iterations
+        np.testing.assert_array_equal(thr[tag].u_final, alone[tag].u_final)
+    small = reqs[:5]
+    one = max(serve.Server.footprint(r) for r in small)
+    tight = _by_tag(serve.ThreadedServer(budget_bytes=one, max_inflight=8).run(small, realtime=False))
+    fp = {r.tag: serve.Server.footprint(r) for r in small}
+    for t in tight:
+        t0 = tight[t].t_admit
+        assert sum(fp[u] for u in tight if tight[u].t_admit <= t0 < tight[u].t_done) <= one
+    bad = serve.Request(nx=512, nt=256, p=1, c=1.2, m=4, u0=inputs.u0_fourier(512, 9), tag="unstable")
+    got = _by_tag(serve.ThreadedServer(max_inflight=4).run(small + [bad], realtime=False))
+    assert got["unstable"].status == mgrit.EUNSTABLE and got["unstable"].u_final is None
