@@ -116,6 +116,111 @@ __global__ void __launch_bounds__(256) step2d_kernel(Step2dArgs a) {
   }
 }
 
+// Whole-wavefront shift of a double by one lane: WAVE_SHR1 (0x138) gives lane
+// l the value of lane l-1, WAVE_SHL1 (0x130) that of lane l+1; the lane
+// without a source reads 0.
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(bits & 0xffffffff), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+// The same step with no LDS, for stencils whose halo fits a wavefront: one
+// wavefront owns a tile of 64 columns (lane = column) by WY rows, every value
+// in registers.  x-neighbours come from whole-wavefront lane shifts, y
+// neighbours from the lane's own registers; each of the NS stencil
+// applications leaves one more ring of SL (left, below) / SR (right, above)
+// points invalid, which the halo absorbs.  Output: the TXR = 64 - NS (SL +
+// SR) middle columns of rows NS SL .. WY - NS SR.  Four independent tiles per
+// workgroup.
+template <int SL, int SR, int NS, int WY>
+__global__ void __launch_bounds__(256) step2d_reg_kernel(Step2dArgs a) {
+  constexpr int HL = NS * SL, HR = NS * SR;
+  constexpr int TXR = WAVE - HL - HR, TYR = WY - HL - HR;
+  constexpr int NT = SL + SR + 1;
+  const int nx = a.nx, ny = a.ny;
+  const int tiles_x = (nx + TXR - 1) / TXR, tiles_y = (ny + TYR - 1) / TYR;
+  const int64_t per_slab = (int64_t)tiles_x * tiles_y;
+  const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= per_slab * a.nb) return;  // whole wavefront leaves together
+  const int64_t b = item / per_slab;
+  const int t = (int)(item - b * per_slab);
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int x0 = (t % tiles_x) * TXR - HL, y0 = (t / tiles_x) * TYR - HL;
+  int gx = x0 + lane;
+  while (gx < 0) gx += nx;
+  while (gx >= nx) gx -= nx;
+  const double *src = a.src + b * a.src_stride;
+  double u[WY], y[WY];
+  const double top = a.coef[NS];
+#pragma unroll
+  for (int r = 0; r < WY; ++r) {
+    int gy = y0 + r;
+    while (gy < 0) gy += ny;
+    while (gy >= ny) gy -= ny;
+    u[r] = src[(int64_t)gy * nx + gx];
+    y[r] = top * u[r];
+  }
+  double tx[NT], ty[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    tx[k] = a.tx[k];
+    ty[k] = a.ty[k];
+  }
+#pragma unroll
+  for (int k = 1; k <= NS; ++k) {
+    const double ci = a.coef[NS - k];
+    // rows are updated in place, bottom to top; the SL previous rows' old
+    // values wait in a ring for the rows above that still read them
+    double ring[SL > 0 ? SL : 1];
+#pragma unroll
+    for (int j = 0; j < SL; ++j) ring[j] = y[k * SL - SL + j];
+#pragma unroll
+    for (int r = k * SL; r < WY - k * SR; ++r) {
+      // x-neighbours y(x + d), d = -SL..SR, by lane shifts
+      double xs[NT];
+      xs[SL] = y[r];
+#pragma unroll
+      for (int d = 1; d <= SL; ++d) xs[SL - d] = lane_shift<0x138>(xs[SL - d + 1]);
+#pragma unroll
+      for (int d = 1; d <= SR; ++d) xs[SL + d] = lane_shift<0x130>(xs[SL + d - 1]);
+      double ax = ci * u[r], ay = 0.0;
+#pragma unroll
+      for (int tt = 0; tt < NT; ++tt) {
+        ax = fma(tx[tt], xs[tt], ax);
+        ay = fma(ty[tt], tt < SL ? ring[tt < SL ? tt : 0] : y[r + tt - SL], ay);
+      }
+#pragma unroll
+      for (int j = 0; j + 1 < SL; ++j) ring[j] = ring[j + 1];
+      if (SL > 0) ring[SL > 0 ? SL - 1 : 0] = y[r];
+      y[r] = ax + ay;
+    }
+  }
+  const int ox = x0 + lane;
+  if (lane < HL || lane >= HL + TXR || ox >= nx) return;
+  double *dst = a.dst + b * a.dst_stride;
+  const double *g = a.g ? a.g + b * a.g_stride : nullptr;
+#pragma unroll
+  for (int r = HL; r < HL + TYR; ++r) {
+    const int oy = y0 + r;
+    if (oy >= ny) break;
+    const int64_t o = (int64_t)oy * nx + ox;
+    double v = y[r];
+    if (g) v += g[o];
+    dst[o] = v;
+  }
+}
+
+template <int SL, int SR, int NS, int WY>
+hipError_t launch_step2d_reg(const Step2dArgs &a, hipStream_t stream) {
+  constexpr int TXR = WAVE - NS * (SL + SR), TYR = WY - NS * (SL + SR);
+  const int64_t tiles = (int64_t)((a.nx + TXR - 1) / TXR) * ((a.ny + TYR - 1) / TYR) * a.nb;
+  hipLaunchKernelGGL((step2d_reg_kernel<SL, SR, NS, WY>), dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
 // dst slab b = transpose of src slab b ([rows][cols] -> [cols][rows]),
 // plus g slab b (already in the destination layout) when given.
 __global__ void __launch_bounds__(256) transpose_kernel(const double *__restrict__ src, int64_t src_stride,
@@ -201,6 +306,10 @@ hipError_t configure_2d_kernels(size_t bytes) {
 
 hipError_t launch_step2d(const Step2dArgs &a, hipStream_t stream) {
   if (a.nb <= 0) return hipSuccess;
+  // register tiles where the halo leaves most of a wavefront (32 rows): the
+  // common ERK1 + U1 and ERK3 + U3 steps; the LDS tiles otherwise
+  if (a.use_reg && a.sl == 2 && a.sr == 1 && a.ncoef == 4) return launch_step2d_reg<2, 1, 3, 24>(a, stream);
+  if (a.use_reg && a.sl == 1 && a.sr == 0 && a.ncoef == 2) return launch_step2d_reg<1, 0, 1, 32>(a, stream);
   const int64_t tiles = (int64_t)((a.nx + TX - 1) / TX) * ((a.ny + TY - 1) / TY);
   const size_t lds = step2d_lds_bytes(a.ncoef, a.sl, a.sr);
   hipLaunchKernelGGL(step2d_kernel, dim3((unsigned)(tiles * a.nb)), dim3(256), lds, stream, a);

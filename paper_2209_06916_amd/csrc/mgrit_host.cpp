@@ -2273,6 +2273,7 @@ mgrit_status mgrit2d_setup(const mgrit2d_problem *P, const mgrit_options *O, voi
   for (int i = 0; i <= fi.tab.s; ++i) f.coef[i] = (double)fi.beta[i];
   f.sl = fi.l;
   f.sr = fi.r;
+  f.use_reg = env_int("MGRIT_2D_LDS", 0) == 0;
   for (int j = 0; j <= fi.l + fi.r; ++j) {
     f.tx[j] = -cx * fi.w[j];
     f.ty[j] = -cy * fi.w[j];

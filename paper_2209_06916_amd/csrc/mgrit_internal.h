@@ -255,6 +255,7 @@ struct Step2dArgs {
   double coef[MAXCOEF];
   int sl, sr;
   double tx[MAXTAPS], ty[MAXTAPS];
+  int use_reg;  // the register-tile kernel where it has an instance (else LDS tiles)
 };
 size_t step2d_lds_bytes(int ncoef, int sl, int sr);
 hipError_t configure_2d_kernels(size_t bytes);

@@ -35,9 +35,14 @@ def _cxy(pr):
     return (pr.velocity_x * pr.dt / ((pr.x_hi - pr.x_lo) / pr.nx), pr.velocity_y * pr.dt / ((pr.y_hi - pr.y_lo) / pr.ny))
 
 
-@pytest.mark.parametrize("nx,ny,p", [(64, 48, 1), (100, 70, 3), (256, 32, 5), (1024, 16, 3), (40, 33, 3)])
-def test_fine_step_matches_oracle(nx, ny, p):
-    _announce("2d fine", nx, ny, p)
+@pytest.mark.parametrize("lds", ["0", "1"])
+@pytest.mark.parametrize("nx,ny,p", [(64, 48, 1), (100, 70, 3), (256, 32, 5), (1024, 16, 3), (40, 33, 3),
+                                     (300, 200, 1), (129, 257, 3)])
+def test_fine_step_matches_oracle(monkeypatch, nx, ny, p, lds):
+    """Register tiles (ERK1 + U1, ERK3 + U3) and LDS tiles (every scheme;
+    MGRIT_2D_LDS=1 forces them) against the oracle."""
+    _announce("2d fine", nx, ny, p, lds)
+    monkeypatch.setenv("MGRIT_2D_LDS", lds)
     pr = mgrit.make_problem_2d(nx, ny, 8, 0.5 if p != 5 else 0.4, p)
     s = mgrit.Solver2D(pr, mgrit.make_options([2]))
     v = np.random.default_rng(nx + ny + p).standard_normal((3, ny, nx))
