@@ -288,8 +288,8 @@ typedef struct {
 typedef struct mgrit2d_handle mgrit2d_handle;
 
 /* Validate, build the hierarchy from options (max_levels, m, min_coarse_nt,
- * nu, rtol, max_iter, diverge_factor; cg_kind must be
- * MGRIT_CG_SL_CORRECTED and precision MGRIT_PREC_FP64, else MGRIT_EINVAL),
+ * nu, rtol, max_iter, diverge_factor, precision, inner_rtol, inner_max_iter;
+ * cg_kind must be MGRIT_CG_SL_CORRECTED, else MGRIT_EINVAL),
  * factorise the x- and y-line operators of every coarse level and allocate
  * the workspace (owned by the handle).  MGRIT_EUNSTABLE when the fine step's
  * amplification factor exceeds 1 on a 256 x 256 grid of frequencies. */
@@ -297,7 +297,10 @@ mgrit_status mgrit2d_setup(const mgrit2d_problem *problem, const mgrit_options *
                            mgrit2d_handle **out);
 /* MGRIT solve; arguments and statuses as mgrit_solve, with [ny][nx] slabs:
  * u0_dev [ny][nx]; v_init_dev [nt+1][ny][nx] or NULL (zero; only C-points
- * are read); u_out_dev [nt+1][ny][nx] or NULL; u_final_dev [ny][nx] or NULL. */
+ * are read); u_out_dev [nt+1][ny][nx] or NULL; u_final_dev [ny][nx] or NULL.
+ * MGRIT_PREC_MIXED as for mgrit_solve: float32 2D MGRIT on the correction
+ * equation inside float64 refinement (the whole space-time array is the
+ * iterate, v_init's every row is read). */
 mgrit_status mgrit2d_solve(mgrit2d_handle *h, const double *u0_dev, const double *v_init_dev, double *u_out_dev,
                            double *u_final_dev, mgrit_stats *stats);
 /* Sequential time-stepping of the fine step: u_out_dev [nt+1][ny][nx]. */

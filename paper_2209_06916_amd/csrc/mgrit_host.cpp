@@ -15,6 +15,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 using namespace mgrit;
@@ -2033,15 +2034,23 @@ namespace {
 struct Line1D {  // a 1D coarse step applied along one axis of every slab
   StepOp op{};
   Layout lay{};
-  LevelDesc *desc = nullptr;
+  LevelDesc *desc = nullptr;    // tables in float64
+  LevelDesc *desc32 = nullptr;  // tables in float32 (mixed precision)
 };
 
 struct Level2 {
   int64_t nt = 0;
-  int m = 0;         // to the next level, 0 on the coarsest
-  Line1D x, y;       // levels >= 1
-  double *c[2] = {nullptr, nullptr};  // C-points, nc + 1 slabs
-  double *r = nullptr;                // C-point residual, nc slabs
+  int m = 0;    // to the next level, 0 on the coarsest
+  Line1D x, y;  // levels >= 1
+};
+
+// The arrays of one precision: per level the C-points (two copies, N_c + 1
+// slabs each) and the C-point residual (N_c slabs); the step and transpose
+// work buffers (cap slabs each) and one zero slab.
+template <class T>
+struct Set2 {
+  std::vector<T *> c0, c1, r;
+  T *w[2] = {nullptr, nullptr}, *t1 = nullptr, *t2 = nullptr, *zero = nullptr;
 };
 
 }  // namespace
@@ -2052,9 +2061,13 @@ struct mgrit2d_handle {
   hipStream_t stream = nullptr;
   std::vector<Level2> lv;
   Step2dArgs fine{};  // fine-step constants (pointers set per launch)
-  int64_t cap = 0;    // slabs the work buffers hold
-  double *w[2] = {nullptr, nullptr}, *t1 = nullptr, *t2 = nullptr;
-  double *zero = nullptr;  // one zero slab
+  int64_t cap = 0;    // slabs each work buffer holds
+  Set2<double> d64;
+  Set2<float> d32;    // mixed precision only
+  // mixed precision: the inner right-hand side and solution (float32), the
+  // outer residual and, without u_out, the outer iterate (float64)
+  float *g32 = nullptr, *e32 = nullptr;
+  double *r64 = nullptr, *u64 = nullptr;
   double *normpart = nullptr, *normsum = nullptr, *normsum_host = nullptr;
   int64_t normpart_len = 0;
   char *arena = nullptr;
@@ -2078,68 +2091,105 @@ mgrit_status fail2(mgrit2d_handle *h, mgrit_status s, const std::string &msg) {
 
 int64_t slab(const mgrit2d_handle *h) { return h->prob.nx * h->prob.ny; }
 
-// dst = Phi_l(src) (+ g) on nb contiguous slabs (g: slab b at g + b g_stride)
-hipError_t apply2d(mgrit2d_handle *h, int l, const double *src, double *dst, int64_t nb, const double *g,
-                   int64_t g_stride) {
-  const int nx = (int)h->prob.nx, ny = (int)h->prob.ny;
-  const int64_t S = slab(h);
-  if (l == 0) {
-    Step2dArgs a = h->fine;
-    a.src = src;
-    a.src_stride = S;
-    a.dst = dst;
-    a.dst_stride = S;
-    a.g = g;
-    a.g_stride = g_stride;
-    a.nb = nb;
-    return launch_step2d(a, h->stream);
-  }
-  const Level2 &L = h->lv[l];
-  // along x: every row of every slab is one 1D vector
+template <class T>
+Set2<T> &set_of(mgrit2d_handle *h);
+template <>
+Set2<double> &set_of<double>(mgrit2d_handle *h) { return h->d64; }
+template <>
+Set2<float> &set_of<float>(mgrit2d_handle *h) { return h->d32; }
+
+hipError_t line_apply(const Line1D &ln, const double *src, double *dst, int64_t count, hipStream_t stream) {
   PassArgs pa{};
   pa.mode = MODE_APPLY;
   pa.m = 1;
-  pa.nint = nb * ny;
+  pa.nint = count;
   pa.cin = src;
-  pa.cout = h->t1;
-  if (hipError_t e = launch_pass(L.x.desc, L.x.op, L.x.lay, pa, h->stream)) return e;
-  if (hipError_t e = launch_transpose(h->t1, S, h->t2, S, nullptr, 0, nb, ny, nx, h->stream)) return e;
+  pa.cout = dst;
+  return launch_pass(ln.desc, ln.op, ln.lay, pa, stream);
+}
+
+hipError_t line_apply(const Line1D &ln, const float *src, float *dst, int64_t count, hipStream_t stream) {
+  PassArgs32 pa{};
+  pa.mode = MODE_APPLY;
+  pa.m = 1;
+  pa.nint = count;
+  pa.cin = src;
+  pa.cout = dst;
+  return launch_pass32(ln.desc32, ln.op, ln.lay, pa, stream);
+}
+
+// dst = Phi_l(src) + g_scale g on nb slabs (src and dst with slab strides;
+// levels >= 1 need contiguous src and dst)
+template <class T>
+hipError_t apply2d(mgrit2d_handle *h, int l, const T *src, int64_t src_stride, T *dst, int64_t dst_stride, int64_t nb,
+                   const T *g, int64_t g_stride, double g_scale = 1.0) {
+  const int nx = (int)h->prob.nx, ny = (int)h->prob.ny;
+  const int64_t S = slab(h);
+  if (l == 0) {
+    const Step2dArgs &f = h->fine;
+    Step2dArgsT<T> a{};
+    a.src = src;
+    a.src_stride = src_stride;
+    a.dst = dst;
+    a.dst_stride = dst_stride;
+    a.g = g;
+    a.g_stride = g_stride;
+    a.g_scale = g_scale;
+    a.nb = nb;
+    a.nx = f.nx;
+    a.ny = f.ny;
+    a.ncoef = f.ncoef;
+    for (int i = 0; i < MAXCOEF; ++i) a.coef[i] = f.coef[i];
+    a.sl = f.sl;
+    a.sr = f.sr;
+    for (int i = 0; i < MAXTAPS; ++i) {
+      a.tx[i] = f.tx[i];
+      a.ty[i] = f.ty[i];
+    }
+    a.use_reg = f.use_reg;
+    return launch_step2d<T>(a, h->stream);
+  }
+  const Level2 &L = h->lv[l];
+  Set2<T> &B = set_of<T>(h);
+  // along x: every row of every slab is one 1D vector
+  if (hipError_t e = line_apply(L.x, src, B.t1, nb * ny, h->stream)) return e;
+  if (hipError_t e = launch_transpose<T>(B.t1, S, B.t2, S, (const T *)nullptr, 0, nb, ny, nx, h->stream)) return e;
   // along y: the rows of the transposed slabs, in place
-  pa.nint = nb * nx;
-  pa.cin = h->t2;
-  pa.cout = h->t2;
-  if (hipError_t e = launch_pass(L.y.desc, L.y.op, L.y.lay, pa, h->stream)) return e;
-  return launch_transpose(h->t2, S, dst, S, g, g_stride, nb, nx, ny, h->stream);
+  if (hipError_t e = line_apply(L.y, B.t2, B.t2, nb * nx, h->stream)) return e;
+  return launch_transpose<T>(B.t2, S, dst, S, g, g_stride, nb, nx, ny, h->stream);
 }
 
 // One relaxation pass (PassMode) of level l over all its CF-intervals at
 // once: the intervals' vectors advance together, one step per launch group.
-mgrit_status relax2d(mgrit2d_handle *h, int l, int mode, const double *cin, double *cout, const double *g, double *r,
-                     double *parent, double *out) {
+// g: right-hand side rows g[n-1] for level point n (NULL = 0).
+template <class T>
+mgrit_status relax2d(mgrit2d_handle *h, int l, int mode, const T *cin, T *cout, const T *g, T *r, T *parent,
+                     T *out) {
   const Level2 &L = h->lv[l];
+  Set2<T> &B = set_of<T>(h);
   const int64_t S = slab(h);
   const int m = L.m;
   const int64_t nc = L.nt / m;
   const int nsteps = (mode == MODE_POST_F || mode == MODE_FINAL_F) ? m - 1 : m;
-  if (mode == MODE_POST_F) HIPCHK2(h, launch_slab_axpy(parent, m * S, cin, S, nc, S, true, h->stream));
-  if (mode == MODE_FINAL_F) HIPCHK2(h, launch_slab_axpy(out, m * S, cin, S, nc, S, false, h->stream));
-  const double *src = cin;
+  if (mode == MODE_POST_F) HIPCHK2(h, launch_slab_axpy<T>(parent, m * S, cin, S, nc, S, true, h->stream));
+  if (mode == MODE_FINAL_F) HIPCHK2(h, launch_slab_axpy<T>(out, m * S, cin, S, nc, S, false, h->stream));
+  const T *src = cin;
   for (int j = 1; j <= nsteps; ++j) {
-    double *dst = h->w[j & 1];
-    HIPCHK2(h, apply2d(h, l, src, dst, nc, g ? g + (j - 1) * S : nullptr, m * S));
-    if (mode == MODE_POST_F) HIPCHK2(h, launch_slab_axpy(parent + j * S, m * S, dst, S, nc, S, true, h->stream));
-    if (mode == MODE_FINAL_F) HIPCHK2(h, launch_slab_axpy(out + j * S, m * S, dst, S, nc, S, false, h->stream));
+    T *dst = B.w[j & 1];
+    HIPCHK2(h, apply2d<T>(h, l, src, S, dst, S, nc, g ? g + (j - 1) * S : nullptr, m * S));
+    if (mode == MODE_POST_F) HIPCHK2(h, launch_slab_axpy<T>(parent + j * S, m * S, dst, S, nc, S, true, h->stream));
+    if (mode == MODE_FINAL_F) HIPCHK2(h, launch_slab_axpy<T>(out + j * S, m * S, dst, S, nc, S, false, h->stream));
     src = dst;
   }
   if (mode == MODE_PASS_A) {
-    if (cout != cin) HIPCHK2(h, launch_slab_axpy(cout, S, cin, S, 1, S, false, h->stream));
-    HIPCHK2(h, launch_slab_axpy(cout + S, S, src, S, nc, S, false, h->stream));
+    if (cout != cin) HIPCHK2(h, launch_slab_axpy<T>(cout, S, cin, S, 1, S, false, h->stream));
+    HIPCHK2(h, launch_slab_axpy<T>(cout + S, S, src, S, nc, S, false, h->stream));
   } else if (mode == MODE_PASS_B) {
-    HIPCHK2(h, launch_slab_resid(src, cin + S, r, nc, S, RESID_BLOCKS, h->normpart, h->stream));
+    HIPCHK2(h, launch_slab_resid<T>(src, cin + S, r, nc, S, RESID_BLOCKS, h->normpart, h->stream));
   } else if (mode == MODE_POST_F) {
-    HIPCHK2(h, launch_slab_axpy(parent + nc * m * S, S, cin + nc * S, S, 1, S, true, h->stream));
+    HIPCHK2(h, launch_slab_axpy<T>(parent + nc * m * S, S, cin + nc * S, S, 1, S, true, h->stream));
   } else if (mode == MODE_FINAL_F) {
-    HIPCHK2(h, launch_slab_axpy(out + nc * m * S, S, cin + nc * S, S, 1, S, false, h->stream));
+    HIPCHK2(h, launch_slab_axpy<T>(out + nc * m * S, S, cin + nc * S, S, 1, S, false, h->stream));
   }
   return MGRIT_OK;
 }
@@ -2147,44 +2197,192 @@ mgrit_status relax2d(mgrit2d_handle *h, int l, int mode, const double *cin, doub
 // Coarse-grid correction below level l-1 (Sec. 2.2, V-cycle): relax level l
 // from zero with right-hand side g, recurse on its residual, post-relax into
 // the parent's C-points; the last level is solved by sequential stepping.
-mgrit_status vcycle2d(mgrit2d_handle *h, int l, const double *g, double *parent) {
+template <class T>
+mgrit_status vcycle2d(mgrit2d_handle *h, int l, const T *g, T *parent) {
   Level2 &L = h->lv[l];
+  Set2<T> &B = set_of<T>(h);
   const int64_t S = slab(h);
   const int nlev = (int)h->lv.size();
   if (l == nlev - 1) {
-    const double *src = h->zero;
+    const T *src = B.zero;
     for (int64_t j = 1; j <= L.nt; ++j) {
-      double *dst = h->w[j & 1];
-      HIPCHK2(h, apply2d(h, l, src, dst, 1, g + (j - 1) * S, S));
-      HIPCHK2(h, launch_slab_axpy(parent + j * S, S, dst, S, 1, S, true, h->stream));
+      T *dst = B.w[j & 1];
+      HIPCHK2(h, apply2d<T>(h, l, src, S, dst, S, 1, g + (j - 1) * S, S));
+      HIPCHK2(h, launch_slab_axpy<T>(parent + j * S, S, dst, S, 1, S, true, h->stream));
       src = dst;
     }
     return MGRIT_OK;
   }
   const int64_t nc = L.nt / L.m;
+  T *c[2] = {B.c0[l], B.c1[l]};
   int cur = 0;
-  HIPCHK2(h, launch_fill(L.c[0], (nc + 1) * S, 0.0, h->stream));
+  HIPCHK2(h, launch_slab_axpy<T>(c[0], S, B.zero, 0, nc + 1, S, false, h->stream));  // zero C-points
   for (int s = 0; s < h->opt.nu; ++s) {
-    const mgrit_status st = relax2d(h, l, MODE_PASS_A, L.c[cur], L.c[1 - cur], g, nullptr, nullptr, nullptr);
+    const mgrit_status st = relax2d<T>(h, l, MODE_PASS_A, c[cur], c[1 - cur], g, nullptr, nullptr, nullptr);
     if (st != MGRIT_OK) return st;
     cur = 1 - cur;
   }
-  mgrit_status st = relax2d(h, l, MODE_PASS_B, L.c[cur], nullptr, g, L.r, nullptr, nullptr);
+  mgrit_status st = relax2d<T>(h, l, MODE_PASS_B, c[cur], nullptr, g, B.r[l], nullptr, nullptr);
   if (st != MGRIT_OK) return st;
-  st = vcycle2d(h, l + 1, L.r, L.c[cur]);
+  st = vcycle2d<T>(h, l + 1, B.r[l], c[cur]);
   if (st != MGRIT_OK) return st;
-  return relax2d(h, l, MODE_POST_F, L.c[cur], nullptr, g, nullptr, parent, nullptr);
+  return relax2d<T>(h, l, MODE_POST_F, c[cur], nullptr, g, nullptr, parent, nullptr);
 }
 
-bool build_line(const SlLevel &S, Line1D &ln, std::vector<double> &tabs_all, std::vector<std::pair<Line1D *, size_t>> &fix,
-                std::vector<size_t> &offs) {
-  ln.op = S.op;
-  ln.lay = S.lay;
-  const size_t base = tabs_all.size();
-  tabs_all.insert(tabs_all.end(), S.tabs.begin(), S.tabs.end());
-  fix.push_back({&ln, base});
-  offs = S.offs;
-  return true;
+double norm2d(mgrit2d_handle *h, int64_t parts, hipError_t &e) {
+  e = launch_reduce(h->normpart, parts, h->normsum, h->stream);
+  if (!e) e = hipMemcpyAsync(h->normsum_host, h->normsum, sizeof(double), hipMemcpyDeviceToHost, h->stream);
+  if (!e) e = hipStreamSynchronize(h->stream);
+  return e ? NAN : std::sqrt(*h->normsum_host);
+}
+
+// MGRIT at level 0 with right-hand side g (NULL: the homogeneous system with
+// u_0 = the C-point row 0 already in c0[0]), from the C-points in c0[0];
+// stops as rule says; the final C-points are in *cfinal.  Float64 solves
+// record the residual history.
+template <class T>
+mgrit_status mgrit2d_iterate(mgrit2d_handle *h, const T *g, const StopRule &rule, int *iters, int *stop, T **cfinal,
+                             std::vector<double> *hist, double *res0_out, double *rho_out, double *prev_out) {
+  Level2 &L0 = h->lv[0];
+  Set2<T> &B = set_of<T>(h);
+  const int m = L0.m;
+  const int64_t nc = L0.nt / m;
+  T *c[2] = {B.c0[0], B.c1[0]};
+  int cur = 0, it = 0;
+  double res0 = NAN, rho = NAN, prev = NAN;
+  for (;;) {
+    for (int s = 0; s < h->opt.nu; ++s) {
+      const mgrit_status st = relax2d<T>(h, 0, MODE_PASS_A, c[cur], c[1 - cur], g, nullptr, nullptr, nullptr);
+      if (st != MGRIT_OK) return st;
+      cur = 1 - cur;
+    }
+    mgrit_status st = relax2d<T>(h, 0, MODE_PASS_B, c[cur], nullptr, g, B.r[0], nullptr, nullptr);
+    if (st != MGRIT_OK) return st;
+    hipError_t e;
+    prev = rho;
+    rho = norm2d(h, nc * RESID_BLOCKS, e);
+    if (e) return fail2(h, MGRIT_EDEVICE, std::string("residual norm: ") + hipGetErrorString(e));
+    if (hist) hist->push_back(rho);
+    if (it == 0) res0 = rho;
+    int code = STOP_NONE;
+    if (!std::isfinite(rho))
+      code = STOP_NONFINITE;
+    else if (rho <= rule.rtol * res0)
+      code = STOP_CONVERGED;
+    else if (rule.stall > 0 && it >= 1 && rho > rule.stall * prev)
+      code = STOP_STALLED;
+    else if (it >= rule.max_iter)
+      code = STOP_MAX_ITER;
+    else if (rule.diverge_factor > 0 && rho > rule.diverge_factor * res0)
+      code = STOP_DIVERGED;
+    if (code != STOP_NONE) {
+      *stop = code;
+      break;
+    }
+    st = vcycle2d<T>(h, 1, B.r[0], c[cur]);
+    if (st != MGRIT_OK) return st;
+    ++it;
+  }
+  *iters = it;
+  *cfinal = c[cur];
+  if (res0_out) *res0_out = res0;
+  if (rho_out) *rho_out = rho;
+  if (prev_out) *prev_out = prev;
+  return MGRIT_OK;
+}
+
+void fill_stats(mgrit_stats *stats, int it, int inner, double res0, double rho, double prev,
+                const std::vector<double> &hist, std::chrono::steady_clock::time_point t0) {
+  if (!stats) return;
+  stats->iterations = it;
+  stats->inner_iterations = inner;
+  stats->res0 = res0;
+  stats->res_final = rho;
+  stats->conv_factor = prev > 0 ? rho / prev : NAN;
+  const int len = (int)hist.size();
+  if (stats->res_history)
+    for (int i = 0; i < std::min(len, stats->res_history_cap); ++i) stats->res_history[i] = hist[i];
+  stats->res_history_len = std::min(len, std::max(stats->res_history_cap, 0));
+  stats->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Mixed precision in 2D: as mp_solve in 1D (float64 space-time residual,
+// test and update; float32 MGRIT on the correction equation).
+mgrit_status mp2d_solve(mgrit2d_handle *h, const double *u0, const double *v_init, double *u_out, double *u_final,
+                        mgrit_stats *stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t S = slab(h);
+  const int64_t nt = h->prob.nt;
+  const int64_t pts = nt * S;
+  double *U = u_out ? u_out : h->u64;
+  if (v_init && v_init != U) {
+    HIPCHK2(h, hipMemcpyAsync(U, v_init, (pts + S) * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  } else if (!v_init) {
+    HIPCHK2(h, launch_fill(U, pts + S, 0.0, h->stream));
+  }
+  HIPCHK2(h, hipMemcpyAsync(U, u0, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  const StopRule inner{h->opt.inner_rtol, h->opt.diverge_factor, h->opt.inner_max_iter, 0.5};
+  std::vector<double> hist;
+  double res0 = NAN, rho = NAN, prev = NAN;
+  int outer = 0, inner_total = 0;
+  mgrit_status status = MGRIT_OK;
+  const int64_t chunk = h->cap;
+  for (;;) {
+    // float64: r_n = Phi u_{n-1} - u_n, n = 1..nt, in chunks of cap slabs
+    for (int64_t n0 = 0; n0 < nt; n0 += chunk) {
+      const int64_t nb = std::min(chunk, nt - n0);
+      HIPCHK2(h, apply2d<double>(h, 0, U + n0 * S, S, h->r64 + n0 * S, S, nb, U + (n0 + 1) * S, S, -1.0));
+    }
+    double acc = 0.0;  // chunk by chunk, in a fixed order
+    for (int64_t n0 = 0; n0 < nt; n0 += chunk) {
+      const int64_t nb = std::min(chunk, nt - n0);
+      HIPCHK2(h, launch_slab_norm(h->r64 + n0 * S, nb, S, RESID_BLOCKS, h->normpart, h->stream));
+      hipError_t e;
+      const double part = norm2d(h, nb * RESID_BLOCKS, e);
+      if (e) return fail2(h, MGRIT_EDEVICE, "outer residual norm");
+      acc += part * part;
+    }
+    prev = rho;
+    rho = std::sqrt(acc);
+    hist.push_back(rho);
+    if (outer == 0) res0 = rho;
+    if (!std::isfinite(rho)) {
+      status = fail2(h, MGRIT_EDIVERGED, "non-finite residual");
+      break;
+    }
+    if (rho <= h->opt.rtol * res0) break;
+    if (outer >= h->opt.max_iter) {
+      status = MGRIT_ENOTCONVERGED;
+      h->err = "max_iter reached";
+      break;
+    }
+    if (h->opt.diverge_factor > 0 && rho > h->opt.diverge_factor * res0) {
+      status = fail2(h, MGRIT_EDIVERGED, "residual grew past diverge_factor * res0");
+      break;
+    }
+    // float32: A e = r from zero, then u += e in float64
+    HIPCHK2(h, launch_round32(h->r64, h->g32, pts, h->stream));
+    const int64_t nc = h->lv[0].nt / h->lv[0].m;
+    HIPCHK2(h, launch_slab_axpy<float>(h->d32.c0[0], S, h->d32.zero, 0, nc + 1, S, false, h->stream));
+    int iters = 0, stop = 0;
+    float *cfin = nullptr;
+    const mgrit_status st =
+        mgrit2d_iterate<float>(h, h->g32, inner, &iters, &stop, &cfin, nullptr, nullptr, nullptr, nullptr);
+    if (st != MGRIT_OK) return st;
+    inner_total += iters;
+    if (stop == STOP_NONFINITE || stop == STOP_DIVERGED) {
+      status = fail2(h, MGRIT_EDIVERGED, "the float32 inner solve diverged");
+      break;
+    }
+    const mgrit_status fs = relax2d<float>(h, 0, MODE_FINAL_F, cfin, nullptr, h->g32, nullptr, nullptr, h->e32);
+    if (fs != MGRIT_OK) return fs;
+    HIPCHK2(h, launch_add32(U, h->e32, pts + S, h->stream));
+    ++outer;
+  }
+  if (u_final) HIPCHK2(h, hipMemcpyAsync(u_final, U + pts, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK2(h, hipStreamSynchronize(h->stream));
+  fill_stats(stats, outer, inner_total, res0, rho, prev, hist, t0);
+  return status;
 }
 
 }  // namespace
@@ -2210,7 +2408,11 @@ mgrit_status mgrit2d_setup(const mgrit2d_problem *P, const mgrit_options *O, voi
   if (O->nu < 0 || O->nu > 8) return bad(MGRIT_EINVAL, "nu must be in 0..8");
   if (O->max_iter < 0 || !(O->rtol >= 0)) return bad(MGRIT_EINVAL, "need max_iter >= 0 and rtol >= 0");
   if (O->cg_kind != MGRIT_CG_SL_CORRECTED) return bad(MGRIT_EINVAL, "2D: corrected semi-Lagrangian coarse step only");
-  if (O->precision != MGRIT_PREC_FP64) return bad(MGRIT_EINVAL, "2D: float64 only");
+  if (O->precision != MGRIT_PREC_FP64 && O->precision != MGRIT_PREC_MIXED) return bad(MGRIT_EINVAL, "unknown precision");
+  const bool mixed = O->precision == MGRIT_PREC_MIXED;
+  if (mixed && !(O->inner_rtol > 0 && O->inner_rtol < 1))
+    return bad(MGRIT_EINVAL, "mixed precision needs 0 < inner_rtol < 1");
+  if (mixed && O->inner_max_iter < 1) return bad(MGRIT_EINVAL, "mixed precision needs inner_max_iter >= 1");
   mgrit_problem p1{};
   p1.velocity = 1;
   p1.x_lo = 0;
@@ -2278,8 +2480,7 @@ mgrit_status mgrit2d_setup(const mgrit2d_problem *P, const mgrit_options *O, voi
     f.tx[j] = -cx * fi.w[j];
     f.ty[j] = -cy * fi.w[j];
   }
-  const size_t lds = step2d_lds_bytes(f.ncoef, f.sl, f.sr);
-  if (lds > LDS_LIMIT) {
+  if (step2d_lds_bytes(f.ncoef, f.sl, f.sr) > LDS_LIMIT) {
     mgrit2d_destroy(h);
     return bad(MGRIT_EINVAL, "2D fine step: halo too wide for LDS");
   }
@@ -2287,41 +2488,54 @@ mgrit_status mgrit2d_setup(const mgrit2d_problem *P, const mgrit_options *O, voi
     mgrit2d_destroy(h);
     return bad(MGRIT_EDEVICE, "configure");
   }
-  // device memory: tables and descriptors (uploaded), then the arrays
+  // ---- device memory: one allocation.  Head (uploaded): the line tables in
+  // float64 (and float32), the line descriptors; then the arrays.
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  std::vector<double> tabs;
-  std::vector<std::pair<Line1D *, size_t>> fix;
-  std::vector<std::vector<size_t>> offs(2 * nlev);
-  for (int l = 1; l < nlev; ++l) {
-    build_line(chx[l - 1], h->lv[l].x, tabs, fix, offs[2 * l]);
-    build_line(chy[l - 1], h->lv[l].y, tabs, fix, offs[2 * l + 1]);
-  }
   const int64_t S = P->nx * P->ny;
   const int64_t nc0 = nts[0] / ms[0];
   h->cap = std::max<int64_t>(nc0, 1);
+  std::vector<size_t> tab_off(2 * nlev, 0), tab_len(2 * nlev, 0);
+  std::vector<double> tabs;
+  for (int l = 1; l < nlev; ++l)
+    for (int ax = 0; ax < 2; ++ax) {
+      const SlLevel &SL = ax == 0 ? chx[l - 1] : chy[l - 1];
+      tab_off[2 * l + ax] = tabs.size();
+      tab_len[2 * l + ax] = SL.tabs.size();
+      tabs.insert(tabs.end(), SL.tabs.begin(), SL.tabs.end());
+    }
   size_t off = 0;
   const size_t o_tabs = off;
   off += al(std::max<size_t>(tabs.size(), 1) * sizeof(double));
+  const size_t o_tabs32 = off;
+  if (mixed) off += al(std::max<size_t>(tabs.size(), 1) * sizeof(float));
   const size_t o_desc = off;
-  off += al(2 * nlev * sizeof(LevelDesc));
+  off += al(4 * nlev * sizeof(LevelDesc));
   const size_t head = off;
-  std::vector<size_t> o_c0(nlev), o_c1(nlev), o_r(nlev);
-  for (int l = 0; l + 1 < nlev; ++l) {
-    const int64_t nc = nts[l] / ms[l];
-    o_c0[l] = off, off += al((nc + 1) * S * sizeof(double));
-    o_c1[l] = off, off += al((nc + 1) * S * sizeof(double));
-    o_r[l] = off, off += al(nc * S * sizeof(double));
+  auto arrays = [&](size_t w, std::vector<size_t> &oc0, std::vector<size_t> &oc1, std::vector<size_t> &orr,
+                    size_t (&ow)[5]) {
+    oc0.assign(nlev, 0);
+    oc1.assign(nlev, 0);
+    orr.assign(nlev, 0);
+    for (int l = 0; l + 1 < nlev; ++l) {
+      const int64_t nc = nts[l] / ms[l];
+      oc0[l] = off, off += al((nc + 1) * S * w);
+      oc1[l] = off, off += al((nc + 1) * S * w);
+      orr[l] = off, off += al(nc * S * w);
+    }
+    for (int i = 0; i < 4; ++i) ow[i] = off, off += al(h->cap * S * w);
+    ow[4] = off, off += al(S * w);  // zero slab
+  };
+  std::vector<size_t> a0, a1, ar, b0, b1, br;
+  size_t wa[5], wb[5];
+  arrays(sizeof(double), a0, a1, ar, wa);
+  size_t o_g32 = 0, o_e32 = 0, o_r64 = 0, o_u64 = 0;
+  if (mixed) {
+    arrays(sizeof(float), b0, b1, br, wb);
+    o_g32 = off, off += al((size_t)(nts[0] * S) * sizeof(float));
+    o_e32 = off, off += al(((size_t)(nts[0] * S) + S) * sizeof(float));
+    o_r64 = off, off += al((size_t)(nts[0] * S) * sizeof(double));
+    o_u64 = off, off += al(((size_t)(nts[0] * S) + S) * sizeof(double));
   }
-  const size_t o_w0 = off;
-  off += al(h->cap * S * sizeof(double));
-  const size_t o_w1 = off;
-  off += al(h->cap * S * sizeof(double));
-  const size_t o_t1 = off;
-  off += al(h->cap * S * sizeof(double));
-  const size_t o_t2 = off;
-  off += al(h->cap * S * sizeof(double));
-  const size_t o_zero = off;
-  off += al(S * sizeof(double));
   h->normpart_len = h->cap * RESID_BLOCKS;
   const size_t o_np = off;
   off += al(h->normpart_len * sizeof(double));
@@ -2332,40 +2546,68 @@ mgrit_status mgrit2d_setup(const mgrit2d_problem *P, const mgrit_options *O, voi
     return bad(MGRIT_ENOMEM, "device workspace");
   }
   char *base = h->arena;
-  double *dtabs = (double *)(base + o_tabs);
   std::vector<char> up(head, 0);
   std::memcpy(up.data() + o_tabs, tabs.data(), tabs.size() * sizeof(double));
+  if (mixed) {
+    float *t32 = (float *)(up.data() + o_tabs32);
+    for (size_t i = 0; i < tabs.size(); ++i) t32[i] = (float)tabs[i];
+  }
   int di = 0;
   for (int l = 1; l < nlev; ++l)
     for (int ax = 0; ax < 2; ++ax) {
+      const SlLevel &SL = ax == 0 ? chx[l - 1] : chy[l - 1];
       Line1D &ln = ax == 0 ? h->lv[l].x : h->lv[l].y;
-      size_t tb = 0;
-      for (auto &fx : fix)
-        if (fx.first == &ln) tb = fx.second;
-      const std::vector<size_t> &of = offs[2 * l + ax];
-      if (of.size() == 2) {
-        ln.op.fw.tab = of[0] == (size_t)-1 ? nullptr : dtabs + tb + of[0];
-        ln.op.bw.tab = of[1] == (size_t)-1 ? nullptr : dtabs + tb + of[1];
+      ln.op = SL.op;
+      ln.lay = SL.lay;
+      for (int prec = 0; prec < (mixed ? 2 : 1); ++prec) {
+        LevelDesc hd{ln.op, ln.lay};
+        const size_t tb = tab_off[2 * l + ax];
+        if (SL.offs.size() == 2) {
+          if (prec == 0) {
+            const double *d = (const double *)(base + o_tabs);
+            hd.op.fw.tab = SL.offs[0] == (size_t)-1 ? nullptr : d + tb + SL.offs[0];
+            hd.op.bw.tab = SL.offs[1] == (size_t)-1 ? nullptr : d + tb + SL.offs[1];
+          } else {
+            const float *d = (const float *)(base + o_tabs32);
+            hd.op.fw.tab = SL.offs[0] == (size_t)-1 ? nullptr : d + tb + SL.offs[0];
+            hd.op.bw.tab = SL.offs[1] == (size_t)-1 ? nullptr : d + tb + SL.offs[1];
+          }
+        }
+        LevelDesc *dd = (LevelDesc *)(base + o_desc) + di++;
+        (prec == 0 ? ln.desc : ln.desc32) = dd;
+        std::memcpy(up.data() + ((char *)dd - base), &hd, sizeof(LevelDesc));
       }
-      ln.desc = (LevelDesc *)(base + o_desc) + di;
-      const LevelDesc hd{ln.op, ln.lay};
-      std::memcpy(up.data() + o_desc + di * sizeof(LevelDesc), &hd, sizeof(LevelDesc));
-      ++di;
     }
-  for (int l = 0; l + 1 < nlev; ++l) {
-    h->lv[l].c[0] = (double *)(base + o_c0[l]);
-    h->lv[l].c[1] = (double *)(base + o_c1[l]);
-    h->lv[l].r = (double *)(base + o_r[l]);
+  auto place = [&](auto &B, const std::vector<size_t> &o0, const std::vector<size_t> &o1,
+                   const std::vector<size_t> &orr, const size_t (&ow)[5]) {
+    using P_ = std::remove_reference_t<decltype(*B.w[0])>;
+    B.c0.assign(nlev, nullptr);
+    B.c1.assign(nlev, nullptr);
+    B.r.assign(nlev, nullptr);
+    for (int l = 0; l + 1 < nlev; ++l) {
+      B.c0[l] = (P_ *)(base + o0[l]);
+      B.c1[l] = (P_ *)(base + o1[l]);
+      B.r[l] = (P_ *)(base + orr[l]);
+    }
+    B.w[0] = (P_ *)(base + ow[0]);
+    B.w[1] = (P_ *)(base + ow[1]);
+    B.t1 = (P_ *)(base + ow[2]);
+    B.t2 = (P_ *)(base + ow[3]);
+    B.zero = (P_ *)(base + ow[4]);
+  };
+  place(h->d64, a0, a1, ar, wa);
+  if (mixed) {
+    place(h->d32, b0, b1, br, wb);
+    h->g32 = (float *)(base + o_g32);
+    h->e32 = (float *)(base + o_e32);
+    h->r64 = (double *)(base + o_r64);
+    h->u64 = (double *)(base + o_u64);
   }
-  h->w[0] = (double *)(base + o_w0);
-  h->w[1] = (double *)(base + o_w1);
-  h->t1 = (double *)(base + o_t1);
-  h->t2 = (double *)(base + o_t2);
-  h->zero = (double *)(base + o_zero);
   h->normpart = (double *)(base + o_np);
   h->normsum = (double *)(base + o_ns);
   if (hipMemcpyAsync(base, up.data(), head, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
-      launch_fill(h->zero, S, 0.0, h->stream) != hipSuccess ||
+      launch_fill(h->d64.zero, S, 0.0, h->stream) != hipSuccess ||
+      (mixed && launch_fill32(h->d32.zero, S, h->stream) != hipSuccess) ||
       hipHostMalloc((void **)&h->normsum_host, sizeof(double)) != hipSuccess) {
     mgrit2d_destroy(h);
     return bad(MGRIT_EDEVICE, "upload");
@@ -2378,76 +2620,46 @@ mgrit_status mgrit2d_solve(mgrit2d_handle *h, const double *u0, const double *v_
                            mgrit_stats *stats) {
   if (!h) return MGRIT_EINVAL;
   if (!u0) return fail2(h, MGRIT_EINVAL, "u0 is required");
+  if (h->opt.precision == MGRIT_PREC_MIXED) return mp2d_solve(h, u0, v_init, u_out, u_final, stats);
   const auto t0 = std::chrono::steady_clock::now();
   Level2 &L0 = h->lv[0];
   const int64_t S = slab(h);
   const int m = L0.m;
   const int64_t nc = L0.nt / m;
-  int cur = 0;
+  double *c0 = h->d64.c0[0];
   if (v_init) {
-    HIPCHK2(h, launch_slab_axpy(L0.c[0], S, v_init, m * S, nc + 1, S, false, h->stream));
+    HIPCHK2(h, launch_slab_axpy<double>(c0, S, v_init, m * S, nc + 1, S, false, h->stream));
   } else {
-    HIPCHK2(h, launch_fill(L0.c[0], (nc + 1) * S, 0.0, h->stream));
+    HIPCHK2(h, launch_fill(c0, (nc + 1) * S, 0.0, h->stream));
   }
-  HIPCHK2(h, hipMemcpyAsync(L0.c[0], u0, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK2(h, hipMemcpyAsync(c0, u0, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  const StopRule rule{h->opt.rtol, h->opt.diverge_factor, h->opt.max_iter, 0.0};
   std::vector<double> hist;
   double res0 = NAN, rho = NAN, prev = NAN;
-  int it = 0;
+  int it = 0, stop = 0;
+  double *cfin = nullptr;
+  const mgrit_status st = mgrit2d_iterate<double>(h, (const double *)nullptr, rule, &it, &stop, &cfin, &hist, &res0,
+                                                  &rho, &prev);
+  if (st != MGRIT_OK) return st;
   mgrit_status status = MGRIT_OK;
-  for (;;) {
-    for (int s = 0; s < h->opt.nu; ++s) {
-      const mgrit_status st = relax2d(h, 0, MODE_PASS_A, L0.c[cur], L0.c[1 - cur], nullptr, nullptr, nullptr, nullptr);
-      if (st != MGRIT_OK) return st;
-      cur = 1 - cur;
-    }
-    mgrit_status st = relax2d(h, 0, MODE_PASS_B, L0.c[cur], nullptr, nullptr, L0.r, nullptr, nullptr);
-    if (st != MGRIT_OK) return st;
-    HIPCHK2(h, launch_reduce(h->normpart, nc * RESID_BLOCKS, h->normsum, h->stream));
-    HIPCHK2(h, hipMemcpyAsync(h->normsum_host, h->normsum, sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK2(h, hipStreamSynchronize(h->stream));
-    prev = rho;
-    rho = std::sqrt(*h->normsum_host);
-    hist.push_back(rho);
-    if (it == 0) res0 = rho;
-    if (!std::isfinite(rho)) {
-      status = fail2(h, MGRIT_EDIVERGED, "non-finite residual");
-      break;
-    }
-    if (rho <= h->opt.rtol * res0) break;
-    if (it >= h->opt.max_iter) {
-      status = MGRIT_ENOTCONVERGED;
-      h->err = "max_iter reached";
-      break;
-    }
-    if (h->opt.diverge_factor > 0 && rho > h->opt.diverge_factor * res0) {
-      status = fail2(h, MGRIT_EDIVERGED, "residual grew past diverge_factor * res0");
-      break;
-    }
-    st = vcycle2d(h, 1, L0.r, L0.c[cur]);
-    if (st != MGRIT_OK) return st;
-    ++it;
+  if (stop == STOP_NONFINITE) {
+    status = fail2(h, MGRIT_EDIVERGED, "non-finite residual");
+  } else if (stop == STOP_MAX_ITER) {
+    status = MGRIT_ENOTCONVERGED;
+    h->err = "max_iter reached";
+  } else if (stop == STOP_DIVERGED) {
+    status = fail2(h, MGRIT_EDIVERGED, "residual grew past diverge_factor * res0");
   }
   if (status == MGRIT_OK || status == MGRIT_ENOTCONVERGED) {
     if (u_out) {
-      const mgrit_status st = relax2d(h, 0, MODE_FINAL_F, L0.c[cur], nullptr, nullptr, nullptr, nullptr, u_out);
-      if (st != MGRIT_OK) return st;
+      const mgrit_status fs = relax2d<double>(h, 0, MODE_FINAL_F, cfin, nullptr, nullptr, nullptr, nullptr, u_out);
+      if (fs != MGRIT_OK) return fs;
     }
     if (u_final)
-      HIPCHK2(h, hipMemcpyAsync(u_final, L0.c[cur] + nc * S, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+      HIPCHK2(h, hipMemcpyAsync(u_final, cfin + nc * S, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
   }
   HIPCHK2(h, hipStreamSynchronize(h->stream));
-  if (stats) {
-    stats->iterations = it;
-    stats->inner_iterations = 0;
-    stats->res0 = res0;
-    stats->res_final = rho;
-    stats->conv_factor = prev > 0 ? rho / prev : NAN;
-    const int len = (int)hist.size();
-    if (stats->res_history)
-      for (int i = 0; i < std::min(len, stats->res_history_cap); ++i) stats->res_history[i] = hist[i];
-    stats->res_history_len = std::min(len, std::max(stats->res_history_cap, 0));
-    stats->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  }
+  fill_stats(stats, it, 0, res0, rho, prev, hist, t0);
   return status;
 }
 
@@ -2455,7 +2667,8 @@ mgrit_status mgrit2d_sequential(mgrit2d_handle *h, const double *u0, double *u_o
   if (!h || !u0 || !u_out) return MGRIT_EINVAL;
   const int64_t S = slab(h);
   HIPCHK2(h, hipMemcpyAsync(u_out, u0, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
-  for (int64_t n = 1; n <= h->prob.nt; ++n) HIPCHK2(h, apply2d(h, 0, u_out + (n - 1) * S, u_out + n * S, 1, nullptr, 0));
+  for (int64_t n = 1; n <= h->prob.nt; ++n)
+    HIPCHK2(h, apply2d<double>(h, 0, u_out + (n - 1) * S, S, u_out + n * S, S, 1, nullptr, 0));
   HIPCHK2(h, hipStreamSynchronize(h->stream));
   return MGRIT_OK;
 }
@@ -2465,7 +2678,7 @@ mgrit_status mgrit2d_apply_step(mgrit2d_handle *h, int32_t level, const double *
   const int64_t S = slab(h);
   for (int64_t b = 0; b < count; b += h->cap) {
     const int64_t nb = std::min<int64_t>(h->cap, count - b);
-    HIPCHK2(h, apply2d(h, level, v_in + b * S, v_out + b * S, nb, nullptr, 0));
+    HIPCHK2(h, apply2d<double>(h, level, v_in + b * S, S, v_out + b * S, S, nb, nullptr, 0));
   }
   HIPCHK2(h, hipStreamSynchronize(h->stream));
   return MGRIT_OK;

@@ -242,13 +242,15 @@ hipError_t launch_tiles_16(const LevelDesc *desc, const TileGeom &tg, const Tile
 // dimension-split operator on a batch of nb [ny][nx] slabs: dst = Phi(src)
 // (+ g).  The Horner coefficients and the x / y stencil taps (-c_x w,
 // -c_y w, offsets -sl..sr) are passed by value.
-struct Step2dArgs {
-  const double *src;
+template <class T>
+struct Step2dArgsT {
+  const T *src;
   int64_t src_stride;
-  double *dst;
+  T *dst;
   int64_t dst_stride;
-  const double *g;  // NULL: no right-hand side
+  const T *g;  // NULL: no right-hand side
   int64_t g_stride;
+  double g_scale;  // dst = Phi(src) + g_scale g
   int64_t nb;
   int nx, ny;
   int ncoef;
@@ -257,19 +259,28 @@ struct Step2dArgs {
   double tx[MAXTAPS], ty[MAXTAPS];
   int use_reg;  // the register-tile kernel where it has an instance (else LDS tiles)
 };
+using Step2dArgs = Step2dArgsT<double>;
+using Step2dArgs32 = Step2dArgsT<float>;
 size_t step2d_lds_bytes(int ncoef, int sl, int sr);
 hipError_t configure_2d_kernels(size_t bytes);
-hipError_t launch_step2d(const Step2dArgs &a, hipStream_t stream);
+template <class T>
+hipError_t launch_step2d(const Step2dArgsT<T> &a, hipStream_t stream);
 // dst slab b = transpose(src slab b) (+ g slab b), src slabs [rows][cols]
-hipError_t launch_transpose(const double *src, int64_t src_stride, double *dst, int64_t dst_stride, const double *g,
-                            int64_t g_stride, int64_t nb, int rows, int cols, hipStream_t stream);
+template <class T>
+hipError_t launch_transpose(const T *src, int64_t src_stride, T *dst, int64_t dst_stride, const T *g, int64_t g_stride,
+                            int64_t nb, int rows, int cols, hipStream_t stream);
 // dst slab b = (dst slab b +) src slab b, n points per slab
-hipError_t launch_slab_axpy(double *dst, int64_t dst_stride, const double *src, int64_t src_stride, int64_t nb,
-                            int64_t n, bool accumulate, hipStream_t stream);
+template <class T>
+hipError_t launch_slab_axpy(T *dst, int64_t dst_stride, const T *src, int64_t src_stride, int64_t nb, int64_t n,
+                            bool accumulate, hipStream_t stream);
 // r = a - c over nb contiguous slabs of n points (r may be NULL); part gets
-// blocks_per_slab partial sums of squares per slab
-hipError_t launch_slab_resid(const double *a, const double *c, double *r, int64_t nb, int64_t n, int blocks_per_slab,
-                             double *part, hipStream_t stream);
+// blocks_per_slab partial sums of squares per slab (float64)
+template <class T>
+hipError_t launch_slab_resid(const T *a, const T *c, T *r, int64_t nb, int64_t n, int blocks_per_slab, double *part,
+                             hipStream_t stream);
+// partial sums of squares of nb contiguous float64 slabs (as launch_slab_resid with c = 0)
+hipError_t launch_slab_norm(const double *a, int64_t nb, int64_t n, int blocks_per_slab, double *part,
+                            hipStream_t stream);
 
 // Launch the step kernel for one pass (mgrit_kernels.hip).  lds_bytes is
 // computed by the launcher.  Returns the HIP error of the launch.

@@ -351,7 +351,7 @@ class Solver2D:
         self._check(st, allow)
         return dict(status=st, iterations=stats.iterations, res0=stats.res0, res_final=stats.res_final,
                     conv_factor=stats.conv_factor, res_history=list(hist[:stats.res_history_len]),
-                    t_solve_s=stats.t_solve_s)
+                    t_solve_s=stats.t_solve_s, inner_iterations=stats.inner_iterations)
 
     def sequential(self, u0, u_out):
         sl = (self.ny, self.nx)

@@ -147,8 +147,11 @@ def test_2d_setup_validation():
     assert st == mgrit.EUNSTABLE
     st, _ = _setup2d_status(mgrit.make_problem_2d(64, 64, 16, 0.5, 2), mgrit.make_options([4]))
     assert st == mgrit.EINVAL
-    st, _ = _setup2d_status(mgrit.make_problem_2d(64, 64, 16, 0.5, 3), mgrit.make_options([4], precision="mixed"))
+    st, _ = _setup2d_status(mgrit.make_problem_2d(64, 64, 16, 0.5, 3), mgrit.make_options([4], coarse="sl_plain"))
     assert st == mgrit.EINVAL
+    st, msg = _setup2d_status(mgrit.make_problem_2d(64, 64, 16, 0.5, 3),
+                              mgrit.make_options([4], precision="mixed", inner_rtol=0.0))
+    assert st == mgrit.EINVAL and "inner" in msg
 
 
 def test_2d_stability_limit_matches_the_oracle_symbol():

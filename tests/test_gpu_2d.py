@@ -111,3 +111,28 @@ def test_sequential_matches_oracle():
     cx, cy = _cxy(pr)
     ref = omg.sequential(a2.MOLStep2D(p, p, cx, cy), u0, nt)
     assert np.max(np.abs(_np(out) - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("case", [dict(nx=64, ny=48, nt=64, p=3, ms=[4, 4]), dict(nx=40, ny=40, nt=32, p=5, ms=[4]),
+                                  dict(nx=96, ny=64, nt=96, p=1, ms=[4, 2, 2])])
+def test_mixed_precision_2d_matches_the_float64_oracle(case):
+    """Float32 2D MGRIT on the correction equation inside float64
+    refinement: within 1e-10 of the oracle's sequential stepping."""
+    _announce("2d mixed", case)
+    nx, ny, nt, p, ms = case["nx"], case["ny"], case["nt"], case["p"], case["ms"]
+    pr = mgrit.make_problem_2d(nx, ny, nt, 0.5 if p != 5 else 0.4, p)
+    cx, cy = _cxy(pr)
+    u0 = inputs.u0_bumps_2d(nx, ny, 8, 0.1, 1004)
+    s = mgrit.Solver2D(pr, mgrit.make_options(ms, max_levels=len(ms) + 1, rtol=1e-12, precision="mixed",
+                                              diverge_factor=0.0))
+    out = torch.empty((nt + 1, ny, nx), dtype=torch.float64, device=DEV)
+    fin = torch.empty((ny, nx), dtype=torch.float64, device=DEV)
+    info = s.solve(_t(u0), u_out=out, u_final=fin)
+    assert info["status"] == mgrit.OK
+    assert 1 <= info["iterations"] <= 6 and info["inner_iterations"] >= info["iterations"]
+    ref = omg.sequential(a2.MOLStep2D(p, p, cx, cy), u0, nt)
+    got = _np(out)
+    assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
+    per_t = np.linalg.norm((got - ref).reshape(nt + 1, -1), axis=1) / np.linalg.norm(ref.reshape(nt + 1, -1), axis=1)
+    assert np.max(per_t) <= 1e-10, np.max(per_t)
+    np.testing.assert_array_equal(_np(fin), got[-1])
