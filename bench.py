@@ -338,8 +338,11 @@ def twod_bench(steps):
     """Config 4: u_t + a.grad u = 0 on [-1, 1)^2, a = (0.85, 1.0),
     nx = ny = nt = 1024, dt = h/2 (c = (0.425, 0.5)), ERK3 + U3, m = 8,
     3 levels (1024 -> 128 -> 16), u0 = 8 seeded Gaussian bumps of width
-    0.1, seeded U[0,1) initial iterate, relative C-point residual 1e-10;
-    against sequential time-stepping of the same fine step on the GPU."""
+    0.1, seeded U[0,1) initial iterate; float64 MGRIT to a C-point residual
+    of 1e-10 of its first one, and mixed precision (float32 inner cycles,
+    float64 refinement) to a full space-time residual of 1e-12 of its first
+    one (it also carries the random F-points); both against sequential
+    time-stepping of the same fine step on the GPU."""
     import torch
     from paper_2209_06916_amd import inputs, mgrit
     dev = torch.device("cuda:0")
@@ -353,17 +356,25 @@ def twod_bench(steps):
     u0_d = torch.from_numpy(u0).to(dev)
     v0[0] = u0_d
     pr = mgrit.make_problem_2d(n, n, nt, 0.5, 3)
-    s = mgrit.Solver2D(pr, mgrit.make_options(ms, max_levels=3, rtol=1e-10, max_iter=30))
     out = torch.empty((nt + 1, n, n), dtype=torch.float64, device=dev)
-    info = s.solve(u0_d, v0, u_out=out)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(steps):
+    res = {}
+    for prec in ("fp64", "mixed"):
+        s = mgrit.Solver2D(pr, mgrit.make_options(ms, max_levels=3, rtol=1e-10 if prec == "fp64" else 1e-12,
+                                                  max_iter=30, precision=prec))
         info = s.solve(u0_d, v0, u_out=out)
-    torch.cuda.synchronize()
-    wall = (time.perf_counter() - t) / steps
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            info = s.solve(u0_d, v0, u_out=out)
+        torch.cuda.synchronize()
+        res[prec] = ((time.perf_counter() - t) / steps, info, out.clone() if prec == "fp64" else None)
+        if prec == "mixed":
+            res[prec] = (res[prec][0], info, None)
+            err_mixed_out = out
+        s.close()
     del v0
     ref = torch.empty_like(out)
+    s = mgrit.Solver2D(pr, mgrit.make_options(ms, max_levels=3))
     s.sequential(u0_d, ref)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -371,13 +382,19 @@ def twod_bench(steps):
         s.sequential(u0_d, ref)
     torch.cuda.synchronize()
     seq = (time.perf_counter() - t) / steps
-    err = (torch.linalg.vector_norm(out - ref) / torch.linalg.vector_norm(ref)).item()
+    rn = torch.linalg.vector_norm(ref)
+    err64 = (torch.linalg.vector_norm(res["fp64"][2] - ref) / rn).item()
+    err32 = (torch.linalg.vector_norm(err_mixed_out - ref) / rn).item()
     dof = n * n * nt
+    w64, i64, _ = res["fp64"]
+    w32, i32, _ = res["mixed"]
     print(json.dumps({"workload": "advection2d-1024x1024x1024-erk3u3-vcycle-m8", "dof": dof, "steps": steps,
-                      "mgrit_ms": 1e3 * wall, "mgrit_dof_per_s": dof / wall, "iterations": info["iterations"],
-                      "res_history": info["res_history"], "sequential_ms": 1e3 * seq,
-                      "sequential_dof_per_s": dof / seq, "mgrit_vs_sequential": seq / wall,
-                      "rel_l2_error_vs_sequential": err}), flush=True)
+                      "mgrit_ms": 1e3 * w64, "mgrit_dof_per_s": dof / w64, "iterations": i64["iterations"],
+                      "rel_l2_error_vs_sequential": err64,
+                      "mixed_ms": 1e3 * w32, "mixed_dof_per_s": dof / w32, "mixed_outer_iterations": i32["iterations"],
+                      "mixed_inner_iterations": i32["inner_iterations"], "mixed_rel_l2_error_vs_sequential": err32,
+                      "sequential_ms": 1e3 * seq, "sequential_dof_per_s": dof / seq,
+                      "mgrit_vs_sequential": seq / w64, "mixed_vs_fp64": w64 / w32}), flush=True)
 
 
 def main():
