@@ -246,6 +246,15 @@ def serve_bench(n, seed):
     t_loop = time.perf_counter() - t
     by1 = {r.tag: r for r in one}
     same = all(np.array_equal(by1[r.tag].u_final, r.u_final) for r in many)
+    # the same stream served in mixed precision (zero initial iterate, so the
+    # float64 and the full space-time residual start from the same norm)
+    mixed_reqs = serve.synthetic_stream(n, seed=seed, rate_hz=0, precision="mixed")
+    serve.ThreadedServer(max_inflight=16).run(mixed_reqs[:16], realtime=False)
+    t = time.perf_counter()
+    mixed = serve.ThreadedServer(max_inflight=16).run(mixed_reqs, realtime=False)
+    t_mixed = time.perf_counter() - t
+    mixed_err = max(float(np.linalg.norm(r.u_final - by1[r.tag].u_final) / np.linalg.norm(by1[r.tag].u_final))
+                    for r in mixed)
     rate = 0.8 * n / t_one
     arrivals = serve.synthetic_stream(n, seed=seed, rate_hz=rate)
     t = time.perf_counter()
@@ -266,6 +275,9 @@ def serve_bench(n, seed):
         "dof_per_s_one_in_flight": dof / t_one,
         "dof_per_s_16_in_flight": dof / t_many,
         "dof_per_s_16_in_flight_polling_loop": dof / t_loop,
+        "mixed_dof_per_s_16_in_flight": dof / t_mixed,
+        "mixed_all_converged": all(r.status == 0 for r in mixed),
+        "mixed_max_rel_diff_vs_fp64": mixed_err,
         "concurrency_speedup": t_one / t_many,
         "same_results_alone_and_in_mix": bool(same),
         "all_converged": all(r.status == 0 for r in many),

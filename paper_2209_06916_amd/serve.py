@@ -40,13 +40,18 @@ class Request:
     max_levels: int = 16
     arrival: float = 0.0  # seconds after the start of the run
     tag: object = None
+    precision: str = "fp64"  # "mixed": float32 inner cycles in float64 refinement (ThreadedServer only)
+    rtol: float = None  # default: 1e-10 of the float64 C-point residual; 1e-12 of the mixed-precision
+    #                     full space-time residual, which gives the same solution error
 
     def problem(self):
         return mgrit.make_problem(self.nx, self.nt, self.c, self.p, self.kind, self.q)
 
     def options(self):
         return mgrit.make_options([self.m], max_levels=self.max_levels, min_coarse_nt=self.min_coarse_nt,
-                                  coarse_launch=1)
+                                  coarse_launch=1, precision=self.precision,
+                                  rtol=self.rtol if self.rtol is not None else (1e-12 if self.precision == "mixed"
+                                                                                else 1e-10))
 
 
 @dataclass
@@ -183,7 +188,7 @@ _ANY_STATUS = (mgrit.OK, mgrit.ENOTCONVERGED, mgrit.EINVAL, mgrit.EUNSTABLE, mgr
 
 
 def synthetic_stream(n, seed, rate_hz, sizes=(256, 512, 1024, 2048, 4096, 8192), orders=(1, 3, 5), ms=(4, 8, 16),
-                     cfl=(0.5, 0.9)):
+                     cfl=(0.5, 0.9), precision="fp64"):
     """Seeded request mix: nx, nt drawn from `sizes`, upwind order p from
     `orders` with ERKp, CFL uniform in `cfl`, coarsening factor from `ms`,
     u0 a seeded 16-mode Fourier sum, Poisson arrivals at `rate_hz`."""
@@ -201,7 +206,7 @@ def synthetic_stream(n, seed, rate_hz, sizes=(256, 512, 1024, 2048, 4096, 8192),
             m //= 2
         t += rng.exponential(1.0 / rate_hz) if rate_hz > 0 else 0.0
         reqs.append(Request(nx=nx, nt=nt, p=p, c=c, m=m, u0=inputs.u0_fourier(nx, seed * 100003 + i), arrival=t,
-                            tag=i))
+                            tag=i, precision=precision))
     return reqs
 
 

@@ -142,3 +142,16 @@ def test_threaded_server_gives_the_same_results_and_respects_the_budget():
     bad = serve.Request(nx=512, nt=256, p=1, c=1.2, m=4, u0=inputs.u0_fourier(512, 9), tag="unstable")
     got = _by_tag(serve.ThreadedServer(max_inflight=4).run(small + [bad], realtime=False))
     assert got["unstable"].status == mgrit.EUNSTABLE and got["unstable"].u_final is None
+
+
+def test_threaded_server_serves_mixed_precision_requests():
+    """Mixed-precision requests (float32 inner cycles in float64 refinement)
+    reach the float64 oracle's sequential solution to 1e-10."""
+    _announce("serving mixed")
+    reqs = serve.synthetic_stream(6, seed=8, rate_hz=0, sizes=(256, 512, 1024), orders=(1, 3, 5), ms=(4, 8),
+                                  precision="mixed")
+    got = _by_tag(serve.ThreadedServer(max_inflight=6).run(reqs, realtime=False))
+    for r in reqs:
+        assert got[r.tag].status == mgrit.OK, r.tag
+        ref = omg.sequential(disc.MOLStep(r.p, "erk", r.p, r.c), r.u0, r.nt)[-1]
+        assert np.linalg.norm(got[r.tag].u_final - ref) <= 1e-10 * np.linalg.norm(ref), r.tag
