@@ -11,11 +11,6 @@ namespace {
 
 constexpr int TX = 64, TY = 16;  // output tile of one workgroup (256 threads)
 
-__device__ __forceinline__ int wrap(int i, int n) {
-  i %= n;
-  return i < 0 ? i + n : i;
-}
-
 // One explicit Runge-Kutta step Phi = R(Z), Z = -(c_x L_p^(x) + c_y L_p^(y)),
 // as the Horner form y <- coef[i] u + Z y, on one TX x TY output tile of one
 // slab.  The tile and a halo of s*l (left/below) and s*r (right/above)
