@@ -100,6 +100,10 @@ typedef struct {
                             C-point residual falls by this factor (> 0)      */
   int32_t inner_max_iter; /* MGRIT_PREC_MIXED: cap on each inner solve's
                             iterations (>= 1)                                 */
+  int32_t tile_tune;     /* explicit schemes, level 0: 0 = tile width from the
+                            launch-cost model; 1 = time the candidate widths
+                            on the device at setup and keep the fastest
+                            (cached per process by nx, m, scheme and N_c)    */
 } mgrit_options;
 
 /* Arithmetic of mgrit_solve.
@@ -136,6 +140,8 @@ typedef struct {
   double eps;           /* shift - K, in [0,1)  (Sec. 3)                     */
   double phi_p;         /* coefficient of D^(p+1) in Psi_l                    */
   double phi_q;         /* coefficient of D^(q+1) (q != p only)               */
+  int32_t tile_p;       /* level 0, explicit schemes: points per lane of the
+                           relaxation tiles (0: no tiles)                      */
 } mgrit_level_desc;
 
 /* Phases timed by the optional profiler (mgrit_profile_enable). */

@@ -1015,6 +1015,64 @@ mgrit_status mgrit_setup_ws(const mgrit_problem *P, const mgrit_options *O, void
 
 namespace {
 
+// Tile-width autotuner of the level-0 explicit relaxation: time pass A with
+// every candidate width on the handle's own buffers (zeroed C-points, three
+// launches after one warm-up) and keep the fastest.  The choice is cached per
+// process by (nx, m, Horner depth, stencil extents, N_c), the things the
+// launch shape depends on; every width gives the same bits, so the choice
+// changes only the time.
+std::mutex g_tune_mu;
+std::map<std::vector<int64_t>, int> g_tune_cache;
+
+hipError_t tune_tiles(mgrit_handle *h, int depth, int sl, int sr) {
+  Level &L0 = h->lv[0];
+  const int nx = (int)h->prob.nx;
+  const int64_t nc = L0.nt / L0.m;
+  const std::vector<int64_t> key{nx, L0.m, depth, sl, sr, nc};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      choose_tiles(nx, L0.m, depth, sl, sr, it->second, L0.tg);
+      return hipSuccess;
+    }
+  }
+  hipError_t e = launch_fill(L0.c[0], (nc + 1) * (int64_t)nx, 0.0, h->stream);
+  if (e) return e;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if ((e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1))) return e;
+  int best_p = L0.tg.P;
+  float best_ms = -1;
+  for (int cand : {8, 16}) {
+    TileGeom tg{};
+    if (!choose_tiles(nx, L0.m, depth, sl, sr, cand, tg)) continue;
+    TileArgs ta{};
+    ta.mode = MODE_PASS_A;
+    ta.m = L0.m;
+    ta.nint = nc;
+    ta.cin = L0.c[0];
+    ta.cout = L0.c[1];
+    ta.normpart = h->normpart;
+    if ((e = launch_tiles(L0.desc, tg, ta, h->stream))) break;
+    if ((e = hipEventRecord(e0, h->stream))) break;
+    for (int r = 0; r < 3 && !e; ++r) e = launch_tiles(L0.desc, tg, ta, h->stream);
+    if (e || (e = hipEventRecord(e1, h->stream)) || (e = hipEventSynchronize(e1))) break;
+    float ms = 0;
+    if ((e = hipEventElapsedTime(&ms, e0, e1))) break;
+    if (best_ms < 0 || ms < best_ms) {
+      best_ms = ms;
+      best_p = cand;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e) return e;
+  choose_tiles(nx, L0.m, depth, sl, sr, best_p, L0.tg);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = best_p;
+  return hipSuccess;
+}
+
 mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *stream, void *ws, uint64_t ws_bytes,
                         mgrit_handle **out) {
   g_setup_error.clear();
@@ -1036,6 +1094,7 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
   if (!(O->rtol >= 0)) return bad(MGRIT_EINVAL, "rtol must be >= 0");
   if (O->cg_kind < 0 || O->cg_kind > 3) return bad(MGRIT_EINVAL, "unknown coarse operator");
   if (O->coarse_launch < 0 || O->coarse_launch > 1) return bad(MGRIT_EINVAL, "coarse_launch must be 0 or 1");
+  if (O->tile_tune < 0 || O->tile_tune > 1) return bad(MGRIT_EINVAL, "tile_tune must be 0 or 1");
   if (O->precision != MGRIT_PREC_FP64 && O->precision != MGRIT_PREC_MIXED) return bad(MGRIT_EINVAL, "unknown precision");
   if (O->precision == MGRIT_PREC_MIXED && !(O->inner_rtol > 0 && O->inner_rtol < 1))
     return bad(MGRIT_EINVAL, "mixed precision needs 0 < inner_rtol < 1");
@@ -1217,7 +1276,15 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
     o_u64 = off, off += al((pts + nx) * sizeof(double));
   }
   h->normpart_len = std::max<int64_t>(P->nt, 1);
-  if (h->lv[0].tiles) h->normpart_len = std::max<int64_t>(h->normpart_len, (P->nt / ms[0]) * h->lv[0].tg.ntiles);
+  if (h->lv[0].tiles) {
+    h->normpart_len = std::max<int64_t>(h->normpart_len, (P->nt / ms[0]) * h->lv[0].tg.ntiles);
+    if (O->tile_tune)  // room for every candidate width
+      for (int cand : {8, 16}) {
+        TileGeom tg{};
+        if (choose_tiles(nx, ms[0], fi.tab.s, fi.l, fi.r, cand, tg))
+          h->normpart_len = std::max<int64_t>(h->normpart_len, (P->nt / ms[0]) * tg.ntiles);
+      }
+  }
   const size_t o_np = off;
   off += al(h->normpart_len * sizeof(double));
   const size_t o_ns = off;
@@ -1310,6 +1377,13 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
   h->normsum_host = (double *)h->host_arena;
   h->ctl_host = (SolveCtl *)(h->host_arena + 128);
   h->ctl_host_dev = (SolveCtl *)(slot_dev + 128);
+  if (O->tile_tune && h->lv[0].tiles && nlev >= 2) {
+    const hipError_t e = tune_tiles(h, fi.tab.s, fi.l, fi.r);
+    if (e != hipSuccess) {
+      mgrit_destroy(h);
+      return bad(MGRIT_EDEVICE, std::string("tile tuning: ") + hipGetErrorString(e));
+    }
+  }
   *out = h;
   return MGRIT_OK;
 }
@@ -1330,6 +1404,7 @@ mgrit_status mgrit_level_info(const mgrit_handle *h, int32_t level, mgrit_level_
   out->eps = L.eps;
   out->phi_p = L.phi_p;
   out->phi_q = L.phi_q;
+  out->tile_p = (level == 0 && L.tiles) ? L.tg.P : 0;
   return MGRIT_OK;
 }
 

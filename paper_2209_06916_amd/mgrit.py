@@ -39,7 +39,7 @@ class Options(ctypes.Structure):
                 ("min_coarse_nt", ctypes.c_int32), ("nu", ctypes.c_int32), ("cg_kind", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("diverge_factor", ctypes.c_double),
                 ("coarse_launch", ctypes.c_int32), ("precision", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
-                ("inner_max_iter", ctypes.c_int32)]
+                ("inner_max_iter", ctypes.c_int32), ("tile_tune", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -59,7 +59,7 @@ class Problem2D(ctypes.Structure):
 class LevelDesc(ctypes.Structure):
     _fields_ = [("nt", ctypes.c_int64), ("m", ctypes.c_int32), ("shift", ctypes.c_double),
                 ("K", ctypes.c_int64), ("eps", ctypes.c_double), ("phi_p", ctypes.c_double),
-                ("phi_q", ctypes.c_double)]
+                ("phi_q", ctypes.c_double), ("tile_p", ctypes.c_int32)]
 
 
 PROF_PHASES = ["fine_relax", "coarse", "final", "sequential", "residual", "other"]
@@ -140,7 +140,8 @@ def make_problem(nx, nt, cfl, p, kind="erk", q=None, velocity=1.0, x_lo=-1.0, x_
 
 
 def make_options(m, max_levels=2, min_coarse_nt=0, nu=1, coarse="sl_corrected", rtol=1e-10, max_iter=30,
-                 diverge_factor=1e8, coarse_launch=0, precision="fp64", inner_rtol=1e-5, inner_max_iter=30):
+                 diverge_factor=1e8, coarse_launch=0, precision="fp64", inner_rtol=1e-5, inner_max_iter=30,
+                 tile_tune=0):
     o = Options()
     o.max_levels = max_levels
     ms = list(m) if isinstance(m, (list, tuple)) else [m]
@@ -156,6 +157,7 @@ def make_options(m, max_levels=2, min_coarse_nt=0, nu=1, coarse="sl_corrected", 
     o.precision = {"fp64": PREC_FP64, "mixed": PREC_MIXED}[precision]
     o.inner_rtol = inner_rtol
     o.inner_max_iter = inner_max_iter
+    o.tile_tune = tile_tune
     return o
 
 
@@ -235,7 +237,7 @@ class Solver:
     def level_info(self, level):
         d = LevelDesc()
         self._check(lib().mgrit_level_info(self.h, level, ctypes.byref(d)))
-        return dict(nt=d.nt, m=d.m, shift=d.shift, K=d.K, eps=d.eps, phi_p=d.phi_p, phi_q=d.phi_q)
+        return dict(nt=d.nt, m=d.m, shift=d.shift, K=d.K, eps=d.eps, phi_p=d.phi_p, phi_q=d.phi_q, tile_p=d.tile_p)
 
     def solve(self, u0, v_init=None, u_out=None, u_final=None, history_cap=128,
               allow=(OK, ENOTCONVERGED)):

@@ -49,7 +49,7 @@ class Request:
 
     def options(self):
         return mgrit.make_options([self.m], max_levels=self.max_levels, min_coarse_nt=self.min_coarse_nt,
-                                  coarse_launch=1, precision=self.precision,
+                                  coarse_launch=1, tile_tune=1, precision=self.precision,
                                   rtol=self.rtol if self.rtol is not None else (1e-12 if self.precision == "mixed"
                                                                                 else 1e-10))
 

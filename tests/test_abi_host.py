@@ -46,6 +46,7 @@ def _setup_status(problem, options):
     (dict(nx=64, nt=32, cfl=0.5, p=1), dict(m=1), mgrit.EINVAL),          # m must be >= 2
     (dict(nx=64, nt=32, cfl=0.5, p=1), dict(m=4, max_levels=3, coarse="ideal"), mgrit.EINVAL),
     (dict(nx=64, nt=32, cfl=0.5, p=3), dict(m=4, coarse="redisc"), mgrit.EUNSTABLE),  # ERK3+U3 at 4 c > c_max
+    (dict(nx=64, nt=32, cfl=0.5, p=1), dict(m=4, tile_tune=2), mgrit.EINVAL),
 ])
 def test_setup_rejects_invalid_problems(kw, opt, expected):
     st, msg = _setup_status(mgrit.make_problem(**kw), mgrit.make_options(**opt))

@@ -440,3 +440,21 @@ def test_tiled_and_slab_relaxation_agree(monkeypatch):
         outs.append((info["iterations"], _np(o)))
     assert outs[0][0] == outs[1][0]
     np.testing.assert_allclose(outs[0][1], outs[1][1], rtol=0, atol=1e-14 * np.max(np.abs(outs[1][1])))
+
+
+@pytest.mark.parametrize("nx,nt,p,m", [(4096, 4096, 3, 8), (1024, 512, 5, 4), (2048, 256, 1, 16)])
+def test_tuned_tiles_give_the_same_solve(nx, nt, p, m):
+    """tile_tune = 1 times the candidate tile widths at setup and keeps the
+    fastest; every width gives the same bits."""
+    _announce("tile tune", nx, nt, p, m)
+    u0 = _t(inputs.u0_fourier(nx, 3))
+    outs = []
+    for tune in (0, 1):
+        s = mgrit.Solver(mgrit.make_problem(nx, nt, 0.8, p),
+                         mgrit.make_options([m], max_levels=16, min_coarse_nt=8, tile_tune=tune))
+        assert s.level_info(0)["tile_p"] in (8, 16)
+        fin = torch.empty(nx, dtype=torch.float64, device=DEV)
+        info = s.solve(u0, u_final=fin)
+        outs.append((info["iterations"], _np(fin)))
+    assert outs[0][0] == outs[1][0]
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
