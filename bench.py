@@ -160,9 +160,10 @@ def summarize_profiles(d):
         rows = list(csv.DictReader(open(serve_csv)))
         tot = sum(float(r["TotalDurationNs"]) for r in rows)
         lines = [f"# rocprofv3 kernel statistics -- workload {SERVE_WORKLOAD}",
-                 "# (bench.py --serve 512: 8 warm-up requests, then the 512-request stream served with 1 and with 16",
-                 "# solves in flight, then with Poisson arrivals; the profiler slows the host loop, so the rates it",
-                 "# prints are lower than without it)",
+                 "# (bench.py --serve 512 as it was before the threaded loop, the tile tuner and the mixed-precision",
+                 "# stream were added: 8 warm-up requests, then the 512-request stream served with 1 and with 16",
+                 "# solves in flight by the polling loop, then with Poisson arrivals; the profiler slows the host loop,",
+                 "# so the rates it prints are lower than without it)",
                  "# command (repository root on the GPU box, after cd /tmp && export TMPDIR=/tmp):",
                  "#   " + PROFILE_COMMANDS["serve"].replace("<dir>", "gpurun_out/prof"),
                  f"# total kernel time {tot / 1e6:.1f} ms over {sum(int(r['Calls']) for r in rows)} launches",

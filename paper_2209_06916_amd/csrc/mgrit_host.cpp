@@ -1015,6 +1015,24 @@ mgrit_status mgrit_setup_ws(const mgrit_problem *P, const mgrit_options *O, void
 
 namespace {
 
+// The kernels' LDS attribute is process-wide and always raised to LDS_LIMIT:
+// set it once per device, before the first handle on that device launches
+// anything, and never again while other threads may be launching.
+std::mutex g_config_mu;
+std::vector<int> g_configured;  // devices done
+
+hipError_t configure_once() {
+  int dev = 0;
+  if (hipError_t e = hipGetDevice(&dev)) return e;
+  std::lock_guard<std::mutex> lk(g_config_mu);
+  for (int d : g_configured)
+    if (d == dev) return hipSuccess;
+  if (hipError_t e = configure_kernels(LDS_LIMIT)) return e;
+  if (hipError_t e = configure_2d_kernels(LDS_LIMIT)) return e;
+  g_configured.push_back(dev);
+  return hipSuccess;
+}
+
 // Tile-width autotuner of the level-0 explicit relaxation: time pass A with
 // every candidate width on the handle's own buffers (zeroed C-points, three
 // launches after one warm-up) and keep the fastest.  The choice is cached per
@@ -1209,7 +1227,7 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
 
   // Every layout chosen above needs at most LDS_LIMIT bytes; the attribute is
   // per kernel and process-wide, so it is always raised to that limit.
-  if (hipError_t e = configure_kernels(LDS_LIMIT)) {
+  if (hipError_t e = configure_once()) {
     mgrit_destroy(h);
     return bad(MGRIT_EDEVICE, std::string("configure: ") + hipGetErrorString(e));
   }
@@ -2559,7 +2577,7 @@ mgrit_status mgrit2d_setup(const mgrit2d_problem *P, const mgrit_options *O, voi
     mgrit2d_destroy(h);
     return bad(MGRIT_EINVAL, "2D fine step: halo too wide for LDS");
   }
-  if (configure_kernels(LDS_LIMIT) != hipSuccess || configure_2d_kernels(LDS_LIMIT) != hipSuccess) {
+  if (configure_once() != hipSuccess) {
     mgrit2d_destroy(h);
     return bad(MGRIT_EDEVICE, "configure");
   }

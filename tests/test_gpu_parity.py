@@ -458,3 +458,19 @@ def test_tuned_tiles_give_the_same_solve(nx, nt, p, m):
         outs.append((info["iterations"], _np(fin)))
     assert outs[0][0] == outs[1][0]
     np.testing.assert_array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("nu", [0, 2])
+def test_relaxation_variants_match_oracle(nu):
+    """F-relaxation (nu = 0, the paper's Fig. 6 variant) and FCFCF (nu = 2)
+    against the oracle on config 1, with config 1's LFA ordering: F converges
+    more slowly than FCF."""
+    _announce("relaxation variant", nu)
+    s, info, got, fin, ref, rinfo = _solve_both(256, 256, 1, "erk", 1, 0.85, [4], nu=nu, max_iter=60)
+    _check_parity(info, got, fin, ref, rinfo, 4)
+    s1, info1, *_ = _solve_both(256, 256, 1, "erk", 1, 0.85, [4], nu=1)
+    if nu == 0:
+        assert info["conv_factor"] > info1["conv_factor"]
+        assert info["iterations"] > info1["iterations"]
+    else:
+        assert info["iterations"] <= info1["iterations"]
