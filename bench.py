@@ -410,6 +410,49 @@ def twod_bench(steps):
                       "mgrit_vs_sequential": seq / w64, "mixed_vs_fp64": w64 / w32}), flush=True)
 
 
+def long_bench(steps):
+    """Long time horizons (nt >> nx), where time-parallelism pays off on one
+    GPU: ERK3 + U3 at c = 0.85, m = 8, V-cycles down to <= 8 coarse steps,
+    seeded 16-mode Fourier u0 and the seeded U[0,1) initial iterate, 1e-10
+    relative C-point residual; against sequential time-stepping (temporal
+    blocking) of the same problem on the GPU."""
+    import torch
+    from paper_2209_06916_amd import inputs, mgrit
+    dev = torch.device("cuda:0")
+    for nx, nt in [(4096, 16384), (1024, 65536), (256, 131072)]:
+        seed = 1002
+        u0 = inputs.u0_fourier(nx, seed)
+        u0_d = torch.from_numpy(u0).to(dev)
+        v0 = torch.from_numpy(inputs.initial_iterate(nt, nx, u0, seed)).to(dev)
+        s = mgrit.Solver(mgrit.make_problem(nx, nt, 0.85, 3),
+                         mgrit.make_options([8], max_levels=16, min_coarse_nt=8, rtol=1e-10, max_iter=30))
+        out = torch.empty((nt + 1, nx), dtype=torch.float64, device=dev)
+        ref = torch.empty_like(out)
+        info = s.solve(u0_d, v0, u_out=out)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            info = s.solve(u0_d, v0, u_out=out)
+        torch.cuda.synchronize()
+        tm = (time.perf_counter() - t) / steps
+        s.sequential(u0_d, ref)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            s.sequential(u0_d, ref)
+        torch.cuda.synchronize()
+        ts = (time.perf_counter() - t) / steps
+        err = (torch.linalg.vector_norm(out - ref) / torch.linalg.vector_norm(ref)).item()
+        print(json.dumps({"workload": f"advection1d-{nx}x{nt}-erk3u3-vcycle-m8", "dof": nx * nt,
+                          "levels": s.num_levels, "iterations": info["iterations"], "mgrit_ms": 1e3 * tm,
+                          "mgrit_dof_per_s": nx * nt / tm, "sequential_ms": 1e3 * ts,
+                          "sequential_dof_per_s": nx * nt / ts, "speedup_vs_sequential": ts / tm,
+                          "rel_l2_error_vs_sequential": err}), flush=True)
+        s.close()
+        del out, ref, v0
+        torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -421,6 +464,8 @@ def main():
                          "COPY_BYTES read + COPY_BYTES written (the counter calibration)")
     ap.add_argument("--serve", type=int, metavar="N", default=0,
                     help="the request-loop benchmark (N independent solves) instead of the single-solve one")
+    ap.add_argument("--long", action="store_true",
+                    help="long time horizons (nt >> nx) against sequential stepping instead of the single-solve bench")
     ap.add_argument("--twod", action="store_true",
                     help="the 2D extension (config 4) against 2D sequential stepping instead of the single-solve bench")
     ap.add_argument("--precision", action="store_true",
@@ -446,6 +491,9 @@ def main():
         return
     if args.twod:
         twod_bench(max(1, min(args.steps, 5)))
+        return
+    if args.long:
+        long_bench(max(1, min(args.steps, 5)))
         return
 
     dev = torch.device("cuda:0")
