@@ -1244,7 +1244,12 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
       grid = std::max<int64_t>(grid, h->lv[l].nt / h->lv[l].m);
       longest = std::max<int64_t>(longest, h->lv[l].m);
     }
-    if (lds > 0 && longest <= 256 && grid <= MAX_PERSISTENT_GRID &&
+    // A grid barrier costs about 35 ns per workgroup (every workgroup's
+    // device-scope release; measured 3 us at 64 workgroups, 9.5 us at 256,
+    // 36 us at 1024), a kernel boundary about 5 us: past 128 workgroups one
+    // launch per pass is faster.
+    const int64_t fast_grid = std::min<int64_t>(MAX_PERSISTENT_GRID, env_int("MGRIT_PERSISTENT_MAX_GRID", 128));
+    if (lds > 0 && longest <= 256 && grid <= fast_grid &&
         grid <= coarse_vcycle_max_grid(h->lv[1].op, h->lv[1].lay, lds)) {
       h->cv_ok = true;
       h->cv_lds = lds;

@@ -474,3 +474,22 @@ def test_relaxation_variants_match_oracle(nu):
         assert info["iterations"] > info1["iterations"]
     else:
         assert info["iterations"] <= info1["iterations"]
+
+
+def test_persistent_cycle_on_a_large_grid_agrees(monkeypatch):
+    """The persistent coarse cycle is used up to 128 workgroups by default;
+    raised to 1024 it runs 512 workgroups here and gives the per-pass bits."""
+    _announce("persistent large grid")
+    nx, nt, ms = 256, 32768, [8, 8, 8]
+    u0 = inputs.u0_fourier(nx, 43)
+    v0 = _t(inputs.initial_iterate(nt, nx, u0, 43))
+    outs = []
+    for flag in ("0", "1"):
+        monkeypatch.setenv("MGRIT_NO_PERSISTENT", flag)
+        monkeypatch.setenv("MGRIT_PERSISTENT_MAX_GRID", "1024")
+        s = mgrit.Solver(mgrit.make_problem(nx, nt, 0.85, 3), mgrit.make_options(ms, max_levels=4))
+        fin = torch.empty(nx, dtype=torch.float64, device=DEV)
+        info = s.solve(_t(u0), v0, u_final=fin)
+        outs.append((info["iterations"], info["res_history"], _np(fin)))
+    assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
+    np.testing.assert_array_equal(outs[0][2], outs[1][2])
