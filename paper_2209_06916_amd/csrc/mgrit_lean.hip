@@ -478,16 +478,22 @@ __device__ __forceinline__ bool wait_expired(unsigned long long t0, const GridSy
 
 // Grid barrier: every workgroup publishes its arrival in its own word, the
 // first wavefront of workgroup 0 polls all of them and releases the new
-// generation, everyone waits for that release.  Every thread's global writes
-// are released at device scope before its workgroup arrives (the workgroup
-// barrier alone does not wait for them), and acquired after the release.
+// generation, everyone waits for that release.  Every wavefront first waits
+// until its own global stores have completed (reached the L2 of its XCD;
+// the workgroup barrier alone only waits for LDS), then after the workgroup
+// barrier thread 0's device-scope release writes that L2 back before the
+// arrival word: one device-scope release (a cache write-back) per workgroup
+// instead of one per wavefront.  Acquired after the release.
 __device__ __forceinline__ bool grid_barrier(GridSync *gs, unsigned &gen, int *ok_lds) {
-  __threadfence();
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0) (expcnt, lgkmcnt unconstrained)
   __syncthreads();
   const unsigned target = gen + 1;
   int ok = 1;
-  if (threadIdx.x == 0)
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // the write-back has completed before the arrival word
     __hip_atomic_store(&gs->arrive[blockIdx.x], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   if (blockIdx.x == 0 && threadIdx.x < WAVE) {
     const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
     for (;;) {
