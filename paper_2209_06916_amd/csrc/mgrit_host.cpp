@@ -506,7 +506,7 @@ constexpr size_t LDS_LIMIT = 160 * 1024;
 // Tile geometry of the level-0 explicit relaxation: the halo is what m steps
 // of (Horner depth) stencil applications consume; pick the points per lane
 // that minimise redundant lane-work (ties: fewer points, more wavefronts).
-bool choose_tiles(int nx, int m, int depth, int sl, int sr, int Pforce, TileGeom &tg) {
+bool choose_tiles(int nx, int m, int depth, int sl, int sr, int Pforce, TileGeom &tg, int comp = 0) {
   static const int Ps[2] = {8, 16};
   const int HL = m * depth * sl, HR = m * depth * sr;
   long best = -1;
@@ -518,7 +518,7 @@ bool choose_tiles(int nx, int m, int depth, int sl, int sr, int Pforce, TileGeom
     const long work = (long)ntiles * WAVE * P;
     if (best < 0 || work < best) {
       best = work;
-      tg = TileGeom{P, HL, HR, (nx + ntiles - 1) / ntiles, ntiles, sl, sr};
+      tg = TileGeom{P, HL, HR, (nx + ntiles - 1) / ntiles, ntiles, sl, sr, comp};
     }
   }
   return best >= 0;
@@ -596,6 +596,7 @@ int env_int(const char *name, int def) {
 struct Level {
   bool tiles = false;  // level-0 explicit relaxation through tile_kernel
   TileGeom tg{};
+  int t_depth = 0, t_sl = 0, t_sr = 0, t_comp = 0;  // the tiles' operator: Horner depth, extents, written out
   bool seq_tiles = false;  // sequential stepping through tile_kernel, seq_T steps per launch
   TileGeom seq_tg{};
   int seq_T = 0;
@@ -895,6 +896,28 @@ bool sl_chain(const FineInfo &fi, int p, int q, double c, const std::vector<int>
 // (eq. MOL_M_def), as a Horner form: ERK R(z) in z = -c L_p (OP_POLY_Z);
 // SDIRK R as a polynomial in w = (I + gamma c L_p)^{-1} (OP_POLY_W), every
 // stage solving with the same periodic banded matrix.
+// An explicit step R(Z) = sum_i beta_i Z^i, Z = -c L_p (eq. MOL_M_def), written
+// out as one circulant stencil: the powers of Z's stencil are convolved and
+// summed in extended precision, offsets -s l .. s r (s = degree of R).  The
+// same operator as the Horner form up to rounding, with s(l + r) + 1 products
+// per point instead of s(l + r + 2).
+void write_out_erk(const FineInfo &fi, double c, StepOp &op) {
+  const int s = fi.tab.s, cl = s * fi.l, cr = s * fi.r, n = cl + cr + 1;
+  std::vector<ld> pw(n, 0), acc(n, 0);  // index: offset + cl
+  pw[cl] = 1;
+  acc[cl] = fi.beta[0];
+  for (int i = 1; i <= s; ++i) {
+    std::vector<ld> nxt(n, 0);
+    for (int o = -(i - 1) * fi.l; o <= (i - 1) * fi.r; ++o)
+      for (int j = -fi.l; j <= fi.r; ++j) nxt[o + j + cl] += pw[o + cl] * (-(ld)c * (ld)fi.w[j + fi.l]);
+    pw.swap(nxt);
+    for (int k = 0; k < n; ++k) acc[k] += fi.beta[i] * pw[k];
+  }
+  op.ct_l = cl;
+  op.ct_r = cr;
+  for (int k = 0; k < n; ++k) op.ctaps[k] = (double)acc[k];
+}
+
 bool build_mol_step(const FineInfo &fi, int rk_kind, double c, int nx, int Lpref, StepOp &op, Layout &lay,
                     std::vector<double> &tabs, std::vector<size_t> &offs, std::string &err) {
   op = StepOp{};
@@ -1042,16 +1065,17 @@ hipError_t configure_once() {
 std::mutex g_tune_mu;
 std::map<std::vector<int64_t>, int> g_tune_cache;
 
-hipError_t tune_tiles(mgrit_handle *h, int depth, int sl, int sr) {
+hipError_t tune_tiles(mgrit_handle *h) {
   Level &L0 = h->lv[0];
+  const int depth = L0.t_depth, sl = L0.t_sl, sr = L0.t_sr, comp = L0.t_comp;
   const int nx = (int)h->prob.nx;
   const int64_t nc = L0.nt / L0.m;
-  const std::vector<int64_t> key{nx, L0.m, depth, sl, sr, nc};
+  const std::vector<int64_t> key{nx, L0.m, depth, sl, sr, comp, nc};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      choose_tiles(nx, L0.m, depth, sl, sr, it->second, L0.tg);
+      choose_tiles(nx, L0.m, depth, sl, sr, it->second, L0.tg, comp);
       return hipSuccess;
     }
   }
@@ -1063,7 +1087,7 @@ hipError_t tune_tiles(mgrit_handle *h, int depth, int sl, int sr) {
   float best_ms = -1;
   for (int cand : {8, 16}) {
     TileGeom tg{};
-    if (!choose_tiles(nx, L0.m, depth, sl, sr, cand, tg)) continue;
+    if (!choose_tiles(nx, L0.m, depth, sl, sr, cand, tg, comp)) continue;
     TileArgs ta{};
     ta.mode = MODE_PASS_A;
     ta.m = L0.m;
@@ -1085,7 +1109,7 @@ hipError_t tune_tiles(mgrit_handle *h, int depth, int sl, int sr) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (e) return e;
-  choose_tiles(nx, L0.m, depth, sl, sr, best_p, L0.tg);
+  choose_tiles(nx, L0.m, depth, sl, sr, best_p, L0.tg, comp);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune_cache[key] = best_p;
   return hipSuccess;
@@ -1158,8 +1182,16 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
     op = StepOp{};
     op.repeat = 1;
     if (P->rk_kind == MGRIT_ERK) {
+      // the tiles apply the step written out as one stencil where an
+      // instance exists for its extents (ERK3 + U3), else by Horner; the
+      // halo, m (depth x extent), is the same either way
+      const int s = fi.tab.s;
+      L0.t_comp = env_int("MGRIT_TILE_COMPOSE", 1) != 0 && s * fi.l == 6 && s * fi.r == 3;
+      L0.t_depth = L0.t_comp ? 1 : s;
+      L0.t_sl = L0.t_comp ? s * fi.l : fi.l;
+      L0.t_sr = L0.t_comp ? s * fi.r : fi.r;
       L0.tiles = env_int("MGRIT_NO_TILES", 0) == 0 &&
-                 choose_tiles(nx, ms[0], fi.tab.s, fi.l, fi.r, env_int("MGRIT_TILE_P", 0), L0.tg);
+                 choose_tiles(nx, ms[0], L0.t_depth, L0.t_sl, L0.t_sr, env_int("MGRIT_TILE_P", 0), L0.tg, L0.t_comp);
       L0.seq_tiles = env_int("MGRIT_NO_TILES", 0) == 0 &&
                      choose_seq_tiles(nx, P->nt, fi.tab.s, fi.l, fi.r, env_int("MGRIT_SEQ_P", 0),
                                       env_int("MGRIT_SEQ_T", 0), L0.seq_tg, L0.seq_T);
@@ -1169,6 +1201,7 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
       mgrit_destroy(h);
       return bad(MGRIT_EINVAL, err);
     }
+    if (L0.t_comp) write_out_erk(fi, c, op);
   }
 
   // ---- coarse operators (eqs. MOL-SL-corrected, MOL-SL-corrected-multilevel)
@@ -1304,7 +1337,7 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
     if (O->tile_tune)  // room for every candidate width
       for (int cand : {8, 16}) {
         TileGeom tg{};
-        if (choose_tiles(nx, ms[0], fi.tab.s, fi.l, fi.r, cand, tg))
+        if (choose_tiles(nx, ms[0], h->lv[0].t_depth, h->lv[0].t_sl, h->lv[0].t_sr, cand, tg, h->lv[0].t_comp))
           h->normpart_len = std::max<int64_t>(h->normpart_len, (P->nt / ms[0]) * tg.ntiles);
       }
   }
@@ -1401,7 +1434,7 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
   h->ctl_host = (SolveCtl *)(h->host_arena + 128);
   h->ctl_host_dev = (SolveCtl *)(slot_dev + 128);
   if (O->tile_tune && h->lv[0].tiles && nlev >= 2) {
-    const hipError_t e = tune_tiles(h, fi.tab.s, fi.l, fi.r);
+    const hipError_t e = tune_tiles(h);
     if (e != hipSuccess) {
       mgrit_destroy(h);
       return bad(MGRIT_EDEVICE, std::string("tile tuning: ") + hipGetErrorString(e));

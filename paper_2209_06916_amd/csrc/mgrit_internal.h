@@ -10,6 +10,7 @@ namespace mgrit {
 constexpr int KMAX = 3;       // max order of one periodic recurrence
 constexpr int MAXTAPS = 8;    // max stencil / interpolation taps
 constexpr int MAXCOEF = 8;    // max Horner coefficients (degree + 1)
+constexpr int MAXCTAPS = 16;  // max taps of an explicit step written out as one stencil
 constexpr int MAXWAVES = 16;  // 1024 threads / 64
 constexpr int WAVE = 64;
 
@@ -51,6 +52,8 @@ struct StepOp {
   double coef[MAXCOEF];
   int st_l, st_r;         // OP_POLY_Z stencil offsets -st_l..st_r
   double taps[MAXTAPS];   // taps[j + st_l]
+  int ct_l, ct_r;         // the whole explicit step R(Z) as one stencil, offsets -ct_l..ct_r
+  double ctaps[MAXCTAPS]; // ctaps[j + ct_l] (level-0 tiles only)
   int sl_l, sl_r;         // OP_SLC interpolation nodes -sl_l..sl_r around i-K
   int sl_K;               // floor(shift) mod nx
   double slw[MAXTAPS];    // slw[j + sl_l]
@@ -219,6 +222,7 @@ struct TileGeom {
   int TW;      // output points per tile (last tile may have fewer)
   int ntiles;  // tiles per interval
   int sl, sr;  // stencil extents (kernel template parameters)
+  int comp;    // 1: one application of the written-out step (ct_l, ct_r), else Horner
 };
 
 struct TileArgs {

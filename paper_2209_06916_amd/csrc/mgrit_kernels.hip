@@ -10,38 +10,53 @@ namespace {
 
 #include "mgrit_device.h"
 
-__global__ void __launch_bounds__(256) reduce_kernel(const double *__restrict__ part, int64_t n,
-                                                      double *__restrict__ out) {
-  __shared__ double red[256];
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) s += part[i];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int d = 128; d > 0; d >>= 1) {
-    if (threadIdx.x < d) red[threadIdx.x] += red[threadIdx.x + d];
-    __syncthreads();
+constexpr int RED_T = 1024;
+
+// Sum of part[0..n) by one workgroup of RED_T threads, in a fixed order (the
+// result does not depend on timing): every thread adds its strided elements
+// with four loads in flight, each wavefront folds its lanes with butterfly
+// shuffles (every lane ends with the same sum), and thread 0 adds the
+// wavefront sums in order.  Only thread 0's return value is the total.
+__device__ double block_sum(const double *__restrict__ part, int64_t n, double *red) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t i = threadIdx.x;
+  for (; i + 3 * RED_T < n; i += 4 * RED_T) {
+    const double a = part[i], b = part[i + RED_T], c = part[i + 2 * RED_T], d = part[i + 3 * RED_T];
+    s0 += a;
+    s1 += b;
+    s2 += c;
+    s3 += d;
   }
-  if (threadIdx.x == 0) out[0] = red[0];
+  for (; i < n; i += RED_T) s0 += part[i];
+  double s = (s0 + s1) + (s2 + s3);
+  for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s = red[0];
+    for (int w = 1; w < RED_T / WAVE; ++w) s += red[w];
+  }
+  return s;
+}
+
+__global__ void __launch_bounds__(RED_T) reduce_kernel(const double *__restrict__ part, int64_t n,
+                                                        double *__restrict__ out) {
+  __shared__ double red[RED_T / WAVE];
+  const double s = block_sum(part, n, red);
+  if (threadIdx.x == 0) out[0] = s;
 }
 
 // Residual norm of one MGRIT iteration and the stopping test (Sec. 2.2: stop
 // once ||r_it|| <= rtol ||r_0||), in the order the solver applies them:
 // non-finite, converged, stalled (inner float32 solves only), iteration
 // limit, growth past diverge_factor ||r_0||.
-__global__ void __launch_bounds__(256) solve_ctl_kernel(const double *__restrict__ part, int64_t n,
+__global__ void __launch_bounds__(RED_T) solve_ctl_kernel(const double *__restrict__ part, int64_t n,
                                                          SolveCtl *ctl, SolveCtl *ctl_host, const GridSync *gs,
                                                          StopRule rule) {
-  __shared__ double red[256];
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) s += part[i];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int d = 128; d > 0; d >>= 1) {
-    if (threadIdx.x < d) red[threadIdx.x] += red[threadIdx.x + d];
-    __syncthreads();
-  }
+  __shared__ double red[RED_T / WAVE];
+  const double ss = block_sum(part, n, red);
   if (threadIdx.x != 0) return;
-  const double rho = sqrt(red[0]);
+  const double rho = sqrt(ss);
   const int it = ctl->it;
   const double prev = ctl->rho;
   const double res0 = it == 0 ? rho : ctl->res0;
@@ -171,7 +186,7 @@ hipError_t launch_tiles(const LevelDesc *desc, const TileGeom &tg, const TileArg
 }
 
 hipError_t launch_reduce(const double *part, int64_t n, double *out, hipStream_t stream) {
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, stream, part, n, out);
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(RED_T), 0, stream, part, n, out);
   return hipGetLastError();
 }
 
@@ -193,7 +208,7 @@ hipError_t launch_fill(double *dst, int64_t n, double value, hipStream_t stream,
 
 hipError_t launch_solve_ctl(const double *part, int64_t n, SolveCtl *ctl, SolveCtl *ctl_host, const GridSync *gs,
                             StopRule rule, hipStream_t stream) {
-  hipLaunchKernelGGL(solve_ctl_kernel, dim3(1), dim3(256), 0, stream, part, n, ctl, ctl_host, gs, rule);
+  hipLaunchKernelGGL(solve_ctl_kernel, dim3(1), dim3(RED_T), 0, stream, part, n, ctl, ctl_host, gs, rule);
   return hipGetLastError();
 }
 

@@ -42,8 +42,12 @@ __device__ __forceinline__ void load_run(const double *__restrict__ row, int g, 
     }
   }
 }
-template <int P, int SL, int SR>
+// COMP: every step is one application of the explicit step written out as a
+// single stencil, u_k <- sum_t ctaps[t] u_{k+t-SL} (SL, SR: its extents);
+// otherwise R(Z) u by Horner, (ncoef - 1) applications of Z (extents SL, SR).
+template <int P, int SL, int SR, bool COMP>
 __global__ void __launch_bounds__(256) tile_kernel(const LevelDesc *__restrict__ desc, TileGeom tg, TileArgs ta) {
+  static_assert(!COMP || (SL <= P && SR <= P && SL + SR + 1 <= MAXCTAPS), "written-out step wider than a lane pair");
   const StepOp &op = desc->op;
   const int nx = desc->lay.nx;
   const int lane = threadIdx.x & (WAVE - 1);
@@ -60,7 +64,7 @@ __global__ void __launch_bounds__(256) tile_kernel(const LevelDesc *__restrict__
   const int ncoef = op.ncoef;
   double taps[SL + SR + 1];
 #pragma unroll
-  for (int t = 0; t <= SL + SR; ++t) taps[t] = op.taps[t];
+  for (int t = 0; t <= SL + SR; ++t) taps[t] = COMP ? op.ctaps[t] : op.taps[t];
   double cf[MAXCOEF];
 #pragma unroll
   for (int i = 0; i < MAXCOEF; ++i) cf[i] = op.coef[i];
@@ -103,6 +107,30 @@ __global__ void __launch_bounds__(256) tile_kernel(const LevelDesc *__restrict__
   const int nsteps = (ta.mode == MODE_FINAL_F) ? ta.m - 1 : ta.m;
   const bool store_steps = ta.mode == MODE_FINAL_F || ta.mode == MODE_SEQ;
   for (int j = 1; j <= nsteps; ++j) {
+    if constexpr (COMP) {
+      double lh[SL > 0 ? SL : 1], rh[SR > 0 ? SR : 1];
+#pragma unroll
+      for (int q = 0; q < SL; ++q) lh[q] = wave_shift<0x138>(u[P - SL + q]);
+#pragma unroll
+      for (int q = 0; q < SR; ++q) rh[q] = wave_shift<0x130>(u[q]);
+      double yn[P];
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t <= SL + SR; ++t) {
+          const int src = k + t - SL;
+          const double v = src < 0 ? lh[(src + SL) < 0 ? 0 : (src + SL)]
+                                   : (src >= P ? rh[(src - P) < SR ? (src - P) : 0] : u[src < P ? src : 0]);
+          acc = t == 0 ? taps[0] * v : fma(taps[t], v, acc);
+        }
+        yn[k] = acc;
+      }
+#pragma unroll
+      for (int k = 0; k < P; ++k) u[k] = yn[k];
+      if (store_steps) store_out(ta.out + (b * ta.m + j) * nxl, u);
+      continue;
+    }
     double y[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) y[k] = top * u[k];
@@ -165,12 +193,22 @@ template <int P>
 hipError_t launch_tiles_p(const LevelDesc *desc, const TileGeom &tg, const TileArgs &ta, hipStream_t stream) {
   const int64_t items = ta.nint * tg.ntiles;
   const dim3 grid((unsigned)((items + 3) / 4)), block(256);
+  if (tg.comp) {
+    // written-out explicit steps: ERK3 + U3 (3 stages x (2, 1))
+    if constexpr (P >= 8) {
+      if (tg.sl == 6 && tg.sr == 3) {
+        hipLaunchKernelGGL((tile_kernel<P, 6, 3, true>), grid, block, 0, stream, desc, tg, ta);
+        return hipGetLastError();
+      }
+    }
+    return hipErrorInvalidValue;
+  }
   switch (tg.sl * 4 + tg.sr) {
-    case 1 * 4 + 0: hipLaunchKernelGGL((tile_kernel<P, 1, 0>), grid, block, 0, stream, desc, tg, ta); break;
-    case 2 * 4 + 0: hipLaunchKernelGGL((tile_kernel<P, 2, 0>), grid, block, 0, stream, desc, tg, ta); break;
-    case 2 * 4 + 1: hipLaunchKernelGGL((tile_kernel<P, 2, 1>), grid, block, 0, stream, desc, tg, ta); break;
-    case 3 * 4 + 1: hipLaunchKernelGGL((tile_kernel<P, 3, 1>), grid, block, 0, stream, desc, tg, ta); break;
-    case 3 * 4 + 2: hipLaunchKernelGGL((tile_kernel<P, 3, 2>), grid, block, 0, stream, desc, tg, ta); break;
+    case 1 * 4 + 0: hipLaunchKernelGGL((tile_kernel<P, 1, 0, false>), grid, block, 0, stream, desc, tg, ta); break;
+    case 2 * 4 + 0: hipLaunchKernelGGL((tile_kernel<P, 2, 0, false>), grid, block, 0, stream, desc, tg, ta); break;
+    case 2 * 4 + 1: hipLaunchKernelGGL((tile_kernel<P, 2, 1, false>), grid, block, 0, stream, desc, tg, ta); break;
+    case 3 * 4 + 1: hipLaunchKernelGGL((tile_kernel<P, 3, 1, false>), grid, block, 0, stream, desc, tg, ta); break;
+    case 3 * 4 + 2: hipLaunchKernelGGL((tile_kernel<P, 3, 2, false>), grid, block, 0, stream, desc, tg, ta); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
