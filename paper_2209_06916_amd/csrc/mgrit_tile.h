@@ -106,7 +106,8 @@ __global__ void __launch_bounds__(256) tile_kernel(const LevelDesc *__restrict__
   // and writes every step.
   const int nsteps = (ta.mode == MODE_FINAL_F) ? ta.m - 1 : ta.m;
   const bool store_steps = ta.mode == MODE_FINAL_F || ta.mode == MODE_SEQ;
-  for (int j = 1; j <= nsteps; ++j) {
+  // one step u <- R(Z) u
+  auto advance = [&]() {
     if constexpr (COMP) {
       double lh[SL > 0 ? SL : 1], rh[SR > 0 ? SR : 1];
 #pragma unroll
@@ -128,57 +129,63 @@ __global__ void __launch_bounds__(256) tile_kernel(const LevelDesc *__restrict__
       }
 #pragma unroll
       for (int k = 0; k < P; ++k) u[k] = yn[k];
-      if (store_steps) store_out(ta.out + (b * ta.m + j) * nxl, u);
-      continue;
-    }
-    double y[P];
+    } else {
+      double y[P];
 #pragma unroll
-    for (int k = 0; k < P; ++k) y[k] = top * u[k];
+      for (int k = 0; k < P; ++k) y[k] = top * u[k];
 #pragma unroll
-    for (int i = MAXCOEF - 2; i >= 0; --i) {
-      if (i > ncoef - 2) continue;  // uniform
-      double lh[SL > 0 ? SL : 1], rh[SR > 0 ? SR : 1];
+      for (int i = MAXCOEF - 2; i >= 0; --i) {
+        if (i > ncoef - 2) continue;  // uniform
+        double lh[SL > 0 ? SL : 1], rh[SR > 0 ? SR : 1];
 #pragma unroll
-      for (int q = 0; q < SL; ++q) lh[q] = wave_shift<0x138>(y[P - SL + q]);
+        for (int q = 0; q < SL; ++q) lh[q] = wave_shift<0x138>(y[P - SL + q]);
 #pragma unroll
-      for (int q = 0; q < SR; ++q) rh[q] = wave_shift<0x130>(y[q]);
-      const double ci = cf[i];
-      double yn[P];
+        for (int q = 0; q < SR; ++q) rh[q] = wave_shift<0x130>(y[q]);
+        const double ci = cf[i];
+        double yn[P];
 #pragma unroll
-      for (int k = 0; k < P; ++k) {
-        double acc = ci * u[k];
+        for (int k = 0; k < P; ++k) {
+          double acc = ci * u[k];
 #pragma unroll
-        for (int t = 0; t <= SL + SR; ++t) {
-          const int src = k + t - SL;
-          const double v = src < 0 ? lh[(src + SL) < 0 ? 0 : (src + SL)]
-                                   : (src >= P ? rh[(src - P) < SR ? (src - P) : 0] : y[src < P ? src : 0]);
-          acc = fma(taps[t], v, acc);
+          for (int t = 0; t <= SL + SR; ++t) {
+            const int src = k + t - SL;
+            const double v = src < 0 ? lh[(src + SL) < 0 ? 0 : (src + SL)]
+                                     : (src >= P ? rh[(src - P) < SR ? (src - P) : 0] : y[src < P ? src : 0]);
+            acc = fma(taps[t], v, acc);
+          }
+          yn[k] = acc;
         }
-        yn[k] = acc;
+#pragma unroll
+        for (int k = 0; k < P; ++k) y[k] = yn[k];
       }
 #pragma unroll
-      for (int k = 0; k < P; ++k) y[k] = yn[k];
+      for (int k = 0; k < P; ++k) u[k] = y[k];
     }
-#pragma unroll
-    for (int k = 0; k < P; ++k) u[k] = y[k];
+  };
+  for (int j = 1; j < nsteps; ++j) {
+    advance();
     if (store_steps) store_out(ta.out + (b * ta.m + j) * nxl, u);
+  }
+  // the last step; pass B first requests the next C-point, whose load then
+  // overlaps the step
+  double cn[P];
+  if (ta.mode == MODE_PASS_B) load_run<P>(ta.cin + (b + 1) * nxl, g0, nx, cn);
+  if (nsteps > 0) {
+    advance();
+    if (store_steps) store_out(ta.out + (b * ta.m + nsteps) * nxl, u);
   }
 
   if (ta.mode == MODE_PASS_A) {
     store_out(ta.cout + (b + 1) * nxl, u);
   } else if (ta.mode == MODE_PASS_B) {
-    const double *c1 = ta.cin + (b + 1) * nxl;
+    double rv[P];
     double ss = 0.0;
-    int g = g0;
 #pragma unroll
     for (int k = 0; k < P; ++k) {
-      if (k >= lo && k < hi) {
-        const double rv = u[k] - c1[g];
-        ta.r[b * nxl + g] = rv;
-        ss = fma(rv, rv, ss);
-      }
-      g = next_periodic(g, nx);
+      rv[k] = u[k] - cn[k];
+      if (k >= lo && k < hi) ss = fma(rv[k], rv[k], ss);
     }
+    store_out(ta.r + b * nxl, rv);
 #pragma unroll
     for (int d = WAVE / 2; d > 0; d >>= 1) ss += __shfl_down(ss, d, WAVE);
     if (lane == 0) ta.normpart[item] = ss;
