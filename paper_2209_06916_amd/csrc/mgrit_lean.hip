@@ -483,7 +483,8 @@ __device__ __forceinline__ bool wait_expired(unsigned long long t0, const GridSy
 // the workgroup barrier alone only waits for LDS), then after the workgroup
 // barrier thread 0's device-scope release writes that L2 back before the
 // arrival word: one device-scope release (a cache write-back) per workgroup
-// instead of one per wavefront.  Acquired after the release.
+// instead of one per wavefront.  After the release thread 0 only acquires
+// (invalidates), since its workgroup's writes went out on arrival.
 __device__ __forceinline__ bool grid_barrier(GridSync *gs, unsigned &gen, int *ok_lds) {
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0) (expcnt, lgkmcnt unconstrained)
   __syncthreads();
@@ -524,7 +525,8 @@ __device__ __forceinline__ bool grid_barrier(GridSync *gs, unsigned &gen, int *o
       }
     }
     if (!ok) atomicExch(&gs->err, 1);
-    __threadfence();
+    // acquire only: this workgroup's own writes were released on arrival
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *ok_lds = ok;
   }
   gen = target;
