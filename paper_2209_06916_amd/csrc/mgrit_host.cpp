@@ -892,10 +892,6 @@ bool sl_chain(const FineInfo &fi, int p, int q, double c, const std::vector<int>
   return true;
 }
 
-// One Runge-Kutta step of the upwind semi-discretisation at CFL c
-// (eq. MOL_M_def), as a Horner form: ERK R(z) in z = -c L_p (OP_POLY_Z);
-// SDIRK R as a polynomial in w = (I + gamma c L_p)^{-1} (OP_POLY_W), every
-// stage solving with the same periodic banded matrix.
 // An explicit step R(Z) = sum_i beta_i Z^i, Z = -c L_p (eq. MOL_M_def), written
 // out as one circulant stencil: the powers of Z's stencil are convolved and
 // summed in extended precision, offsets -s l .. s r (s = degree of R).  The
@@ -918,6 +914,10 @@ void write_out_erk(const FineInfo &fi, double c, StepOp &op) {
   for (int k = 0; k < n; ++k) op.ctaps[k] = (double)acc[k];
 }
 
+// One Runge-Kutta step of the upwind semi-discretisation at CFL c
+// (eq. MOL_M_def), as a Horner form: ERK R(z) in z = -c L_p (OP_POLY_Z);
+// SDIRK R as a polynomial in w = (I + gamma c L_p)^{-1} (OP_POLY_W), every
+// stage solving with the same periodic banded matrix.
 bool build_mol_step(const FineInfo &fi, int rk_kind, double c, int nx, int Lpref, StepOp &op, Layout &lay,
                     std::vector<double> &tabs, std::vector<size_t> &offs, std::string &err) {
   op = StepOp{};
