@@ -120,7 +120,12 @@ PROFILE_COMMANDS = {
              "python3 bench.py --steps 2 --warmup 1 --traffic-probe",
     "serve": "rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/serve -o run -- "
              "python3 bench.py --serve 512",
+    "sq": "rocprofv3 --pmc SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_INSTS_VALU "
+          "SQ_ACTIVE_INST_VALU SQ_INSTS_LDS --output-format csv -d <dir>/sq -o run -- "
+          "python3 bench.py --steps 1 --warmup 0 --traffic-probe",
 }
+SQ_COUNTERS = ["SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_INSTS_VALU",
+               "SQ_ACTIVE_INST_VALU", "SQ_INSTS_LDS"]
 SERVE_WORKLOAD = "served-advection1d-512-requests"
 DOMINANT_KERNEL = "coarse_vcycle_kernel<4, 2, 16, 4>"
 
@@ -173,6 +178,38 @@ def summarize_profiles(d):
             lines.append(f"  {_short(r['Name']):52s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
                          f"{float(r['TotalDurationNs']) / 1e6:10.3f} {100 * float(r['TotalDurationNs']) / tot:6.2f}%")
         with open(os.path.join(prof_dir, f"kernel_stats_{SERVE_WORKLOAD}.txt"), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+
+    sq_csv = os.path.join(d, "sq", "run_counter_collection.csv")
+    if os.path.exists(sq_csv):
+        per = {}
+        for r in csv.DictReader(open(sq_csv)):
+            k = _short(r["Kernel_Name"])
+            if k.startswith("at::") or k.startswith("__amd"):
+                continue
+            key = (r.get("Dispatch_Id") or r.get("Correlation_Id"), r["Counter_Name"])
+            per.setdefault(k, {}).setdefault(r["Counter_Name"], {})
+            per[k][r["Counter_Name"]][key[0]] = per[k][r["Counter_Name"]].get(key[0], 0.0) + float(r["Counter_Value"])
+        lines = [f"# rocprofv3 SQ counters -- workload {WORKLOAD}",
+                 "# (one MGRIT solve, no warm-up; values summed over the device per dispatch, then averaged over",
+                 "# dispatches; wave-cycle counters as the hardware counts them)",
+                 "# command (repository root on the GPU box, after cd /tmp && export TMPDIR=/tmp):",
+                 "#   " + PROFILE_COMMANDS["sq"].replace("<dir>", "gpurun_out/prof"),
+                 "#", "# kernel: dispatches; " + ", ".join(SQ_COUNTERS) + " (per dispatch)",
+                 "#   derived: VALU and LDS instructions per wavefront; WAIT_INST_ANY / WAVE_CYCLES (dependency",
+                 "#   waits); ACTIVE_INST_VALU / WAVE_CYCLES (VALU issue)"]
+        for k, cs in sorted(per.items()):
+            avg = {c: float(np.mean(list(cs[c].values()))) for c in SQ_COUNTERS if c in cs}
+            nd = max(len(v) for v in cs.values())
+            lines.append(f"  {k}: {nd} dispatches; " + ", ".join(f"{avg.get(c, float('nan')):.4g}" for c in SQ_COUNTERS))
+            w = avg.get("SQ_WAVES", 0.0)
+            wc = avg.get("SQ_WAVE_CYCLES", 0.0)
+            if w > 0 and wc > 0:
+                lines.append(f"    VALU/wave {avg.get('SQ_INSTS_VALU', 0.0) / w:.0f}, LDS/wave "
+                             f"{avg.get('SQ_INSTS_LDS', 0.0) / w:.0f}, dependency waits "
+                             f"{avg.get('SQ_WAIT_INST_ANY', 0.0) / wc:.2f}, VALU issue "
+                             f"{avg.get('SQ_ACTIVE_INST_VALU', 0.0) / wc:.2f} of wave-cycles")
+        with open(os.path.join(prof_dir, f"counters_{WORKLOAD}.txt"), "w") as fh:
             fh.write("\n".join(lines) + "\n")
 
     def counters(sub, name):
