@@ -491,6 +491,51 @@ def long_bench(steps):
         torch.cuda.empty_cache()
 
 
+def fig4_bench(steps):
+    """The paper's strong-scaling problems (Fig. 4), on one GPU instead of
+    1024 CPU processes: nx x nt = 4096 x 16384, MGRIT V-cycles with m = 16 on
+    the first level and 4 below, coarsening until fewer than two time points
+    would result, FCF relaxation, 1e-10 relative residual; ERK1+U1 and ERK3+U3
+    at 85% of their CFL limits (Table 2), SDIRK1+U1 at CFL 1 and SDIRK3+U3 at
+    CFL 5; u0 = sin^4(pi x) and the seeded U[0,1) initial iterate.  Against
+    sequential time-stepping of the same problem on the GPU."""
+    import torch
+    from paper_2209_06916_amd import inputs, mgrit
+    dev = torch.device("cuda:0")
+    nx, nt, seed = 4096, 16384, 1004
+    u0 = inputs.u0_sin4(nx)
+    u0_d = torch.from_numpy(u0).to(dev)
+    v0 = torch.from_numpy(inputs.initial_iterate(nt, nx, u0, seed)).to(dev)
+    out = torch.empty((nt + 1, nx), dtype=torch.float64, device=dev)
+    ref = torch.empty_like(out)
+    for kind, p, c in [("erk", 1, 0.85 * 1.0), ("erk", 3, 0.85 * 1.62589), ("sdirk", 1, 1.0), ("sdirk", 3, 5.0)]:
+        s = mgrit.Solver(mgrit.make_problem(nx, nt, c, p, kind=kind),
+                         mgrit.make_options([16, 4], max_levels=16, min_coarse_nt=4, rtol=1e-10, max_iter=60))
+        info = s.solve(u0_d, v0, u_out=out)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            info = s.solve(u0_d, v0, u_out=out)
+        torch.cuda.synchronize()
+        tm = (time.perf_counter() - t) / steps
+        s.sequential(u0_d, ref)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            s.sequential(u0_d, ref)
+        torch.cuda.synchronize()
+        ts = (time.perf_counter() - t) / steps
+        err = (torch.linalg.vector_norm(out - ref) / torch.linalg.vector_norm(ref)).item()
+        print(json.dumps({"workload": f"advection1d-{nx}x{nt}-{kind}{p}u{p}-cfl{c:.4g}-vcycle-m16-4",
+                          "dof": nx * nt, "levels": s.num_levels, "status": info["status"],
+                          "iterations": info["iterations"], "mgrit_ms": 1e3 * tm, "mgrit_dof_per_s": nx * nt / tm,
+                          "sequential_ms": 1e3 * ts, "sequential_dof_per_s": nx * nt / ts,
+                          "speedup_vs_sequential": ts / tm, "rel_l2_error_vs_sequential": err}), flush=True)
+        s.close()
+    del out, ref, v0
+    torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -504,6 +549,9 @@ def main():
                     help="the request-loop benchmark (N independent solves) instead of the single-solve one")
     ap.add_argument("--long", action="store_true",
                     help="long time horizons (nt >> nx) against sequential stepping instead of the single-solve bench")
+    ap.add_argument("--fig4", action="store_true",
+                    help="the paper's strong-scaling problems (4096 x 16384, four schemes) against sequential "
+                         "stepping instead of the single-solve bench")
     ap.add_argument("--twod", action="store_true",
                     help="the 2D extension (config 4) against 2D sequential stepping instead of the single-solve bench")
     ap.add_argument("--precision", action="store_true",
@@ -532,6 +580,9 @@ def main():
         return
     if args.long:
         long_bench(max(1, min(args.steps, 5)))
+        return
+    if args.fig4:
+        fig4_bench(max(1, min(args.steps, 5)))
         return
 
     dev = torch.device("cuda:0")

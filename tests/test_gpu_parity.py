@@ -284,6 +284,20 @@ def test_full_solve_matches_oracle(case):
     _check_parity(info, got, fin, ref, rinfo, case["ms"][0])
 
 
+@pytest.mark.parametrize("kind,p,c", [("erk", 1, 0.85), ("erk", 3, 0.85 * 1.62589), ("sdirk", 1, 1.0),
+                                      ("sdirk", 3, 5.0)])
+def test_strong_scaling_problems_match_oracle(kind, p, c):
+    """The four problems of the paper's strong-scaling study (Fig. 4: ERK at
+    85% of the Table 2 CFL limits, SDIRK1 at CFL 1, SDIRK3 at CFL 5; m = 16
+    on the first level and 4 below, down to fewer than two coarse points
+    after one more coarsening), at nx x nt = 256 x 1024 instead of
+    4096 x 16384: same iterations and iterates as the oracle."""
+    _announce("fig4", kind, p, c)
+    s, info, got, fin, ref, rinfo = _solve_both(256, 1024, p, kind, p, c, [16, 4, 4], max_iter=60)
+    assert s.num_levels == 4
+    _check_parity(info, got, fin, ref, rinfo, 16)
+
+
 @pytest.mark.parametrize("case", [
     dict(nx=64, nt=256, p=1, kind="sdirk", q=1, c=1.0, ms=[4], max_iter=60),
     dict(nx=96, nt=128, p=3, kind="sdirk", q=3, c=2.0, ms=[4, 4], max_iter=60),
