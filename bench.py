@@ -146,7 +146,8 @@ def summarize_profiles(d):
     rows = list(csv.DictReader(open(os.path.join(d, "trace", "run_kernel_stats.csv"))))
     tot = sum(float(r["TotalDurationNs"]) for r in rows)
     lines = [f"# rocprofv3 kernel statistics -- workload {WORKLOAD}",
-             "# (10 timed + 2 warm-up MGRIT solves, then 4 runs of sequential time-stepping of the same problem)",
+             "# (MGRIT solves: 2 warm-up, 3 with every phase timed by events, 10 timed; then 4 runs of sequential",
+             "# time-stepping of the same problem; then 6 MGRIT solves without the final F-pass)",
              "# command (repository root on the GPU box, after cd /tmp && export TMPDIR=/tmp):",
              "#   " + PROFILE_COMMANDS["trace"].replace("<dir>", "gpurun_out/prof"),
              "#", f"# {'kernel':52s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'share':>7s}"]
