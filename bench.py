@@ -678,9 +678,12 @@ def main():
     avg_s = prof[dom]["total_ms"] / prof[dom]["launches"] / 1e3
     flops = flops_s / launches
     bytes_ = bytes_s / launches
+    persistent = launches <= it + 1.5  # one coarse launch per iteration, else one per pass
     kernel = {"fine_relax": "tile_kernel<8, 6, 3, true>: level-0 F/C relaxation and C-point residual",
-              "coarse": "coarse_vcycle_kernel<4, 2, 16, 4>: every coarse-level pass of a V-cycle in one persistent "
-                        "launch (SL step + periodic banded solve)",
+              "coarse": ("coarse_vcycle_kernel<4, 2, 16, 4>: every coarse-level pass of a V-cycle in one persistent "
+                         "launch (SL step + periodic banded solve)") if persistent else
+                        ("slc_kernel<4, 2, 16, 4>: one coarse-level pass per launch (SL step + periodic banded "
+                         "solve)"),
               "final": "tile_kernel<8, 6, 3, true>: final F-relaxation writing the space-time solution"}[dom]
     ai = flops / bytes_
     ridge = FP64_VALU_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
