@@ -699,7 +699,8 @@ def main():
     if os.path.exists(tfile):
         with open(tfile) as fh:
             t = json.load(fh)
-        if t.get("source_hash") == kernel_source_hash() and t.get("phase") == dom and t.get("workload") == WORKLOAD:
+        if (t.get("source_hash") == kernel_source_hash() and t.get("phase") == dom and t.get("workload") == WORKLOAD
+                and (dom != "coarse" or persistent)):
             traffic = t.get("bytes_per_launch")
     roof["traffic"] = traffic
     roof["kernel"] = kernel
