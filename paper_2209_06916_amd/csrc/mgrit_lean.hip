@@ -37,8 +37,8 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
   return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
 }
 
-template <int K>
-__device__ __forceinline__ void ld_mat(const double *p, double (&M)[K * K]) {
+template <int K, class TP>
+__device__ __forceinline__ void ld_mat(TP p, double (&M)[K * K]) {
 #pragma unroll
   for (int i = 0; i < K * K; ++i) M[i] = p[i];
 }
@@ -94,8 +94,8 @@ struct LaneMats {
 // One Kogge-Stone step inside 16-lane rows: add H^D times the state D lanes
 // back in processing order (row_shr forward, row_shl backward; lanes without
 // such a neighbour receive 0 and keep their value).
-template <int K, bool REV, int D>
-__device__ __forceinline__ void row_step(double (&inc)[K], const double *tab) {
+template <int K, bool REV, int D, class TP>
+__device__ __forceinline__ void row_step(double (&inc)[K], TP tab) {
   double M[K * K];
   ld_mat<K>(tab + D * K * K, M);
   double o[K];
@@ -106,8 +106,8 @@ __device__ __forceinline__ void row_step(double (&inc)[K], const double *tab) {
 
 // Periodic recurrence x_i += sum_m a[m] x_{i-1-m} (REV: x_{i+1+m}) over the
 // workgroup's 16-point chunks; pre_barrier() runs just before the barrier.
-template <int L, int K, int NW, bool REV, bool HOIST, class Hook>
-__device__ __forceinline__ void lean_rec(double (&x)[L], const double (&a)[K], const double *tab,
+template <int L, int K, int NW, bool REV, bool HOIST, class TP, class Hook>
+__device__ __forceinline__ void lean_rec(double (&x)[L], const double (&a)[K], TP tab,
                                          const LaneMats<K, HOIST> &lm, double *Q, Hook pre_barrier) {
   constexpr int KK = K * K;
   constexpr int LH = L / 2;  // two interleaved sub-chains per lane
@@ -308,6 +308,10 @@ __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, 
   }
   const int lane = tid & (WAVE - 1);
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // the wave-uniform scan matrices are read through the scalar cache from
+  // the device copy of the tables (constant address space)
+  typedef const __attribute__((address_space(4))) double *ConstTab;
+  const ConstTab ctf = (ConstTab)op.fw.tab, ctb = (ConstTab)op.bw.tab;
   LaneMats<K, HOIST> lmf, lmb;
   lmf.init(tab_f, hsrc_f, lane & 15, lane, wave);
   lmb.init(tab_b, hsrc_b, (WAVE - 1 - lane) & 15, WAVE - 1 - lane, NW - 1 - wave);
@@ -376,8 +380,8 @@ __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, 
         if (jj >= 0 && jj < L) y[jj] = fma(w[t], val, y[jj]);
       }
     }
-    lean_rec<L, K, NW, false>(y, af, tab_f, lmf, qf, [] {});
-    lean_rec<L, K, NW, true>(y, ab, tab_b, lmb, qb, [&] {
+    lean_rec<L, K, NW, false>(y, af, ctf, lmf, qf, [] {});
+    lean_rec<L, K, NW, true>(y, ab, ctb, lmb, qb, [&] {
       if (add_g) {  // g_n -> v in chunk order, then fetch the next step's row
 #pragma unroll
         for (int q = 0; q < L / 2; ++q) {
