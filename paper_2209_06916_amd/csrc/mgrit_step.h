@@ -60,8 +60,8 @@ __device__ __forceinline__ void window_combine(const T *vec, int start, int cnt,
   }
 }
 
-template <int K, class T>
-__device__ __forceinline__ void matvec_add(const T *H, const T (&x)[K], T (&acc)[K]) {
+template <int K, class T, class TP>
+__device__ __forceinline__ void matvec_add(TP H, const T (&x)[K], T (&acc)[K]) {
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     T s = acc[i];
@@ -76,9 +76,15 @@ __device__ __forceinline__ void matvec_add(const T *H, const T (&x)[K], T (&acc)
 // same chunks in reversed thread order).  vt: this thread's position in
 // processing order; A: threads owning points; tab: LDS copy of
 // [Hpow[0..64], Hlast, Wwrap] (K*K each); scr: LDS scratch of 2*MAXWAVES*K.
+template <class T>
+using ConstPtr = const __attribute__((address_space(4))) T *;
+
+// tab: the LDS copy of the tables (lane-dependent reads); ctab: the same
+// tables in device memory, read through the scalar cache where the index is
+// the same for the whole wavefront.
 template <int L, int K, bool REV, class T>
 __device__ __forceinline__ void recurrence(T (&x)[L], int cnt, int vt, int A, int NT, const T (&ain)[KMAX],
-                                           const T *tab, T *scr) {
+                                           const T *tab, ConstPtr<T> ctab, T *scr) {
   constexpr int KK = K * K;
   T a[K];
 #pragma unroll
@@ -120,7 +126,7 @@ __device__ __forceinline__ void recurrence(T (&x)[L], int cnt, int vt, int A, in
     T t[K];
 #pragma unroll
     for (int m = 0; m < K; ++m) t[m] = inc[m];
-    matvec_add<K>(tab + d * KK, o, t);
+    matvec_add<K>(ctab + d * KK, o, t);
     const bool take = vl >= d;
 #pragma unroll
     for (int m = 0; m < K; ++m) inc[m] = take ? t[m] : inc[m];
@@ -148,9 +154,9 @@ __device__ __forceinline__ void recurrence(T (&x)[L], int cnt, int vt, int A, in
   // 4. one thread: carry into its wavefront, the periodic wrap s_0, and the
   //    carries X'_w (with s_0 folded in) of every wavefront
   if (vt == A - 1) {
-    const T *H64 = tab + WAVE * KK;
-    const T *Hlast = tab + (WAVE + 1) * KK;
-    const T *Wwrap = tab + (WAVE + 2) * KK;
+    const ConstPtr<T> H64 = ctab + WAVE * KK;
+    const ConstPtr<T> Hlast = ctab + (WAVE + 1) * KK;
+    const ConstPtr<T> Wwrap = ctab + (WAVE + 2) * KK;
     T X[K];
 #pragma unroll
     for (int m = 0; m < K; ++m) X[m] = 0.0;
@@ -215,11 +221,11 @@ __device__ __forceinline__ void recurrence(T (&x)[L], int cnt, int vt, int A, in
 
 template <int L, bool REV, class T>
 __device__ __forceinline__ void recurrence_k(T (&x)[L], int cnt, int vt, int A, int NT, int k,
-                                             const T (&a)[KMAX], const T *tab, T *scr) {
+                                             const T (&a)[KMAX], const T *tab, ConstPtr<T> ctab, T *scr) {
   switch (k) {
-    case 1: recurrence<L, 1, REV>(x, cnt, vt, A, NT, a, tab, scr); break;
-    case 2: recurrence<L, 2, REV>(x, cnt, vt, A, NT, a, tab, scr); break;
-    case 3: recurrence<L, 3, REV>(x, cnt, vt, A, NT, a, tab, scr); break;
+    case 1: recurrence<L, 1, REV>(x, cnt, vt, A, NT, a, tab, ctab, scr); break;
+    case 2: recurrence<L, 2, REV>(x, cnt, vt, A, NT, a, tab, ctab, scr); break;
+    case 3: recurrence<L, 3, REV>(x, cnt, vt, A, NT, a, tab, ctab, scr); break;
     default: break;
   }
 }
@@ -246,6 +252,7 @@ template <class T>
 struct Lds {
   T *vec0, *vec1;   // padded vectors (vec1 == vec0 unless double-buffered)
   T *tab_f, *tab_b; // recurrence tables
+  ConstPtr<T> ctab_f, ctab_b;  // the same tables in device memory (uniform reads)
   T *scr_f, *scr_b; // recurrence scratch
   double *red;      // reduction scratch
 };
@@ -255,10 +262,10 @@ template <int L, class T>
 __device__ __forceinline__ void solve(T (&y)[L], int cnt, const OpRegs<T> &R, const Layout &lay, const Lds<T> &S) {
   const int tid = threadIdx.x;
   const int nx = lay.nx;
-  if (R.kf > 0) recurrence_k<L, false>(y, cnt, tid, lay.A, lay.T, R.kf, R.af, S.tab_f, S.scr_f);
+  if (R.kf > 0) recurrence_k<L, false>(y, cnt, tid, lay.A, lay.T, R.kf, R.af, S.tab_f, S.ctab_f, S.scr_f);
   if (R.kb > 0) {
     if (!lay.ragged) {
-      recurrence_k<L, true>(y, cnt, lay.T - 1 - tid, lay.A, lay.T, R.kb, R.ab, S.tab_b, S.scr_b);
+      recurrence_k<L, true>(y, cnt, lay.T - 1 - tid, lay.A, lay.T, R.kb, R.ab, S.tab_b, S.ctab_b, S.scr_b);
     } else {
       // redistribute so that thread t owns indices nx-1-(tL+j), j = 0..cnt-1
       T *vec = S.vec0;
@@ -270,7 +277,7 @@ __device__ __forceinline__ void solve(T (&y)[L], int cnt, const OpRegs<T> &R, co
       __syncthreads();
 #pragma unroll
       for (int j = 0; j < L; ++j) y[j] = (j < cnt) ? vec[padix(nx - 1 - (base + j))] : 0.0;
-      recurrence_k<L, false>(y, cnt, tid, lay.A, lay.T, R.kb, R.ab, S.tab_b, S.scr_b);
+      recurrence_k<L, false>(y, cnt, tid, lay.A, lay.T, R.kb, R.ab, S.tab_b, S.ctab_b, S.scr_b);
       __syncthreads();
 #pragma unroll
       for (int j = 0; j < L; ++j)
@@ -473,6 +480,8 @@ __global__ void __launch_bounds__(MAXT) step_kernel(const LevelDesc *__restrict_
   S.vec1 = sm + lo.vec1;
   S.tab_f = sm + lo.tab_f;
   S.tab_b = sm + lo.tab_b;
+  S.ctab_f = (ConstPtr<T>)op.fw.tab;
+  S.ctab_b = (ConstPtr<T>)op.bw.tab;
   S.scr_f = sm + lo.scr_f;
   S.scr_b = sm + lo.scr_b;
   S.red = smem + lo.red;
