@@ -18,7 +18,9 @@ namespace {
 // wavefront totals are published, every wavefront folds them and the
 // periodic wrap into its own carry (a short chain computed redundantly), so
 // no thread waits for a serial one.  The scan's lane-dependent matrix powers
-// are loaded into registers once per launch for K <= 2.
+// are loaded into registers once per launch for K <= 2; the matrices every
+// lane of a wavefront shares are read through the scalar cache from device
+// memory, which keeps them out of LDS and out of vector registers.
 // ---------------------------------------------------------------------------
 // Cross-lane move of a double with a DPP row shift (bound_ctrl: lanes whose
 // source lies outside their 16-lane row read 0).

@@ -19,8 +19,10 @@
 // constant transfer matrix H = M^L (M the companion matrix), one thread that
 // folds the wavefront totals and the closed-form periodic wrap
 // s_0 = W (H_last E_{A-1} + q_{A-1}) into per-wavefront carries, and a
-// homogeneous correction pass.  Everything the scan reads (powers of H, the
-// wrap matrix) is staged in LDS once per launch; operator coefficients are
+// homogeneous correction pass.  The scan's matrices (powers of H, the wrap
+// matrix) are read through the scalar cache from device memory where every
+// lane of a wavefront reads the same one, and from a copy staged in LDS once
+// per launch where the power depends on the lane; operator coefficients are
 // held in registers.  No MFMA: nothing here is a dense contraction.
 #pragma once
 
