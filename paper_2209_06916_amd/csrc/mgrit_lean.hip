@@ -636,6 +636,16 @@ hipError_t slc_set_lds(size_t bytes) {
   MGRIT_LEAN_SHAPES(MGRIT_SLC_LDS, 4, 2)
   MGRIT_LEAN_SHAPES(MGRIT_SLC_LDS, 6, 3)
 #undef MGRIT_SLC_LDS
+  // The persistent coarse cycle's instances get the same process-wide limit
+  // here, once, so that no later setup changes it while launches are in flight.
+#define MGRIT_CV_LDS(Wv, Kv, Lv, NWv)                                                                       \
+  if (e == hipSuccess)                                                                                     \
+    e = hipFuncSetAttribute((const void *)coarse_vcycle_kernel<Wv, Kv, Lv, NWv>,                           \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  MGRIT_LEAN_SHAPES(MGRIT_CV_LDS, 2, 1)
+  MGRIT_LEAN_SHAPES(MGRIT_CV_LDS, 4, 2)
+  MGRIT_LEAN_SHAPES(MGRIT_CV_LDS, 6, 3)
+#undef MGRIT_CV_LDS
   return e;
 }
 
@@ -668,14 +678,12 @@ size_t coarse_vcycle_lds(const StepOp &op, const Layout &lay, int nlevels) {
     }                                                                               \
   } while (0)
 
+// Occupancy query only: the LDS attribute was raised to the device limit once,
+// before any launch (configure_lean_kernels).
 int coarse_vcycle_max_grid(const StepOp &op, const Layout &lay, size_t lds) {
   if (!lean_slc_applies(op, lay)) return 0;
-#define MGRIT_CV_GRID(Wv, Kv, Lv, NWv)                                                                    \
-  case lean_key(Wv, Kv, Lv, NWv):                                                                         \
-    return hipFuncSetAttribute((const void *)coarse_vcycle_kernel<Wv, Kv, Lv, NWv>,                       \
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess        \
-               ? coarse_vcycle_grid<Wv, Kv, Lv, NWv>(lds)                                                 \
-               : 0;
+#define MGRIT_CV_GRID(Wv, Kv, Lv, NWv) \
+  case lean_key(Wv, Kv, Lv, NWv): return coarse_vcycle_grid<Wv, Kv, Lv, NWv>(lds);
   MGRIT_CV_SWITCH(MGRIT_CV_GRID, 0);
 #undef MGRIT_CV_GRID
 }

@@ -56,3 +56,11 @@ def u0_bumps_2d(nx, ny, count, width, seed, lo=-1.0, hi=1.0):
         dy = (y - cy + L / 2) % L - L / 2
         out += np.exp(-(dx * dx + dy * dy) / (2.0 * width * width))
     return out
+
+
+def sign_vector(n, seed):
+    """A seeded vector of +-1 entries: the weights of the per-time-point
+    projections that full-size parity tests compare (a random sign vector sees
+    an error e of any shape with magnitude about ||e||_2)."""
+    rng = np.random.default_rng(seed)
+    return np.where(rng.random(n) < 0.5, -1.0, 1.0)
