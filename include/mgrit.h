@@ -142,6 +142,16 @@ typedef struct {
   double phi_q;         /* coefficient of D^(q+1) (q != p only)               */
   int32_t tile_p;       /* level 0, explicit schemes: points per lane of the
                            relaxation tiles (0: no tiles)                      */
+  int32_t win_L;        /* points per thread of the windowed step kernel,
+                           which takes each periodic recurrence of the
+                           level's banded solves by truncated carries: the
+                           state entering a chunk is summed from the
+                           zero-state end states of the win_D chunks before
+                           it, exact to rounding because the recurrence
+                           decays (setup checks the bound); 0: the step runs
+                           with an exact workgroup-wide scan                 */
+  int32_t win_D[2];     /* those chunk counts for the causal and the
+                           anti-causal recurrence (0: none)                  */
 } mgrit_level_desc;
 
 /* Phases timed by the optional profiler (mgrit_profile_enable). */

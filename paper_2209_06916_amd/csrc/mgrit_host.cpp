@@ -476,6 +476,52 @@ void recurrence_tables(int k, const ld *a, const Layout &lay, std::vector<double
   }
 }
 
+// Truncated-carry plan of one recurrence (order k, coefficients a) on n
+// points in chunks of L (the windowed step kernel).  H = M^L: the state
+// entering a chunk is sum_{d < D} H^d Z_{t-1-d} up to H^D E, so D is the
+// first power with ||H^D||_inf <= 2^-60 (the error relative to max |y|, well
+// below float64 rounding); the correction of point e of a chunk is row 0 of
+// M^{e+1} times the carry, and hc ends where the rows' 1-norms fall below
+// 2^-60.  Tables: H^1..H^{D-1}, then the L correction rows.  Fails when the
+// carry would reach round the whole periodic mesh or past WIN_DMAX chunks.
+bool window_tables(int k, const ld *a, int L, int n, int &D, int &hc, std::vector<double> &out) {
+  const ld eps = std::ldexp((ld)1, -60);
+  std::vector<ld> M(k * k, 0);
+  for (int m = 0; m < k; ++m) M[m] = a[m];
+  for (int i = 1; i < k; ++i) M[i * k + (i - 1)] = 1;
+  auto norm_inf = [&](const std::vector<ld> &A) {
+    ld best = 0;
+    for (int r = 0; r < k; ++r) {
+      ld s = 0;
+      for (int c = 0; c < k; ++c) s += std::fabs(A[r * k + c]);
+      best = std::max(best, s);
+    }
+    return best;
+  };
+  std::vector<ld> H = identity(k);
+  for (int i = 0; i < L; ++i) H = matmul(H, M, k);
+  out.clear();
+  std::vector<ld> P = H;
+  D = 1;
+  while (norm_inf(P) > eps) {
+    for (ld v : P) out.push_back((double)v);
+    P = matmul(P, H, k);
+    if (++D > WIN_DMAX || (int64_t)(D + 1) * L > n) return false;
+  }
+  std::vector<ld> R = M;
+  hc = 0;
+  for (int e = 0; e < L; ++e) {
+    ld s = 0;
+    for (int c = 0; c < k; ++c) {
+      out.push_back((double)R[c]);
+      s += std::fabs(R[c]);
+    }
+    if (s > eps) hc = e + 1;
+    R = matmul(R, M, k);
+  }
+  return true;
+}
+
 // Work distribution: L points per thread (a kernel template parameter).
 Layout choose_layout(int nx, int Lpref) {
   static const int Ls[4] = {16, 8, 4, 2};
@@ -747,6 +793,41 @@ bool attach_solve(StepOp &op, const std::map<int, ld> &taps, const Layout &lay, 
     tabs.insert(tabs.end(), t.begin(), t.end());
   } else {
     offsets.push_back((size_t)-1);
+  }
+  // truncated-carry plan for the windowed kernel: 32 points per thread where
+  // that gives whole wavefronts (MGRIT_WIN_L = 16 or 32 forces one), and
+  // only when both recurrences have a short enough carry
+  op.win_L = 0;
+  const int nx = lay.nx;
+  const int Lenv = env_int("MGRIT_WIN_L", 0);
+  if (env_int("MGRIT_NO_WINDOW", 0) == 0 && op.has_solve && (op.kind == OP_POLY_W || op.kind == OP_SLC)) {
+    for (int Lw : {32, 16}) {
+      if (Lenv && Lw != Lenv) continue;
+      const int nthr = nx / Lw;
+      if (nx != nthr * Lw || nthr % WAVE || nthr > (Lw == 32 ? 512 : 1024) || nthr < WAVE) continue;
+      if (!window_instance(op.kind, F.kf, F.kb, Lw)) continue;
+      std::vector<double> tf, tb;
+      int Df = 1, hf = 0, Db = 1, hb = 0;
+      if (F.kf > 0 && !window_tables(F.kf, F.a, Lw, nx, Df, hf, tf)) continue;
+      if (F.kb > 0 && !window_tables(F.kb, F.b, Lw, nx, Db, hb, tb)) continue;
+      op.win_L = Lw;
+      op.fw.D = Df;
+      op.fw.hc = hf;
+      op.bw.D = Db;
+      op.bw.hc = hb;
+      offsets.push_back(tf.empty() ? (size_t)-1 : tabs.size());
+      tabs.insert(tabs.end(), tf.begin(), tf.end());
+      offsets.push_back(tb.empty() ? (size_t)-1 : tabs.size());
+      tabs.insert(tabs.end(), tb.begin(), tb.end());
+      break;
+    }
+  }
+  if (op.kind == OP_POLY_W) {
+    ld ci = 1;
+    for (int i = 0; i < op.ncoef; ++i) {
+      op.wcoef[i] = (double)((ld)op.coef[i] * ci);
+      ci /= F.C;
+    }
   }
   return true;
 }
@@ -1374,9 +1455,13 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
       Lv.tabs = (double *)(base + o_tab[l]);
       std::memcpy(up.data() + o_tab[l], tabs[l].data(), tabs[l].size() * sizeof(double));
     }
-    if (offs[l].size() == 2) {
+    if (offs[l].size() >= 2) {
       Lv.op.fw.tab = offs[l][0] == none ? nullptr : Lv.tabs + offs[l][0];
       Lv.op.bw.tab = offs[l][1] == none ? nullptr : Lv.tabs + offs[l][1];
+    }
+    if (offs[l].size() >= 4) {
+      Lv.op.fw.wtab = offs[l][2] == none ? nullptr : Lv.tabs + offs[l][2];
+      Lv.op.bw.wtab = offs[l][3] == none ? nullptr : Lv.tabs + offs[l][3];
     }
     Lv.desc = (LevelDesc *)(base + o_desc[l]);
     const LevelDesc hd{Lv.op, Lv.lay};
@@ -1393,9 +1478,13 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
         float *dst = (float *)(up.data() + o_tab32[l]);
         for (size_t i = 0; i < tabs[l].size(); ++i) dst[i] = (float)tabs[l][i];
       }
-      if (offs[l].size() == 2) {
+      if (offs[l].size() >= 2) {
         hd32.op.fw.tab = offs[l][0] == none ? nullptr : Lv.tabs32 + offs[l][0];
         hd32.op.bw.tab = offs[l][1] == none ? nullptr : Lv.tabs32 + offs[l][1];
+      }
+      if (offs[l].size() >= 4) {
+        hd32.op.fw.wtab = offs[l][2] == none ? nullptr : Lv.tabs32 + offs[l][2];
+        hd32.op.bw.wtab = offs[l][3] == none ? nullptr : Lv.tabs32 + offs[l][3];
       }
       Lv.desc32 = (LevelDesc *)(base + o_desc32[l]);
       std::memcpy(up.data() + o_desc32[l], &hd32, sizeof(LevelDesc));
@@ -1461,6 +1550,10 @@ mgrit_status mgrit_level_info(const mgrit_handle *h, int32_t level, mgrit_level_
   out->phi_p = L.phi_p;
   out->phi_q = L.phi_q;
   out->tile_p = (level == 0 && L.tiles) ? L.tg.P : 0;
+  const bool win = window_applies(L.op, L.lay) && !(level >= 1 && lean_slc_applies(L.op, L.lay));
+  out->win_L = win ? L.op.win_L : 0;
+  out->win_D[0] = win && L.op.fw.k > 0 ? L.op.fw.D : 0;
+  out->win_D[1] = win && L.op.bw.k > 0 ? L.op.bw.D : 0;
   return MGRIT_OK;
 }
 
@@ -2693,17 +2786,16 @@ mgrit_status mgrit2d_setup(const mgrit2d_problem *P, const mgrit_options *O, voi
       for (int prec = 0; prec < (mixed ? 2 : 1); ++prec) {
         LevelDesc hd{ln.op, ln.lay};
         const size_t tb = tab_off[2 * l + ax];
-        if (SL.offs.size() == 2) {
-          if (prec == 0) {
-            const double *d = (const double *)(base + o_tabs);
-            hd.op.fw.tab = SL.offs[0] == (size_t)-1 ? nullptr : d + tb + SL.offs[0];
-            hd.op.bw.tab = SL.offs[1] == (size_t)-1 ? nullptr : d + tb + SL.offs[1];
-          } else {
-            const float *d = (const float *)(base + o_tabs32);
-            hd.op.fw.tab = SL.offs[0] == (size_t)-1 ? nullptr : d + tb + SL.offs[0];
-            hd.op.bw.tab = SL.offs[1] == (size_t)-1 ? nullptr : d + tb + SL.offs[1];
-          }
-        }
+        // the level's tables: scan tables, then (when present) the windowed plan's
+        auto tab_at = [&](size_t i) -> const void * {
+          if (i >= SL.offs.size() || SL.offs[i] == (size_t)-1) return nullptr;
+          if (prec == 0) return (const double *)(base + o_tabs) + tb + SL.offs[i];
+          return (const float *)(base + o_tabs32) + tb + SL.offs[i];
+        };
+        hd.op.fw.tab = tab_at(0);
+        hd.op.bw.tab = tab_at(1);
+        hd.op.fw.wtab = tab_at(2);
+        hd.op.bw.wtab = tab_at(3);
         LevelDesc *dd = (LevelDesc *)(base + o_desc) + di++;
         (prec == 0 ? ln.desc : ln.desc32) = dd;
         std::memcpy(up.data() + ((char *)dd - base), &hd, sizeof(LevelDesc));

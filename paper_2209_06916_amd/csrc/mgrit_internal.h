@@ -43,7 +43,16 @@ struct Recurrence {
   int k;
   double a[KMAX];
   const void *tab;  // the tables in the precision of the kernels that read them
+  // Truncated-carry evaluation (the windowed step kernel, mgrit_window.h):
+  // the state entering a chunk is the sum over the D chunks before it of
+  // H^d (their zero-state end states), H = M^{win_L}; the first hc points of
+  // a chunk take the homogeneous correction.  wtab: [D-1][k][k] H^d
+  // (d = 1..D-1), then [win_L][k] row 0 of M^{e+1}, in the kernels' precision.
+  int D;
+  int hc;
+  const void *wtab;
 };
+constexpr int WIN_DMAX = 12;  // longest carry the windowed kernel accepts
 
 struct StepOp {
   int kind;
@@ -60,6 +69,11 @@ struct StepOp {
   int has_solve;          // T != I
   double cinv;            // 1/C of the factorisation
   Recurrence fw, bw;
+  // windowed step kernel (0: not available): points per thread, nx = threads
+  // * win_L; OP_POLY_W takes Horner coefficients in G = B^{-1} F^{-1}
+  // (wcoef[i] = coef[i] / C^i), OP_SLC folds 1/C into the interpolation weights
+  int win_L;
+  double wcoef[MAXCOEF];
 };
 
 // Work distribution of one nx-vector over a workgroup.
@@ -348,6 +362,54 @@ size_t coarse_vcycle_lds(const StepOp &op, const Layout &lay, int nlevels);
 int coarse_vcycle_max_grid(const StepOp &op, const Layout &lay, size_t lds);
 hipError_t launch_coarse_vcycle(const CoarsePlan &plan, const StepOp &op, const Layout &lay, int64_t grid,
                                 size_t lds, GridSync *gs, const int *stop, hipStream_t stream);
+
+// LDS of the windowed step kernel (in elements of the kernel's precision;
+// red in doubles): OP_SLC's padded vector, two areas of published
+// recurrence states and the reduction scratch.  When they do not fit beside
+// the vector (nx = 16384 in float64) the states reuse the vector's words.
+struct WinLds {
+  int pub0, pub1, red, bytes, alias;
+};
+constexpr __host__ __device__ inline WinLds win_lds(int kind, int nx, int nt, int kw, int wsize) {
+  WinLds o{};
+  const int pv = kind == OP_SLC ? nx + (nx >> 4) + 1 : 0;
+  const int pubn = nt * kw;
+  int end = pv + 2 * pubn;
+  if (kind == OP_SLC && (size_t)(end * wsize + 8) / 8 * 8 + MAXWAVES * 8 > 160 * 1024) {
+    o.alias = 1;
+    end = pv;
+    o.pub0 = 0;
+    o.pub1 = pubn;
+  } else {
+    o.pub0 = pv;
+    o.pub1 = pv + pubn;
+  }
+  o.red = (end * wsize + 7) / 8;  // in doubles
+  o.bytes = (o.red + MAXWAVES) * 8;
+  return o;
+}
+
+// The windowed step kernel (mgrit_window.h): OP_POLY_W and OP_SLC operators
+// whose recurrences have a truncated-carry plan (op.win_L > 0).
+// Instances: SDIRK stage matrices of the odd upwind orders (recurrence orders
+// (1,0), (2,1), (3,2)), symmetric coarse operators (k, k), k = 1..3; 16 or
+// 32 points per thread.
+inline bool window_instance(int kind, int kf, int kb, int L) {
+  const bool orders = kind == OP_POLY_W ? (kf >= 1 && kf <= 3 && kb == kf - 1)
+                                        : (kind == OP_SLC && kf >= 1 && kf <= 3 && kb == kf);
+  return orders && (L == 16 || L == 32);
+}
+inline bool window_applies(const StepOp &op, const Layout &lay) {
+  if (op.win_L <= 0 || !op.has_solve || !window_instance(op.kind, op.fw.k, op.bw.k, op.win_L)) return false;
+  const int nt = lay.nx / op.win_L;
+  return lay.nx == nt * op.win_L && nt % WAVE == 0 && nt <= 1024 && (op.win_L == 16 || nt <= 512);
+}
+hipError_t launch_window(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs &pa,
+                         hipStream_t stream);
+hipError_t launch_window32(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs32 &pa,
+                           hipStream_t stream);
+hipError_t configure_window_kernels64(size_t bytes);
+hipError_t configure_window_kernels32(size_t bytes);
 
 // The lean coarse-step kernel (mgrit_lean.hip) for layouts where
 // lean_slc_applies() holds, and its LDS attribute.

@@ -124,6 +124,8 @@ size_t lds_bytes_for(const Layout &lay, int has_solve) {
 hipError_t configure_kernels(size_t bytes) {
   hipError_t e;
   if ((e = configure_lean_kernels(bytes))) return e;
+  if ((e = configure_window_kernels64(bytes))) return e;
+  if ((e = configure_window_kernels32(bytes))) return e;
   if ((e = configure_step_poly_z(bytes))) return e;
   if ((e = configure_step_poly_w(bytes))) return e;
   if ((e = configure_step_slc(bytes))) return e;
@@ -135,6 +137,7 @@ hipError_t configure_kernels(size_t bytes) {
 hipError_t launch_pass32(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs32 &pa,
                          hipStream_t stream) {
   if (pa.nint <= 0) return hipSuccess;
+  if (window_applies(op, lay)) return launch_window32(desc, op, lay, pa, stream);
   const size_t lds = lds_bytes_for(lay, op.has_solve);
   switch (op.kind) {
     case OP_POLY_Z: return launch_step32_poly_z(desc, lay, pa, lds, stream);
@@ -166,6 +169,7 @@ hipError_t launch_pass(const LevelDesc *desc, const StepOp &op, const Layout &la
                        hipStream_t stream) {
   if (pa.nint <= 0) return hipSuccess;
   if (lean_slc_applies(op, lay)) return launch_lean(desc, op, lay, pa, stream);
+  if (window_applies(op, lay)) return launch_window(desc, op, lay, pa, stream);
   const size_t lds = lds_bytes_for(lay, op.has_solve);
   switch (op.kind) {
     case OP_POLY_Z: return launch_step_poly_z(desc, lay, pa, lds, stream);

@@ -637,11 +637,16 @@ hipError_t slc_set_lds(size_t bytes) {
   MGRIT_LEAN_SHAPES(MGRIT_SLC_LDS, 6, 3)
 #undef MGRIT_SLC_LDS
   // The persistent coarse cycle's instances get the same process-wide limit
-  // here, once, so that no later setup changes it while launches are in flight.
+  // (less their static LDS) here, once, so that no later setup changes it
+  // while launches are in flight.
 #define MGRIT_CV_LDS(Wv, Kv, Lv, NWv)                                                                       \
-  if (e == hipSuccess)                                                                                     \
-    e = hipFuncSetAttribute((const void *)coarse_vcycle_kernel<Wv, Kv, Lv, NWv>,                           \
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) {                                                                                   \
+    hipFuncAttributes fa{};                                                                                \
+    e = hipFuncGetAttributes(&fa, (const void *)coarse_vcycle_kernel<Wv, Kv, Lv, NWv>);                    \
+    if (e == hipSuccess)                                                                                   \
+      e = hipFuncSetAttribute((const void *)coarse_vcycle_kernel<Wv, Kv, Lv, NWv>,                         \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)(bytes - fa.sharedSizeBytes)); \
+  }
   MGRIT_LEAN_SHAPES(MGRIT_CV_LDS, 2, 1)
   MGRIT_LEAN_SHAPES(MGRIT_CV_LDS, 4, 2)
   MGRIT_LEAN_SHAPES(MGRIT_CV_LDS, 6, 3)

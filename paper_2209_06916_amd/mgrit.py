@@ -59,7 +59,8 @@ class Problem2D(ctypes.Structure):
 class LevelDesc(ctypes.Structure):
     _fields_ = [("nt", ctypes.c_int64), ("m", ctypes.c_int32), ("shift", ctypes.c_double),
                 ("K", ctypes.c_int64), ("eps", ctypes.c_double), ("phi_p", ctypes.c_double),
-                ("phi_q", ctypes.c_double), ("tile_p", ctypes.c_int32)]
+                ("phi_q", ctypes.c_double), ("tile_p", ctypes.c_int32), ("win_L", ctypes.c_int32),
+                ("win_D", ctypes.c_int32 * 2)]
 
 
 PROF_PHASES = ["fine_relax", "coarse", "final", "sequential", "residual", "other"]
@@ -237,7 +238,8 @@ class Solver:
     def level_info(self, level):
         d = LevelDesc()
         self._check(lib().mgrit_level_info(self.h, level, ctypes.byref(d)))
-        return dict(nt=d.nt, m=d.m, shift=d.shift, K=d.K, eps=d.eps, phi_p=d.phi_p, phi_q=d.phi_q, tile_p=d.tile_p)
+        return dict(nt=d.nt, m=d.m, shift=d.shift, K=d.K, eps=d.eps, phi_p=d.phi_p, phi_q=d.phi_q, tile_p=d.tile_p,
+                    win_L=d.win_L, win_D=(d.win_D[0], d.win_D[1]))
 
     def solve(self, u0, v_init=None, u_out=None, u_final=None, history_cap=128,
               allow=(OK, ENOTCONVERGED)):

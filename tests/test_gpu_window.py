@@ -1,0 +1,157 @@
+"""GPU parity of the windowed step kernel (periodic banded solves by truncated
+carries) against the FP64 oracle, and against the exact workgroup-scan
+kernel it replaces, at the sizes where setup selects it: nx a multiple of
+1024 (16 points per thread) or 2048 (32), SDIRK steps with U1/U3/U5 stage
+matrices (Sec. 4.3) and corrected semi-Lagrangian coarse steps at nx = 16384
+(eq. MOL-SL-corrected-multilevel).
+
+Tolerances as in test_gpu_parity: single operator applications elementwise
+at 1e-13 of the vector's max-norm; full solves with identical iteration
+counts, <= 1e-12 per time point and residual histories within 1e-8.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import discretization as disc
+from oracle import mgrit as omg
+from paper_2209_06916_amd import inputs, mgrit
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _announce(*args):
+    print("CASE", *args, flush=True)
+
+
+# (nx, p, q, c, forced points per thread or 0)
+FINE = [
+    (16384, 5, 3, 0.5, 0), (16384, 5, 3, 0.5, 16), (8192, 3, 3, 1.0, 0), (4096, 1, 1, 1.0, 0),
+    (2048, 3, 3, 5.0, 16), (1024, 3, 3, 5.0, 0), (4096, 5, 2, 0.8, 0), (2048, 1, 3, 0.3, 32),
+]
+
+
+@pytest.mark.parametrize("nx,p,q,c,L", FINE)
+def test_windowed_sdirk_steps_match_oracle_and_scan(monkeypatch, nx, p, q, c, L):
+    _announce("window fine", nx, p, q, c, L)
+    if L:
+        monkeypatch.setenv("MGRIT_WIN_L", str(L))
+    rng = np.random.default_rng(nx + 7 * p + q)
+    v = rng.standard_normal((3, nx))
+    s = mgrit.Solver(mgrit.make_problem(nx, 8, c, p, "sdirk", q), mgrit.make_options(2, coarse="ideal"))
+    info = s.level_info(0)
+    assert info["win_L"] == (L or (32 if (nx // 32) % 64 == 0 else 16)), info
+    assert info["win_D"][0] >= 1 and (info["win_D"][1] >= 1) == (p > 1)
+    out = torch.empty((3, nx), dtype=torch.float64, device=DEV)
+    s.apply_step(0, _t(v), out, 4)
+    got = _np(out)
+    step = disc.MOLStep(p, "sdirk", q, c)
+    ref = v.copy()
+    for _ in range(4):
+        ref = step(ref)
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(got - ref)) <= 1e-13 * scale * max(1.0, c)
+    # the exact-scan kernel on the same input
+    monkeypatch.setenv("MGRIT_NO_WINDOW", "1")
+    g = mgrit.Solver(mgrit.make_problem(nx, 8, c, p, "sdirk", q), mgrit.make_options(2, coarse="ideal"))
+    assert g.level_info(0)["win_L"] == 0
+    out2 = torch.empty_like(out)
+    g.apply_step(0, _t(v), out2, 4)
+    assert np.max(np.abs(_np(out2) - got)) <= 1e-13 * scale * max(1.0, c)
+
+
+def test_slow_decay_falls_back_to_the_scan():
+    """SDIRK1 + U1 at CFL 5 on 1024 points: the causal recurrence decays by
+    0.83 per point, so no carry of at most 12 chunks is exact; the scan
+    kernel runs and still matches the oracle."""
+    _announce("window fallback")
+    nx, c = 1024, 5.0
+    s = mgrit.Solver(mgrit.make_problem(nx, 8, c, 1, "sdirk", 1), mgrit.make_options(2, coarse="ideal"))
+    assert s.level_info(0)["win_L"] == 0
+    v = np.random.default_rng(3).standard_normal((2, nx))
+    out = torch.empty((2, nx), dtype=torch.float64, device=DEV)
+    s.apply_step(0, _t(v), out, 2)
+    step = disc.MOLStep(1, "sdirk", 1, c)
+    ref = step(step(v))
+    assert np.max(np.abs(_np(out) - ref)) <= 1e-13 * np.max(np.abs(ref)) * c
+
+
+@pytest.mark.parametrize("p,kind,q,c,ms", [(5, "sdirk", 3, 0.5, [16, 16, 4]), (3, "erk", 3, 0.85, [8, 8]),
+                                           (1, "erk", 1, 0.85, [4, 4])])
+def test_windowed_coarse_steps_match_oracle(p, kind, q, c, ms):
+    """Coarse levels at nx = 16384 (beyond the lean kernel's shapes): the
+    corrected semi-Lagrangian step with a windowed solve wherever its
+    recurrences decay fast enough, against the oracle's FFT solve."""
+    nx = 16384
+    _announce("window coarse", p, kind, q, c, ms)
+    nt = int(np.prod(ms)) * 2
+    s = mgrit.Solver(mgrit.make_problem(nx, nt, c, p, kind, q), mgrit.make_options(ms, max_levels=len(ms) + 1))
+    recs = disc.correction_coefficients(p, kind, q, c, ms)
+    v = np.random.default_rng(p + nt).standard_normal((2, nx))
+    windowed = 0
+    for lev, rec in enumerate(recs, start=1):
+        windowed += s.level_info(lev)["win_L"] > 0
+        out = torch.empty((2, nx), dtype=torch.float64, device=DEV)
+        s.apply_step(lev, _t(v), out, 3)
+        psi = disc.CorrectedSLStep(p, q, rec["shift"], rec["phi_p"], rec["phi_q"])
+        ref = psi(psi(psi(v)))
+        assert np.max(np.abs(_np(out) - ref)) <= 1e-13 * np.max(np.abs(ref)) * max(1.0, abs(rec["phi_p"])), lev
+    assert windowed >= 1
+
+
+def _solve_both(nx, nt, p, kind, q, c, ms, seed):
+    u0 = inputs.u0_fourier(nx, seed)
+    v0 = inputs.initial_iterate(nt, nx, u0, seed)
+    s = mgrit.Solver(mgrit.make_problem(nx, nt, c, p, kind, q), mgrit.make_options(ms, max_levels=len(ms) + 1))
+    out = torch.empty((nt + 1, nx), dtype=torch.float64, device=DEV)
+    info = s.solve(_t(u0), _t(v0), u_out=out)
+    H = omg.Hierarchy(nx, nt, p, kind, q, c, ms)
+    ref, rinfo = omg.solve(H, u0, v0)
+    return s, info, _np(out), ref, rinfo
+
+
+@pytest.mark.parametrize("case", [
+    dict(nx=2048, nt=256, p=5, kind="sdirk", q=3, c=0.5, ms=[16, 4]),
+    dict(nx=1024, nt=256, p=1, kind="sdirk", q=1, c=1.0, ms=[4, 4, 4]),
+    dict(nx=4096, nt=64, p=3, kind="sdirk", q=3, c=5.0, ms=[8]),
+    dict(nx=16384, nt=32, p=3, kind="erk", q=3, c=0.85, ms=[4, 4]),
+    dict(nx=16384, nt=64, p=5, kind="sdirk", q=3, c=0.5, ms=[16, 4]),
+])
+def test_windowed_full_solves_match_oracle(case):
+    _announce("window solve", case)
+    s, info, got, ref, rinfo = _solve_both(case["nx"], case["nt"], case["p"], case["kind"], case["q"], case["c"],
+                                           case["ms"], seed=1100 + case["nx"] % 97)
+    assert any(s.level_info(l)["win_L"] > 0 for l in range(s.num_levels))
+    assert info["iterations"] == rinfo["iterations"]
+    np.testing.assert_allclose(info["res_history"], rinfo["res_history"], rtol=1e-8,
+                               atol=1e-14 * rinfo["res_history"][0])
+    per_t = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert np.max(per_t) <= 1e-12, np.max(per_t)
+
+
+def test_windowed_mixed_precision_matches_oracle():
+    """Float32 instances in the inner solves: 2048 x 256, SDIRK3 + U5, c = 0.5."""
+    nx, nt, ms = 2048, 256, [16, 4]
+    _announce("window mixed")
+    u0 = inputs.u0_fourier(nx, 1201)
+    v0 = inputs.initial_iterate(nt, nx, u0, 1201)
+    s = mgrit.Solver(mgrit.make_problem(nx, nt, 0.5, 5, "sdirk", 3),
+                     mgrit.make_options(ms, max_levels=3, precision="mixed", rtol=1e-12))
+    assert s.level_info(0)["win_L"] > 0
+    out = torch.empty((nt + 1, nx), dtype=torch.float64, device=DEV)
+    info = s.solve(_t(u0), _t(v0), u_out=out)
+    assert info["status"] == mgrit.OK
+    seq = omg.sequential(disc.MOLStep(5, "sdirk", 3, 0.5), u0, nt)
+    err = np.linalg.norm(_np(out) - seq) / np.linalg.norm(seq)
+    assert err <= 1e-10, err
