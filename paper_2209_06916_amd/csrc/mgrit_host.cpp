@@ -480,11 +480,10 @@ void recurrence_tables(int k, const ld *a, const Layout &lay, std::vector<double
 // points in chunks of L (the windowed step kernel).  H = M^L: the state
 // entering a chunk is sum_{d < D} H^d Z_{t-1-d} up to H^D E, so D is the
 // first power with ||H^D||_inf <= 2^-60 (the error relative to max |y|, well
-// below float64 rounding); the correction of point e of a chunk is row 0 of
-// M^{e+1} times the carry, and hc ends where the rows' 1-norms fall below
-// 2^-60.  Tables: H^1..H^{D-1}, then the L correction rows.  Fails when the
-// carry would reach round the whole periodic mesh or past WIN_DMAX chunks.
-bool window_tables(int k, const ld *a, int L, int n, int &D, int &hc, std::vector<double> &out) {
+// below float64 rounding).  Tables: H^1..H^{D-1}, then M^{L/2} (the kernel
+// runs the two halves of a chunk as separate chains).  Fails when the carry
+// would reach round the whole periodic mesh or past WIN_DMAX chunks.
+bool window_tables(int k, const ld *a, int L, int n, int &D, std::vector<double> &out) {
   const ld eps = std::ldexp((ld)1, -60);
   std::vector<ld> M(k * k, 0);
   for (int m = 0; m < k; ++m) M[m] = a[m];
@@ -508,17 +507,9 @@ bool window_tables(int k, const ld *a, int L, int n, int &D, int &hc, std::vecto
     P = matmul(P, H, k);
     if (++D > WIN_DMAX || (int64_t)(D + 1) * L > n) return false;
   }
-  std::vector<ld> R = M;
-  hc = 0;
-  for (int e = 0; e < L; ++e) {
-    ld s = 0;
-    for (int c = 0; c < k; ++c) {
-      out.push_back((double)R[c]);
-      s += std::fabs(R[c]);
-    }
-    if (s > eps) hc = e + 1;
-    R = matmul(R, M, k);
-  }
+  std::vector<ld> G = identity(k);
+  for (int i = 0; i < L / 2; ++i) G = matmul(G, M, k);
+  for (ld v : G) out.push_back((double)v);
   return true;
 }
 
@@ -795,26 +786,25 @@ bool attach_solve(StepOp &op, const std::map<int, ld> &taps, const Layout &lay, 
     offsets.push_back((size_t)-1);
   }
   // truncated-carry plan for the windowed kernel: 32 points per thread where
-  // that gives whole wavefronts (MGRIT_WIN_L = 16 or 32 forces one), and
-  // only when both recurrences have a short enough carry
+  // that still gives at least 256 threads, else 16 (MGRIT_WIN_L = 16 or 32
+  // forces one), and only when both recurrences have a short enough carry
   op.win_L = 0;
   const int nx = lay.nx;
   const int Lenv = env_int("MGRIT_WIN_L", 0);
   if (env_int("MGRIT_NO_WINDOW", 0) == 0 && op.has_solve && (op.kind == OP_POLY_W || op.kind == OP_SLC)) {
     for (int Lw : {32, 16}) {
-      if (Lenv && Lw != Lenv) continue;
+      if (Lenv ? Lw != Lenv : (Lw == 32 && nx < 32 * 256)) continue;
       const int nthr = nx / Lw;
       if (nx != nthr * Lw || nthr % WAVE || nthr > (Lw == 32 ? 512 : 1024) || nthr < WAVE) continue;
       if (!window_instance(op.kind, F.kf, F.kb, Lw)) continue;
+      if (op.kind == OP_SLC && op.sl_l + op.sl_r + 1 != 2 * F.kf) continue;
       std::vector<double> tf, tb;
-      int Df = 1, hf = 0, Db = 1, hb = 0;
-      if (F.kf > 0 && !window_tables(F.kf, F.a, Lw, nx, Df, hf, tf)) continue;
-      if (F.kb > 0 && !window_tables(F.kb, F.b, Lw, nx, Db, hb, tb)) continue;
+      int Df = 1, Db = 1;
+      if (F.kf > 0 && !window_tables(F.kf, F.a, Lw, nx, Df, tf)) continue;
+      if (F.kb > 0 && !window_tables(F.kb, F.b, Lw, nx, Db, tb)) continue;
       op.win_L = Lw;
       op.fw.D = Df;
-      op.fw.hc = hf;
       op.bw.D = Db;
-      op.bw.hc = hb;
       offsets.push_back(tf.empty() ? (size_t)-1 : tabs.size());
       tabs.insert(tabs.end(), tf.begin(), tf.end());
       offsets.push_back(tb.empty() ? (size_t)-1 : tabs.size());

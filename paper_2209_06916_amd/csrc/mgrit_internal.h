@@ -45,11 +45,9 @@ struct Recurrence {
   const void *tab;  // the tables in the precision of the kernels that read them
   // Truncated-carry evaluation (the windowed step kernel, mgrit_window.h):
   // the state entering a chunk is the sum over the D chunks before it of
-  // H^d (their zero-state end states), H = M^{win_L}; the first hc points of
-  // a chunk take the homogeneous correction.  wtab: [D-1][k][k] H^d
-  // (d = 1..D-1), then [win_L][k] row 0 of M^{e+1}, in the kernels' precision.
+  // H^d (their zero-state end states), H = M^{win_L}.  wtab: [D-1][k][k] H^d
+  // (d = 1..D-1), then M^{win_L/2}, in the kernels' precision.
   int D;
-  int hc;
   const void *wtab;
 };
 constexpr int WIN_DMAX = 12;  // longest carry the windowed kernel accepts
@@ -370,9 +368,9 @@ hipError_t launch_coarse_vcycle(const CoarsePlan &plan, const StepOp &op, const 
 struct WinLds {
   int pub0, pub1, red, bytes, alias;
 };
-constexpr __host__ __device__ inline WinLds win_lds(int kind, int nx, int nt, int kw, int wsize) {
+constexpr __host__ __device__ inline WinLds win_lds(int kind, int nx, int nt, int kw, int wsize, int L) {
   WinLds o{};
-  const int pv = kind == OP_SLC ? nx + (nx >> 4) + 1 : 0;
+  const int pv = kind == OP_SLC ? nx + nx / L + 1 : 0;
   const int pubn = nt * kw;
   int end = pv + 2 * pubn;
   if (kind == OP_SLC && (size_t)(end * wsize + 8) / 8 * 8 + MAXWAVES * 8 > 160 * 1024) {
@@ -401,6 +399,7 @@ inline bool window_instance(int kind, int kf, int kb, int L) {
 }
 inline bool window_applies(const StepOp &op, const Layout &lay) {
   if (op.win_L <= 0 || !op.has_solve || !window_instance(op.kind, op.fw.k, op.bw.k, op.win_L)) return false;
+  if (op.kind == OP_SLC && op.sl_l + op.sl_r + 1 != 2 * op.fw.k) return false;  // the gather has 2k taps
   const int nt = lay.nx / op.win_L;
   return lay.nx == nt * op.win_L && nt % WAVE == 0 && nt <= 1024 && (op.win_L == 16 || nt <= 512);
 }

@@ -353,7 +353,7 @@ __device__ __forceinline__ void apply_step(T (&u)[L], int cnt, const OpRegs<T> &
 // The chain of time steps of one pass (see PassMode): load the start vector,
 // advance it step by step with step(u) (all threads together), and do the
 // mode's per-step and final memory work.  cnt: points of this thread.
-template <int L, class T, class Step>
+template <int L, class T, int PREFETCH = (L <= 16 ? 3 : 0), class Step>
 __device__ __forceinline__ void run_chain(const PassArgsT<T> &pa, int nx, int cnt, double *red, Step step) {
   const int tid = threadIdx.x;
   const int base = tid * L;
@@ -394,22 +394,21 @@ __device__ __forceinline__ void run_chain(const PassArgsT<T> &pa, int nx, int cn
     store_chunk<L>(pa.parent + (b * m) * nxl, base, cnt, pv);
   }
 
-  // the chain of time steps (single call site of the step); for short chunks
-  // the rows this step adds are loaded before the step so their latency
-  // overlaps it
-  constexpr bool PREFETCH = L <= 16;
+  // the chain of time steps (single call site of the step); the rows this
+  // step adds are loaded before the step so their latency overlaps it where
+  // PREFETCH says so (bit 0: right-hand side, bit 1: parent; by default for
+  // short chunks)
+  constexpr bool PRE_G = PREFETCH & 1, PRE_P = PREFETCH & 2;
   for (int j = 1; j <= nsteps; ++j) {
     const int64_t n = (mode == MODE_SEQ) ? (int64_t)j : b * m + j;  // level point index
-    T gv[PREFETCH ? L : 1], pv[PREFETCH ? L : 1];
-    if (PREFETCH) {
-      if (add_g) load_chunk<PREFETCH ? L : 1>(pa.g + (n - 1) * nxl, base, cnt, gv);
-      if (add_parent) load_chunk<PREFETCH ? L : 1>(pa.parent + n * nxl, base, cnt, pv);
-    }
+    T gv[PRE_G ? L : 1], pv[PRE_P ? L : 1];
+    if (PRE_G && add_g) load_chunk<PRE_G ? L : 1>(pa.g + (n - 1) * nxl, base, cnt, gv);
+    if (PRE_P && add_parent) load_chunk<PRE_P ? L : 1>(pa.parent + n * nxl, base, cnt, pv);
     step(u);
     if (add_g) {
-      if (PREFETCH) {
+      if (PRE_G) {
 #pragma unroll
-        for (int q = 0; q < (PREFETCH ? L : 1); ++q) u[q] += gv[q];
+        for (int q = 0; q < (PRE_G ? L : 1); ++q) u[q] += gv[q];
       } else {
         const T *gr = pa.g + (n - 1) * nxl + base;
 #pragma unroll
@@ -419,10 +418,10 @@ __device__ __forceinline__ void run_chain(const PassArgsT<T> &pa, int nx, int cn
     }
     if (add_parent) {
       T *pr = pa.parent + n * nxl + base;
-      if (PREFETCH) {
+      if (PRE_P) {
 #pragma unroll
-        for (int q = 0; q < (PREFETCH ? L : 1); ++q) pv[q] += u[q];
-        store_chunk<PREFETCH ? L : 1>(pa.parent + n * nxl, base, cnt, pv);
+        for (int q = 0; q < (PRE_P ? L : 1); ++q) pv[q] += u[q];
+        store_chunk<PRE_P ? L : 1>(pa.parent + n * nxl, base, cnt, pv);
       } else {
 #pragma unroll
         for (int q = 0; q < L; ++q)

@@ -12,11 +12,12 @@
 // Z the chunks' zero-state end states and M the companion matrix; when
 // ||H^D|| is below rounding (checked on the host in extended precision) the
 // first D terms are the state to rounding.  A recurrence then costs a
-// zero-state pass over the chunk, one workgroup barrier after the end states
-// are published in LDS, the D-term carry and a correction over the first hc
-// points of the chunk (the homogeneous response, row 0 of M^{e+1} times the
-// carry, through the scalar cache).  No wavefront scan and no single-thread
-// fold; the carry and correction matrices are wave-uniform.
+// zero-state pass over the chunk that only keeps its end state, one
+// workgroup barrier after the end states are published in LDS, the D-term
+// carry (wave-uniform matrices through the scalar cache), and the pass over
+// the chunk again from the exact entering state.  No wavefront scan, no
+// single-thread fold, no per-point tables.  Both passes run the two halves
+// of a chunk as independent chains.
 //
 // The layout is nx = NT * L exactly (every chunk full); thread t owns points
 // [tL, tL + L).
@@ -26,8 +27,7 @@ template <int K, class T>
 struct WinDir {
   T a[K > 0 ? K : 1];
   int D;            // predecessor chunks in the carry
-  int hc;           // corrected points per chunk
-  ConstPtr<T> tab;  // [D-1][K][K] H^d, d = 1..D-1, then [L][K] row 0 of M^{e+1}
+  ConstPtr<T> tab;  // [D-1][K][K] H^d, d = 1..D-1, then [K][K] M^{L/2}
 };
 
 template <int K, class T>
@@ -35,34 +35,71 @@ __device__ __forceinline__ void win_dir_load(WinDir<K, T> &W, const Recurrence &
 #pragma unroll
   for (int m = 0; m < (K > 0 ? K : 1); ++m) W.a[m] = (T)rc.a[m < KMAX ? m : 0];
   W.D = rc.D;
-  W.hc = rc.hc;
   W.tab = (ConstPtr<T>)rc.wtab;
+}
+
+// The recurrence over the two halves of a chunk at once, each from its own
+// state (sa: entering the first half in processing order, sb: the second;
+// s[m] is the value m+1 places back): two independent chains interleaved.
+// STORE: overwrite x with the result.
+template <int L, int K, bool REV, bool STORE, class T>
+__device__ __forceinline__ void win_pass2(T (&x)[L], const T (&a)[K], T (&sa)[K], T (&sb)[K]) {
+  constexpr int H = L / 2;
+#pragma unroll
+  for (int e = 0; e < H; ++e) {
+    const int ja = REV ? (L - 1 - e) : e;
+    const int jb = REV ? (H - 1 - e) : (H + e);
+    T va = x[ja], vb = x[jb];
+#pragma unroll
+    for (int m = K - 1; m >= 0; --m) {
+      va = fma(a[m], sa[m], va);
+      vb = fma(a[m], sb[m], vb);
+    }
+#pragma unroll
+    for (int m = K - 1; m > 0; --m) {
+      sa[m] = sa[m - 1];
+      sb[m] = sb[m - 1];
+    }
+    sa[0] = va;
+    sb[0] = vb;
+    if (STORE) {
+      x[ja] = va;
+      x[jb] = vb;
+    }
+  }
+}
+
+// acc += A x (A row-major K x K, wave-uniform)
+template <int K, class T>
+__device__ __forceinline__ void win_mv(ConstPtr<T> A, const T (&x)[K], T (&acc)[K]) {
+#pragma unroll
+  for (int r = 0; r < K; ++r) {
+    T v = acc[r];
+#pragma unroll
+    for (int c = 0; c < K; ++c) v = fma(A[r * K + c], x[c], v);
+    acc[r] = v;
+  }
 }
 
 // One periodic recurrence over the workgroup's chunks (REV: the anti-causal
 // one, processing each chunk from its last point and taking the carry from
 // the following chunks).  pub: LDS words for the NT published end states.
+// The halves of a chunk run as two chains: the chunk's zero-state end state
+// is Z_b + G Z_a, and the state entering the second half is Z_a + G E, with
+// G = M^{L/2} and Z_a, Z_b the halves' zero-state end states.
 template <int L, int K, bool REV, class T>
 __device__ __forceinline__ void win_rec(T (&y)[L], const WinDir<K, T> &W, T *pub, int tid, int NT) {
-  // 1. zero-state pass; s[m] = y of the point m+1 places back in processing order
-  T s[K];
+  const ConstPtr<T> G = W.tab + (W.D - 1) * K * K;
+  // 1. end state of the chunk from a zero state
+  T za[K], zb[K];
 #pragma unroll
-  for (int m = 0; m < K; ++m) s[m] = T(0);
+  for (int m = 0; m < K; ++m) za[m] = zb[m] = T(0);
+  win_pass2<L, K, REV, false>(y, W.a, za, zb);
+  win_mv<K>(G, za, zb);
+  // 2. publish it, then sum the carry from the D chunks before this one in
+  //    processing order (periodic in the thread index)
 #pragma unroll
-  for (int e = 0; e < L; ++e) {
-    const int j = REV ? (L - 1 - e) : e;
-    T v = y[j];
-#pragma unroll
-    for (int m = K - 1; m >= 0; --m) v = fma(W.a[m], s[m], v);
-#pragma unroll
-    for (int m = K - 1; m > 0; --m) s[m] = s[m - 1];
-    s[0] = v;
-    y[j] = v;
-  }
-  // 2. publish the end state, then gather the carry from the D chunks before
-  //    this one in processing order (periodic in the thread index)
-#pragma unroll
-  for (int m = 0; m < K; ++m) pub[tid * K + m] = s[m];
+  for (int m = 0; m < K; ++m) pub[tid * K + m] = zb[m];
   __syncthreads();
   int src = REV ? (tid + 1 == NT ? 0 : tid + 1) : (tid == 0 ? NT - 1 : tid - 1);
   T E[K];
@@ -73,26 +110,47 @@ __device__ __forceinline__ void win_rec(T (&y)[L], const WinDir<K, T> &W, T *pub
     T z[K];
 #pragma unroll
     for (int m = 0; m < K; ++m) z[m] = pub[src * K + m];
-    const ConstPtr<T> Hd = W.tab + (d - 1) * K * K;
-#pragma unroll
-    for (int r = 0; r < K; ++r) {
-      T acc = E[r];
-#pragma unroll
-      for (int c = 0; c < K; ++c) acc = fma(Hd[r * K + c], z[c], acc);
-      E[r] = acc;
-    }
+    win_mv<K>(W.tab + (d - 1) * K * K, z, E);
   }
-  // 3. homogeneous correction of the first hc points
-  const ConstPtr<T> C = W.tab + (W.D - 1) * K * K;
+  // 3. the chunk again from the exact entering states of its halves
+  win_mv<K>(G, E, za);
+  win_pass2<L, K, REV, true>(y, W.a, E, za);
+}
+
+// The padded LDS vector of OP_SLC steps: one pad word after every L points,
+// so that the chunks of consecutive threads start in different banks.
+template <int L>
+__device__ __forceinline__ int win_pad(int i) {
+  return i + i / L;
+}
+
+// out[j] += sum_{t < W} w[t] * v[start + j + t] (indices periodic,
+// 0 <= start < nx) from the padded LDS vector; each value is read once and
+// scattered into the outputs it feeds.
+template <int L, int W, class T>
+__device__ __forceinline__ void win_gather(const T *vec, int start, int nx, const T (&w)[MAXTAPS], T (&out)[L]) {
+  if (start + L + W - 1 <= nx) {
 #pragma unroll
-  for (int e = 0; e < L; ++e) {
-    if (e < W.hc) {  // uniform
-      const int j = REV ? (L - 1 - e) : e;
-      T v = y[j];
+    for (int e = 0; e < L + W - 1; ++e) {
+      const T v = vec[win_pad<L>(start + e)];
 #pragma unroll
-      for (int m = 0; m < K; ++m) v = fma(C[e * K + m], E[m], v);
-      y[j] = v;
+      for (int t = 0; t < W; ++t) {
+        const int j = e - t;
+        if (j >= 0 && j < L) out[j] = fma(w[t], v, out[j]);
+      }
     }
+    return;
+  }
+  int idx = start;
+#pragma unroll
+  for (int e = 0; e < L + W - 1; ++e) {
+    const T v = vec[win_pad<L>(idx)];
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+      const int j = e - t;
+      if (j >= 0 && j < L) out[j] = fma(w[t], v, out[j]);
+    }
+    idx = next_periodic(idx, nx);
   }
 }
 
@@ -101,15 +159,15 @@ template <int KF, int KB, class T>
 struct WinOp {
   int repeat;
   int ncoef;
-  const double *coef;  // OP_POLY_W: Horner coefficients in G = B^{-1} F^{-1} (1/C folded in)
+  const double *coef;  // OP_POLY_W: Horner coefficients in B^{-1} F^{-1} (1/C folded in)
   T top;
-  int width, off;      // OP_SLC: interpolation taps (1/C folded in) and their start offset
-  T w[MAXTAPS];
+  int off;             // OP_SLC: start offset of the interpolation taps
+  T w[MAXTAPS];        // OP_SLC: interpolation weights (1/C folded in)
   WinDir<KF, T> f;
   WinDir<KB, T> b;
 };
 
-// y <- G y = B^{-1} F^{-1} y.  pub0/pub1: the published-state areas.  With no
+// y <- B^{-1} F^{-1} y.  pub0/pub1: the published-state areas.  With no
 // anti-causal factor the causal recurrence alternates between them (flip), so
 // that a recurrence never overwrites words another thread has yet to read.
 template <int L, int KF, int KB, class T>
@@ -131,7 +189,7 @@ __global__ void __launch_bounds__(MAXT) wstep_kernel(const LevelDesc *__restrict
   const int nx = desc->lay.nx;
   const int NT = blockDim.x;
   const int tid = threadIdx.x;
-  const WinLds lo = win_lds(KIND, nx, NT, KW, (int)sizeof(T));
+  const WinLds lo = win_lds(KIND, nx, NT, KW, (int)sizeof(T), L);
   T *sm = reinterpret_cast<T *>(smem);
   T *vec = sm;  // OP_SLC: the padded vector
   T *pub0 = sm + lo.pub0, *pub1 = sm + lo.pub1;
@@ -143,7 +201,6 @@ __global__ void __launch_bounds__(MAXT) wstep_kernel(const LevelDesc *__restrict
   R.coef = op.wcoef;
   R.top = KIND == OP_POLY_W ? (T)op.wcoef[op.ncoef - 1] : T(0);
   if (KIND == OP_SLC) {
-    R.width = op.sl_l + op.sl_r + 1;
     R.off = op.sl_K + op.sl_l;
 #pragma unroll
     for (int t = 0; t < MAXTAPS; ++t) R.w[t] = (T)(op.slw[t] * op.cinv);
@@ -152,20 +209,23 @@ __global__ void __launch_bounds__(MAXT) wstep_kernel(const LevelDesc *__restrict
   win_dir_load<KB, T>(R.b, op.bw);
 
   int flip = 0;
-  run_chain<L, T>(pa, nx, L, red, [&](T (&u)[L]) {
+  // the rows a step adds are read after the step: loading them before it
+  // (into registers) measured slower at 32 points per thread
+  run_chain<L, T, 0>(pa, nx, L, red, [&](T (&u)[L]) {
     const int base = tid * L;
     for (int rep = 0; rep < R.repeat; ++rep) {
       T y[L];
       if (KIND == OP_SLC) {
         __syncthreads();  // every thread has finished the previous gather
-        chunk_to_lds<L>(vec, base, L, u);
+#pragma unroll
+        for (int j = 0; j < L; ++j) vec[win_pad<L>(base + j)] = u[j];
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < L; ++j) y[j] = T(0);
-        window_combine<L>(vec, wrap_lo(base - R.off, nx), L, R.width, nx, R.w, y);
+        win_gather<L, 2 * KF>(vec, wrap_lo(base - R.off, nx), nx, R.w, y);
         if (lo.alias) __syncthreads();  // the published states reuse the vector's words
         win_solve<L, KF, KB>(y, R, pub0, pub1, flip, tid, NT);
-      } else {  // OP_POLY_W: Phi u = sum_i wcoef[i] G^i u by Horner
+      } else {  // OP_POLY_W: Phi u = sum_i wcoef[i] (B^{-1} F^{-1})^i u by Horner
 #pragma unroll
         for (int j = 0; j < L; ++j) y[j] = R.top * u[j];
         for (int i = R.ncoef - 2; i >= 0; --i) {

@@ -27,7 +27,7 @@ hipError_t MGRIT_WIN_LAUNCH(const LevelDesc *desc, const StepOp &op, const Layou
   const int nt = lay.nx / L;
   const int maxt = nt <= 256 ? 256 : (nt <= 512 ? 512 : 1024);
   const int kw = op.fw.k > op.bw.k ? op.fw.k : (op.bw.k > 0 ? op.bw.k : 1);
-  const WinLds lo = win_lds(op.kind, lay.nx, nt, kw, (int)sizeof(MGRIT_WIN_T));
+  const WinLds lo = win_lds(op.kind, lay.nx, nt, kw, (int)sizeof(MGRIT_WIN_T), L);
   const size_t lds = (size_t)lo.bytes;
 #define MGRIT_WIN_CASE(Lv, KINDv, KFv, KBv, MAXTv)                                                              \
   case win_key(Lv, KINDv, KFv, KBv, MAXTv):                                                                     \

@@ -51,7 +51,7 @@ def test_windowed_sdirk_steps_match_oracle_and_scan(monkeypatch, nx, p, q, c, L)
     v = rng.standard_normal((3, nx))
     s = mgrit.Solver(mgrit.make_problem(nx, 8, c, p, "sdirk", q), mgrit.make_options(2, coarse="ideal"))
     info = s.level_info(0)
-    assert info["win_L"] == (L or (32 if (nx // 32) % 64 == 0 else 16)), info
+    assert info["win_L"] == (L or (32 if nx >= 8192 else 16)), info
     assert info["win_D"][0] >= 1 and (info["win_D"][1] >= 1) == (p > 1)
     out = torch.empty((3, nx), dtype=torch.float64, device=DEV)
     s.apply_step(0, _t(v), out, 4)
