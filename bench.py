@@ -1,17 +1,19 @@
 """Benchmark: MGRIT solves of periodic linear advection on one MI355X.
 
 One step = one complete MGRIT solve, to a 1e-10 relative residual, of the
-workload 'advection1d-4096x4096-erk3u3-vcycle-m8': u_t + u_x = 0 on [-1, 1),
-nx = nt = 4096, CFL 0.85, third-order upwind + three-stage ERK3, V-cycle with
-m = 8 down to 8 coarse steps (4096 -> 512 -> 64 -> 8), FCF relaxation, the
-corrected semi-Lagrangian coarse operator, FP64, seeded 16-mode Fourier u0 and
-a uniformly random initial iterate.  The timed region starts with the inputs in
-HBM and ends with the whole space-time solution [nt+1][nx] written to HBM.
+workload 'advection1d-16384x16384-sdirk3u5-vcycle-m16': u_t + u_x = 0 on
+[-1, 1), nx = nt = 16384, CFL 0.5, fifth-order upwind + three-stage SDIRK3
+(a periodic banded solve per stage), V-cycle with m = 16
+(16384 -> 1024 -> 64 -> 4), FCF relaxation, the corrected semi-Lagrangian
+coarse operator, FP64, seeded 16-mode Fourier u0 and a uniformly random
+initial iterate (seed 1003).  The timed region starts with the inputs in HBM
+and ends with the whole space-time solution [nt+1][nx] written to HBM.
 
 Printed as one JSON line: space-time DOF/s (nx*nt per solve), p50/p99 solve
 latency, the sequential GPU time-stepping baseline, the roofline of the
-dominant kernel (timed live with HIP events on the library's stream) and the
-oracle timed on host cores on a bounded sample.
+dominant kernel (timed live with HIP events on the library's stream), the
+oracle timed on host cores on a bounded sample, and the same solve in mixed
+precision and the 4096 x 4096 ERK3 + U3 workload as extra keys.
 """
 import argparse
 import hashlib
@@ -25,12 +27,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-NX = NT = 4096
-CFL = 0.85
-P = Q = 3
-MS = [8, 8, 8]
-SEED = 1002
-WORKLOAD = "advection1d-4096x4096-erk3u3-vcycle-m8"
+# The workloads (seeded synthetic inputs; the paper uses no dataset).
+WORKLOADS = {
+    "config3": dict(name="advection1d-16384x16384-sdirk3u5-vcycle-m16", nx=16384, nt=16384, cfl=0.5, p=5,
+                    kind="sdirk", q=3, ms=[16, 16, 16], seed=1003, scheme="SDIRK3+U5"),
+    "config2": dict(name="advection1d-4096x4096-erk3u3-vcycle-m8", nx=4096, nt=4096, cfl=0.85, p=3, kind="erk",
+                    q=3, ms=[8, 8, 8], seed=1002, scheme="ERK3+U3"),
+}
+HEADLINE = WORKLOADS["config3"]
+WORKLOAD = HEADLINE["name"]
 
 COPY_BYTES = 1 << 30
 
@@ -49,32 +54,55 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def phi_flops_per_dof():
-    """Algorithmic flops per point per fine step (one FMA = 2 flops): the ERK3
-    step R(Z) with the U3 stencil (2 left, 1 right) written out as one stencil
-    of 3 (2 + 1) + 1 = 10 taps, the form the level-0 tiles apply."""
-    stages, left, right = 3, 2, 1
-    return 2 * (stages * (left + right) + 1)
+def phi_flops_per_dof(wl):
+    """Algorithmic flops per point per fine step (one FMA = 2 flops), in the
+    form the level-0 kernels evaluate.  ERK3 + U3: R(Z) written out as one
+    stencil of s (l + r) + 1 = 10 taps.  SDIRK: R as a polynomial of degree s
+    in W = (I + gamma c L_p)^{-1}, each W one causal recurrence of order
+    (p+1)/2 and one anti-causal of order (p-1)/2 (1/C folded into the
+    coefficients), plus one Horner term per power: s (p + 1) for U5 + SDIRK3,
+    18 FMAs.  (The Butcher stage form of SDIRK3 + U5, with an explicit U5
+    product and a banded LU solve per stage, counts about 116 flops; the
+    windowed kernel executes each recurrence twice, 66 flops.)"""
+    stages = 3
+    if wl["kind"] == "erk":
+        left, right = (wl["p"] + 1) // 2, (wl["p"] - 1) // 2
+        return 2 * (stages * (left + right) + 1)
+    kf, kb = (wl["p"] + 1) // 2, (wl["p"] - 1) // 2
+    return 2 * (stages * (kf + kb) + stages)
 
 
-def cpu_baseline(u0, v0):
-    """The oracle, unmodified, timed on one host core on the same workload: one
-    complete V-cycle solve to 1e-10 (nx = nt = 4096, hierarchy 4096 -> 512 ->
-    64 -> 8), several seconds of CPU work."""
+def psi_flops_per_dof(wl):
+    """Algorithmic flops per point of one coarse step Psi = T^{-1} S: p+1
+    interpolation taps, then the causal and anti-causal recurrences of order
+    k = (p+1)/2 each and the scale by 1/C."""
+    k = (wl["p"] + 1) // 2
+    return 2 * ((wl["p"] + 1) + 2 * k + 1)
+
+
+def cpu_baseline(wl):
+    """The oracle, unmodified, timed on one host core on a bounded sample of
+    the workload: a complete V-cycle MGRIT solve to 1e-10 of its first 512
+    time steps (nx = 16384, m = 16, 512 -> 32 -> 2; 10-40 s of CPU work).
+    The whole 16384 x 16384 solve takes the oracle about 48 minutes."""
     from oracle import mgrit as omg
+    from paper_2209_06916_amd import inputs
     from threadpoolctl import threadpool_limits
-    nt_s = NT
-    H = omg.Hierarchy(NX, nt_s, P, "erk", Q, CFL, MS)
+    nx, nt_s, ms = wl["nx"], 512, [16, 16]
+    u0 = inputs.u0_fourier(nx, wl["seed"])
+    v0 = inputs.initial_iterate(nt_s, nx, u0, wl["seed"])
+    H = omg.Hierarchy(nx, nt_s, wl["p"], wl["kind"], wl["q"], wl["cfl"], ms)
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        _, info = omg.solve(H, u0, v0[: nt_s + 1], rtol=1e-10, max_iter=30)
+        _, info = omg.solve(H, u0, v0, rtol=1e-10, max_iter=30)
         dt = time.perf_counter() - t0
-    return dict(value=NX * nt_s / dt, unit="DOF/s", cores=1, kind="oracle",
-                sample=f"one oracle V-cycle MGRIT solve to 1e-10 of the whole workload (nx={NX}, nt={nt_s}, "
-                       f"m=8, {info['iterations']} iterations, {dt:.1f} s)")
+    return dict(value=nx * nt_s / dt, unit="DOF/s", cores=1, kind="oracle",
+                sample=f"one oracle V-cycle MGRIT solve to 1e-10 of the first {nt_s} time steps of the workload "
+                       f"(nx={nx}, m=16, levels {nt_s} -> {nt_s // 16} -> 1, {info['iterations']} iterations, "
+                       f"{dt:.1f} s on one core)")
 
 
-def phase_work(iterations):
+def phase_work(wl, iterations):
     """Algorithmic (flops, bytes, working launches) per solve of each profiled phase.
 
     Rows are nx doubles.  Level 0 (nc0 = nt/m intervals): pass A reads C_k and
@@ -87,12 +115,12 @@ def phase_work(iterations):
     parent rows.  Every Psi application: semi-Lagrangian taps and the forward and
     backward recurrences of order (p+1)/2.  Final pass: nt - nc0 fine steps,
     reads the C-points and writes all nt+1 rows."""
+    NX, NT, MS = wl["nx"], wl["nt"], wl["ms"]
     row = NX * 8
     nc0 = NT // MS[0]
     passes = iterations + 1  # pre-relaxation of every iteration and of the last check
-    fine = (2 * passes * NT * NX * phi_flops_per_dof(), passes * (2 + 3) * nc0 * row, 2 * passes)
-    k = (P + 1) // 2
-    psi_flops = 2 * ((P + 1) + 2 * (2 * k + 1) + 1)
+    fine = (2 * passes * NT * NX * phi_flops_per_dof(wl), passes * (2 + 3) * nc0 * row, 2 * passes)
+    psi_flops = psi_flops_per_dof(wl)
     apps = rows = launches = 0
     nt_l = NT
     for lev, m in enumerate(MS):
@@ -107,13 +135,13 @@ def phase_work(iterations):
             rows += nt_l + 2 * nt_l
             launches += 1
     coarse = (iterations * apps * NX * psi_flops, iterations * rows * row, iterations * launches)
-    final = ((NT - nc0) * NX * phi_flops_per_dof(), ((NT + 1) + (nc0 + 1)) * row, 1)
+    final = ((NT - nc0) * NX * phi_flops_per_dof(wl), ((NT + 1) + (nc0 + 1)) * row, 1)
     return {"fine_relax": fine, "coarse": coarse, "final": final}
 
 
 PROFILE_COMMANDS = {
     "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/trace -o run -- "
-             "python3 bench.py --steps 10 --warmup 2 --no-cpu-baseline",
+             "python3 bench.py --steps 10 --warmup 2 --no-cpu-baseline --no-extras",
     "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/fetch -o run -- "
              "python3 bench.py --steps 2 --warmup 1 --traffic-probe",
     "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/write -o run -- "
@@ -127,7 +155,6 @@ PROFILE_COMMANDS = {
 SQ_COUNTERS = ["SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_INSTS_VALU",
                "SQ_ACTIVE_INST_VALU", "SQ_INSTS_LDS"]
 SERVE_WORKLOAD = "served-advection1d-512-requests"
-DOMINANT_KERNEL = "coarse_vcycle_kernel<4, 2, 16, 4>"
 
 
 def _short(name):
@@ -147,17 +174,18 @@ def summarize_profiles(d):
     tot = sum(float(r["TotalDurationNs"]) for r in rows)
     lines = [f"# rocprofv3 kernel statistics -- workload {WORKLOAD}",
              "# (MGRIT solves: 2 warm-up, 3 with every phase timed by events, 10 timed; then 4 runs of sequential",
-             "# time-stepping of the same problem; then 6 MGRIT solves without the final F-pass)",
+             "# time-stepping of the same problem; then 4 MGRIT solves without the final F-pass)",
              "# command (repository root on the GPU box, after cd /tmp && export TMPDIR=/tmp):",
              "#   " + PROFILE_COMMANDS["trace"].replace("<dir>", "gpurun_out/prof"),
              "#", f"# {'kernel':52s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'share':>7s}"]
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
         lines.append(f"  {_short(r['Name']):52s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
                      f"{float(r['TotalDurationNs']) / 1e6:10.3f} {100 * float(r['TotalDurationNs']) / tot:6.2f}%")
-    lines += ["#", "# coarse_vcycle_kernel<4, 2, 16, 4>: every coarse-level pass of one V-cycle (levels 1-3) in one launch",
-              "# (the last launch of each solve returns at once); tile_kernel<8, 6, 3, true>: level-0 relaxation passes",
-              "# and the final F-relaxation (ERK3 written out as one 10-tap stencil); tile_kernel<4, 2, 1, false>:",
-              "# sequential time-stepping (blocks of 16 steps, Horner form);",
+    lines += ["#", "# wstep_kernel<32, 1, 3, 2, 512, double>: SDIRK3 + U5 steps (32 points per thread, 512 threads);",
+              "#   grid 524288: level-0 relaxation passes (1024 intervals) and the final F-pass; grid 512: sequential",
+              "#   time-stepping (one workgroup, 16384 steps)",
+              "# wstep_kernel<32, 2, 3, 3, 512, double>: corrected semi-Lagrangian steps of levels 1-3, one launch per",
+              "#   pass (the last correction of each solve returns at once)",
               "# solve_ctl_kernel: residual norm + stopping test."]
     with open(os.path.join(prof_dir, f"kernel_stats_{WORKLOAD}.txt"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
@@ -240,25 +268,27 @@ def summarize_profiles(d):
              f"#   WRITE_SIZE read {write[copy_name][-1]:.1f} KiB for {copy_kib:.0f} KiB -> scale {wscale:.4f}",
              "#", f"# {'kernel':40s} {'dispatches':>10s} {'FETCH_KiB/disp':>15s} {'WRITE_KiB/disp':>15s} "
                   f"{'scaled_MB/disp':>15s}"]
-    result = None
+    # per dispatch: the median (the level-0 kernel also runs the one final
+    # F-pass of each solve, which writes every time point)
+    result = {}
     for k in fetch:
         if k == copy_name or k not in write or k.startswith("at::"):
             continue
-        fk = float(np.mean(fetch[k]))
-        wk = float(np.mean(write[k]))
+        fk = float(np.median(fetch[k]))
+        wk = float(np.median(write[k]))
         mb = (fk * fscale + wk * wscale) * 1024 / 1e6
         lines.append(f"  {k:40s} {len(fetch[k]):10d} {fk:15.1f} {wk:15.1f} {mb:15.2f}")
-        if k == DOMINANT_KERNEL:
-            result = dict(fetch_kib=fk, write_kib=wk, bytes=(fk * fscale + wk * wscale) * 1024)
+        for ph, kn in PHASE_KERNELS.items():
+            if k == kn and ph != "final":
+                result[ph] = dict(kernel=k, fetch_kib_per_dispatch=fk, write_kib_per_dispatch=wk,
+                                  bytes_per_launch=(fk * fscale + wk * wscale) * 1024)
     with open(os.path.join(prof_dir, f"traffic_{WORKLOAD}.txt"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
-    if result is not None:
+    if result:
         with open(os.path.join(prof_dir, "traffic.json"), "w") as fh:
-            json.dump({"workload": WORKLOAD, "phase": "coarse", "kernel": DOMINANT_KERNEL,
-                       "source_hash": kernel_source_hash(), "bytes_per_launch": result["bytes"],
-                       "fetch_scale": fscale, "write_scale": wscale, "fetch_kib_per_dispatch": result["fetch_kib"],
-                       "write_kib_per_dispatch": result["write_kib"],
-                       "source": f"profiles/traffic_{WORKLOAD}.txt"}, fh, indent=1)
+            json.dump({"workload": WORKLOAD, "source_hash": kernel_source_hash(), "fetch_scale": fscale,
+                       "write_scale": wscale, "phases": result, "source": f"profiles/traffic_{WORKLOAD}.txt"},
+                      fh, indent=1)
     print("\n".join(lines))
 
 
@@ -449,110 +479,188 @@ def twod_bench(steps):
                       "mgrit_vs_sequential": seq / w64, "mixed_vs_fp64": w64 / w32}), flush=True)
 
 
-def long_bench(steps):
-    """Long time horizons (nt >> nx), where time-parallelism pays off on one
-    GPU: ERK3 + U3 at c = 0.85, m = 8, V-cycles down to <= 8 coarse steps,
-    seeded 16-mode Fourier u0 and the seeded U[0,1) initial iterate, 1e-10
-    relative C-point residual; against sequential time-stepping (temporal
-    blocking) of the same problem on the GPU."""
+# The kernel of each phase at the headline workload (names as rocprofv3 prints them).
+PHASE_KERNELS = {
+    "fine_relax": "wstep_kernel<32, 1, 3, 2, 512, double>",
+    "coarse": "wstep_kernel<32, 2, 3, 3, 512, double>",
+    "final": "wstep_kernel<32, 1, 3, 2, 512, double>",
+}
+PHASE_TEXT = {
+    "fine_relax": "level-0 F/C relaxation and C-point residual: SDIRK3 steps, R as a polynomial in the stage "
+                  "solve, each periodic banded solve by truncated-carry recurrences (windowed step kernel)",
+    "coarse": "coarse levels, one launch per pass: corrected semi-Lagrangian step + periodic banded solve by "
+              "truncated-carry recurrences (windowed step kernel)",
+    "final": "final F-relaxation writing the space-time solution (windowed step kernel)",
+}
+
+
+def solve_bench(wl, steps, warmup, profile_dominant=True):
+    """Time `steps` complete solves of workload wl after `warmup` untimed ones;
+    per-phase GPU time from a few untimed solves with every phase bracketed
+    by events, then the dominant phase's launches timed live (with the
+    library's event profiler, on its stream) during the timed solves."""
     import torch
     from paper_2209_06916_amd import inputs, mgrit
     dev = torch.device("cuda:0")
-    for nx, nt in [(4096, 16384), (1024, 65536), (256, 131072)]:
-        seed = 1002
-        u0 = inputs.u0_fourier(nx, seed)
-        u0_d = torch.from_numpy(u0).to(dev)
-        v0 = torch.from_numpy(inputs.initial_iterate(nt, nx, u0, seed)).to(dev)
-        s = mgrit.Solver(mgrit.make_problem(nx, nt, 0.85, 3),
-                         mgrit.make_options([8], max_levels=16, min_coarse_nt=8, rtol=1e-10, max_iter=30))
-        out = torch.empty((nt + 1, nx), dtype=torch.float64, device=dev)
-        ref = torch.empty_like(out)
-        info = s.solve(u0_d, v0, u_out=out)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(steps):
-            info = s.solve(u0_d, v0, u_out=out)
-        torch.cuda.synchronize()
-        tm = (time.perf_counter() - t) / steps
-        s.sequential(u0_d, ref)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(steps):
-            s.sequential(u0_d, ref)
-        torch.cuda.synchronize()
-        ts = (time.perf_counter() - t) / steps
-        err = (torch.linalg.vector_norm(out - ref) / torch.linalg.vector_norm(ref)).item()
-        print(json.dumps({"workload": f"advection1d-{nx}x{nt}-erk3u3-vcycle-m8", "dof": nx * nt,
-                          "levels": s.num_levels, "iterations": info["iterations"], "mgrit_ms": 1e3 * tm,
-                          "mgrit_dof_per_s": nx * nt / tm, "sequential_ms": 1e3 * ts,
-                          "sequential_dof_per_s": nx * nt / ts, "speedup_vs_sequential": ts / tm,
-                          "rel_l2_error_vs_sequential": err}), flush=True)
-        s.close()
-        del out, ref, v0
-        torch.cuda.empty_cache()
-
-
-def fig4_bench(steps):
-    """The paper's strong-scaling problems (Fig. 4), on one GPU instead of
-    1024 CPU processes: nx x nt = 4096 x 16384, MGRIT V-cycles with m = 16 on
-    the first level and 4 below, coarsening until fewer than two time points
-    would result, FCF relaxation, 1e-10 relative residual; ERK1+U1 and ERK3+U3
-    at 85% of their CFL limits (Table 2), SDIRK1+U1 at CFL 1 and SDIRK3+U3 at
-    CFL 5; u0 = sin^4(pi x) and the seeded U[0,1) initial iterate.  Against
-    sequential time-stepping of the same problem on the GPU."""
-    import torch
-    from paper_2209_06916_amd import inputs, mgrit
-    dev = torch.device("cuda:0")
-    nx, nt, seed = 4096, 16384, 1004
-    u0 = inputs.u0_sin4(nx)
+    nx, nt = wl["nx"], wl["nt"]
+    u0 = inputs.u0_fourier(nx, wl["seed"])
     u0_d = torch.from_numpy(u0).to(dev)
-    v0 = torch.from_numpy(inputs.initial_iterate(nt, nx, u0, seed)).to(dev)
+    v0_d = torch.from_numpy(inputs.initial_iterate(nt, nx, u0, wl["seed"])).to(dev)
     out = torch.empty((nt + 1, nx), dtype=torch.float64, device=dev)
-    ref = torch.empty_like(out)
-    for kind, p, c in [("erk", 1, 0.85 * 1.0), ("erk", 3, 0.85 * 1.62589), ("sdirk", 1, 1.0), ("sdirk", 3, 5.0)]:
-        s = mgrit.Solver(mgrit.make_problem(nx, nt, c, p, kind=kind),
-                         mgrit.make_options([16, 4], max_levels=16, min_coarse_nt=4, rtol=1e-10, max_iter=60))
-        info = s.solve(u0_d, v0, u_out=out)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(steps):
-            info = s.solve(u0_d, v0, u_out=out)
-        torch.cuda.synchronize()
-        tm = (time.perf_counter() - t) / steps
-        s.sequential(u0_d, ref)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(steps):
-            s.sequential(u0_d, ref)
-        torch.cuda.synchronize()
-        ts = (time.perf_counter() - t) / steps
-        err = (torch.linalg.vector_norm(out - ref) / torch.linalg.vector_norm(ref)).item()
-        print(json.dumps({"workload": f"advection1d-{nx}x{nt}-{kind}{p}u{p}-cfl{c:.4g}-vcycle-m16-4",
-                          "dof": nx * nt, "levels": s.num_levels, "status": info["status"],
-                          "iterations": info["iterations"], "mgrit_ms": 1e3 * tm, "mgrit_dof_per_s": nx * nt / tm,
-                          "sequential_ms": 1e3 * ts, "sequential_dof_per_s": nx * nt / ts,
-                          "speedup_vs_sequential": ts / tm, "rel_l2_error_vs_sequential": err}), flush=True)
-        s.close()
-    del out, ref, v0
+    prob = mgrit.make_problem(nx, nt, wl["cfl"], wl["p"], wl["kind"], wl["q"])
+    opts = mgrit.make_options(wl["ms"], max_levels=len(wl["ms"]) + 1, rtol=1e-10, max_iter=30)
+    solver = mgrit.Solver(prob, opts)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        solver.solve(u0_d, v0_d, u_out=out)
+    torch.cuda.synchronize()
+
+    solver.profile_enable(["fine_relax", "coarse", "final"])
+    solver.profile_read(reset=True)
+    nphase = max(3, min(warmup, 5))
+    for _ in range(nphase):
+        solver.solve(u0_d, v0_d, u_out=out)
+    torch.cuda.synchronize()
+    phase_prof = solver.profile_read(reset=True)
+    dom = max(phase_prof, key=lambda k: phase_prof[k]["total_ms"])
+    solver.profile_enable([dom] if profile_dominant else [])
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    iters = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        starts[k].record(stream)
+        info = solver.solve(u0_d, v0_d, u_out=out)
+        ends[k].record(stream)
+        iters.append(info["iterations"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = solver.profile_read(reset=True)
+    solver.profile_enable([])
+    lat_ms = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
+
+    # sequential GPU time-stepping baseline (same u0, same Phi)
+    seq_out = torch.empty_like(out)
+    solver.sequential(u0_d, seq_out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nseq = 3
+    for _ in range(nseq):
+        solver.sequential(u0_d, seq_out)
+    torch.cuda.synchronize()
+    seq_s = (time.perf_counter() - t1) / nseq
+    err = (torch.linalg.vector_norm(out - seq_out) / torch.linalg.vector_norm(seq_out)).item()
+    del seq_out
+
+    # the final-time-only variant: the same solve without the final F-pass
+    # (u(t_nt) is a C-point), for callers that need only the last state
+    fin = torch.empty((nx,), dtype=torch.float64, device=dev)
+    nfin = max(3, steps // 5)
+    solver.solve(u0_d, v0_d, u_final=fin)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(nfin):
+        solver.solve(u0_d, v0_d, u_final=fin)
+    torch.cuda.synchronize()
+    fin_s = (time.perf_counter() - t2) / nfin
+    solver.close()
+    del out, v0_d
     torch.cuda.empty_cache()
+
+    dof = nx * nt
+    it = int(np.median(iters))
+    res = dict(wall=wall, steps=steps, iterations=it, lat_ms=lat_ms, seq_s=seq_s, fin_s=fin_s, dof=dof,
+               err_vs_sequential=err, phase_ms={k: v["total_ms"] / nphase for k, v in phase_prof.items()
+                                                 if v["launches"]})
+    if profile_dominant:
+        # Work per solve over kernel time per solve.  The coarse phase also
+        # counts the launches of the last iteration's correction, queued before
+        # the stopping test is known and returning at once: they add time, no work.
+        flops_s, bytes_s, _ = phase_work(wl, it)[dom]
+        launches = prof[dom]["launches"] / steps
+        avg_s = prof[dom]["total_ms"] / prof[dom]["launches"] / 1e3
+        res.update(dom=dom, launches=launches, avg_s=avg_s, flops=flops_s / launches, bytes=bytes_s / launches)
+    return res
+
+
+def roofline(wl, r):
+    flops, bytes_, avg_s, dom = r["flops"], r["bytes"], r["avg_s"], r["dom"]
+    ai = flops / bytes_
+    ridge = FP64_VALU_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if ai >= ridge:
+        achieved = flops / avg_s / 1e12
+        roof = dict(bound="alu", achieved=achieved, peak=FP64_VALU_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=achieved / FP64_VALU_PEAK_TFLOPS)
+    else:
+        achieved = bytes_ / avg_s / 1e9
+        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS)
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tfile):
+        with open(tfile) as fh:
+            t = json.load(fh)
+        if t.get("source_hash") == kernel_source_hash() and t.get("workload") == wl["name"]:
+            traffic = t.get("phases", {}).get(dom, {}).get("bytes_per_launch")
+    roof["traffic"] = traffic
+    roof["kernel"] = PHASE_KERNELS[dom] + ": " + PHASE_TEXT[dom]
+    roof["phase"] = dom
+    roof["avg_launch_us"] = avg_s * 1e6
+    roof["launches_per_solve"] = r["launches"]
+    roof["algorithmic_flops_per_launch"] = flops
+    roof["algorithmic_bytes_per_launch"] = bytes_
+    return roof
+
+
+def mixed_bench(wl, steps):
+    """The headline workload in mixed precision: float32 inner MGRIT cycles on
+    the correction equation inside float64 refinement (full space-time
+    residual, update and stopping test on the GPU), to 1e-12 of the first
+    full space-time residual (it carries the random F-points, so this gives
+    the float64 solve's solution error); error against float64 sequential
+    stepping on the GPU."""
+    import torch
+    from paper_2209_06916_amd import inputs, mgrit
+    dev = torch.device("cuda:0")
+    nx, nt = wl["nx"], wl["nt"]
+    u0 = inputs.u0_fourier(nx, wl["seed"])
+    u0_d = torch.from_numpy(u0).to(dev)
+    v0_d = torch.from_numpy(inputs.initial_iterate(nt, nx, u0, wl["seed"])).to(dev)
+    prob = mgrit.make_problem(nx, nt, wl["cfl"], wl["p"], wl["kind"], wl["q"])
+    s = mgrit.Solver(prob, mgrit.make_options(wl["ms"], max_levels=len(wl["ms"]) + 1, rtol=1e-12, max_iter=30,
+                                              precision="mixed"))
+    out = torch.empty((nt + 1, nx), dtype=torch.float64, device=dev)
+    info = s.solve(u0_d, v0_d, u_out=out)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        info = s.solve(u0_d, v0_d, u_out=out)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t) / steps
+    ref = torch.empty_like(out)
+    s.sequential(u0_d, ref)
+    err = (torch.linalg.vector_norm(out - ref) / torch.linalg.vector_norm(ref)).item()
+    s.close()
+    del out, ref, v0_d
+    torch.cuda.empty_cache()
+    return {"ms_per_solve": 1e3 * wall, "dof_per_s": nx * nt / wall, "status": info["status"],
+            "outer_iterations": info["iterations"], "inner_iterations": info["inner_iterations"],
+            "rel_l2_error_vs_sequential": err}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline workload (no mixed-precision and 4096 x 4096 keys)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for hardware-counter runs: a few solves plus one elementwise copy of "
                          "COPY_BYTES read + COPY_BYTES written (the counter calibration)")
     ap.add_argument("--serve", type=int, metavar="N", default=0,
                     help="the request-loop benchmark (N independent solves) instead of the single-solve one")
-    ap.add_argument("--long", action="store_true",
-                    help="long time horizons (nt >> nx) against sequential stepping instead of the single-solve bench")
-    ap.add_argument("--fig4", action="store_true",
-                    help="the paper's strong-scaling problems (4096 x 16384, four schemes) against sequential "
-                         "stepping instead of the single-solve bench")
     ap.add_argument("--twod", action="store_true",
                     help="the 2D extension (config 4) against 2D sequential stepping instead of the single-solve bench")
     ap.add_argument("--precision", action="store_true",
@@ -569,7 +677,6 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2209_06916_amd import inputs, mgrit
     if args.serve:
         serve_bench(args.serve, seed=1005)
         return
@@ -579,137 +686,30 @@ def main():
     if args.twod:
         twod_bench(max(1, min(args.steps, 5)))
         return
-    if args.long:
-        long_bench(max(1, min(args.steps, 5)))
-        return
-    if args.fig4:
-        fig4_bench(max(1, min(args.steps, 5)))
-        return
 
-    dev = torch.device("cuda:0")
-    u0 = inputs.u0_fourier(NX, SEED)
-    v0 = inputs.initial_iterate(NT, NX, u0, SEED)
-    u0_d = torch.from_numpy(u0).to(dev)
-    v0_d = torch.from_numpy(v0).to(dev)
-    out = torch.empty((NT + 1, NX), dtype=torch.float64, device=dev)
-    prob = mgrit.make_problem(NX, NT, CFL, P, "erk", Q)
-    opts = mgrit.make_options(MS, max_levels=len(MS) + 1, rtol=1e-10, max_iter=30)
-    solver = mgrit.Solver(prob, opts)
-    stream = torch.cuda.current_stream()
-
-    for _ in range(args.warmup):
-        solver.solve(u0_d, v0_d, u_out=out)
-    torch.cuda.synchronize()
+    wl = HEADLINE
     if args.traffic_probe:
-        for _ in range(args.steps):
-            solver.solve(u0_d, v0_d, u_out=out)
+        from paper_2209_06916_amd import inputs, mgrit
+        dev = torch.device("cuda:0")
+        u0 = inputs.u0_fourier(wl["nx"], wl["seed"])
+        u0_d = torch.from_numpy(u0).to(dev)
+        v0_d = torch.from_numpy(inputs.initial_iterate(wl["nt"], wl["nx"], u0, wl["seed"])).to(dev)
+        out = torch.empty((wl["nt"] + 1, wl["nx"]), dtype=torch.float64, device=dev)
+        s = mgrit.Solver(mgrit.make_problem(wl["nx"], wl["nt"], wl["cfl"], wl["p"], wl["kind"], wl["q"]),
+                         mgrit.make_options(wl["ms"], max_levels=len(wl["ms"]) + 1))
+        for _ in range(args.warmup + args.steps):
+            s.solve(u0_d, v0_d, u_out=out)
         x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
         y = torch.empty_like(x)
         torch.mul(x, 1.0, out=y)
         torch.cuda.synchronize()
-        print(json.dumps({"traffic_probe": True, "copy_bytes": COPY_BYTES, "solves": args.steps}), flush=True)
+        print(json.dumps({"traffic_probe": True, "copy_bytes": COPY_BYTES, "solves": args.warmup + args.steps}),
+              flush=True)
         return
 
-    # Per-phase GPU time from a few untimed solves with every phase's launches
-    # bracketed by events; each event costs GPU time (≈74 of them per solve),
-    # so the timed solves bracket only the dominant phase's launches.
-    solver.profile_enable(["fine_relax", "coarse", "final"])
-    solver.profile_read(reset=True)
-    nphase = max(3, args.warmup)
-    for _ in range(nphase):
-        solver.solve(u0_d, v0_d, u_out=out)
-    torch.cuda.synchronize()
-    phase_prof = solver.profile_read(reset=True)
-    dom = max(phase_prof, key=lambda k: phase_prof[k]["total_ms"])
-    solver.profile_enable([dom])
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    iters = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        starts[k].record(stream)
-        info = solver.solve(u0_d, v0_d, u_out=out)
-        ends[k].record(stream)
-        iters.append(info["iterations"])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    prof = solver.profile_read(reset=True)
-    solver.profile_enable([])
-    lat_ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
-
-    # sequential GPU time-stepping baseline (same u0, same Phi)
-    seq_out = torch.empty_like(out)
-    solver.sequential(u0_d, seq_out)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    nseq = 3
-    for _ in range(nseq):
-        solver.sequential(u0_d, seq_out)
-    torch.cuda.synchronize()
-    seq_s = (time.perf_counter() - t1) / nseq
-
-    # the final-time-only variant: the same solve without the final F-pass
-    # (u(t_nt) is a C-point), for callers that need only the last state
-    fin = torch.empty((NX,), dtype=torch.float64, device=dev)
-    nfin = max(5, args.steps // 5)
-    solver.solve(u0_d, v0_d, u_final=fin)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for _ in range(nfin):
-        solver.solve(u0_d, v0_d, u_final=fin)
-    torch.cuda.synchronize()
-    fin_s = (time.perf_counter() - t2) / nfin
-
-    dof = NX * NT
-    value = dof * args.steps / wall
-    ms_per_step = 1e3 * wall / args.steps
-
-    # the dominant kernel (by GPU time among the phases), timed live over the
-    # timed solves
-    it = int(np.median(iters))
-    # Work per solve over kernel time per solve.  The coarse phase also counts
-    # the launch(es) of the last iteration's correction, queued before the
-    # stopping test is known and returning at once: they add time, no work.
-    # (With the persistent coarse cycle there is one coarse launch per
-    # iteration, else one per pass.)
-    flops_s, bytes_s, _ = phase_work(it)[dom]
-    launches = prof[dom]["launches"] / args.steps
-    avg_s = prof[dom]["total_ms"] / prof[dom]["launches"] / 1e3
-    flops = flops_s / launches
-    bytes_ = bytes_s / launches
-    persistent = launches <= it + 1.5  # one coarse launch per iteration, else one per pass
-    kernel = {"fine_relax": "tile_kernel<8, 6, 3, true>: level-0 F/C relaxation and C-point residual",
-              "coarse": ("coarse_vcycle_kernel<4, 2, 16, 4>: every coarse-level pass of a V-cycle in one persistent "
-                         "launch (SL step + periodic banded solve)") if persistent else
-                        ("slc_kernel<4, 2, 16, 4>: one coarse-level pass per launch (SL step + periodic banded "
-                         "solve)"),
-              "final": "tile_kernel<8, 6, 3, true>: final F-relaxation writing the space-time solution"}[dom]
-    ai = flops / bytes_
-    ridge = FP64_VALU_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
-    if ai >= ridge:
-        achieved = flops / avg_s / 1e12
-        roof = dict(bound="alu", achieved=achieved, peak=FP64_VALU_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=achieved / FP64_VALU_PEAK_TFLOPS)
-    else:
-        achieved = bytes_ / avg_s / 1e9
-        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS)
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tfile):
-        with open(tfile) as fh:
-            t = json.load(fh)
-        if (t.get("source_hash") == kernel_source_hash() and t.get("phase") == dom and t.get("workload") == WORKLOAD
-                and (dom != "coarse" or persistent)):
-            traffic = t.get("bytes_per_launch")
-    roof["traffic"] = traffic
-    roof["kernel"] = kernel
-    roof["phase"] = dom
-    roof["avg_launch_us"] = avg_s * 1e6
-    roof["launches_per_solve"] = launches
-    roof["algorithmic_flops_per_launch"] = flops
-    roof["algorithmic_bytes_per_launch"] = bytes_
-
+    r = solve_bench(wl, args.steps, args.warmup)
+    dof = r["dof"]
+    value = dof * args.steps / r["wall"]
     line = {
         "metric": "space-time DOF/s to 1e-10 residual vs seq. stepping; p50/p99 solve latency",
         "value": value,
@@ -717,28 +717,42 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": 1e3 * r["wall"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "nx": NX, "nt": NT, "cfl": CFL, "scheme": "ERK3+U3",
-                   "hierarchy": [NT, NT // 8, NT // 64, NT // 512], "relaxation": "FCF",
-                   "coarse_operator": "semi-Lagrangian + implicit truncation correction", "rtol": 1e-10},
-        "iterations": int(np.median(iters)),
-        "latency_ms_p50": float(np.percentile(lat_ms, 50)),
-        "latency_ms_p99": float(np.percentile(lat_ms, 99)),
-        "sequential_gpu_dof_per_s": dof / seq_s,
-        "sequential_gpu_ms": seq_s * 1e3,
-        "final_time_only_ms": fin_s * 1e3,
-        "final_time_only_dof_per_s": dof / fin_s,
-        "speedup_vs_sequential": (dof / seq_s) and value / (dof / seq_s),
-        "phase_ms_per_solve": {k: v["total_ms"] / nphase for k, v in phase_prof.items() if v["launches"]},
-        "roofline": roof,
+        "config": {"workload": wl["name"], "nx": wl["nx"], "nt": wl["nt"], "cfl": wl["cfl"], "scheme": wl["scheme"],
+                   "hierarchy": [wl["nt"] // int(np.prod(wl["ms"][:i])) for i in range(len(wl["ms"]) + 1)],
+                   "relaxation": "FCF", "coarse_operator": "semi-Lagrangian + implicit truncation correction",
+                   "rtol": 1e-10},
+        "iterations": r["iterations"],
+        "latency_ms_p50": float(np.percentile(r["lat_ms"], 50)),
+        "latency_ms_p99": float(np.percentile(r["lat_ms"], 99)),
+        "sequential_gpu_dof_per_s": dof / r["seq_s"],
+        "sequential_gpu_ms": r["seq_s"] * 1e3,
+        "speedup_vs_sequential": value / (dof / r["seq_s"]),
+        "rel_l2_error_vs_sequential": r["err_vs_sequential"],
+        "final_time_only_ms": r["fin_s"] * 1e3,
+        "final_time_only_dof_per_s": dof / r["fin_s"],
+        "phase_ms_per_solve": r["phase_ms"],
+        "roofline": roofline(wl, r),
     }
+    if not args.no_extras:
+        line["mixed"] = mixed_bench(wl, max(2, min(args.steps, 5)))
+        line["mixed"]["speedup_vs_fp64"] = line["ms_per_step"] / line["mixed"]["ms_per_solve"]
+        wl2 = WORKLOADS["config2"]
+        r2 = solve_bench(wl2, max(args.steps, 20), args.warmup, profile_dominant=False)
+        v2 = r2["dof"] * r2["steps"] / r2["wall"]
+        line["config2"] = {"workload": wl2["name"], "dof_per_s": v2, "ms_per_solve": 1e3 * r2["wall"] / r2["steps"],
+                           "iterations": r2["iterations"], "sequential_gpu_ms": r2["seq_s"] * 1e3,
+                           "speedup_vs_sequential": v2 / (r2["dof"] / r2["seq_s"]),
+                           "latency_ms_p50": float(np.percentile(r2["lat_ms"], 50)),
+                           "latency_ms_p99": float(np.percentile(r2["lat_ms"], 99)),
+                           "phase_ms_per_solve": r2["phase_ms"]}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(u0, v0)
+        line["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(line), flush=True)
 
 

@@ -1,0 +1,66 @@
+"""Write the oracle's solve of the 2D workload to tests/golden/config4_oracle.npz
+(and a text summary beside it).
+
+Calls only the oracle (oracle.advection2d, oracle.mgrit) and the seeded input
+generators; nothing here comes from the HIP path.  The workload (the paper's
+1D method extended by dimension splitting): u_t + a.grad u = 0 on [-1, 1)^2,
+a = (0.85, 1.0), nx = ny = nt = N, dt = h/2 (c = (0.425, 0.5)), third-order
+upwind per axis inside every stage of ERK3, FCF relaxation, V-cycles with
+m = 8 (N -> N/8 -> N/64 levels), the dimension-split corrected
+semi-Lagrangian coarse step, stopping when the C-point residual 2-norm falls
+by 1e-10; u0 = 8 seeded Gaussian bumps of width 0.1, initial iterate
+U[0, 1), seed 1004.
+
+Stored (sampled; the whole [N+1, N, N] solution is 8.6 GB at N = 1024):
+  iterations, res_history   -- coarse-grid corrections and residual norms
+  norms[n]                  -- ||u_n||_2 for every time point n
+  proj[n]                   -- <w, u_n> with w = inputs.sign_vector(N*N, 78)
+  c_sample[k]               -- u_{8k}[::16, ::16], every C-point
+  rows, row_index           -- full time points at a few n
+Usage: make_config4.py [N] (default 1024; N = 512 takes about 1/16 of the
+time and memory).
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle import advection2d as a2  # noqa: E402
+from oracle import mgrit as omg  # noqa: E402
+from paper_2209_06916_amd import inputs  # noqa: E402
+
+
+def main(n=1024):
+    out = os.path.join(HERE, "config4_oracle.npz" if n == 1024 else "config4_oracle_%d.npz" % n)
+    t0 = time.time()
+    nt, ms, seed = n, [8, 8], 1004
+    u0 = inputs.u0_bumps_2d(n, n, 8, 0.1, seed)
+    v0 = np.random.default_rng(seed).random((nt + 1, n, n))
+    v0[0] = u0
+    h = 2.0 / n
+    dt = 0.5 * h
+    H = a2.Hierarchy2D(n, n, nt, 3, 3, 0.85 * dt / h, 1.0 * dt / h, ms)
+    u, info = omg.solve(H, u0, v0, rtol=1e-10, max_iter=30, nu=1)
+    del v0
+    w = inputs.sign_vector(n * n, 78)
+    flat = u.reshape(nt + 1, n * n)
+    rows = [1, 7, 8, 9, nt // 2, nt - 1, nt]
+    np.savez(out, iterations=np.int64(info["iterations"]), res_history=np.array(info["res_history"]),
+             norms=np.linalg.norm(flat, axis=1), proj=flat @ w, c_sample=u[::8, ::16, ::16].copy(),
+             rows=u[rows].copy(), row_index=np.array(rows, dtype=np.int64))
+    with open(os.path.splitext(out)[0] + ".txt", "w") as fh:
+        fh.write("# oracle solve, 2D, nx = ny = nt = %d, ERK3+U3 split, dt = h/2, m = 8 (3 levels), seed 1004\n" % n)
+        fh.write("# written by tests/golden/make_config4.py in %.0f s\n" % (time.time() - t0))
+        fh.write("iterations %d\n" % info["iterations"])
+        for i, r in enumerate(info["res_history"]):
+            fh.write("res %d %.17e\n" % (i, r))
+    print("iterations", info["iterations"], "time %.0f s" % (time.time() - t0), flush=True)
+
+
+if __name__ == "__main__":
+    main(int(sys.argv[1]) if len(sys.argv) > 1 else 1024)
