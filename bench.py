@@ -266,22 +266,28 @@ def summarize_profiles(d):
              f"# calibration: the probe's elementwise copy ({copy_name}) reads and writes {COPY_BYTES >> 20} MiB",
              f"#   FETCH_SIZE read {fetch[copy_name][-1]:.1f} KiB for {copy_kib:.0f} KiB -> scale {fscale:.4f}",
              f"#   WRITE_SIZE read {write[copy_name][-1]:.1f} KiB for {copy_kib:.0f} KiB -> scale {wscale:.4f}",
+             "# per dispatch: mean over dispatches (level-0 kernel: median, see below)",
              "#", f"# {'kernel':40s} {'dispatches':>10s} {'FETCH_KiB/disp':>15s} {'WRITE_KiB/disp':>15s} "
                   f"{'scaled_MB/disp':>15s}"]
-    # per dispatch: the median (the level-0 kernel also runs the one final
-    # F-pass of each solve, which writes every time point)
+    # per dispatch: the mean, as the bench averages its launch durations;
+    # for the level-0 kernel the median, since it also runs the one final
+    # F-pass of each solve, which writes every time point
     result = {}
     for k in fetch:
         if k == copy_name or k not in write or k.startswith("at::"):
             continue
-        fk = float(np.median(fetch[k]))
-        wk = float(np.median(write[k]))
+        avg = np.median if k == PHASE_KERNELS["fine_relax"] else np.mean
+        fk = float(avg(fetch[k]))
+        wk = float(avg(write[k]))
         mb = (fk * fscale + wk * wscale) * 1024 / 1e6
         lines.append(f"  {k:40s} {len(fetch[k]):10d} {fk:15.1f} {wk:15.1f} {mb:15.2f}")
         for ph, kn in PHASE_KERNELS.items():
             if k == kn and ph != "final":
                 result[ph] = dict(kernel=k, fetch_kib_per_dispatch=fk, write_kib_per_dispatch=wk,
                                   bytes_per_launch=(fk * fscale + wk * wscale) * 1024)
+    lines += ["#", f"# {PHASE_KERNELS['fine_relax']}: level-0 passes and the final F-pass (median: a pass A",
+              "#   reads and writes the 1025 C-point rows, 2 x 134 MB); " + PHASE_KERNELS["coarse"] + ":",
+              "#   every coarse-level pass of levels 1-3 (mean over the passes of a V-cycle)"]
     with open(os.path.join(prof_dir, f"traffic_{WORKLOAD}.txt"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     if result:

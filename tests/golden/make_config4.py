@@ -15,8 +15,8 @@ Stored (sampled; the whole [N+1, N, N] solution is 8.6 GB at N = 1024):
   iterations, res_history   -- coarse-grid corrections and residual norms
   norms[n]                  -- ||u_n||_2 for every time point n
   proj[n]                   -- <w, u_n> with w = inputs.sign_vector(N*N, 78)
-  c_sample[k]               -- u_{8k}[::16, ::16], every C-point
-  rows, row_index           -- full time points at a few n
+  c_sample[k]               -- u_{8k}[::N/32, ::N/32] (32 x 32 values), every C-point
+  rows, row_index           -- u_n[::N/128, ::N/128] (128 x 128 values) at a few n
 Usage: make_config4.py [N] (default 1024; N = 512 takes about 1/16 of the
 time and memory).
 """
@@ -50,9 +50,10 @@ def main(n=1024):
     w = inputs.sign_vector(n * n, 78)
     flat = u.reshape(nt + 1, n * n)
     rows = [1, 7, 8, 9, nt // 2, nt - 1, nt]
+    cs, rs = n // 32, n // 128
     np.savez(out, iterations=np.int64(info["iterations"]), res_history=np.array(info["res_history"]),
-             norms=np.linalg.norm(flat, axis=1), proj=flat @ w, c_sample=u[::8, ::16, ::16].copy(),
-             rows=u[rows].copy(), row_index=np.array(rows, dtype=np.int64))
+             norms=np.linalg.norm(flat, axis=1), proj=flat @ w, c_sample=u[::8, ::cs, ::cs].copy(),
+             rows=u[rows][:, ::rs, ::rs].copy(), row_index=np.array(rows, dtype=np.int64))
     with open(os.path.splitext(out)[0] + ".txt", "w") as fh:
         fh.write("# oracle solve, 2D, nx = ny = nt = %d, ERK3+U3 split, dt = h/2, m = 8 (3 levels), seed 1004\n" % n)
         fh.write("# written by tests/golden/make_config4.py in %.0f s\n" % (time.time() - t0))
