@@ -40,6 +40,7 @@ extern "C" {
 
 #define MGRIT_MAX_LEVELS 16
 #define MGRIT_MAX_NX 16384 /* one spatial slab per workgroup, kept in LDS */
+#define MGRIT_NOALLOC_BYTES (64u << 20) /* workspace of mgrit_solve_noalloc, per device */
 
 typedef enum {
   MGRIT_OK = 0,
@@ -212,6 +213,23 @@ mgrit_status mgrit_setup_ws(const mgrit_problem *problem, const mgrit_options *o
  * (else in the handle's workspace); max_iter bounds the outer iterations. */
 mgrit_status mgrit_solve(mgrit_handle *h, const double *u0_dev, const double *v_init_dev,
                          double *u_out_dev, double *u_final_dev, mgrit_stats *stats);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * float64 solve as mgrit_setup + mgrit_solve + mgrit_destroy in one call that
+ * allocates nothing.  Its workspace is one file-scope device array of
+ * MGRIT_NOALLOC_BYTES per GPU, kept until the process ends; every call on a
+ * GPU reuses that GPU's array, so calls that overlap on one GPU (from several
+ * threads or streams) race and must be serialised by the caller.  Arguments
+ * as mgrit_setup and mgrit_solve (the caller owns u0_dev, v_init_dev,
+ * u_out_dev, u_final_dev and stats); work runs on hip_stream and the call
+ * synchronises it, the host waiting for each iteration's stopping decision.
+ * MGRIT_EINVAL, with mgrit_last_error(NULL) saying why, for a problem whose
+ * workspace (mgrit_workspace_bytes) exceeds MGRIT_NOALLOC_BYTES, for
+ * MGRIT_PREC_MIXED and for tile_tune != 0; other outcomes as mgrit_solve. */
+mgrit_status mgrit_solve_noalloc(const mgrit_problem *problem, const mgrit_options *options, void *hip_stream,
+                                 const double *u0_dev, const double *v_init_dev, double *u_out_dev,
+                                 double *u_final_dev, mgrit_stats *stats);
 
 /* The same solve in steps, for request loops that keep several solves in
  * flight (one handle and one stream each).  mgrit_solve_start queues the

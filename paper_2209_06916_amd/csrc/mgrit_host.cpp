@@ -683,6 +683,12 @@ struct mgrit_handle {
   size_t arena_bytes = 0;
   bool owns_arena = false;     // false: the caller's workspace (mgrit_setup_ws)
   char *host_arena = nullptr;  // pinned words: normsum_host, ctl_host
+  // allocation-free mode (mgrit_solve_noalloc): no pinned words and no
+  // events; the iteration state is copied to this host word after each
+  // stopping test and the host waits for it
+  bool noalloc = false;
+  SolveCtl ctl_local{};
+  double norm_local = 0;
   std::string err;
   // the solve in progress (mgrit_solve_start .. mgrit_solve_finish)
   struct {
@@ -755,7 +761,7 @@ void pinned_slot_give(char *host) {
 }
 
 mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *stream, void *ws, uint64_t ws_bytes,
-                        mgrit_handle **out);
+                        mgrit_handle **out, bool noalloc = false);
 
 // Build the StepOp of a solve-free or solve-carrying operator.
 bool attach_solve(StepOp &op, const std::map<int, ld> &taps, const Layout &lay, std::vector<double> &tabs,
@@ -1187,7 +1193,7 @@ hipError_t tune_tiles(mgrit_handle *h) {
 }
 
 mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *stream, void *ws, uint64_t ws_bytes,
-                        mgrit_handle **out) {
+                        mgrit_handle **out, bool noalloc) {
   g_setup_error.clear();
   if (out) *out = nullptr;
   if (!P || !O || !out) {
@@ -1502,7 +1508,16 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
     return bad(MGRIT_EDEVICE, "table upload");
   }
   // pinned host words: the norm read back by mgrit_residual and the mapped,
-  // coherent copy of the iteration state
+  // coherent copy of the iteration state (allocation-free mode: plain host
+  // words, filled by copies the host waits for)
+  if (noalloc) {
+    h->noalloc = true;
+    h->normsum_host = &h->norm_local;
+    h->ctl_host = &h->ctl_local;
+    h->ctl_host_dev = nullptr;
+    *out = h;
+    return MGRIT_OK;
+  }
   char *slot_dev = nullptr;
   if (!pinned_slot_take(h->host_arena, slot_dev) ||
       hipEventCreateWithFlags(&h->ctl_ev, hipEventDisableTiming) != hipSuccess) {
@@ -1746,7 +1761,12 @@ mgrit_status queue_iteration(mgrit_handle *h) {
   }
   HIPCHK(h, run_fine(h, MGRIT_PROF_FINE_RELAX, MODE_PASS_B, L0.c[ss.cur], nullptr, L0.r, nullptr));
   HIPCHK(h, launch_solve_ctl(h->normpart, fine_norm_parts(h), h->ctl, h->ctl_host_dev, h->gsync, rule, h->stream));
-  HIPCHK(h, hipEventRecord(h->ctl_ev, h->stream));
+  if (h->noalloc) {
+    // the state the host reads once the correction below has been queued
+    HIPCHK(h, hipMemcpyAsync(&h->ctl_local, h->ctl, sizeof(SolveCtl), hipMemcpyDeviceToHost, h->stream));
+  } else {
+    HIPCHK(h, hipEventRecord(h->ctl_ev, h->stream));
+  }
   h->guard = &h->ctl->stop;
   const mgrit_status st = vcycle(h, L0.r, L0.c[ss.cur]);
   h->guard = nullptr;
@@ -2910,3 +2930,67 @@ void mgrit2d_destroy(mgrit2d_handle *h) {
 }
 
 }  // extern "C"
+
+namespace mgrit {
+
+// The allocation-free solve behind mgrit_solve_noalloc (mgrit_noalloc.hip):
+// set up a float64 handle inside the device workspace ws (no device, pinned
+// or event allocations), solve with the host waiting for each stopping
+// decision, and release the host-side handle.  Messages go to the
+// thread's setup-error string (mgrit_last_error(NULL)).
+mgrit_status noalloc_solve(const mgrit_problem *P, const mgrit_options *O, void *stream, void *ws,
+                           uint64_t ws_bytes, const double *u0, const double *v_init, double *u_out,
+                           double *u_final, mgrit_stats *stats) {
+  if (!P || !O) {
+    g_setup_error = "null argument";
+    return MGRIT_EINVAL;
+  }
+  if (O->precision != MGRIT_PREC_FP64) {
+    g_setup_error = "the allocation-free solve runs float64 problems only";
+    return MGRIT_EINVAL;
+  }
+  if (O->tile_tune) {
+    g_setup_error = "the allocation-free solve takes no tile tuning (it times launches with events)";
+    return MGRIT_EINVAL;
+  }
+  if (!u0) {
+    g_setup_error = "u0 is required";
+    return MGRIT_EINVAL;
+  }
+  uint64_t need = 0;
+  mgrit_status st = mgrit_workspace_bytes(P, O, &need);
+  if (st != MGRIT_OK) {
+    g_setup_error = "invalid problem or options";
+    return st;
+  }
+  if (need > ws_bytes) {
+    g_setup_error = "the problem needs " + std::to_string(need) + " bytes of workspace; the allocation-free solve has " +
+                    std::to_string(ws_bytes);
+    return MGRIT_EINVAL;
+  }
+  mgrit_handle *h = nullptr;
+  st = setup_impl(P, O, stream, ws, ws_bytes, &h, true);
+  if (st != MGRIT_OK) return st;
+  auto &ss = h->ss;
+  st = mgrit_solve_start(h, u0, v_init, u_out, u_final);
+  while (st == MGRIT_OK && !ss.finished) {
+    // the iteration's state reached ctl_local by a copy queued before its
+    // coarse-grid correction; the next iteration is queued after the decision
+    if (hipError_t e = hipStreamSynchronize(h->stream)) {
+      st = hipfail(h, e, "stream");
+      break;
+    }
+    st = take_decision(h);
+    if (st == MGRIT_OK && !ss.finished) st = queue_iteration(h);
+  }
+  if (st == MGRIT_OK) {
+    st = mgrit_solve_finish(h, stats);
+  } else {
+    (void)hipStreamSynchronize(h->stream);
+  }
+  g_setup_error = (st == MGRIT_OK) ? std::string() : h->err;
+  mgrit_destroy(h);
+  return st;
+}
+
+}  // namespace mgrit

@@ -70,7 +70,7 @@ class Profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64 * len(PROF_PHASES)), ("total_ms", ctypes.c_double * len(PROF_PHASES))]
 
 
-EXPORTED = ["mgrit_setup", "mgrit_setup_ws", "mgrit_solve", "mgrit_solve_start", "mgrit_solve_advance", "mgrit_solve_finish",
+EXPORTED = ["mgrit_setup", "mgrit_setup_ws", "mgrit_solve", "mgrit_solve_noalloc", "mgrit_solve_start", "mgrit_solve_advance", "mgrit_solve_finish",
             "mgrit_workspace_bytes", "mgrit_residual", "mgrit_sequential", "mgrit_apply_step",
             "mgrit_num_levels", "mgrit_level_info", "mgrit_lfa_rho", "mgrit_profile_enable",
             "mgrit_profile_read", "mgrit_status_string", "mgrit_last_error", "mgrit_destroy",
@@ -95,6 +95,8 @@ def lib():
         L.mgrit_setup_ws.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options), vp, vp, ctypes.c_uint64,
                                      ctypes.POINTER(vp)]
         L.mgrit_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(Stats)]
+        L.mgrit_solve_noalloc.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options), vp, vp, vp, vp, vp,
+                                          ctypes.POINTER(Stats)]
         L.mgrit_solve_start.argtypes = [vp, vp, vp, vp, vp]
         L.mgrit_solve_advance.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
         L.mgrit_solve_finish.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -127,7 +129,7 @@ def lib():
         L.mgrit2d_destroy.restype = None
         for name in ("mgrit2d_setup", "mgrit2d_solve", "mgrit2d_sequential", "mgrit2d_apply_step"):
             getattr(L, name).restype = ctypes.c_int
-        for name in ("mgrit_setup", "mgrit_setup_ws", "mgrit_solve", "mgrit_solve_start", "mgrit_solve_advance", "mgrit_solve_finish",
+        for name in ("mgrit_setup", "mgrit_setup_ws", "mgrit_solve", "mgrit_solve_noalloc", "mgrit_solve_start", "mgrit_solve_advance", "mgrit_solve_finish",
                      "mgrit_workspace_bytes", "mgrit_residual", "mgrit_sequential", "mgrit_apply_step",
                      "mgrit_level_info", "mgrit_lfa_rho", "mgrit_profile_enable", "mgrit_profile_read"):
             getattr(L, name).restype = ctypes.c_int
@@ -160,6 +162,27 @@ def make_options(m, max_levels=2, min_coarse_nt=0, nu=1, coarse="sl_corrected", 
     o.inner_max_iter = inner_max_iter
     o.tile_tune = tile_tune
     return o
+
+
+def solve_noalloc(problem, options, u0, v_init=None, u_out=None, u_final=None, stream=None, history_cap=128,
+                  allow=(OK, ENOTCONVERGED)):
+    """mgrit_solve_noalloc: the float64 solve in one call that allocates no
+    device memory (its workspace is the library's per-device static array)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    nx, nt = problem.nx, problem.nt
+    hist = (ctypes.c_double * history_cap)()
+    stats = Stats()
+    stats.res_history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+    stats.res_history_cap = history_cap
+    st = lib().mgrit_solve_noalloc(ctypes.byref(problem), ctypes.byref(options), ctypes.c_void_p(stream.cuda_stream),
+                                   _ptr(u0, (nx,)), _ptr(v_init, (nt + 1, nx)), _ptr(u_out, (nt + 1, nx)),
+                                   _ptr(u_final, (nx,)), ctypes.byref(stats))
+    if st not in allow:
+        raise MgritError(st, lib().mgrit_last_error(None).decode())
+    return dict(status=st, iterations=stats.iterations, res0=stats.res0, res_final=stats.res_final,
+                conv_factor=stats.conv_factor, res_history=list(hist[:stats.res_history_len]))
 
 
 def workspace_bytes(problem, options):
