@@ -668,6 +668,10 @@ struct mgrit_handle {
   SolveCtl *ctl = nullptr;       // device iteration state of mgrit_solve
   SolveCtl *ctl_host = nullptr;  // pinned coherent copy, read once per iteration
   SolveCtl *ctl_host_dev = nullptr;  // the same memory as the device addresses it
+  // mixed precision: the outer refinement loop's state, on the device, and
+  // its pinned copy
+  SolveCtl *octl = nullptr;
+  SolveCtl *octl_host = nullptr, *octl_host_dev = nullptr;
   hipEvent_t ctl_ev = nullptr;
   const int *guard = nullptr;    // stop flag handed to the passes being queued
   // persistent coarse V-cycle (one cooperative launch per iteration)
@@ -1424,6 +1428,8 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
   off += al(sizeof(double));
   const size_t o_ctl = off;
   off += al(sizeof(SolveCtl));
+  const size_t o_octl = off;
+  off += al(sizeof(SolveCtl));
   if (ws) {
     if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) {
       mgrit_destroy(h);
@@ -1501,6 +1507,7 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
   h->normpart = (double *)(base + o_np);
   h->normsum = (double *)(base + o_ns);
   h->ctl = (SolveCtl *)(base + o_ctl);
+  h->octl = (SolveCtl *)(base + o_octl);
   // on the handle's stream, where all of its work goes; the source is
   // pageable, so the call returns once it has been staged
   if (hipMemcpyAsync(base, up.data(), head, hipMemcpyHostToDevice, h->stream) != hipSuccess) {
@@ -1524,7 +1531,10 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
     mgrit_destroy(h);
     return bad(MGRIT_ENOMEM, "pinned host words");
   }
+  static_assert(sizeof(SolveCtl) <= 64, "pinned slot layout: norm at 0, outer state at 64, state at 128");
   h->normsum_host = (double *)h->host_arena;
+  h->octl_host = (SolveCtl *)(h->host_arena + 64);
+  h->octl_host_dev = (SolveCtl *)(slot_dev + 64);
   h->ctl_host = (SolveCtl *)(h->host_arena + 128);
   h->ctl_host_dev = (SolveCtl *)(slot_dev + 128);
   if (O->tile_tune && h->lv[0].tiles && nlev >= 2) {
@@ -1880,8 +1890,11 @@ mgrit_status vcycle32(mgrit_handle *h, int l, const float *g, float *parent) {
 
 // Float32 MGRIT for A e = g32 (rows 1..nt), e_0 = 0, zero initial iterate,
 // until the C-point residual falls by inner_rtol (or inner_max_iter); every
-// row of e lands in e32.  Returns the iterations performed in *iters.
-mgrit_status inner_solve(mgrit_handle *h, int *iters, int *stop) {
+// row of e lands in e32.  Queued behind the outer stopping decision: every
+// launch skips itself once *gate (the outer stop flag) is set, which the
+// inner state reports as STOP_OUTER.  Returns the iterations performed in
+// *iters and the inner stop code in *stop.
+mgrit_status inner_solve(mgrit_handle *h, const int *gate, int *iters, int *stop) {
   Level &L0 = h->lv[0];
   const int nx = (int)h->prob.nx;
   const int64_t nc = L0.nt / L0.m;
@@ -1889,9 +1902,13 @@ mgrit_status inner_solve(mgrit_handle *h, int *iters, int *stop) {
   // iterate: an iteration that gains less than a factor 2 ends the solve
   const StopRule rule{h->opt.inner_rtol, h->opt.diverge_factor, h->opt.inner_max_iter, 0.5};
   int cur = 0;
-  HIPCHK(h, launch_fill32(L0.c32[0], (nc + 1) * (int64_t)nx, h->stream));
-  HIPCHK(h, hipMemsetAsync(h->ctl, 0, sizeof(SolveCtl), h->stream));
+  HIPCHK(h, launch_ctl_reset(h->ctl, gate, h->stream));
+  h->guard = &h->ctl->stop;
+  HIPCHK(h, launch_fill32(L0.c32[0], (nc + 1) * (int64_t)nx, h->stream, h->guard));
   for (;;) {
+    // every launch of the iteration skips itself once the inner state has
+    // stopped (its correction is queued before the decision is known)
+    h->guard = &h->ctl->stop;
     for (int s = 0; s < h->opt.nu; ++s) {
       HIPCHK(h, run_pass32(h, L0, MGRIT_PROF_FINE_RELAX, MODE_PASS_A, L0.m, nc, L0.c32[cur], L0.c32[1 - cur], h->g32,
                            nullptr, nullptr, nullptr, 0));
@@ -1901,9 +1918,6 @@ mgrit_status inner_solve(mgrit_handle *h, int *iters, int *stop) {
                          nullptr, nullptr, 0));
     HIPCHK(h, launch_solve_ctl(h->normpart, nc, h->ctl, h->ctl_host_dev, nullptr, rule, h->stream));
     HIPCHK(h, hipEventRecord(h->ctl_ev, h->stream));
-    // the correction is queued before the decision is known and skips
-    // itself once the stop flag is set
-    h->guard = &h->ctl->stop;
     const mgrit_status st = vcycle32(h, 1, L0.r32, L0.c32[cur]);
     h->guard = nullptr;
     if (st != MGRIT_OK) return st;
@@ -1915,8 +1929,10 @@ mgrit_status inner_solve(mgrit_handle *h, int *iters, int *stop) {
       break;
     }
   }
+  h->guard = gate;
   HIPCHK(h, run_pass32(h, L0, MGRIT_PROF_FINAL, MODE_FINAL_F, L0.m, nc, L0.c32[cur], nullptr, h->g32, nullptr, nullptr,
                        h->e32, 0));
+  h->guard = nullptr;
   return MGRIT_OK;
 }
 
@@ -1939,41 +1955,45 @@ mgrit_status mp_solve(mgrit_handle *h, const double *u0, const double *v_init, d
   double res0 = NAN, rho = NAN, prev = NAN;
   int outer = 0, inner_total = 0;
   mgrit_status status = MGRIT_OK;
+  // the outer loop's state lives on the device: its norm and stopping test
+  // (then max_iter, then growth) run in solve_ctl_kernel, and the refinement
+  // step queued behind it skips itself once the test says stop; the host
+  // reads the decision from pinned memory while that step runs
+  const StopRule orule{h->opt.rtol, h->opt.diverge_factor, h->opt.max_iter, 0.0};
+  const int *ostop = &h->octl->stop;
+  HIPCHK(h, hipMemsetAsync(h->octl, 0, sizeof(SolveCtl), h->stream));
   for (;;) {
-    // float64: r = g - A u at every time point, and its norm
+    // float64: r = g - A u at every time point, its norm and the test
     HIPCHK(h, run_pass(h, L0, MGRIT_PROF_RESIDUAL, MODE_RESID, 1, nt, U, nullptr, nullptr, h->r64, nullptr, nullptr,
                        0));
-    hipError_t e;
-    prev = rho;
-    rho = reduce_norm(h, nt, e);
-    if (e) return hipfail(h, e, "outer residual norm");
-    hist.push_back(rho);
-    if (outer == 0) res0 = rho;
-    if (!std::isfinite(rho)) {
-      status = fail(h, MGRIT_EDIVERGED, "non-finite residual");
-      break;
-    }
-    if (rho <= h->opt.rtol * res0) break;
-    if (outer >= h->opt.max_iter) {
-      status = MGRIT_ENOTCONVERGED;
-      h->err = "max_iter reached";
-      break;
-    }
-    if (h->opt.diverge_factor > 0 && rho > h->opt.diverge_factor * res0) {
-      status = fail(h, MGRIT_EDIVERGED, "residual grew past diverge_factor * res0");
-      break;
-    }
-    // float32: A e = r, then u += e in float64
-    HIPCHK(h, launch_round32(h->r64, h->g32, pts, h->stream));
+    HIPCHK(h, launch_solve_ctl(h->normpart, nt, h->octl, h->octl_host_dev, nullptr, orule, h->stream));
+    // float32: A e = r, then u += e in float64; all skipped after a stop
+    HIPCHK(h, launch_round32(h->r64, h->g32, pts, h->stream, ostop));
     int iters = 0, stop = 0;
-    const mgrit_status st = inner_solve(h, &iters, &stop);
+    const mgrit_status st = inner_solve(h, ostop, &iters, &stop);
     if (st != MGRIT_OK) return st;
+    // the inner solve's first decision came after the outer one: the outer
+    // state in pinned memory is current
+    const SolveCtl oc = *h->octl_host;
+    prev = rho;
+    rho = oc.rho;
+    res0 = oc.res0;
+    hist.push_back(rho);
+    if (oc.stop != STOP_NONE) {
+      if (oc.stop == STOP_NONFINITE) status = fail(h, MGRIT_EDIVERGED, "non-finite residual");
+      if (oc.stop == STOP_MAX_ITER) {
+        status = MGRIT_ENOTCONVERGED;
+        h->err = "max_iter reached";
+      }
+      if (oc.stop == STOP_DIVERGED) status = fail(h, MGRIT_EDIVERGED, "residual grew past diverge_factor * res0");
+      break;
+    }
     inner_total += iters;
     if (stop == STOP_NONFINITE || stop == STOP_DIVERGED) {
       status = fail(h, MGRIT_EDIVERGED, "the float32 inner solve diverged");
       break;
     }
-    HIPCHK(h, launch_add32(U, h->e32, pts + nx, h->stream));
+    HIPCHK(h, launch_add32(U, h->e32, pts + nx, h->stream, ostop));
     ++outer;
   }
   if (u_final) HIPCHK(h, hipMemcpyAsync(u_final, U + pts, nx * sizeof(double), hipMemcpyDeviceToDevice, h->stream));

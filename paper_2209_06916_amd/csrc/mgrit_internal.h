@@ -207,7 +207,8 @@ enum StopCode : int {
   STOP_NONFINITE = 3,
   STOP_DIVERGED = 4,
   STOP_DEVICE = 5,  // a persistent launch gave up at a grid barrier
-  STOP_STALLED = 6  // the residual fell by less than StopRule::stall in one iteration
+  STOP_STALLED = 6,  // the residual fell by less than StopRule::stall in one iteration
+  STOP_OUTER = 7     // an inner solve queued behind an outer stop: skipped
 };
 struct SolveCtl {
   double res0;  // ||r_0||
@@ -314,14 +315,16 @@ hipError_t launch_fill(double *dst, int64_t n, double value, hipStream_t stream,
 hipError_t launch_pass32(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs32 &pa,
                          hipStream_t stream);
 hipError_t launch_fill32(float *dst, int64_t n, hipStream_t stream, const int *stop = nullptr);
-// dst[i] = (float) src[i]
-hipError_t launch_round32(const double *src, float *dst, int64_t n, hipStream_t stream);
-// u[i] += (double) e[i]
-hipError_t launch_add32(double *u, const float *e, int64_t n, hipStream_t stream);
+// dst[i] = (float) src[i] (nothing once *stop != 0, when stop is given)
+hipError_t launch_round32(const double *src, float *dst, int64_t n, hipStream_t stream, const int *stop = nullptr);
+// u[i] += (double) e[i] (nothing once *stop != 0, when stop is given)
+hipError_t launch_add32(double *u, const float *e, int64_t n, hipStream_t stream, const int *stop = nullptr);
+// *ctl = zero state, stopped with STOP_OUTER when gate && *gate
+hipError_t launch_ctl_reset(SolveCtl *ctl, const int *gate, hipStream_t stream);
 // Sum the n norm partials in a fixed order, set ctl->rho = sqrt(sum) and take
 // the stopping decision of iteration ctl->it (ctl zeroed before the first
-// call of a solve); the new state is also written to ctl_host (pinned host
-// memory) when it is not NULL.
+// call of a solve; a state that has stopped stays as it is); the state is
+// also written to ctl_host (pinned host memory) when it is not NULL.
 struct GridSync;
 hipError_t launch_solve_ctl(const double *part, int64_t n, SolveCtl *ctl, SolveCtl *ctl_host, const GridSync *gs,
                             StopRule rule, hipStream_t stream);

@@ -56,6 +56,10 @@ __global__ void __launch_bounds__(RED_T) solve_ctl_kernel(const double *__restri
   __shared__ double red[RED_T / WAVE];
   const double ss = block_sum(part, n, red);
   if (threadIdx.x != 0) return;
+  if (ctl->stop != STOP_NONE) {  // a stop is final (the passes before this launch were skipped)
+    if (ctl_host) *ctl_host = *ctl;
+    return;
+  }
   const double rho = sqrt(ss);
   const int it = ctl->it;
   const double prev = ctl->rho;
@@ -103,14 +107,26 @@ __global__ void fill32_kernel(float *__restrict__ dst, int64_t n, const int *sto
     dst[i] = 0.0f;
 }
 
-__global__ void round32_kernel(const double *__restrict__ src, float *__restrict__ dst, int64_t n) {
+__global__ void round32_kernel(const double *__restrict__ src, float *__restrict__ dst, int64_t n, const int *stop) {
+  if (stop && *stop) return;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = (float)src[i];
 }
 
-__global__ void add32_kernel(double *__restrict__ u, const float *__restrict__ e, int64_t n) {
+__global__ void add32_kernel(double *__restrict__ u, const float *__restrict__ e, int64_t n, const int *stop) {
+  if (stop && *stop) return;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     u[i] += (double)e[i];
+}
+
+// Start a solve's iteration state: zero, or already stopped (STOP_OUTER)
+// when the gate is set (the outer refinement loop has stopped, so the inner
+// solve queued behind its decision does nothing).
+__global__ void ctl_reset_kernel(SolveCtl *ctl, const int *gate) {
+  if (threadIdx.x != 0) return;
+  SolveCtl c{};
+  c.stop = (gate && *gate) ? STOP_OUTER : STOP_NONE;
+  *ctl = c;
 }
 
 unsigned grid_for(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 65536); }
@@ -153,15 +169,20 @@ hipError_t launch_fill32(float *dst, int64_t n, hipStream_t stream, const int *s
   return hipGetLastError();
 }
 
-hipError_t launch_round32(const double *src, float *dst, int64_t n, hipStream_t stream) {
+hipError_t launch_round32(const double *src, float *dst, int64_t n, hipStream_t stream, const int *stop) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(round32_kernel, dim3(grid_for(n)), dim3(256), 0, stream, src, dst, n);
+  hipLaunchKernelGGL(round32_kernel, dim3(grid_for(n)), dim3(256), 0, stream, src, dst, n, stop);
   return hipGetLastError();
 }
 
-hipError_t launch_add32(double *u, const float *e, int64_t n, hipStream_t stream) {
+hipError_t launch_add32(double *u, const float *e, int64_t n, hipStream_t stream, const int *stop) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(add32_kernel, dim3(grid_for(n)), dim3(256), 0, stream, u, e, n);
+  hipLaunchKernelGGL(add32_kernel, dim3(grid_for(n)), dim3(256), 0, stream, u, e, n, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_ctl_reset(SolveCtl *ctl, const int *gate, hipStream_t stream) {
+  hipLaunchKernelGGL(ctl_reset_kernel, dim3(1), dim3(64), 0, stream, ctl, gate);
   return hipGetLastError();
 }
 

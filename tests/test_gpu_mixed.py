@@ -121,3 +121,25 @@ def test_mixed_solve_keeps_the_iterate_in_its_workspace_without_u_out():
     assert info["status"] == mgrit.OK
     ref = omg.sequential(disc.MOLStep(3, "erk", 3, 0.8), u0, nt)[-1]
     assert np.linalg.norm(fin.cpu().numpy() - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_outer_test_on_the_device_matches_the_residual_entry_point():
+    """The float64 outer loop takes its norm and stopping decision on the
+    device: its last recorded residual is the norm mgrit_residual computes
+    for the returned iterate, and an outer iteration limit ends the loop
+    with ENOTCONVERGED after exactly that many refinement steps."""
+    _announce("mixed outer decisions")
+    nx, nt, ms = 1024, 256, [4, 4]
+    u0 = _t(inputs.u0_fourier(nx, 11))
+    for max_iter, want in ((1, mgrit.ENOTCONVERGED), (20, mgrit.OK)):
+        opts = mgrit.make_options(ms, max_levels=3, rtol=1e-12, max_iter=max_iter, precision="mixed",
+                                  diverge_factor=0.0)
+        s = mgrit.Solver(mgrit.make_problem(nx, nt, 0.85, 3), opts)
+        out = torch.empty((nt + 1, nx), dtype=torch.float64, device=DEV)
+        info = s.solve(u0, u_out=out)
+        assert info["status"] == want
+        assert len(info["res_history"]) == info["iterations"] + 1
+        if max_iter == 1:
+            assert info["iterations"] == 1
+        assert s.residual(out) == pytest.approx(info["res_final"], rel=1e-13)
+        s.close()
