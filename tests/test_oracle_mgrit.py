@@ -264,3 +264,97 @@ def test_rediscretisation_converges_slower_than_the_corrected_sl_operator():
         _, info = mgrit.solve(H, u0, v, rtol=1e-10, max_iter=30)
         its[coarse] = info["iterations"]
     assert its["redisc"] > its["sl_corrected"]
+
+
+def _dense_operator(step, nx):
+    """The matrix of a linear time-stepper: its action on the unit vectors."""
+    return step(np.eye(nx)).T
+
+
+def _dense_vcycle_iterates(Phis, ms, u0, v_init, iters, nu=1):
+    """MGRIT of Sec. 2.2 written out with dense space-time matrices, as an
+    independent rewrite of the oracle's schedule: on each level the system
+    A v = g with A block lower bidiagonal (I on the diagonal, -Phi_l below);
+    F-relaxation solves A_FF v_F = g_F - A_FC v_C, C-relaxation sets
+    v_C = g_C - A_CF v_F, the C-point residual r_C = (g - A v)_C is injected
+    as the next level's right-hand side (its first entry, C-point 0, is 0),
+    the next level starts from zero, the coarsest level is solved directly,
+    the correction is added at the C-points and F-relaxation follows.
+    Returns the C-points after every level-0 pre-relaxation (what the
+    oracle records as iterates)."""
+    nx = len(u0)
+
+    def system(l, nt):
+        A = np.eye((nt + 1) * nx)
+        for n in range(1, nt + 1):
+            A[n * nx:(n + 1) * nx, (n - 1) * nx:n * nx] = -Phis[l]
+        return A
+
+    def split(nt, m):
+        cidx = np.concatenate([np.arange(k * nx, (k + 1) * nx) for k in range(0, nt + 1, m)])
+        fidx = np.setdiff1d(np.arange((nt + 1) * nx), cidx)
+        return cidx, fidx
+
+    def f_relax(A, v, g, cidx, fidx):
+        v[fidx] = np.linalg.solve(A[np.ix_(fidx, fidx)], g[fidx] - A[np.ix_(fidx, cidx)] @ v[cidx])
+
+    def c_relax(A, v, g, cidx, fidx):
+        v[cidx] = g[cidx] - A[np.ix_(cidx, fidx)] @ v[fidx]
+
+    def cycle(l, nt, g):
+        A = system(l, nt)
+        if l == len(ms):
+            return np.linalg.solve(A, g)
+        m = ms[l]
+        cidx, fidx = split(nt, m)
+        v = np.zeros_like(g)
+        f_relax(A, v, g, cidx, fidx)
+        for _ in range(nu):
+            c_relax(A, v, g, cidx, fidx)
+            f_relax(A, v, g, cidx, fidx)
+        r = (g - A @ v)[cidx]
+        e = cycle(l + 1, nt // m, r)
+        v[cidx] += e
+        f_relax(A, v, g, cidx, fidx)
+        return v
+
+    nt = v_init.shape[0] - 1
+    m = ms[0]
+    A = system(0, nt)
+    cidx, fidx = split(nt, m)
+    g = np.zeros((nt + 1) * nx)
+    g[:nx] = u0
+    v = v_init.reshape(-1).copy()
+    v[:nx] = u0
+    out = []
+    for it in range(iters):
+        f_relax(A, v, g, cidx, fidx)
+        for _ in range(nu):
+            c_relax(A, v, g, cidx, fidx)
+            f_relax(A, v, g, cidx, fidx)
+        out.append(v[cidx].reshape(-1, nx).copy())
+        r = (g - A @ v)[cidx]
+        v[cidx] += cycle(1, nt // m, r)
+    return out
+
+
+@pytest.mark.parametrize("p,kind,q,c", [(1, "erk", 1, 0.85), (3, "erk", 3, 1.2), (5, "sdirk", 3, 0.5),
+                                        (3, "sdirk", 3, 5.0)])
+def test_vcycle_iterates_equal_a_dense_rewrite(p, kind, q, c):
+    """Three-level V-cycles (nx = 8, nt = 32, m = 2: 32 -> 16 -> 8 steps,
+    FCF): every iterate of the oracle equals the dense-matrix rewrite of the
+    cycle (block solves, injection, correction) with the same per-level
+    operators as dense matrices, to 1e-14 of the iterate's size, or u kappa
+    where larger (u = 2^-53, kappa the largest condition number of the level
+    operators: the dense solves' rounding grows with it; SDIRK3 + U3 at
+    c = 5 has kappa = 1.1e3)."""
+    nx, nt, ms = 8, 32, [2, 2]
+    H = mgrit.Hierarchy(nx, nt, p, kind, q, c, ms)
+    u0, v = _problem(nx, nt, seed=13)
+    _, info = mgrit.solve(H, u0, v, rtol=0.0, max_iter=6, record=True)
+    Phis = [_dense_operator(st, nx) for st in H.steps]
+    tol = max(1e-14, 2.0 ** -53 * max(np.linalg.cond(P) for P in Phis))
+    dense = _dense_vcycle_iterates(Phis, ms, u0, v, len(info["iterates"]))
+    assert len(dense) == 7
+    for it, (a, b) in enumerate(zip(info["iterates"], dense)):
+        assert np.max(np.abs(a - b)) <= tol * max(1.0, np.max(np.abs(b))), (it, np.max(np.abs(a - b)))
