@@ -76,7 +76,19 @@ typedef struct {
   double cfl;           /* c = alpha dt / h > 0                               */
   int32_t upwind_order; /* p in 1..5; the SL coarse operators need odd p      */
   int32_t rk_kind;      /* mgrit_rk_kind                                      */
-  int32_t rk_order;     /* q: ERK 1..5, SDIRK 1..3                            */
+  int32_t rk_order;     /* q: ERK 1..5, SDIRK 1..3 (built-in tableaux); with
+                           rk_stages > 0 the order the tableau claims        */
+  int32_t rk_stages;    /* 0: the built-in tableau of (rk_kind, rk_order);
+                           s in 1..7: the Butcher tableau below (Sec. 4.2).
+                           MGRIT_ERK needs rk_A strictly lower triangular,
+                           MGRIT_SDIRK lower triangular with one diagonal
+                           value gamma > 0 (singly diagonally implicit).  It
+                           must satisfy the linear order conditions
+                           b^T A^{j-1} 1 = 1/j!, j = 1..rk_order, to 1e-12,
+                           else setup returns MGRIT_EINVAL.  Both arrays are
+                           host memory, read during setup only.             */
+  const double *rk_A;   /* [s][s] row-major Butcher matrix                   */
+  const double *rk_b;   /* [s] weights                                        */
 } mgrit_problem;
 
 /* MGRIT parameters (Sec. 2.2, 6.3). */

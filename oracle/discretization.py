@@ -258,10 +258,11 @@ class MOLStep:
     The SDIRK solves use ``circulant_solve`` (FFT), not a banded factorisation.
     """
 
-    def __init__(self, p, kind, q, c):
+    def __init__(self, p, kind, q, c, tab=None):
         self.p, self.kind, self.q, self.c = p, kind, q, float(c)
         self.w = upwind_weights(p)
-        self.A, self.b = tableau(kind, q)
+        # tab: a caller's Butcher tableau (A, b) in place of the built-in one
+        self.A, self.b = tableau(kind, q) if tab is None else (np.asarray(tab[0], float), np.asarray(tab[1], float))
 
     def __call__(self, u):
         u = np.asarray(u, dtype=float)
@@ -373,7 +374,7 @@ def dmat_weights(k):
 # Correction coefficients (eqs. varphi-constant-MOL-SL, MOL-SL-corrected-multilevel)
 # ---------------------------------------------------------------------------
 
-def correction_coefficients(p, kind, q, c, ms):
+def correction_coefficients(p, kind, q, c, ms, tab=None):
     """Per-level coefficients for coarse levels l = 1..len(ms).
 
     ``ms[l-1]`` is the coarsening factor from level l-1 to level l, so level l
@@ -395,7 +396,7 @@ def correction_coefficients(p, kind, q, c, ms):
         phi_p,l = (-1)^{p+1} [-m_l f(eps_{l-1}) + f(eps_l)] + m_l phi_p,l-1,
         phi_q,l = (prod_{k<=l} m_k) (-c)^{q+1} e_RK.
     """
-    A, b = tableau(kind, q)
+    A, b = tableau(kind, q) if tab is None else (np.asarray(tab[0], float), np.asarray(tab[1], float))
     efd = e_fd_closed_form(p)
     erk = e_rk(A, b, q)
     sgn = (-1.0) ** (p + 1)

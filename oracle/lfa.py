@@ -32,16 +32,17 @@ def rho_two_level(lam, mu, m, nu):
         return float(np.max(np.abs(lam) ** (m * nu) * np.abs(lam ** m - mu) / (1.0 - np.abs(mu))))
 
 
-def rho_for(p, kind, q, c, m, nu=1, coarse="sl_corrected", n=1 << 11, drop=10):
+def rho_for(p, kind, q, c, m, nu=1, coarse="sl_corrected", n=1 << 11, drop=10, tab=None):
     """Two-level LFA estimate for the fine step (kind, q)+Up at CFL c and
-    coarsening factor m with the given coarse operator."""
+    coarsening factor m with the given coarse operator (tab: an optional
+    Butcher tableau in place of the built-in one)."""
     om = omega_samples(n, drop)
-    fine = disc.MOLStep(p, kind, q, c)
+    fine = disc.MOLStep(p, kind, q, c, tab)
     lam = fine.symbol(om)
     if coarse == "redisc":
-        mu = disc.MOLStep(p, kind, q, m * c).symbol(om)
+        mu = disc.MOLStep(p, kind, q, m * c, tab).symbol(om)
     else:
-        rec = disc.correction_coefficients(p, kind, q, c, [m])[0]
+        rec = disc.correction_coefficients(p, kind, q, c, [m], tab)[0]
         if coarse == "sl_plain":
             st = disc.CorrectedSLStep(p, q, rec["shift"], 0.0, 0.0)
         else:

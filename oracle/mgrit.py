@@ -33,14 +33,15 @@ from . import discretization as disc
 class Hierarchy:
     """Time-steppers and sizes of every level.
 
-    ``coarse`` selects the coarse operator: "sl_corrected" (the paper's
+    ``tab``: an optional Butcher tableau (A, b) in place of the built-in
+    one of (kind, q).  ``coarse`` selects the coarse operator: "sl_corrected" (the paper's
     eq. MOL-SL-corrected-multilevel), "sl_plain" (phi = 0), "ideal"
     (Psi = Phi^m; only meaningful for two levels) or "redisc" (the fine
     Runge-Kutta + upwind step taken with the level's step, i.e. at CFL number
     c m_0 ... m_{l-1}: the rediscretisation of Sec. 5 and Theorem 1).
     """
 
-    def __init__(self, nx, nt, p, kind, q, c, ms, coarse="sl_corrected"):
+    def __init__(self, nx, nt, p, kind, q, c, ms, coarse="sl_corrected", tab=None):
         self.nx, self.nt = nx, nt
         self.space = (nx,)  # shape of one time point's vector
         self.p, self.kind, self.q, self.c = p, kind, q, float(c)
@@ -50,7 +51,7 @@ class Hierarchy:
             if self.nts[-1] % m != 0:
                 raise ValueError("nt must be divisible by the product of the coarsening factors")
             self.nts.append(self.nts[-1] // m)
-        fine = disc.MOLStep(p, kind, q, c)
+        fine = disc.MOLStep(p, kind, q, c, tab)
         self.steps = [fine]
         self.coeffs = []
         if coarse == "ideal":
@@ -61,9 +62,9 @@ class Hierarchy:
             prod = 1
             for m in self.ms:
                 prod *= m
-                self.steps.append(disc.MOLStep(p, kind, q, self.c * prod))
+                self.steps.append(disc.MOLStep(p, kind, q, self.c * prod, tab))
         else:
-            self.coeffs = disc.correction_coefficients(p, kind, q, c, self.ms)
+            self.coeffs = disc.correction_coefficients(p, kind, q, c, self.ms, tab)
             for rec in self.coeffs:
                 if coarse == "sl_plain":
                     st = disc.CorrectedSLStep(p, q, rec["shift"], 0.0, 0.0)

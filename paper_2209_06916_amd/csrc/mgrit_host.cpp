@@ -210,6 +210,54 @@ bool make_tableau(int kind, int q, Tableau &T) {
   return false;
 }
 
+// A caller's Butcher tableau (rk_stages > 0): explicit = strictly lower
+// triangular A; singly diagonally implicit = lower triangular A with one
+// diagonal value gamma > 0 (every stage then solves with the same matrix,
+// which the polynomial-in-W form of the step needs).
+bool custom_tableau(const mgrit_problem &P, Tableau &T, std::string &err) {
+  const int s = P.rk_stages;
+  if (s < 1 || s > MAXCOEF - 1 || !P.rk_A || !P.rk_b) {
+    err = "custom tableau: rk_stages must be in 1..7 with rk_A and rk_b given";
+    return false;
+  }
+  T.s = s;
+  T.A.assign(s * s, 0);
+  T.b.assign(s, 0);
+  for (int i = 0; i < s * s; ++i) T.A[i] = P.rk_A[i];
+  for (int i = 0; i < s; ++i) T.b[i] = P.rk_b[i];
+  for (int i = 0; i < s * s; ++i)
+    if (!std::isfinite((double)T.A[i])) err = "custom tableau: non-finite entry";
+  for (int i = 0; i < s; ++i)
+    if (!std::isfinite((double)T.b[i])) err = "custom tableau: non-finite weight";
+  if (!err.empty()) return false;
+  for (int i = 0; i < s; ++i)
+    for (int j = i + 1; j < s; ++j)
+      if (T.A[i * s + j] != 0) {
+        err = "custom tableau: rk_A must be lower triangular";
+        return false;
+      }
+  if (P.rk_kind == MGRIT_ERK) {
+    for (int i = 0; i < s; ++i)
+      if (T.A[i * s + i] != 0) {
+        err = "custom explicit tableau: rk_A must be strictly lower triangular";
+        return false;
+      }
+  } else {
+    const ld g = T.A[0];
+    for (int i = 0; i < s; ++i)
+      if (T.A[i * s + i] != g) {
+        err = "custom implicit tableau: every diagonal entry of rk_A must equal the same gamma";
+        return false;
+      }
+    if (!(g > 0)) {
+      err = "custom implicit tableau: gamma must be positive";
+      return false;
+    }
+    T.gamma = g;
+  }
+  return true;
+}
+
 // Taylor coefficients beta_j of R(z) = 1 + z b^T (I - zA)^{-1} 1:
 // beta_0 = 1, beta_j = b^T A^{j-1} 1 (eq. RK_stab_def).
 std::vector<ld> rk_series(const Tableau &T, int jmax) {
@@ -845,7 +893,25 @@ mgrit_status fine_info(const mgrit_problem &P, FineInfo &fi, std::string &err) {
     err = "upwind_order must be in 1..5";
     return MGRIT_EINVAL;
   }
-  if (!make_tableau(P.rk_kind, P.rk_order, fi.tab)) {
+  if (P.rk_kind != MGRIT_ERK && P.rk_kind != MGRIT_SDIRK) {
+    err = "rk_kind must be MGRIT_ERK or MGRIT_SDIRK";
+    return MGRIT_EINVAL;
+  }
+  if (P.rk_stages != 0) {
+    if (!custom_tableau(P, fi.tab, err)) return MGRIT_EINVAL;
+    if (P.rk_order < 1 || P.rk_order > 2 * MAXCOEF) {
+      err = "custom tableau: rk_order out of range";
+      return MGRIT_EINVAL;
+    }
+    // the linear order conditions b^T A^{j-1} 1 = 1/j!, j = 1..q (Sec. 4.2)
+    const std::vector<ld> beta = rk_series(fi.tab, P.rk_order);
+    for (int j = 1; j <= P.rk_order; ++j)
+      if (std::fabs(beta[j] - 1 / factorial(j)) > 1e-12L / factorial(j)) {
+        err = "custom tableau fails the linear order condition b^T A^" + std::to_string(j - 1) + " 1 = 1/" +
+              std::to_string(j) + "!";
+        return MGRIT_EINVAL;
+      }
+  } else if (!make_tableau(P.rk_kind, P.rk_order, fi.tab)) {
     err = "unsupported Runge-Kutta method (ERK 1..5, SDIRK 1..3)";
     return MGRIT_EINVAL;
   }

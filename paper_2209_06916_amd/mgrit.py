@@ -31,7 +31,9 @@ class MgritError(RuntimeError):
 class Problem(ctypes.Structure):
     _fields_ = [("velocity", ctypes.c_double), ("x_lo", ctypes.c_double), ("x_hi", ctypes.c_double),
                 ("nx", ctypes.c_int64), ("nt", ctypes.c_int64), ("cfl", ctypes.c_double),
-                ("upwind_order", ctypes.c_int32), ("rk_kind", ctypes.c_int32), ("rk_order", ctypes.c_int32)]
+                ("upwind_order", ctypes.c_int32), ("rk_kind", ctypes.c_int32), ("rk_order", ctypes.c_int32),
+                ("rk_stages", ctypes.c_int32), ("rk_A", ctypes.POINTER(ctypes.c_double)),
+                ("rk_b", ctypes.POINTER(ctypes.c_double))]
 
 
 class Options(ctypes.Structure):
@@ -137,9 +139,19 @@ def lib():
     return _lib
 
 
-def make_problem(nx, nt, cfl, p, kind="erk", q=None, velocity=1.0, x_lo=-1.0, x_hi=1.0):
+def make_problem(nx, nt, cfl, p, kind="erk", q=None, velocity=1.0, x_lo=-1.0, x_hi=1.0, tableau=None):
+    """tableau: optional (A, b) Butcher tableau of `kind` (q is then the
+    order it claims); None selects the built-in tableau of (kind, q)."""
     q = p if q is None else q
-    return Problem(velocity, x_lo, x_hi, nx, nt, cfl, p, ERK if kind == "erk" else SDIRK, q)
+    pr = Problem(velocity, x_lo, x_hi, nx, nt, cfl, p, ERK if kind == "erk" else SDIRK, q)
+    if tableau is not None:
+        A = [float(x) for row in tableau[0] for x in row]
+        b = [float(x) for x in tableau[1]]
+        pr._arrays = ((ctypes.c_double * len(A))(*A), (ctypes.c_double * len(b))(*b))  # kept alive with pr
+        pr.rk_stages = len(b)
+        pr.rk_A = ctypes.cast(pr._arrays[0], ctypes.POINTER(ctypes.c_double))
+        pr.rk_b = ctypes.cast(pr._arrays[1], ctypes.POINTER(ctypes.c_double))
+    return pr
 
 
 def make_options(m, max_levels=2, min_coarse_nt=0, nu=1, coarse="sl_corrected", rtol=1e-10, max_iter=30,

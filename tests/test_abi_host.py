@@ -172,3 +172,38 @@ def test_2d_stability_limit_matches_the_oracle_symbol():
     below, _ = _setup2d_status(mgrit.make_problem_2d(64, 64, 16, lo * 0.999, 3), mgrit.make_options([4]))
     above, _ = _setup2d_status(mgrit.make_problem_2d(64, 64, 16, hi * 1.001, 3), mgrit.make_options([4]))
     assert below != mgrit.EUNSTABLE and above == mgrit.EUNSTABLE
+
+
+# Caller tableaux (Sec. 4.2): the four-stage third-order SSP method (its
+# stability polynomial has z^4/48, unlike the built-in ERK3) and the
+# two-stage third-order SDIRK method, gamma = (3 + sqrt 3)/6.
+SSP43 = ([[0, 0, 0, 0], [0.5, 0, 0, 0], [0.5, 0.5, 0, 0], [1 / 6, 1 / 6, 1 / 6, 0]], [1 / 6, 1 / 6, 1 / 6, 0.5])
+G23 = (3 + 3 ** 0.5) / 6
+SDIRK23 = ([[G23, 0], [1 - 2 * G23, G23]], [0.5, 0.5])
+
+
+@pytest.mark.parametrize("kind,q,tab,msg", [
+    ("erk", 3, ([[0, 0], [1, 0]], [0.5, 0.5]), "order condition"),        # Heun claims order 3
+    ("erk", 2, ([[0.1, 0], [1, 0]], [0.5, 0.5]), "strictly lower"),
+    ("sdirk", 2, ([[0.3, 0], [0.4, 0.5]], [0.5, 0.5]), "same gamma"),
+    ("sdirk", 1, ([[0.5, 0.1], [0.2, 0.5]], [0.5, 0.5]), "lower triangular"),
+    ("sdirk", 1, ([[-0.5, 0], [1.5, -0.5]], [0.5, 0.5]), "positive"),
+    ("erk", 1, ([[0] * 8 for _ in range(8)], [1] + [0] * 7), "1..7"),
+])
+def test_setup_rejects_invalid_tableaux(kind, q, tab, msg):
+    st, err = _setup_status(mgrit.make_problem(64, 32, 0.5, 3, kind, q, tableau=tab), mgrit.make_options(4))
+    assert st == mgrit.EINVAL, err
+    assert msg in err
+
+
+@pytest.mark.parametrize("p,kind,q,c,m,tab", [(3, "erk", 3, 1.0, 4, SSP43), (3, "sdirk", 3, 2.0, 8, SDIRK23),
+                                              (5, "erk", 3, 0.8, 8, SSP43)])
+def test_host_lfa_with_a_caller_tableau_matches_oracle(p, kind, q, c, m, tab):
+    """The host reads a caller's tableau: its LFA estimate (the fine step's
+    symbol and the correction coefficient's e_RK) equals the oracle's with
+    the same tableau, and differs from the built-in scheme's."""
+    got = mgrit.lfa_rho(mgrit.make_problem(256, 256, c, p, kind, q, tableau=tab), mgrit.make_options(m))
+    ref = lfa.rho_for(p, kind, q, c, m, tab=tab)
+    assert got == pytest.approx(ref, rel=1e-6)
+    builtin = lfa.rho_for(p, kind, q, c, m)
+    assert abs(builtin - ref) > 1e-4 * ref

@@ -322,6 +322,35 @@ def test_rediscretised_coarse_operator_matches_oracle(case):
     _check_parity(info, got, fin, ref, rinfo, case["ms"][0])
 
 
+SSP43 = ([[0, 0, 0, 0], [0.5, 0, 0, 0], [0.5, 0.5, 0, 0], [1 / 6, 1 / 6, 1 / 6, 0]], [1 / 6, 1 / 6, 1 / 6, 0.5])
+G23 = (3 + 3 ** 0.5) / 6
+SDIRK23 = ([[G23, 0], [1 - 2 * G23, G23]], [0.5, 0.5])
+
+
+@pytest.mark.parametrize("case", [
+    dict(nx=256, nt=256, p=3, kind="erk", q=3, c=1.0, ms=[4, 4], tab=SSP43),
+    dict(nx=2048, nt=128, p=3, kind="sdirk", q=3, c=2.0, ms=[8], tab=SDIRK23),
+    dict(nx=100, nt=64, p=5, kind="erk", q=3, c=0.8, ms=[4, 4], tab=SSP43),
+])
+def test_caller_tableau_solves_match_oracle(case):
+    """A Butcher tableau passed at the boundary (Sec. 4.2): the four-stage
+    third-order SSP method and the two-stage third-order SDIRK method, fine
+    steps and the correction coefficients' e_RK both from it; same
+    iterations and iterates as the oracle with the same tableau."""
+    c = case
+    _announce("tableau", c["kind"], c["nx"], c["nt"])
+    u0 = inputs.u0_fourier(c["nx"], 1401)
+    v0 = inputs.initial_iterate(c["nt"], c["nx"], u0, 1401)
+    s = mgrit.Solver(mgrit.make_problem(c["nx"], c["nt"], c["c"], c["p"], c["kind"], c["q"], tableau=c["tab"]),
+                     mgrit.make_options(c["ms"], max_levels=len(c["ms"]) + 1))
+    out = torch.empty((c["nt"] + 1, c["nx"]), dtype=torch.float64, device=DEV)
+    fin = torch.empty((c["nx"],), dtype=torch.float64, device=DEV)
+    info = s.solve(_t(u0), _t(v0), u_out=out, u_final=fin)
+    H = omg.Hierarchy(c["nx"], c["nt"], c["p"], c["kind"], c["q"], c["c"], c["ms"], tab=c["tab"])
+    ref, rinfo = omg.solve(H, u0, v0)
+    _check_parity(info, _np(out), _np(fin), ref, rinfo, c["ms"][0])
+
+
 def test_ideal_coarse_operator_one_iteration():
     _announce("ideal")
     s, info, got, fin, ref, rinfo = _solve_both(128, 128, 3, "erk", 3, 1.0, [8], coarse="ideal")

@@ -378,3 +378,19 @@ def test_dense_corrected_solve_matches_fft_solve():
         for j, wj in disc.sl_weights(3, eps).items():
             S[i, (i - K + j) % nx] += wj
     np.testing.assert_allclose(psi(v), np.linalg.solve(M, S @ v), atol=1e-13)
+
+
+def test_caller_tableau_stage_form_matches_its_stability_polynomial():
+    """The stage-form step with a caller's tableau (the four-stage
+    third-order SSP method) acts on each Fourier mode by its stability
+    polynomial R(z) = 1 + z + z^2/2 + z^3/6 + z^4/48 (z = -c Lhat(omega))."""
+    A = [[0, 0, 0, 0], [0.5, 0, 0, 0], [0.5, 0.5, 0, 0], [1 / 6, 1 / 6, 1 / 6, 0]]
+    b = [1 / 6, 1 / 6, 1 / 6, 0.5]
+    nx, c = 64, 0.9
+    st = disc.MOLStep(3, "erk", 3, c, (A, b))
+    k = 5
+    x = np.exp(2j * np.pi * k * np.arange(nx) / nx)
+    z = -c * disc.stencil_symbol(disc.upwind_weights(3), 2 * np.pi * k / nx)
+    R = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 48
+    got = st(x.real) + 1j * st(x.imag)
+    assert np.max(np.abs(got - R * x)) <= 1e-14
