@@ -117,6 +117,14 @@ typedef struct {
                             launch-cost model; 1 = time the candidate widths
                             on the device at setup and keep the fastest
                             (cached per process by nx, m, scheme and N_c)    */
+  uint64_t init_seed;    /* initial iterate when mgrit_solve gets no v_init:
+                            0 = zero; otherwise every point (n, i), n >= 1,
+                            that the solve reads (the C-points; in mixed
+                            precision every point) is U[0,1) from SplitMix64
+                            seeded with init_seed: the k-th output,
+                            k = (n-1) nx + i, mixes init_seed + (k+1) *
+                            0x9E3779B97F4A7C15 and keeps its top 53 bits
+                            (the paper's random initial iterate, Sec. 5.3) */
 } mgrit_options;
 
 /* Arithmetic of mgrit_solve.
@@ -212,8 +220,10 @@ mgrit_status mgrit_setup_ws(const mgrit_problem *problem, const mgrit_options *o
 /* Solve the one-step system u_{n+1} = Phi u_n, u_0 = u0 (eq. one-step-general)
  * with MGRIT.
  *   u0_dev      [nx], required.
- *   v_init_dev  [nt+1][nx] initial iterate, or NULL for zero; only its
- *               C-points (rows k*m[0]) are read, row 0 is replaced by u0.
+ *   v_init_dev  [nt+1][nx] initial iterate; only its C-points (rows
+ *               k*m[0]) are read, row 0 is replaced by u0.  NULL: the
+ *               seeded U[0,1) iterate of options.init_seed, or zero when
+ *               init_seed is 0 (the 2D solve always takes zero).
  *   u_out_dev   [nt+1][nx] receives the final iterate at every time point,
  *               or NULL.
  *   u_final_dev [nx] receives row nt of the final iterate, or NULL.

@@ -2013,6 +2013,8 @@ mgrit_status mp_solve(mgrit_handle *h, const double *u0, const double *v_init, d
   // outer iterate: v_init (or zero) with row 0 = u0
   if (v_init && v_init != U) {
     HIPCHK(h, hipMemcpyAsync(U, v_init, (pts + nx) * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  } else if (!v_init && h->opt.init_seed) {
+    HIPCHK(h, launch_splitmix_rows(U + nx, nt, 1, 1, nx, h->opt.init_seed, h->stream));
   } else if (!v_init) {
     HIPCHK(h, launch_fill(U, pts + nx, 0.0, h->stream));
   }
@@ -2100,9 +2102,11 @@ mgrit_status mgrit_solve_start(mgrit_handle *h, const double *u0, const double *
   Level &L0 = h->lv[0];
   const int nx = (int)h->prob.nx;
   const int64_t nc = L0.nt / L0.m;
-  // initial C-points
+  // initial C-points: v_init's, seeded U[0,1), or zero
   if (v_init) {
     HIPCHK(h, launch_gather_rows(v_init, L0.m, L0.c[0], nc + 1, nx, h->stream));
+  } else if (h->opt.init_seed) {
+    HIPCHK(h, launch_splitmix_rows(L0.c[0] + nx, nc, L0.m, L0.m, nx, h->opt.init_seed, h->stream));
   } else {
     HIPCHK(h, launch_fill(L0.c[0], (nc + 1) * (int64_t)nx, 0.0, h->stream));
   }

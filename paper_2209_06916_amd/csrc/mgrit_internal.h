@@ -311,6 +311,10 @@ hipError_t launch_reduce(const double *part, int64_t n, double *out, hipStream_t
 hipError_t launch_gather_rows(const double *src, int64_t stride, double *dst, int64_t rows, int nx,
                               hipStream_t stream);
 hipError_t launch_fill(double *dst, int64_t n, double value, hipStream_t stream, const int *stop = nullptr);
+// rows r = 0..rows-1 of dst: time points n0 + r dn of the seeded U[0,1)
+// initial iterate (SplitMix64 output (n-1) nx + i at point (n, i))
+hipError_t launch_splitmix_rows(double *dst, int64_t rows, int64_t n0, int64_t dn, int nx, uint64_t seed,
+                                hipStream_t stream);
 // Float32 passes of the generic step kernel (mixed precision).
 hipError_t launch_pass32(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs32 &pa,
                          hipStream_t stream);

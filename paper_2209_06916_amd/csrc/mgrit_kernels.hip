@@ -95,6 +95,25 @@ __global__ void gather_rows_kernel(const double *__restrict__ src, int64_t strid
   }
 }
 
+// Seeded U[0,1) rows from SplitMix64 in counter form: dst row r holds time
+// point n = n0 + r * dn, and point (n, i) takes output k = (n-1) nx + i, i.e.
+// the state seed + (k+1) * gamma mixed, its top 53 bits scaled by 2^-53.
+__global__ void splitmix_rows_kernel(double *__restrict__ dst, int64_t rows, int64_t n0, int64_t dn, int nx,
+                                     uint64_t seed) {
+  const int64_t total = rows * (int64_t)nx;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / nx;
+    const int64_t col = i - r * nx;
+    const uint64_t k = (uint64_t)((n0 + r * dn - 1) * (int64_t)nx + col);
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    dst[i] = (double)(z >> 11) * 0x1p-53;
+  }
+}
+
 __global__ void fill_kernel(double *__restrict__ dst, int64_t n, double value, const int *stop) {
   if (stop && *stop) return;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -221,6 +240,15 @@ hipError_t launch_gather_rows(const double *src, int64_t stride, double *dst, in
   if (total <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
   hipLaunchKernelGGL(gather_rows_kernel, dim3(blocks), dim3(256), 0, stream, src, stride, dst, rows, nx);
+  return hipGetLastError();
+}
+
+hipError_t launch_splitmix_rows(double *dst, int64_t rows, int64_t n0, int64_t dn, int nx, uint64_t seed,
+                                hipStream_t stream) {
+  const int64_t total = rows * (int64_t)nx;
+  if (total <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(splitmix_rows_kernel, dim3(blocks), dim3(256), 0, stream, dst, rows, n0, dn, nx, seed);
   return hipGetLastError();
 }
 

@@ -41,7 +41,7 @@ class Options(ctypes.Structure):
                 ("min_coarse_nt", ctypes.c_int32), ("nu", ctypes.c_int32), ("cg_kind", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("diverge_factor", ctypes.c_double),
                 ("coarse_launch", ctypes.c_int32), ("precision", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
-                ("inner_max_iter", ctypes.c_int32), ("tile_tune", ctypes.c_int32)]
+                ("inner_max_iter", ctypes.c_int32), ("tile_tune", ctypes.c_int32), ("init_seed", ctypes.c_uint64)]
 
 
 class Stats(ctypes.Structure):
@@ -156,7 +156,7 @@ def make_problem(nx, nt, cfl, p, kind="erk", q=None, velocity=1.0, x_lo=-1.0, x_
 
 def make_options(m, max_levels=2, min_coarse_nt=0, nu=1, coarse="sl_corrected", rtol=1e-10, max_iter=30,
                  diverge_factor=1e8, coarse_launch=0, precision="fp64", inner_rtol=1e-5, inner_max_iter=30,
-                 tile_tune=0):
+                 tile_tune=0, init_seed=0):
     o = Options()
     o.max_levels = max_levels
     ms = list(m) if isinstance(m, (list, tuple)) else [m]
@@ -173,6 +173,7 @@ def make_options(m, max_levels=2, min_coarse_nt=0, nu=1, coarse="sl_corrected", 
     o.inner_rtol = inner_rtol
     o.inner_max_iter = inner_max_iter
     o.tile_tune = tile_tune
+    o.init_seed = init_seed
     return o
 
 

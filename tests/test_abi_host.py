@@ -207,3 +207,27 @@ def test_host_lfa_with_a_caller_tableau_matches_oracle(p, kind, q, c, m, tab):
     assert got == pytest.approx(ref, rel=1e-6)
     builtin = lfa.rho_for(p, kind, q, c, m)
     assert abs(builtin - ref) > 1e-4 * ref
+
+
+def test_seeded_initial_iterate_is_splitmix64():
+    """The seeded initial iterate's generator (inputs.splitmix64, the counter
+    form the library's kernel also computes) equals SplitMix64 run as the
+    stateful generator of its definition, written here with Python integers."""
+    from paper_2209_06916_amd import inputs
+    M = (1 << 64) - 1
+
+    def stateful(seed, n):
+        x, out = seed, []
+        for _ in range(n):
+            x = (x + 0x9E3779B97F4A7C15) & M
+            z = x
+            z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+            z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+            out.append(z ^ (z >> 31))
+        return out
+
+    for seed in (1, 1003, (1 << 64) - 5):
+        assert [int(v) for v in inputs.splitmix64(seed, np.arange(300))] == stateful(seed, 300)
+    v = inputs.initial_iterate_splitmix(4, 8, np.zeros(8), 1003)
+    assert np.all((v[1:] >= 0) & (v[1:] < 1))
+    assert v[2, 3] == (stateful(1003, 8 + 4)[-1] >> 11) * 2.0 ** -53

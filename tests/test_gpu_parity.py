@@ -580,3 +580,25 @@ def test_persistent_cycle_on_a_large_grid_agrees(monkeypatch):
         outs.append((info["iterations"], info["res_history"], _np(fin)))
     assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
     np.testing.assert_array_equal(outs[0][2], outs[1][2])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_seeded_initial_iterate_matches_the_explicit_one(precision):
+    """mgrit_solve without v_init and with options.init_seed draws the
+    SplitMix64 iterate on the device: the solve equals, bit for bit, the one
+    given that iterate (inputs.initial_iterate_splitmix) explicitly."""
+    _announce("seed", precision)
+    nx, nt, seed = 512, 256, 987654321
+    u0 = inputs.u0_fourier(nx, 3)
+    v0 = inputs.initial_iterate_splitmix(nt, nx, u0, seed)
+    prob = mgrit.make_problem(nx, nt, 0.85, 3)
+    kw = dict(max_levels=3, precision=precision, rtol=1e-10 if precision == "fp64" else 1e-12)
+    outs, infos = [], []
+    for v, sd in ((None, seed), (_t(v0), 0)):
+        s = mgrit.Solver(prob, mgrit.make_options([4, 4], init_seed=sd, **kw))
+        out = torch.empty((nt + 1, nx), dtype=torch.float64, device=DEV)
+        infos.append(s.solve(_t(u0), v, u_out=out))
+        outs.append(_np(out))
+    assert infos[0]["iterations"] == infos[1]["iterations"]
+    assert infos[0]["res_history"] == infos[1]["res_history"]
+    np.testing.assert_array_equal(outs[0], outs[1])
