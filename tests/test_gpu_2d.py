@@ -11,6 +11,7 @@ import torch
 
 from oracle import advection2d as a2
 from oracle import mgrit as omg
+from golden_check import check_against_golden, golden
 from paper_2209_06916_amd import inputs, mgrit
 
 pytestmark = pytest.mark.gpu
@@ -136,3 +137,39 @@ def test_mixed_precision_2d_matches_the_float64_oracle(case):
     per_t = np.linalg.norm((got - ref).reshape(nt + 1, -1), axis=1) / np.linalg.norm(ref.reshape(nt + 1, -1), axis=1)
     assert np.max(per_t) <= 1e-10, np.max(per_t)
     np.testing.assert_array_equal(_np(fin), got[-1])
+
+
+@pytest.mark.parametrize("n", [512, 1024])
+def test_config4_matches_the_oracles_stored_solve(n):
+    """Config 4 (u_t + a.grad u = 0, a = (0.85, 1.0), nx = ny = nt = n,
+    dt = h/2, ERK3 + U3 split, m = 8, 3 levels, 8 seeded bumps, seed 1004)
+    against the oracle's own solve of it, stored sampled by
+    tests/golden/make_config4.py: identical iterations and residual
+    history, every time point's norm and projection, the C-points' and a
+    few time points' samples.  n = 1024 is config 4 itself; n = 512 is the
+    same workload at half the resolution."""
+    import os
+    name = "config4_oracle.npz" if n == 1024 else "config4_oracle_%d.npz" % n
+    if not os.path.exists(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)):
+        pytest.skip("the oracle's stored solve at this size is not in tests/golden")
+    _announce("config4 golden", n)
+    g = golden(name)
+    nt, seed = n, 1004
+    u0 = inputs.u0_bumps_2d(n, n, 8, 0.1, seed)
+    rng = np.random.default_rng(seed)
+    v0 = torch.empty((nt + 1, n, n), dtype=torch.float64, device=DEV)
+    for k in range(0, nt + 1, 64):  # the same U[0,1) stream, drawn in blocks of rows
+        rows = min(64, nt + 1 - k)
+        v0[k:k + rows] = torch.from_numpy(rng.random((rows, n, n))).to(DEV)
+    v0[0] = _t(u0)
+    pr = mgrit.make_problem_2d(n, n, nt, 0.5, 3)
+    s = mgrit.Solver2D(pr, mgrit.make_options([8, 8], max_levels=3, rtol=1e-10, max_iter=30))
+    out = torch.empty((nt + 1, n, n), dtype=torch.float64, device=DEV)
+    info = s.solve(_t(u0), v0, u_out=out)
+    del v0
+    torch.cuda.synchronize()
+    assert info["status"] == mgrit.OK
+    cs, rs = n // 32, n // 128
+    check_against_golden(info, out, g, out[::8, ::cs, ::cs].cpu().numpy(), 8, 78,
+                         row_sample=lambda r: r[:, ::rs, ::rs])
+    s.close()

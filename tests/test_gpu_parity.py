@@ -15,6 +15,7 @@ import torch
 
 from oracle import discretization as disc
 from oracle import mgrit as omg
+from golden_check import check_against_golden, golden
 from paper_2209_06916_amd import inputs, mgrit
 
 pytestmark = pytest.mark.gpu
@@ -410,57 +411,12 @@ def test_config2_full_size_matches_oracle():
     _check_parity(info, got, fin, ref, rinfo, 8)
 
 
-def _golden(name):
-    import os
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
-    with np.load(path) as z:
-        return {k: z[k] for k in z.files}
-
-
-def _time_point_tol(n):
-    """Per-time-point bar for solutions n steps from t = 0: 1e-12, or 2 n u
-    (u = 2^-53) where that is larger.  Two implementations that round each
-    application of the same non-expansive step differently drift apart by up
-    to about n u after n dependent steps, so past n = 4096 the bar grows with
-    n (at n = 16384 it is 3.6e-12)."""
-    return np.maximum(1e-12, 2.0 * np.asarray(n, dtype=float) * 2.0 ** -53)
-
-
-def _check_against_golden(info, out, g, c_sample, m, w_seed):
-    """The oracle's full-size solve, stored sampled (see the scripts that
-    write the golden files): identical iteration count, residual history,
-    per-time-point norms and projections, every C-point's sampled values
-    (c_sample: the same sampling of the GPU solution, C-points every m steps)
-    and a few whole time points, each within _time_point_tol."""
-    assert info["iterations"] == int(g["iterations"])
-    np.testing.assert_allclose(info["res_history"], g["res_history"], rtol=1e-8, atol=1e-14 * g["res_history"][0])
-    flat = out.reshape(out.shape[0], -1)
-    tol_t = _time_point_tol(np.arange(flat.shape[0]))
-    norms = torch.linalg.vector_norm(flat, dim=1).cpu().numpy()
-    e_norm = np.abs(norms - g["norms"]) / g["norms"] / tol_t
-    # <w, e_n> for a random sign vector w is about ||e_n||: 1e-12 of ||u_n||
-    # per time point, with a factor 8 for the spread of a random projection
-    w = torch.from_numpy(inputs.sign_vector(flat.shape[1], w_seed)).to(DEV)
-    proj = (flat @ w).cpu().numpy()
-    e_proj = np.abs(proj - g["proj"]) / g["norms"] / (8 * tol_t)
-    ref_s = g["c_sample"].reshape(len(g["c_sample"]), -1)
-    got_s = c_sample.reshape(len(c_sample), -1)
-    e_c = np.linalg.norm(got_s - ref_s, axis=1) / np.linalg.norm(ref_s, axis=1) / tol_t[::m]
-    rows = out[torch.from_numpy(g["row_index"]).to(DEV)].cpu().numpy()
-    ref_r = g["rows"].reshape(len(g["rows"]), -1)
-    e_r = (np.linalg.norm(rows.reshape(len(rows), -1) - ref_r, axis=1) / np.linalg.norm(ref_r, axis=1) /
-           tol_t[g["row_index"]])
-    print("error / bar: norms %.2f, projections %.2f, C-point samples %.2f, whole time points %.2f"
-          % (e_norm.max(), e_proj.max(), e_c.max(), e_r.max()))
-    assert e_norm.max() <= 1 and e_proj.max() <= 1 and e_c.max() <= 1 and e_r.max() <= 1
-
-
 def test_config3_full_size_matches_oracle():
     """nx = nt = 16384, CFL 0.5, U5 + SDIRK3, m = 16, 16384 -> 1024 -> 64 -> 4,
     seed 1003, against the oracle's own solve of the same workload
     (tests/golden/config3_oracle.npz, written by make_config3.py)."""
     _announce("config3 full")
-    g = _golden("config3_oracle.npz")
+    g = golden("config3_oracle.npz")
     nx = nt = 16384
     u0 = inputs.u0_fourier(nx, 1003)
     v0 = inputs.initial_iterate(nt, nx, u0, 1003)
@@ -471,7 +427,7 @@ def test_config3_full_size_matches_oracle():
     del v0
     torch.cuda.synchronize()
     assert info["status"] == mgrit.OK
-    _check_against_golden(info, out, g, out[::16, ::256].cpu().numpy(), 16, 77)
+    check_against_golden(info, out, g, out[::16, ::256].cpu().numpy(), 16, 77)
 
 
 # --------------------------------------------------------------------------
