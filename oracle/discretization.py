@@ -423,24 +423,84 @@ def correction_coefficients(p, kind, q, c, ms, tab=None):
     return out
 
 
+def gmres(apply_a, b, rtol, maxit):
+    """Approximate solution of A x = b by GMRES (Saad and Schultz, 1986):
+    x0 = 0, the Arnoldi basis of the Krylov space by modified Gram-Schmidt,
+    the least-squares problem by Givens rotations; stops once the residual
+    2-norm is at most rtol ||b||_2 (Sec. 6.3: reduced by two orders of
+    magnitude), or after maxit iterations, or at an exact breakdown.  Returns
+    (x, iterations)."""
+    b = np.asarray(b, dtype=float)
+    beta = float(np.sqrt(np.dot(b, b)))
+    if beta == 0.0:
+        return np.zeros_like(b), 0
+    V = [b / beta]
+    R = np.zeros((maxit + 1, maxit))
+    cs, sn = np.zeros(maxit), np.zeros(maxit)
+    g = np.zeros(maxit + 1)
+    g[0] = beta
+    k = 0
+    for j in range(maxit):
+        w = apply_a(V[j])
+        h = np.zeros(j + 2)
+        for i in range(j + 1):
+            h[i] = np.dot(w, V[i])
+            w = w - h[i] * V[i]
+        h[j + 1] = float(np.sqrt(np.dot(w, w)))
+        # earlier rotations on the new column, then the one that zeroes h[j+1]
+        for i in range(j):
+            h[i], h[i + 1] = cs[i] * h[i] + sn[i] * h[i + 1], -sn[i] * h[i] + cs[i] * h[i + 1]
+        den = float(np.hypot(h[j], h[j + 1]))
+        cs[j], sn[j] = h[j] / den, h[j + 1] / den
+        h[j], h[j + 1] = den, 0.0
+        g[j], g[j + 1] = cs[j] * g[j], -sn[j] * g[j]
+        R[: j + 1, j] = h[: j + 1]
+        k = j + 1
+        if abs(g[j + 1]) <= rtol * beta or den == 0.0 or j + 1 == maxit:
+            break
+        nrm = float(np.sqrt(np.dot(w, w)))
+        if nrm == 0.0:
+            break
+        V.append(w / nrm)
+    y = np.zeros(k)
+    for i in range(k - 1, -1, -1):
+        y[i] = (g[i] - np.dot(R[i, i + 1:k], y[i + 1:k])) / R[i, i]
+    x = np.zeros_like(b)
+    for i in range(k):
+        x = x + y[i] * V[i]
+    return x, k
+
+
 class CorrectedSLStep:
     """Coarse time-stepper of eq. (MOL-SL-corrected-multilevel):
         Psi = (I - phi_p D^(p+1) - phi_q D^(q+1))^{-1} S_p^(Delta),
     i.e. a semi-Lagrangian step followed by one implicit periodic solve,
-    done here by FFT diagonalisation (``circulant_solve``)."""
+    done here by FFT diagonalisation (``circulant_solve``), or, with
+    ``gmres=(rtol, maxit)``, approximately by GMRES from a zero start for
+    every vector (Sec. 6.3)."""
 
-    def __init__(self, p, q, shift, phi_p, phi_q=0.0):
+    def __init__(self, p, q, shift, phi_p, phi_q=0.0, gmres=None):
         self.p, self.q, self.shift = p, q, float(shift)
         self.phi_p, self.phi_q = float(phi_p), float(phi_q)
+        self.gmres = gmres
         w = {j: -self.phi_p * d for j, d in dmat_weights(p + 1).items()}
         if self.phi_q != 0.0:
             for j, d in dmat_weights(q + 1).items():
                 w[j] = w.get(j, 0.0) - self.phi_q * d
         self.corr_weights = w  # stencil of -(phi_p D_p + phi_q D_q)
 
+    def apply_t(self, x):
+        """T x = (I - phi_p D^(p+1) - phi_q D^(q+1)) x."""
+        return x + apply_stencil(x, self.corr_weights)
+
     def __call__(self, v):
         y = sl_apply(np.asarray(v, dtype=float), self.p, self.shift)
-        return circulant_solve(y, self.corr_weights, 1.0, 1.0)
+        if self.gmres is None:
+            return circulant_solve(y, self.corr_weights, 1.0, 1.0)
+        rtol, maxit = self.gmres
+        flat = y.reshape(-1, y.shape[-1])
+        out = np.array([gmres(self.apply_t, row, rtol, maxit)[0] for row in flat])
+        return out.reshape(y.shape)
 
     def symbol(self, omega):
         """mu(omega) = Shat / (1 - phi_p Dhat_p - phi_q Dhat_q)."""

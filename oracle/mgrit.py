@@ -34,14 +34,16 @@ class Hierarchy:
     """Time-steppers and sizes of every level.
 
     ``tab``: an optional Butcher tableau (A, b) in place of the built-in
-    one of (kind, q).  ``coarse`` selects the coarse operator: "sl_corrected" (the paper's
+    one of (kind, q).  ``gmres``: (rtol, maxit) to apply the corrected
+    coarse operators' periodic solves approximately by GMRES (Sec. 6.3)
+    instead of exactly.  ``coarse`` selects the coarse operator: "sl_corrected" (the paper's
     eq. MOL-SL-corrected-multilevel), "sl_plain" (phi = 0), "ideal"
     (Psi = Phi^m; only meaningful for two levels) or "redisc" (the fine
     Runge-Kutta + upwind step taken with the level's step, i.e. at CFL number
     c m_0 ... m_{l-1}: the rediscretisation of Sec. 5 and Theorem 1).
     """
 
-    def __init__(self, nx, nt, p, kind, q, c, ms, coarse="sl_corrected", tab=None):
+    def __init__(self, nx, nt, p, kind, q, c, ms, coarse="sl_corrected", tab=None, gmres=None):
         self.nx, self.nt = nx, nt
         self.space = (nx,)  # shape of one time point's vector
         self.p, self.kind, self.q, self.c = p, kind, q, float(c)
@@ -69,7 +71,7 @@ class Hierarchy:
                 if coarse == "sl_plain":
                     st = disc.CorrectedSLStep(p, q, rec["shift"], 0.0, 0.0)
                 elif coarse == "sl_corrected":
-                    st = disc.CorrectedSLStep(p, q, rec["shift"], rec["phi_p"], rec["phi_q"])
+                    st = disc.CorrectedSLStep(p, q, rec["shift"], rec["phi_p"], rec["phi_q"], gmres=gmres)
                 else:
                     raise ValueError(coarse)
                 self.steps.append(st)

@@ -394,3 +394,26 @@ def test_caller_tableau_stage_form_matches_its_stability_polynomial():
     R = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 48
     got = st(x.real) + 1j * st(x.imag)
     assert np.max(np.abs(got - R * x)) <= 1e-14
+
+
+def test_gmres_matches_a_library_gmres_and_the_direct_solve():
+    """The oracle's GMRES (zero start, modified Gram-Schmidt, Givens) on the
+    corrected coarse operators' periodic systems: stopped at a 1e-2 relative
+    residual or 20 iterations it equals scipy's GMRES with the same rule
+    (restart 20, one cycle); run to convergence it equals the FFT solve."""
+    import scipy.sparse.linalg as sla
+    rng = np.random.default_rng(1)
+    for rec in disc.correction_coefficients(3, "erk", 3, 0.85 * disc.cfl_limit(3), [8, 8]):
+        st = disc.CorrectedSLStep(3, 3, rec["shift"], rec["phi_p"], rec["phi_q"], gmres=(1e-2, 20))
+        nx = 256
+        b = rng.standard_normal(nx)
+        x, k = disc.gmres(st.apply_t, b, 1e-2, 20)
+        A = sla.LinearOperator((nx, nx), matvec=lambda v: st.apply_t(np.asarray(v, float)), dtype=float)
+        xs, _ = sla.gmres(A, b, rtol=1e-2, atol=0.0, restart=20, maxiter=1)
+        assert 1 <= k <= 20
+        assert np.linalg.norm(x - xs) <= 1e-12 * np.linalg.norm(xs)
+        res = np.linalg.norm(b - st.apply_t(x)) / np.linalg.norm(b)
+        assert res <= 1e-2 or k == 20
+        xe, _ = disc.gmres(st.apply_t, b, 1e-15, nx)
+        xd = disc.circulant_solve(b, st.corr_weights, 1.0, 1.0)
+        assert np.linalg.norm(xe - xd) <= 1e-12 * np.linalg.norm(xd)
