@@ -125,6 +125,16 @@ typedef struct {
                             k = (n-1) nx + i, mixes init_seed + (k+1) *
                             0x9E3779B97F4A7C15 and keeps its top 53 bits
                             (the paper's random initial iterate, Sec. 5.3) */
+  int32_t coarse_solve;  /* MGRIT_CG_SL_CORRECTED's periodic solves: 0 =
+                            exact (factorised banded recurrences); 1 =
+                            approximate, GMRES from a zero start on every
+                            coarse-step application until the residual falls
+                            by gmres_rtol or after gmres_max_iter iterations
+                            (Sec. 6.3; float64 1D solves only, nx a
+                            multiple of 128)                                */
+  double gmres_rtol;     /* e.g. 1e-2 (two orders of magnitude)              */
+  int32_t gmres_max_iter; /* 1..32; the paper: 10 (ERK1+U1), 20 (ERK3+U3,
+                            ERK5+U5)                                        */
 } mgrit_options;
 
 /* Arithmetic of mgrit_solve.
@@ -173,6 +183,9 @@ typedef struct {
                            with an exact workgroup-wide scan                 */
   int32_t win_D[2];     /* those chunk counts for the causal and the
                            anti-causal recurrence (0: none)                  */
+  int32_t gmres_max_iter; /* level >= 1 with coarse_solve = 1: the GMRES
+                           iteration cap of its approximate solves (0: the
+                           periodic solve is exact)                          */
 } mgrit_level_desc;
 
 /* Phases timed by the optional profiler (mgrit_profile_enable). */

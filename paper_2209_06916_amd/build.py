@@ -14,7 +14,7 @@ LIB = os.path.join(PKG, "libmgrit.so")
 CSRC = os.path.join(PKG, "csrc")
 SOURCES = [os.path.join(CSRC, f) for f in ("mgrit_step_poly_z.hip", "mgrit_step_poly_w.hip", "mgrit_step_slc.hip",
                                            "mgrit_step32_poly_z.hip", "mgrit_step32_poly_w.hip", "mgrit_step32_slc.hip",
-                                           "mgrit_lean.hip", "mgrit_window.hip", "mgrit_window32.hip", "mgrit_noalloc.hip",
+                                           "mgrit_lean.hip", "mgrit_window.hip", "mgrit_window32.hip", "mgrit_noalloc.hip", "mgrit_gmres.hip",
                                            "mgrit_tile4.hip", "mgrit_tile8.hip", "mgrit_tile16.hip",
                                            "mgrit_kernels.hip", "mgrit_2d.hip", "mgrit_host.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

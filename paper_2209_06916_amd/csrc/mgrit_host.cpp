@@ -1289,6 +1289,14 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
     return bad(MGRIT_EINVAL, "mixed precision needs 0 < inner_rtol < 1");
   if (O->precision == MGRIT_PREC_MIXED && O->inner_max_iter < 1)
     return bad(MGRIT_EINVAL, "mixed precision needs inner_max_iter >= 1");
+  if (O->coarse_solve < 0 || O->coarse_solve > 1) return bad(MGRIT_EINVAL, "coarse_solve must be 0 or 1");
+  if (O->coarse_solve == 1) {
+    if (O->cg_kind != MGRIT_CG_SL_CORRECTED)
+      return bad(MGRIT_EINVAL, "GMRES coarse solves apply to the corrected semi-Lagrangian operator only");
+    if (O->precision != MGRIT_PREC_FP64) return bad(MGRIT_EINVAL, "GMRES coarse solves run in float64 only");
+    if (O->gmres_max_iter < 1 || O->gmres_max_iter > GMRES_MAX) return bad(MGRIT_EINVAL, "gmres_max_iter must be in 1..32");
+    if (!(O->gmres_rtol > 0 && O->gmres_rtol < 1)) return bad(MGRIT_EINVAL, "gmres_rtol must be in (0, 1)");
+  }
   const bool sl_coarse = O->cg_kind == MGRIT_CG_SL_CORRECTED || O->cg_kind == MGRIT_CG_SL_PLAIN;
   if (sl_coarse && P->upwind_order % 2 == 0)
     return bad(MGRIT_EINVAL, "semi-Lagrangian coarse operators need odd upwind order");
@@ -1373,6 +1381,28 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
       Lv.lay = S.lay;
       tabs[l] = std::move(S.tabs);
       offs[l] = std::move(S.offs);
+      if (O->coarse_solve == 1) {
+        // T = I - phi_p D^(p+1) - phi_q D^(q+1) applied as its stencil,
+        // solved by GMRES (Sec. 6.3)
+        std::map<int, ld> t;
+        t[0] += 1;
+        for (auto &kv : dmat(p + 1)) t[kv.first] -= (ld)Lv.phi_p * kv.second;
+        if (Lv.phi_q != 0)
+          for (auto &kv : dmat(q + 1)) t[kv.first] -= (ld)Lv.phi_q * kv.second;
+        int tk = 0;
+        for (auto &kv : t) tk = std::max(tk, std::abs(kv.first));
+        StepOp &op = Lv.op;
+        op.gmres_max = O->gmres_max_iter;
+        op.gmres_rtol = O->gmres_rtol;
+        op.t_k = tk;
+        for (int j = 0; j < MAXTAPS; ++j) op.ttaps[j] = 0;
+        for (auto &kv : t) op.ttaps[kv.first + tk] = (double)kv.second;
+        op.win_L = 0;
+        if (2 * tk + 1 > MAXTAPS || Lv.lay.ragged || gmres_lds_bytes(Lv.lay, op.gmres_max) > LDS_LIMIT) {
+          mgrit_destroy(h);
+          return bad(MGRIT_EINVAL, "GMRES coarse solves need nx a multiple of 128 and at most 16384 points");
+        }
+      }
     }
   } else {
     ld prod = 1;
@@ -1463,6 +1493,13 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
     o_c1[l] = off, off += al((rows + 1) * nx * sizeof(double));
     o_r[l] = off, off += al(std::max<size_t>(rows * nx, 1) * sizeof(double));
   }
+  std::vector<size_t> o_kry(nlev, none);  // GMRES bases of the coarse levels
+  for (int l = 1; l < nlev; ++l)
+    if (h->lv[l].op.gmres_max > 0) {
+      const int64_t cap = (l < nlev - 1) ? h->lv[l].nt / h->lv[l].m : 1;
+      h->lv[l].op.krylov_cap = cap;
+      o_kry[l] = off, off += al((size_t)cap * (h->lv[l].op.gmres_max + 1) * nx * sizeof(double));
+    }
   std::vector<size_t> o_c32a(nlev, none), o_c32b(nlev, none), o_r32(nlev, none);
   size_t o_g32 = none, o_e32 = none, o_r64 = none, o_u64 = none;
   if (mixed) {
@@ -1531,6 +1568,7 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
       Lv.op.fw.wtab = offs[l][2] == none ? nullptr : Lv.tabs + offs[l][2];
       Lv.op.bw.wtab = offs[l][3] == none ? nullptr : Lv.tabs + offs[l][3];
     }
+    if (o_kry[l] != none) Lv.op.krylov = (double *)(base + o_kry[l]);
     Lv.desc = (LevelDesc *)(base + o_desc[l]);
     const LevelDesc hd{Lv.op, Lv.lay};
     std::memcpy(up.data() + o_desc[l], &hd, sizeof(LevelDesc));
@@ -1635,6 +1673,7 @@ mgrit_status mgrit_level_info(const mgrit_handle *h, int32_t level, mgrit_level_
   out->win_L = win ? L.op.win_L : 0;
   out->win_D[0] = win && L.op.fw.k > 0 ? L.op.fw.D : 0;
   out->win_D[1] = win && L.op.bw.k > 0 ? L.op.bw.D : 0;
+  out->gmres_max_iter = (level >= 1 && L.op.kind == OP_SLC) ? L.op.gmres_max : 0;
   return MGRIT_OK;
 }
 
@@ -2203,6 +2242,12 @@ mgrit_status mgrit_workspace_bytes(const mgrit_problem *P, const mgrit_options *
   *bytes = n * sizeof(double) +
            (uint64_t)nts.size() * (2 * RTAB_ALL * KMAX * KMAX * sizeof(double) + sizeof(LevelDesc) + 5 * 256) +
            sizeof(GridSync) + 4 * 256 + sizeof(SolveCtl);
+  if (O->coarse_solve == 1) {  // GMRES bases: (gmres_max + 1) vectors per interval of each coarse level
+    for (size_t l = 1; l < nts.size(); ++l) {
+      const uint64_t cap = (l + 1 < nts.size()) ? (uint64_t)(nts[l] / ms[l]) : 1;
+      *bytes += cap * (uint64_t)(std::max(O->gmres_max_iter, 1) + 1) * (uint64_t)P->nx * sizeof(double) + 256;
+    }
+  }
   if (O->precision == MGRIT_PREC_MIXED) {
     // float32 copies of the level arrays and tables, the inner right-hand
     // side and solution (float32), the outer residual and iterate (float64)
@@ -2732,6 +2777,7 @@ mgrit_status mgrit2d_setup(const mgrit2d_problem *P, const mgrit_options *O, voi
   if (O->nu < 0 || O->nu > 8) return bad(MGRIT_EINVAL, "nu must be in 0..8");
   if (O->max_iter < 0 || !(O->rtol >= 0)) return bad(MGRIT_EINVAL, "need max_iter >= 0 and rtol >= 0");
   if (O->cg_kind != MGRIT_CG_SL_CORRECTED) return bad(MGRIT_EINVAL, "2D: corrected semi-Lagrangian coarse step only");
+  if (O->coarse_solve != 0) return bad(MGRIT_EINVAL, "2D: the coarse solves are exact (coarse_solve = 0)");
   if (O->precision != MGRIT_PREC_FP64 && O->precision != MGRIT_PREC_MIXED) return bad(MGRIT_EINVAL, "unknown precision");
   const bool mixed = O->precision == MGRIT_PREC_MIXED;
   if (mixed && !(O->inner_rtol > 0 && O->inner_rtol < 1))

@@ -72,7 +72,17 @@ struct StepOp {
   // (wcoef[i] = coef[i] / C^i), OP_SLC folds 1/C into the interpolation weights
   int win_L;
   double wcoef[MAXCOEF];
+  // OP_SLC with GMRES coarse solves (gmres_max > 0): T itself as a symmetric
+  // stencil ttaps[d + t_k], d = -t_k..t_k, and per-workgroup Krylov storage
+  // krylov + b (gmres_max + 1) nx for workgroup b < krylov_cap
+  int gmres_max;
+  double gmres_rtol;
+  int t_k;
+  double ttaps[MAXTAPS];
+  double *krylov;
+  int64_t krylov_cap;
 };
+constexpr int GMRES_MAX = 32;
 
 // Work distribution of one nx-vector over a workgroup.
 struct Layout {
@@ -160,6 +170,7 @@ constexpr __host__ __device__ inline LeanLds lean_lds_offsets(int nx, int K) {
 // equal forward/backward orders, no repetition, and recurrence tables built
 // for 16-point chunks that cover nx exactly.
 inline bool lean_slc_applies(const StepOp &op, const Layout &lay) {
+  if (op.gmres_max > 0) return false;
   const int W = op.sl_l + op.sl_r + 1;
   const int nw = lay.L > 0 ? lay.nx / (WAVE * lay.L) : 0;
   return op.kind == OP_SLC && op.has_solve && op.repeat == 1 && !lay.ragged && lay.A == lay.T &&
@@ -405,7 +416,7 @@ inline bool window_instance(int kind, int kf, int kb, int L) {
   return orders && (L == 16 || L == 32);
 }
 inline bool window_applies(const StepOp &op, const Layout &lay) {
-  if (op.win_L <= 0 || !op.has_solve || !window_instance(op.kind, op.fw.k, op.bw.k, op.win_L)) return false;
+  if (op.gmres_max > 0 || op.win_L <= 0 || !op.has_solve || !window_instance(op.kind, op.fw.k, op.bw.k, op.win_L)) return false;
   if (op.kind == OP_SLC && op.sl_l + op.sl_r + 1 != 2 * op.fw.k) return false;  // the gather has 2k taps
   const int nt = lay.nx / op.win_L;
   return lay.nx == nt * op.win_L && nt % WAVE == 0 && nt <= 1024 && (op.win_L == 16 || nt <= 512);
@@ -415,6 +426,11 @@ hipError_t launch_window(const LevelDesc *desc, const StepOp &op, const Layout &
 hipError_t launch_window32(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs32 &pa,
                            hipStream_t stream);
 hipError_t configure_window_kernels64(size_t bytes);
+// Corrected SL steps with GMRES solves (mgrit_gmres.hip), float64.
+hipError_t launch_gmres(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs &pa,
+                        hipStream_t stream);
+hipError_t configure_gmres_kernels(size_t bytes);
+size_t gmres_lds_bytes(const Layout &lay, int kmax);
 hipError_t configure_window_kernels32(size_t bytes);
 
 // The lean coarse-step kernel (mgrit_lean.hip) for layouts where

@@ -161,6 +161,7 @@ hipError_t configure_kernels(size_t bytes) {
   if ((e = configure_lean_kernels(bytes))) return e;
   if ((e = configure_window_kernels64(bytes))) return e;
   if ((e = configure_window_kernels32(bytes))) return e;
+  if ((e = configure_gmres_kernels(bytes))) return e;
   if ((e = configure_step_poly_z(bytes))) return e;
   if ((e = configure_step_poly_w(bytes))) return e;
   if ((e = configure_step_slc(bytes))) return e;
@@ -208,6 +209,7 @@ hipError_t launch_ctl_reset(SolveCtl *ctl, const int *gate, hipStream_t stream) 
 hipError_t launch_pass(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs &pa,
                        hipStream_t stream) {
   if (pa.nint <= 0) return hipSuccess;
+  if (op.kind == OP_SLC && op.gmres_max > 0) return launch_gmres(desc, op, lay, pa, stream);
   if (lean_slc_applies(op, lay)) return launch_lean(desc, op, lay, pa, stream);
   if (window_applies(op, lay)) return launch_window(desc, op, lay, pa, stream);
   const size_t lds = lds_bytes_for(lay, op.has_solve);

@@ -41,7 +41,8 @@ class Options(ctypes.Structure):
                 ("min_coarse_nt", ctypes.c_int32), ("nu", ctypes.c_int32), ("cg_kind", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("diverge_factor", ctypes.c_double),
                 ("coarse_launch", ctypes.c_int32), ("precision", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
-                ("inner_max_iter", ctypes.c_int32), ("tile_tune", ctypes.c_int32), ("init_seed", ctypes.c_uint64)]
+                ("inner_max_iter", ctypes.c_int32), ("tile_tune", ctypes.c_int32), ("init_seed", ctypes.c_uint64),
+                ("coarse_solve", ctypes.c_int32), ("gmres_rtol", ctypes.c_double), ("gmres_max_iter", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -62,7 +63,7 @@ class LevelDesc(ctypes.Structure):
     _fields_ = [("nt", ctypes.c_int64), ("m", ctypes.c_int32), ("shift", ctypes.c_double),
                 ("K", ctypes.c_int64), ("eps", ctypes.c_double), ("phi_p", ctypes.c_double),
                 ("phi_q", ctypes.c_double), ("tile_p", ctypes.c_int32), ("win_L", ctypes.c_int32),
-                ("win_D", ctypes.c_int32 * 2)]
+                ("win_D", ctypes.c_int32 * 2), ("gmres_max_iter", ctypes.c_int32)]
 
 
 PROF_PHASES = ["fine_relax", "coarse", "final", "sequential", "residual", "other"]
@@ -156,7 +157,9 @@ def make_problem(nx, nt, cfl, p, kind="erk", q=None, velocity=1.0, x_lo=-1.0, x_
 
 def make_options(m, max_levels=2, min_coarse_nt=0, nu=1, coarse="sl_corrected", rtol=1e-10, max_iter=30,
                  diverge_factor=1e8, coarse_launch=0, precision="fp64", inner_rtol=1e-5, inner_max_iter=30,
-                 tile_tune=0, init_seed=0):
+                 tile_tune=0, init_seed=0, gmres=None):
+    """gmres: (rtol, max_iter) to solve the corrected coarse operators'
+    periodic systems approximately by GMRES (Sec. 6.3); None: exactly."""
     o = Options()
     o.max_levels = max_levels
     ms = list(m) if isinstance(m, (list, tuple)) else [m]
@@ -174,6 +177,8 @@ def make_options(m, max_levels=2, min_coarse_nt=0, nu=1, coarse="sl_corrected", 
     o.inner_max_iter = inner_max_iter
     o.tile_tune = tile_tune
     o.init_seed = init_seed
+    if gmres is not None:
+        o.coarse_solve, o.gmres_rtol, o.gmres_max_iter = 1, gmres[0], gmres[1]
     return o
 
 
@@ -275,7 +280,7 @@ class Solver:
         d = LevelDesc()
         self._check(lib().mgrit_level_info(self.h, level, ctypes.byref(d)))
         return dict(nt=d.nt, m=d.m, shift=d.shift, K=d.K, eps=d.eps, phi_p=d.phi_p, phi_q=d.phi_q, tile_p=d.tile_p,
-                    win_L=d.win_L, win_D=(d.win_D[0], d.win_D[1]))
+                    win_L=d.win_L, win_D=(d.win_D[0], d.win_D[1]), gmres_max_iter=d.gmres_max_iter)
 
     def solve(self, u0, v_init=None, u_out=None, u_final=None, history_cap=128,
               allow=(OK, ENOTCONVERGED)):

@@ -231,3 +231,29 @@ def test_seeded_initial_iterate_is_splitmix64():
     v = inputs.initial_iterate_splitmix(4, 8, np.zeros(8), 1003)
     assert np.all((v[1:] >= 0) & (v[1:] < 1))
     assert v[2, 3] == (stateful(1003, 8 + 4)[-1] >> 11) * 2.0 ** -53
+
+
+@pytest.mark.parametrize("kw,opt,msg", [
+    (dict(nx=256, nt=64, cfl=0.85, p=3), dict(m=4, gmres=(1e-2, 0)), "gmres_max_iter"),
+    (dict(nx=256, nt=64, cfl=0.85, p=3), dict(m=4, gmres=(1e-2, 33)), "gmres_max_iter"),
+    (dict(nx=256, nt=64, cfl=0.85, p=3), dict(m=4, gmres=(0.0, 20)), "gmres_rtol"),
+    (dict(nx=256, nt=64, cfl=0.85, p=3), dict(m=4, gmres=(1.0, 20)), "gmres_rtol"),
+    (dict(nx=256, nt=64, cfl=0.85, p=3), dict(m=4, coarse="sl_plain", gmres=(1e-2, 20)), "corrected"),
+    (dict(nx=256, nt=64, cfl=0.85, p=3), dict(m=4, precision="mixed", gmres=(1e-2, 20)), "float64"),
+    (dict(nx=200, nt=64, cfl=0.85, p=3), dict(m=4, gmres=(1e-2, 20)), "multiple of 128"),
+])
+def test_setup_rejects_invalid_gmres_options(kw, opt, msg):
+    st, err = _setup_status(mgrit.make_problem(**kw), mgrit.make_options(**opt))
+    assert st == mgrit.EINVAL, err
+    assert msg in err
+
+
+def test_gmres_workspace_holds_the_krylov_bases():
+    """The workspace grows by (gmres_max_iter + 1) vectors per CF-interval of
+    every coarse level (one interval on the coarsest), rounded up per level."""
+    prob = mgrit.make_problem(256, 64, 0.85, 3)
+    exact = mgrit.workspace_bytes(prob, mgrit.make_options([4, 4], max_levels=3))
+    approx = mgrit.workspace_bytes(prob, mgrit.make_options([4, 4], max_levels=3, gmres=(1e-2, 20)))
+    basis = 21 * 256 * 8
+    assert approx - exact >= (16 // 4 + 1) * basis
+    assert approx - exact <= (16 // 4 + 1) * basis + 4096
