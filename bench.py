@@ -147,7 +147,7 @@ PROFILE_COMMANDS = {
     "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/write -o run -- "
              "python3 bench.py --steps 2 --warmup 1 --traffic-probe",
     "serve": "rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/serve -o run -- "
-             "python3 bench.py --serve 512",
+             "python3 bench.py --serve 512 --no-extras",
     "sq": "rocprofv3 --pmc SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_INSTS_VALU "
           "SQ_ACTIVE_INST_VALU SQ_INSTS_LDS --output-format csv -d <dir>/sq -o run -- "
           "python3 bench.py --steps 1 --warmup 0 --traffic-probe",
@@ -170,34 +170,37 @@ def summarize_profiles(d):
     probe's 1 GiB elementwise copy)."""
     import csv
     prof_dir = os.path.join(ROOT, "profiles")
-    rows = list(csv.DictReader(open(os.path.join(d, "trace", "run_kernel_stats.csv"))))
-    tot = sum(float(r["TotalDurationNs"]) for r in rows)
-    lines = [f"# rocprofv3 kernel statistics -- workload {WORKLOAD}",
-             "# (MGRIT solves: 2 warm-up, 3 with every phase timed by events, 10 timed; then 4 runs of sequential",
-             "# time-stepping of the same problem; then 4 MGRIT solves without the final F-pass)",
-             "# command (repository root on the GPU box, after cd /tmp && export TMPDIR=/tmp):",
-             "#   " + PROFILE_COMMANDS["trace"].replace("<dir>", "gpurun_out/prof"),
-             "#", f"# {'kernel':52s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'share':>7s}"]
-    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
-        lines.append(f"  {_short(r['Name']):52s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
-                     f"{float(r['TotalDurationNs']) / 1e6:10.3f} {100 * float(r['TotalDurationNs']) / tot:6.2f}%")
-    lines += ["#", "# wstep_kernel<32, 1, 3, 2, 512, double>: SDIRK3 + U5 steps (32 points per thread, 512 threads);",
-              "#   grid 524288: level-0 relaxation passes (1024 intervals) and the final F-pass; grid 512: sequential",
-              "#   time-stepping (one workgroup, 16384 steps)",
-              "# wstep_kernel<32, 2, 3, 3, 512, double>: corrected semi-Lagrangian steps of levels 1-3, one launch per",
-              "#   pass (the last correction of each solve returns at once)",
-              "# solve_ctl_kernel: residual norm + stopping test."]
-    with open(os.path.join(prof_dir, f"kernel_stats_{WORKLOAD}.txt"), "w") as fh:
-        fh.write("\n".join(lines) + "\n")
+    trace_csv = os.path.join(d, "trace", "run_kernel_stats.csv")
+    if os.path.exists(trace_csv):
+        rows = list(csv.DictReader(open(trace_csv)))
+        tot = sum(float(r["TotalDurationNs"]) for r in rows)
+        lines = [f"# rocprofv3 kernel statistics -- workload {WORKLOAD}",
+                 "# (MGRIT solves: 2 warm-up, 3 with every phase timed by events, 10 timed; then 4 runs of sequential",
+                 "# time-stepping of the same problem; then 4 MGRIT solves without the final F-pass)",
+                 "# command (repository root on the GPU box, after cd /tmp && export TMPDIR=/tmp):",
+                 "#   " + PROFILE_COMMANDS["trace"].replace("<dir>", "gpurun_out/prof"),
+                 "#", f"# {'kernel':52s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'share':>7s}"]
+        for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+            lines.append(f"  {_short(r['Name']):52s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
+                         f"{float(r['TotalDurationNs']) / 1e6:10.3f} {100 * float(r['TotalDurationNs']) / tot:6.2f}%")
+        lines += ["#", "# wstep_kernel<32, 1, 3, 2, 512, double>: SDIRK3 + U5 steps (32 points per thread, 512 threads);",
+                  "#   grid 524288: level-0 relaxation passes (1024 intervals) and the final F-pass; grid 512: sequential",
+                  "#   time-stepping (one workgroup, 16384 steps)",
+                  "# wstep_kernel<32, 2, 3, 3, 512, double>: corrected semi-Lagrangian steps of levels 1-3, one launch per",
+                  "#   pass (the last correction of each solve returns at once)",
+                  "# solve_ctl_kernel: residual norm + stopping test."]
+        with open(os.path.join(prof_dir, f"kernel_stats_{WORKLOAD}.txt"), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
 
     serve_csv = os.path.join(d, "serve", "run_kernel_stats.csv")
     if os.path.exists(serve_csv):
         rows = list(csv.DictReader(open(serve_csv)))
         tot = sum(float(r["TotalDurationNs"]) for r in rows)
         lines = [f"# rocprofv3 kernel statistics -- workload {SERVE_WORKLOAD}",
-                 "# (bench.py --serve 512 as it was before the threaded loop, the tile tuner and the mixed-precision",
-                 "# stream were added: 8 warm-up requests, then the 512-request stream served with 1 and with 16",
-                 "# solves in flight by the polling loop, then with Poisson arrivals; the profiler slows the host loop,",
+                 "# (bench.py --serve 512 --no-extras: 2 x 16 warm-up requests, then the float64 512-request stream",
+                 "# served with 1 in flight (polling loop), 16 in flight (one host thread per request), 16 in flight",
+                 "# (polling loop), then with Poisson arrivals; the mixed-precision stream is not traced; the profiler",
+                 "# slows the host loop,",
                  "# so the rates it prints are lower than without it)",
                  "# command (repository root on the GPU box, after cd /tmp && export TMPDIR=/tmp):",
                  "#   " + PROFILE_COMMANDS["serve"].replace("<dir>", "gpurun_out/prof"),
@@ -241,6 +244,9 @@ def summarize_profiles(d):
         with open(os.path.join(prof_dir, f"counters_{WORKLOAD}.txt"), "w") as fh:
             fh.write("\n".join(lines) + "\n")
 
+    if not (os.path.exists(os.path.join(d, "fetch", "run_counter_collection.csv")) and
+            os.path.exists(os.path.join(d, "write", "run_counter_collection.csv"))):
+        return
     def counters(sub, name):
         per = {}
         order = []
@@ -298,14 +304,19 @@ def summarize_profiles(d):
     print("\n".join(lines))
 
 
-def serve_bench(n, seed):
+def _progress(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def serve_bench(n, seed, with_mixed=True):
     """Config 5: n independent 1D solves (nx, nt in 256..8192, ERK1/3/5 with
     the matching upwind order, CFL U(0.5, 0.9), m in {4, 8, 16}, multilevel
     down to <= 8 coarse steps, seeded 16-mode Fourier u0, zero initial
     iterate).  Throughput with one solve in flight and with up to 16 in
     flight (all requests queued at once; one host thread per request in
     flight, and the single-thread polling loop for comparison), then latency
-    under Poisson arrivals at 0.8x the single-stream capacity."""
+    under Poisson arrivals at 0.8x the single-stream capacity.  with_mixed:
+    also serve the stream in mixed precision."""
     from paper_2209_06916_amd import serve
     reqs = serve.synthetic_stream(n, seed=seed, rate_hz=0)
     dof = sum(r.nx * r.nt for r in reqs)
@@ -314,23 +325,29 @@ def serve_bench(n, seed):
     t = time.perf_counter()
     one = serve.Server(max_inflight=1).run(reqs, realtime=False)
     t_one = time.perf_counter() - t
+    _progress(f"serve: one in flight {t_one:.2f} s")
     t = time.perf_counter()
     many = serve.ThreadedServer(max_inflight=16).run(reqs, realtime=False)
     t_many = time.perf_counter() - t
+    _progress(f"serve: 16 in flight, threaded {t_many:.2f} s")
     t = time.perf_counter()
     serve.Server(max_inflight=16).run(reqs, realtime=False)
     t_loop = time.perf_counter() - t
+    _progress(f"serve: 16 in flight, polling {t_loop:.2f} s")
     by1 = {r.tag: r for r in one}
     same = all(np.array_equal(by1[r.tag].u_final, r.u_final) for r in many)
     # the same stream served in mixed precision (zero initial iterate, so the
     # float64 and the full space-time residual start from the same norm)
-    mixed_reqs = serve.synthetic_stream(n, seed=seed, rate_hz=0, precision="mixed")
-    serve.ThreadedServer(max_inflight=16).run(mixed_reqs[:16], realtime=False)
-    t = time.perf_counter()
-    mixed = serve.ThreadedServer(max_inflight=16).run(mixed_reqs, realtime=False)
-    t_mixed = time.perf_counter() - t
-    mixed_err = max(float(np.linalg.norm(r.u_final - by1[r.tag].u_final) / np.linalg.norm(by1[r.tag].u_final))
-                    for r in mixed)
+    mixed, t_mixed, mixed_err = [], float("nan"), float("nan")
+    if with_mixed:
+        mixed_reqs = serve.synthetic_stream(n, seed=seed, rate_hz=0, precision="mixed")
+        serve.ThreadedServer(max_inflight=16).run(mixed_reqs[:16], realtime=False)
+        t = time.perf_counter()
+        mixed = serve.ThreadedServer(max_inflight=16).run(mixed_reqs, realtime=False)
+        t_mixed = time.perf_counter() - t
+        _progress(f"serve: mixed precision {t_mixed:.2f} s")
+        mixed_err = max(float(np.linalg.norm(r.u_final - by1[r.tag].u_final) / np.linalg.norm(by1[r.tag].u_final))
+                        for r in mixed)
     rate = 0.8 * n / t_one
     arrivals = serve.synthetic_stream(n, seed=seed, rate_hz=rate)
     t = time.perf_counter()
@@ -351,9 +368,9 @@ def serve_bench(n, seed):
         "dof_per_s_one_in_flight": dof / t_one,
         "dof_per_s_16_in_flight": dof / t_many,
         "dof_per_s_16_in_flight_polling_loop": dof / t_loop,
-        "mixed_dof_per_s_16_in_flight": dof / t_mixed,
-        "mixed_all_converged": all(r.status == 0 for r in mixed),
-        "mixed_max_rel_diff_vs_fp64": mixed_err,
+        "mixed_dof_per_s_16_in_flight": dof / t_mixed if mixed else None,
+        "mixed_all_converged": bool(mixed) and all(r.status == 0 for r in mixed),
+        "mixed_max_rel_diff_vs_fp64": mixed_err if mixed else None,
         "concurrency_speedup": t_one / t_many,
         "same_results_alone_and_in_mix": bool(same),
         "all_converged": all(r.status == 0 for r in many),
@@ -661,7 +678,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="only the headline workload (no mixed-precision and 4096 x 4096 keys)")
+                    help="only the headline workload (no mixed-precision and 4096 x 4096 keys); with --serve: "
+                         "no mixed-precision stream")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for hardware-counter runs: a few solves plus one elementwise copy of "
                          "COPY_BYTES read + COPY_BYTES written (the counter calibration)")
@@ -684,7 +702,7 @@ def main():
 
     import torch
     if args.serve:
-        serve_bench(args.serve, seed=1005)
+        serve_bench(args.serve, seed=1005, with_mixed=not args.no_extras)
         return
     if args.precision:
         precision_bench(max(1, min(args.steps, 5)))
