@@ -17,8 +17,15 @@ __device__ __forceinline__ int wrap_lo(int i, int nx) {
   return i;
 }
 
+// Rows of the level arrays live in device memory: they are read and written
+// through global-address-space pointers (a flat access would also count
+// against the LDS wait counter and hold up the next LDS wait).
+template <class T>
+using GlobalPtr = __attribute__((address_space(1))) T *;
+
 template <int L, class T>
-__device__ __forceinline__ void load_chunk(const T *__restrict__ row, int base, int cnt, T (&x)[L]) {
+__device__ __forceinline__ void load_chunk(const T *__restrict__ row_, int base, int cnt, T (&x)[L]) {
+  const GlobalPtr<const T> row = (GlobalPtr<const T>)row_;
   if (cnt == L) {
 #pragma unroll
     for (int j = 0; j < L; ++j) x[j] = row[base + j];
@@ -29,7 +36,8 @@ __device__ __forceinline__ void load_chunk(const T *__restrict__ row, int base, 
 }
 
 template <int L, class T>
-__device__ __forceinline__ void store_chunk(T *__restrict__ row, int base, int cnt, const T (&x)[L]) {
+__device__ __forceinline__ void store_chunk(T *__restrict__ row_, int base, int cnt, const T (&x)[L]) {
+  const GlobalPtr<T> row = (GlobalPtr<T>)row_;
   if (cnt == L) {
 #pragma unroll
     for (int j = 0; j < L; ++j) row[base + j] = x[j];

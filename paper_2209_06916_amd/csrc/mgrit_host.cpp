@@ -845,10 +845,12 @@ bool attach_solve(StepOp &op, const std::map<int, ld> &taps, const Layout &lay, 
   }
   // truncated-carry plan for the windowed kernel: 32 points per thread where
   // that still gives at least 256 threads, else 16 (MGRIT_WIN_L = 16 or 32
-  // forces one), and only when both recurrences have a short enough carry
+  // forces one, MGRIT_WIN_L_COARSE for the coarse operators only), and only
+  // when both recurrences have a short enough carry
   op.win_L = 0;
   const int nx = lay.nx;
-  const int Lenv = env_int("MGRIT_WIN_L", 0);
+  const int Lenv = (op.kind == OP_SLC && env_int("MGRIT_WIN_L_COARSE", 0)) ? env_int("MGRIT_WIN_L_COARSE", 0)
+                                                                          : env_int("MGRIT_WIN_L", 0);
   if (env_int("MGRIT_NO_WINDOW", 0) == 0 && op.has_solve && (op.kind == OP_POLY_W || op.kind == OP_SLC)) {
     for (int Lw : {32, 16}) {
       if (Lenv ? Lw != Lenv : (Lw == 32 && nx < 32 * 256)) continue;

@@ -410,19 +410,19 @@ __device__ __forceinline__ void run_chain(const PassArgsT<T> &pa, int nx, int cn
 #pragma unroll
         for (int q = 0; q < (PRE_G ? L : 1); ++q) u[q] += gv[q];
       } else {
-        const T *gr = pa.g + (n - 1) * nxl + base;
+        const GlobalPtr<const T> gr = (GlobalPtr<const T>)(pa.g + (n - 1) * nxl + base);
 #pragma unroll
         for (int q = 0; q < L; ++q)
           if (q < cnt) u[q] += gr[q];
       }
     }
     if (add_parent) {
-      T *pr = pa.parent + n * nxl + base;
       if (PRE_P) {
 #pragma unroll
         for (int q = 0; q < (PRE_P ? L : 1); ++q) pv[q] += u[q];
         store_chunk<PRE_P ? L : 1>(pa.parent + n * nxl, base, cnt, pv);
       } else {
+        const GlobalPtr<T> pr = (GlobalPtr<T>)(pa.parent + n * nxl + base);
 #pragma unroll
         for (int q = 0; q < L; ++q)
           if (q < cnt) pr[q] += u[q];

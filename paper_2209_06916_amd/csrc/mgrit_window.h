@@ -154,6 +154,187 @@ __device__ __forceinline__ void win_gather(const T *vec, int start, int nx, cons
   }
 }
 
+// The chain of OP_SLC steps of one workgroup with the state between steps
+// held in the padded LDS vector instead of in the threads' chunks.  A step
+// gathers from the vector and solves in the chunk layout; its result goes
+// back to the vector, and every row access (the initial row, the right-hand
+// side added after a step, the parent rows a post-relaxation adds into, the
+// rows written out) walks the vector in the coalesced order i = k NT + t:
+// consecutive lanes touch consecutive words, where the chunk layout would
+// touch one cache line per lane.  Modes and row roles as in run_chain.
+// The coalesced walks recompute their addresses from an opaque copy of the
+// thread index in every phase: hoisted out of the step loop, the 2 x L
+// addresses of a walk would stay live across the step, which already needs
+// nearly every register.
+struct WalkIdx {
+  int t;   // thread index
+  int nt;  // threads
+};
+__device__ __forceinline__ WalkIdx walk_idx() {
+  WalkIdx w{(int)threadIdx.x, (int)blockDim.x};
+  asm volatile("" : "+v"(w.t), "+v"(w.nt));
+  return w;
+}
+
+template <int L, class T, class Step>
+__device__ __forceinline__ void run_chain_slc(const PassArgsT<T> &pa, int nx, T *vec, double *red, Step step) {
+  typedef __attribute__((address_space(1))) T *gT;
+  typedef const __attribute__((address_space(1))) T *gcT;
+  // rows move in NB batches of H loads per thread issued together (larger
+  // batches run out of registers at 32 points per thread)
+  constexpr int H = 8, NB = L / H;
+  const int64_t b = blockIdx.x;
+  const int64_t nxl = nx;
+  const int m = pa.m;
+  const int mode = pa.mode;
+  int nsteps;
+  switch (mode) {
+    case MODE_PASS_A: nsteps = m; break;
+    case MODE_PASS_B: nsteps = m; break;
+    case MODE_POST_F: nsteps = m - 1; break;
+    case MODE_FINAL_F: nsteps = m - 1; break;
+    case MODE_SEQ: nsteps = m; break;
+    case MODE_APPLY: nsteps = m; break;
+    default: nsteps = 1; break;  // MODE_RESID
+  }
+  const int64_t row0 = (mode == MODE_SEQ) ? 0 : b;
+  const bool add_g = pa.g && mode != MODE_APPLY && mode != MODE_RESID;
+  const bool add_parent = mode == MODE_POST_F || (mode == MODE_SEQ && pa.parent);
+  const bool store_out = mode == MODE_FINAL_F || (mode == MODE_SEQ && pa.out);
+
+  // the initial row, and what the modes do with it
+  {
+    const gcT cin = (gcT)(pa.cin + row0 * nxl);
+    const gT c0 = (gT)pa.cout;
+    const gT o0 = (gT)(mode == MODE_FINAL_F ? pa.out + (b * m) * nxl : pa.out);
+    const gT p0 = (gT)(pa.parent + (b * m) * nxl);
+    for (int h = 0; h < NB; ++h) {
+      const WalkIdx w = walk_idx();
+      const int tid = w.t, NT = w.nt;
+      T x[H];
+#pragma unroll
+      for (int k = 0; k < H; ++k) x[k] = pa.zero_init ? T(0) : cin[(h * H + k) * NT + tid];
+#pragma unroll
+      for (int k = 0; k < H; ++k) vec[win_pad<L>((h * H + k) * NT + tid)] = x[k];
+      if (mode == MODE_PASS_A && b == 0) {
+#pragma unroll
+        for (int k = 0; k < H; ++k) c0[(h * H + k) * NT + tid] = x[k];
+      }
+      if (mode == MODE_FINAL_F || (mode == MODE_SEQ && pa.out)) {
+#pragma unroll
+        for (int k = 0; k < H; ++k) o0[(h * H + k) * NT + tid] = x[k];
+      }
+      if (mode == MODE_POST_F) {
+        T pv[H];
+#pragma unroll
+        for (int k = 0; k < H; ++k) pv[k] = p0[(h * H + k) * NT + tid];
+#pragma unroll
+        for (int k = 0; k < H; ++k) p0[(h * H + k) * NT + tid] = pv[k] + x[k];
+      }
+    }
+  }
+  __syncthreads();
+
+  for (int j = 1; j <= nsteps; ++j) {
+    const int64_t n = (mode == MODE_SEQ) ? (int64_t)j : b * m + j;  // level point index
+    {
+      T y[L];
+      step(y);
+      __syncthreads();  // every thread has finished its gather (and, aliased, its solve)
+      const int base = (int)threadIdx.x * L;
+#pragma unroll
+      for (int q = 0; q < L; ++q) vec[win_pad<L>(base + q)] = y[q];
+    }
+    __syncthreads();
+    if (add_g || add_parent || store_out) {
+      const gcT g = (gcT)(pa.g + (n - 1) * nxl);
+      const gT pr = (gT)(pa.parent + n * nxl);
+      const gT o = (gT)(pa.out + n * nxl);
+      for (int h = 0; h < NB; ++h) {
+        const WalkIdx w = walk_idx();
+        const int tid = w.t, NT = w.nt;
+        T x[H];
+#pragma unroll
+        for (int k = 0; k < H; ++k) x[k] = vec[win_pad<L>((h * H + k) * NT + tid)];
+        if (add_g) {
+          T gv[H];
+#pragma unroll
+          for (int k = 0; k < H; ++k) gv[k] = g[(h * H + k) * NT + tid];
+#pragma unroll
+          for (int k = 0; k < H; ++k) {
+            x[k] += gv[k];
+            vec[win_pad<L>((h * H + k) * NT + tid)] = x[k];
+          }
+        }
+        if (add_parent) {
+          T pv[H];
+#pragma unroll
+          for (int k = 0; k < H; ++k) pv[k] = pr[(h * H + k) * NT + tid];
+#pragma unroll
+          for (int k = 0; k < H; ++k) pr[(h * H + k) * NT + tid] = pv[k] + x[k];
+        }
+        if (store_out) {
+#pragma unroll
+          for (int k = 0; k < H; ++k) o[(h * H + k) * NT + tid] = x[k];
+        }
+      }
+      if (add_g) __syncthreads();
+    }
+  }
+
+  // post-chain actions (the vector holds the chain's last point)
+  if (mode == MODE_PASS_A || mode == MODE_APPLY) {
+    const WalkIdx w = walk_idx();
+    const int tid = w.t, NT = w.nt;
+    const gT c1 = (gT)(pa.cout + (mode == MODE_PASS_A ? b + 1 : b) * nxl);
+#pragma unroll
+    for (int k = 0; k < L; ++k) c1[k * NT + tid] = vec[win_pad<L>(k * NT + tid)];
+  } else if (mode == MODE_PASS_B || mode == MODE_RESID) {
+    const gcT c1 = (gcT)(pa.cin + (b + 1) * nxl);
+    const gT r = (gT)(pa.r + b * nxl);
+    double ss = 0.0;
+    for (int h = 0; h < NB; ++h) {
+      const WalkIdx w = walk_idx();
+      const int tid = w.t, NT = w.nt;
+      T x[H];
+#pragma unroll
+      for (int k = 0; k < H; ++k) x[k] = c1[(h * H + k) * NT + tid];
+#pragma unroll
+      for (int k = 0; k < H; ++k) {
+        x[k] = vec[win_pad<L>((h * H + k) * NT + tid)] - x[k];
+        ss = fma((double)x[k], (double)x[k], ss);
+      }
+      if (pa.r) {
+#pragma unroll
+        for (int k = 0; k < H; ++k) r[(h * H + k) * NT + tid] = x[k];
+      }
+    }
+    const double tot = block_sum(ss, red);
+    if (threadIdx.x == 0) pa.normpart[b] = tot;
+  } else if (mode == MODE_POST_F || mode == MODE_FINAL_F) {
+    if (b == pa.nint - 1) {
+      const gcT cl = (gcT)(pa.cin + pa.nint * nxl);
+      const gT row = (gT)((mode == MODE_POST_F ? pa.parent : pa.out) + (pa.nint * m) * nxl);
+      for (int h = 0; h < NB; ++h) {
+        const WalkIdx w = walk_idx();
+        const int tid = w.t, NT = w.nt;
+        T x[H];
+#pragma unroll
+        for (int k = 0; k < H; ++k) x[k] = cl[(h * H + k) * NT + tid];
+        if (mode == MODE_POST_F) {
+          T pv[H];
+#pragma unroll
+          for (int k = 0; k < H; ++k) pv[k] = row[(h * H + k) * NT + tid];
+#pragma unroll
+          for (int k = 0; k < H; ++k) x[k] += pv[k];
+        }
+#pragma unroll
+        for (int k = 0; k < H; ++k) row[(h * H + k) * NT + tid] = x[k];
+      }
+    }
+  }
+}
+
 // Operator constants of the windowed kernel.
 template <int KF, int KB, class T>
 struct WinOp {
@@ -209,13 +390,35 @@ __global__ void __launch_bounds__(MAXT) wstep_kernel(const LevelDesc *__restrict
   win_dir_load<KB, T>(R.b, op.bw);
 
   int flip = 0;
+  // OP_SLC with the chain state in LDS; with 1024 threads (128 registers per
+  // thread) the coalesced batches do not fit, and the state stays in the chunks
+  if constexpr (KIND == OP_SLC && MAXT <= 512) {
+    const int base = tid * L;
+    // y = Psi^repeat of the vector; the vector holds the input on entry
+    run_chain_slc<L, T>(pa, nx, vec, red, [&](T (&y)[L]) {
+      for (int rep = 0; rep < R.repeat; ++rep) {
+        if (rep > 0) {
+          __syncthreads();  // every thread has finished the previous gather
+#pragma unroll
+          for (int j = 0; j < L; ++j) vec[win_pad<L>(base + j)] = y[j];
+          __syncthreads();
+        }
+#pragma unroll
+        for (int j = 0; j < L; ++j) y[j] = T(0);
+        win_gather<L, 2 * KF>(vec, wrap_lo(base - R.off, nx), nx, R.w, y);
+        if (lo.alias) __syncthreads();  // the published states reuse the vector's words
+        win_solve<L, KF, KB>(y, R, pub0, pub1, flip, tid, NT);
+      }
+    });
+    return;
+  }
   // the rows a step adds are read after the step: loading them before it
   // (into registers) measured slower at 32 points per thread
   run_chain<L, T, 0>(pa, nx, L, red, [&](T (&u)[L]) {
     const int base = tid * L;
     for (int rep = 0; rep < R.repeat; ++rep) {
       T y[L];
-      if (KIND == OP_SLC) {
+      if constexpr (KIND == OP_SLC) {
         __syncthreads();  // every thread has finished the previous gather
 #pragma unroll
         for (int j = 0; j < L; ++j) vec[win_pad<L>(base + j)] = u[j];
