@@ -176,6 +176,15 @@ __device__ __forceinline__ WalkIdx walk_idx() {
   return w;
 }
 
+// p[0] += v as a device-scope atomic whose result is not returned: the add
+// happens in the L2 cache, so the lane never waits for the old value.  Each
+// element receives one such add per launch, so the sum is the plain
+// correctly rounded a + b.
+template <class T>
+__device__ __forceinline__ void add_in_cache(T *p, T v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int L, class T, class Step>
 __device__ __forceinline__ void run_chain_slc(const PassArgsT<T> &pa, int nx, T *vec, double *red, Step step) {
   typedef __attribute__((address_space(1))) T *gT;
@@ -207,7 +216,6 @@ __device__ __forceinline__ void run_chain_slc(const PassArgsT<T> &pa, int nx, T 
     const gcT cin = (gcT)(pa.cin + row0 * nxl);
     const gT c0 = (gT)pa.cout;
     const gT o0 = (gT)(mode == MODE_FINAL_F ? pa.out + (b * m) * nxl : pa.out);
-    const gT p0 = (gT)(pa.parent + (b * m) * nxl);
     for (int h = 0; h < NB; ++h) {
       const WalkIdx w = walk_idx();
       const int tid = w.t, NT = w.nt;
@@ -225,11 +233,8 @@ __device__ __forceinline__ void run_chain_slc(const PassArgsT<T> &pa, int nx, T 
         for (int k = 0; k < H; ++k) o0[(h * H + k) * NT + tid] = x[k];
       }
       if (mode == MODE_POST_F) {
-        T pv[H];
 #pragma unroll
-        for (int k = 0; k < H; ++k) pv[k] = p0[(h * H + k) * NT + tid];
-#pragma unroll
-        for (int k = 0; k < H; ++k) p0[(h * H + k) * NT + tid] = pv[k] + x[k];
+        for (int k = 0; k < H; ++k) add_in_cache(pa.parent + (b * m) * nxl + (h * H + k) * NT + tid, x[k]);
       }
     }
   }
@@ -248,7 +253,6 @@ __device__ __forceinline__ void run_chain_slc(const PassArgsT<T> &pa, int nx, T 
     __syncthreads();
     if (add_g || add_parent || store_out) {
       const gcT g = (gcT)(pa.g + (n - 1) * nxl);
-      const gT pr = (gT)(pa.parent + n * nxl);
       const gT o = (gT)(pa.out + n * nxl);
       for (int h = 0; h < NB; ++h) {
         const WalkIdx w = walk_idx();
@@ -267,11 +271,8 @@ __device__ __forceinline__ void run_chain_slc(const PassArgsT<T> &pa, int nx, T 
           }
         }
         if (add_parent) {
-          T pv[H];
 #pragma unroll
-          for (int k = 0; k < H; ++k) pv[k] = pr[(h * H + k) * NT + tid];
-#pragma unroll
-          for (int k = 0; k < H; ++k) pr[(h * H + k) * NT + tid] = pv[k] + x[k];
+          for (int k = 0; k < H; ++k) add_in_cache(pa.parent + n * nxl + (h * H + k) * NT + tid, x[k]);
         }
         if (store_out) {
 #pragma unroll
@@ -322,14 +323,13 @@ __device__ __forceinline__ void run_chain_slc(const PassArgsT<T> &pa, int nx, T 
 #pragma unroll
         for (int k = 0; k < H; ++k) x[k] = cl[(h * H + k) * NT + tid];
         if (mode == MODE_POST_F) {
-          T pv[H];
 #pragma unroll
-          for (int k = 0; k < H; ++k) pv[k] = row[(h * H + k) * NT + tid];
+          for (int k = 0; k < H; ++k)
+            add_in_cache(pa.parent + (pa.nint * m) * nxl + (h * H + k) * NT + tid, x[k]);
+        } else {
 #pragma unroll
-          for (int k = 0; k < H; ++k) x[k] += pv[k];
+          for (int k = 0; k < H; ++k) row[(h * H + k) * NT + tid] = x[k];
         }
-#pragma unroll
-        for (int k = 0; k < H; ++k) row[(h * H + k) * NT + tid] = x[k];
       }
     }
   }
