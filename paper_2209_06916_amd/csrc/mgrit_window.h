@@ -168,11 +168,11 @@ __device__ __forceinline__ void win_gather(const T *vec, int start, int nx, cons
 // nearly every register.
 struct WalkIdx {
   int t;   // thread index
-  int nt;  // threads
+  int nt;  // threads (wave-uniform)
 };
-__device__ __forceinline__ WalkIdx walk_idx() {
-  WalkIdx w{(int)threadIdx.x, (int)blockDim.x};
-  asm volatile("" : "+v"(w.t), "+v"(w.nt));
+__device__ __forceinline__ WalkIdx walk_idx(const WalkIdx &w0) {
+  WalkIdx w = w0;
+  asm volatile("" : "+v"(w.t), "+s"(w.nt));
   return w;
 }
 
@@ -193,6 +193,9 @@ __device__ __forceinline__ void run_chain_slc(const PassArgsT<T> &pa, int nx, T 
   // batches run out of registers at 32 points per thread)
   constexpr int H = 8, NB = L / H;
   const int64_t b = blockIdx.x;
+  // the thread index and count, read once (blockDim is a memory load, and its
+  // wait would also wait for every store and atomic in flight)
+  const WalkIdx w0{(int)threadIdx.x, __builtin_amdgcn_readfirstlane((int)blockDim.x)};
   const int64_t nxl = nx;
   const int m = pa.m;
   const int mode = pa.mode;
@@ -217,7 +220,7 @@ __device__ __forceinline__ void run_chain_slc(const PassArgsT<T> &pa, int nx, T 
     const gT c0 = (gT)pa.cout;
     const gT o0 = (gT)(mode == MODE_FINAL_F ? pa.out + (b * m) * nxl : pa.out);
     for (int h = 0; h < NB; ++h) {
-      const WalkIdx w = walk_idx();
+      const WalkIdx w = walk_idx(w0);
       const int tid = w.t, NT = w.nt;
       T x[H];
 #pragma unroll
@@ -255,7 +258,7 @@ __device__ __forceinline__ void run_chain_slc(const PassArgsT<T> &pa, int nx, T 
       const gcT g = (gcT)(pa.g + (n - 1) * nxl);
       const gT o = (gT)(pa.out + n * nxl);
       for (int h = 0; h < NB; ++h) {
-        const WalkIdx w = walk_idx();
+        const WalkIdx w = walk_idx(w0);
         const int tid = w.t, NT = w.nt;
         T x[H];
 #pragma unroll
@@ -285,7 +288,7 @@ __device__ __forceinline__ void run_chain_slc(const PassArgsT<T> &pa, int nx, T 
 
   // post-chain actions (the vector holds the chain's last point)
   if (mode == MODE_PASS_A || mode == MODE_APPLY) {
-    const WalkIdx w = walk_idx();
+    const WalkIdx w = walk_idx(w0);
     const int tid = w.t, NT = w.nt;
     const gT c1 = (gT)(pa.cout + (mode == MODE_PASS_A ? b + 1 : b) * nxl);
 #pragma unroll
@@ -295,7 +298,7 @@ __device__ __forceinline__ void run_chain_slc(const PassArgsT<T> &pa, int nx, T 
     const gT r = (gT)(pa.r + b * nxl);
     double ss = 0.0;
     for (int h = 0; h < NB; ++h) {
-      const WalkIdx w = walk_idx();
+      const WalkIdx w = walk_idx(w0);
       const int tid = w.t, NT = w.nt;
       T x[H];
 #pragma unroll
@@ -317,7 +320,7 @@ __device__ __forceinline__ void run_chain_slc(const PassArgsT<T> &pa, int nx, T 
       const gcT cl = (gcT)(pa.cin + pa.nint * nxl);
       const gT row = (gT)((mode == MODE_POST_F ? pa.parent : pa.out) + (pa.nint * m) * nxl);
       for (int h = 0; h < NB; ++h) {
-        const WalkIdx w = walk_idx();
+        const WalkIdx w = walk_idx(w0);
         const int tid = w.t, NT = w.nt;
         T x[H];
 #pragma unroll
