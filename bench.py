@@ -183,6 +183,21 @@ def summarize_profiles(d):
         for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
             lines.append(f"  {_short(r['Name']):52s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
                          f"{float(r['TotalDurationNs']) / 1e6:10.3f} {100 * float(r['TotalDurationNs']) / tot:6.2f}%")
+        trace_csv = os.path.join(d, "trace", "run_kernel_trace.csv")
+        if os.path.exists(trace_csv):
+            # the same kernel runs several launch shapes (relaxation passes,
+            # sequential stepping): durations per shape, from the kernel trace
+            shapes = {}
+            for r in csv.DictReader(open(trace_csv)):
+                k = _short(r["Kernel_Name"])
+                if not k.startswith("wstep_kernel"):
+                    continue
+                wgs = int(r["Grid_Size_X"]) // max(1, int(r["Workgroup_Size_X"]))
+                shapes.setdefault((k, wgs), []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+            lines += ["#", "# per launch shape (kernel trace; workgroups per launch):",
+                      f"# {'kernel':44s} {'workgroups':>10s} {'calls':>6s} {'avg_us':>10s} {'median_us':>10s}"]
+            for (k, wgs), ds in sorted(shapes.items(), key=lambda kv: -sum(kv[1])):
+                lines.append(f"  {k:44s} {wgs:10d} {len(ds):6d} {float(np.mean(ds)):10.2f} {float(np.median(ds)):10.2f}")
         lines += ["#", "# wstep_kernel<32, 1, 3, 2, 512, double>: SDIRK3 + U5 steps (32 points per thread, 512 threads);",
                   "#   grid 524288: level-0 relaxation passes (1024 intervals) and the final F-pass; grid 512: sequential",
                   "#   time-stepping (one workgroup, 16384 steps)",
