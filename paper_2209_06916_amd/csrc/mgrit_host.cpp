@@ -727,10 +727,11 @@ struct mgrit_handle {
   size_t cv_lds = 0;
   int64_t cv_grid = 0;
   GridSync *gsync = nullptr;
-  // mixed precision: the inner right-hand side and solution (float32), the
-  // outer residual and, when the caller keeps no u_out, the outer iterate
+  // mixed precision: the inner right-hand side (the outer residual, which
+  // the residual kernel writes rounded) and solution (float32) and, when the
+  // caller keeps no u_out, the outer iterate
   float *g32 = nullptr, *e32 = nullptr;
-  double *r64 = nullptr, *u64 = nullptr;
+  double *u64 = nullptr;
   char *arena = nullptr;       // every device buffer of the handle
   size_t arena_bytes = 0;
   bool owns_arena = false;     // false: the caller's workspace (mgrit_setup_ws)
@@ -1381,6 +1382,7 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
       Lv.phi_q = S.phi_q;
       Lv.op = S.op;
       Lv.lay = S.lay;
+      Lv.op.no_lean = env_int("MGRIT_NO_LEAN", 0);
       tabs[l] = std::move(S.tabs);
       offs[l] = std::move(S.offs);
       if (O->coarse_solve == 1) {
@@ -1503,7 +1505,7 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
       o_kry[l] = off, off += al((size_t)cap * (h->lv[l].op.gmres_max + 1) * nx * sizeof(double));
     }
   std::vector<size_t> o_c32a(nlev, none), o_c32b(nlev, none), o_r32(nlev, none);
-  size_t o_g32 = none, o_e32 = none, o_r64 = none, o_u64 = none;
+  size_t o_g32 = none, o_e32 = none, o_u64 = none;
   if (mixed) {
     for (int l = 0; l + 1 < nlev; ++l) {
       const size_t rows = (size_t)(h->lv[l].nt / h->lv[l].m);
@@ -1514,7 +1516,6 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
     const size_t pts = (size_t)P->nt * nx;
     o_g32 = off, off += al(pts * sizeof(float));
     o_e32 = off, off += al((pts + nx) * sizeof(float));
-    o_r64 = off, off += al(pts * sizeof(double));
     o_u64 = off, off += al((pts + nx) * sizeof(double));
   }
   h->normpart_len = std::max<int64_t>(P->nt, 1);
@@ -1606,7 +1607,6 @@ mgrit_status setup_impl(const mgrit_problem *P, const mgrit_options *O, void *st
   if (mixed) {
     h->g32 = (float *)(base + o_g32);
     h->e32 = (float *)(base + o_e32);
-    h->r64 = (double *)(base + o_r64);
     h->u64 = (double *)(base + o_u64);
   }
   if (o_gs != none) h->gsync = (GridSync *)(base + o_gs);  // zero from the upload
@@ -1709,7 +1709,8 @@ void harvest_events(mgrit_handle *h) {
 }
 
 hipError_t run_pass(mgrit_handle *h, const Level &L, int phase, int mode, int m, int64_t nint, const double *cin,
-                    double *cout, const double *g, double *r, double *parent, double *out, int zero_init) {
+                    double *cout, const double *g, double *r, double *parent, double *out, int zero_init,
+                    float *r32 = nullptr) {
   PassArgs pa{};
   pa.mode = mode;
   pa.m = m;
@@ -1719,6 +1720,7 @@ hipError_t run_pass(mgrit_handle *h, const Level &L, int phase, int mode, int m,
   pa.cout = cout;
   pa.g = g;
   pa.r = r;
+  pa.r32 = r32;
   pa.parent = parent;
   pa.out = out;
   pa.normpart = h->normpart;
@@ -2070,14 +2072,23 @@ mgrit_status mp_solve(mgrit_handle *h, const double *u0, const double *v_init, d
   // reads the decision from pinned memory while that step runs
   const StopRule orule{h->opt.rtol, h->opt.diverge_factor, h->opt.max_iter, 0.0};
   const int *ostop = &h->octl->stop;
+  // each residual workgroup takes rk consecutive time points, so that every
+  // row of the iterate is read once (plus one row per workgroup), while
+  // keeping at least 1024 workgroups (four per CU)
+  int rk = 1;
+  for (int k : {16, 8, 4, 2})
+    if (nt % k == 0 && nt / k >= 1024) {
+      rk = k;
+      break;
+    }
   HIPCHK(h, hipMemsetAsync(h->octl, 0, sizeof(SolveCtl), h->stream));
   for (;;) {
-    // float64: r = g - A u at every time point, its norm and the test
-    HIPCHK(h, run_pass(h, L0, MGRIT_PROF_RESIDUAL, MODE_RESID, 1, nt, U, nullptr, nullptr, h->r64, nullptr, nullptr,
-                       0));
-    HIPCHK(h, launch_solve_ctl(h->normpart, nt, h->octl, h->octl_host_dev, nullptr, orule, h->stream));
+    // float64: r = g - A u at every time point, its norm and the test; the
+    // kernel writes r rounded to float32, the inner right-hand side
+    HIPCHK(h, run_pass(h, L0, MGRIT_PROF_RESIDUAL, MODE_RESID, rk, nt / rk, U, nullptr, nullptr, nullptr, nullptr,
+                       nullptr, 0, h->g32));
+    HIPCHK(h, launch_solve_ctl(h->normpart, nt / rk, h->octl, h->octl_host_dev, nullptr, orule, h->stream));
     // float32: A e = r, then u += e in float64; all skipped after a stop
-    HIPCHK(h, launch_round32(h->r64, h->g32, pts, h->stream, ostop));
     int iters = 0, stop = 0;
     const mgrit_status st = inner_solve(h, ostop, &iters, &stop);
     if (st != MGRIT_OK) return st;
@@ -2252,14 +2263,14 @@ mgrit_status mgrit_workspace_bytes(const mgrit_problem *P, const mgrit_options *
   }
   if (O->precision == MGRIT_PREC_MIXED) {
     // float32 copies of the level arrays and tables, the inner right-hand
-    // side and solution (float32), the outer residual and iterate (float64)
+    // side and solution (float32), the outer iterate (float64)
     uint64_t n32 = 0;
     for (size_t l = 0; l + 1 < nts.size(); ++l) {
       const uint64_t nc = (uint64_t)(nts[l] / ms[l]);
       n32 += (2 * (nc + 1) + nc) * (uint64_t)P->nx;
     }
     const uint64_t pts = (uint64_t)P->nt * (uint64_t)P->nx;
-    *bytes += n32 * sizeof(float) + (2 * pts + P->nx) * sizeof(float) + (2 * pts + P->nx) * sizeof(double) +
+    *bytes += n32 * sizeof(float) + (2 * pts + P->nx) * sizeof(float) + (pts + P->nx) * sizeof(double) +
               (uint64_t)nts.size() * (2 * RTAB_ALL * KMAX * KMAX * sizeof(float) + sizeof(LevelDesc) + 5 * 256) +
               4 * 256;
   }

@@ -77,6 +77,7 @@ struct StepOp {
   // krylov + b (gmres_max + 1) nx for workgroup b < krylov_cap
   int gmres_max;
   double gmres_rtol;
+  int no_lean;  // OP_SLC: keep this operator off the lean kernel (setup's choice)
   int t_k;
   double ttaps[MAXTAPS];
   double *krylov;
@@ -170,7 +171,7 @@ constexpr __host__ __device__ inline LeanLds lean_lds_offsets(int nx, int K) {
 // equal forward/backward orders, no repetition, and recurrence tables built
 // for 16-point chunks that cover nx exactly.
 inline bool lean_slc_applies(const StepOp &op, const Layout &lay) {
-  if (op.gmres_max > 0) return false;
+  if (op.gmres_max > 0 || op.no_lean) return false;
   const int W = op.sl_l + op.sl_r + 1;
   const int nw = lay.L > 0 ? lay.nx / (WAVE * lay.L) : 0;
   return op.kind == OP_SLC && op.has_solve && op.repeat == 1 && !lay.ragged && lay.A == lay.T &&
@@ -186,7 +187,7 @@ enum PassMode : int {
   MODE_FINAL_F = 3,  // F-relaxation writing every time point to the output
   MODE_SEQ = 4,      // sequential stepping over all steps (one workgroup)
   MODE_APPLY = 5,    // independent vectors, nsteps applications each
-  MODE_RESID = 6     // one step per time point: space-time residual
+  MODE_RESID = 6     // space-time residual: m consecutive time points per workgroup, one step each
 };
 
 template <class T>
@@ -199,6 +200,7 @@ struct PassArgsT {
   T *cout;            // PASS_A: [nint+1][nx]; APPLY: [nint][nx]
   const T *g;         // right-hand side rows, g[n-1] for level point n; NULL = 0
   T *r;               // PASS_B: [nint][nx] residual; RESID: [nint][nx] or NULL
+  float *r32;         // RESID (float64 kernels): the residual rounded to float32, or NULL
   T *parent;          // POST_F / SEQ: parent C-point rows to add into
   T *out;             // FINAL_F / SEQ: output rows
   double *normpart;   // PASS_B / RESID: per-workgroup partial sum of squares

@@ -371,9 +371,10 @@ __device__ __forceinline__ void run_chain(const PassArgsT<T> &pa, int nx, int cn
     case MODE_FINAL_F: nsteps = m - 1; break;
     case MODE_SEQ: nsteps = m; break;
     case MODE_APPLY: nsteps = m; break;
-    default: nsteps = 1; break;  // MODE_RESID
+    default: nsteps = m; break;  // MODE_RESID: m consecutive time points per workgroup
   }
-  const int64_t row0 = (mode == MODE_SEQ) ? 0 : b;
+  const int64_t row0 = (mode == MODE_SEQ) ? 0 : (mode == MODE_RESID ? b * m : b);
+  double rss = 0.0;  // MODE_RESID: sum of squares of this workgroup's residual rows
   if (pa.zero_init) {
 #pragma unroll
     for (int j = 0; j < L; ++j) u[j] = 0.0;
@@ -429,12 +430,31 @@ __device__ __forceinline__ void run_chain(const PassArgsT<T> &pa, int nx, int cn
       }
     }
     if (store_out) store_chunk<L>(pa.out + n * nxl, base, cnt, u);
+    if (mode == MODE_RESID) {
+      // r_{n-1} = Phi u_{n-1} - u_n; the next step starts from u_n itself
+      T c1[L];
+      load_chunk<L>(pa.cin + n * nxl, base, cnt, c1);
+#pragma unroll
+      for (int q = 0; q < L; ++q) {
+        u[q] -= c1[q];
+        if (q < cnt) rss = fma((double)u[q], (double)u[q], rss);
+      }
+      if (pa.r) store_chunk<L>(pa.r + (n - 1) * nxl, base, cnt, u);
+      if (pa.r32) {
+        float u32[L];
+#pragma unroll
+        for (int q = 0; q < L; ++q) u32[q] = (float)u[q];
+        store_chunk<L>(pa.r32 + (n - 1) * nxl, base, cnt, u32);
+      }
+#pragma unroll
+      for (int q = 0; q < L; ++q) u[q] = c1[q];
+    }
   }
 
   // post-chain actions
   if (mode == MODE_PASS_A) {
     store_chunk<L>(pa.cout + (b + 1) * nxl, base, cnt, u);
-  } else if (mode == MODE_PASS_B || mode == MODE_RESID) {
+  } else if (mode == MODE_PASS_B) {
     const T *__restrict__ c1 = pa.cin + (b + 1) * nxl;
     double ss = 0.0;
 #pragma unroll
@@ -446,6 +466,9 @@ __device__ __forceinline__ void run_chain(const PassArgsT<T> &pa, int nx, int cn
     }
     if (pa.r) store_chunk<L>(pa.r + b * nxl, base, cnt, u);
     const double tot = block_sum(ss, red);
+    if (tid == 0) pa.normpart[b] = tot;
+  } else if (mode == MODE_RESID) {
+    const double tot = block_sum(rss, red);
     if (tid == 0) pa.normpart[b] = tot;
   } else if (mode == MODE_POST_F || mode == MODE_FINAL_F) {
     if (b == pa.nint - 1) {
