@@ -390,10 +390,10 @@ struct WinLds {
 };
 constexpr __host__ __device__ inline WinLds win_lds(int kind, int nx, int nt, int kw, int wsize, int L) {
   WinLds o{};
-  const int pv = kind == OP_SLC ? nx + nx / L + 1 : 0;
+  const int pv = nx + nx / L + 1;  // the padded vector (OP_SLC: gather; OP_POLY_W: row staging)
   const int pubn = nt * kw;
   int end = pv + 2 * pubn;
-  if (kind == OP_SLC && (size_t)(end * wsize + 8) / 8 * 8 + MAXWAVES * 8 > 160 * 1024) {
+  if ((size_t)(end * wsize + 8) / 8 * 8 + MAXWAVES * 8 > 160 * 1024) {
     o.alias = 1;
     end = pv;
     o.pub0 = 0;

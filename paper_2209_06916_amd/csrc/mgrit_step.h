@@ -353,8 +353,72 @@ __device__ __forceinline__ void apply_step(T (&u)[L], int cnt, const OpRegs<T> &
 // The chain of time steps of one pass (see PassMode): load the start vector,
 // advance it step by step with step(u) (all threads together), and do the
 // mode's per-step and final memory work.  cnt: points of this thread.
-template <int L, class T, int PREFETCH = (L <= 16 ? 3 : 0), class Step>
-__device__ __forceinline__ void run_chain(const PassArgsT<T> &pa, int nx, int cnt, double *red, Step step) {
+// Coalesced row walks (i = k NT + t) recompute their addresses from an
+// opaque copy of the thread index in every phase: hoisted out of a step loop,
+// the 2 L addresses of a walk would stay live across steps that already need
+// nearly every register.
+struct WalkIdx {
+  int t;   // thread index
+  int nt;  // threads (wave-uniform)
+};
+__device__ __forceinline__ WalkIdx walk_idx(const WalkIdx &w0) {
+  WalkIdx w = w0;
+  asm volatile("" : "+v"(w.t), "+s"(w.nt));
+  return w;
+}
+
+// A row moved between global memory and the threads' chunks (L points per
+// thread, nx = NT L) through an LDS staging vector padded like the
+// windowed kernel's (one word after every L points), so that the global side
+// is coalesced: one cache line per 16 lanes instead of one per lane.  Every
+// thread must call; both end with a barrier, so the staging words are free
+// again on return.
+template <int L, class T>
+__device__ __forceinline__ void staged_load(const T *row, T (&x)[L], T *stage, const WalkIdx &w0) {
+  typedef const __attribute__((address_space(1))) T *gcT;
+  __syncthreads();  // the staging words are free
+  {
+    const WalkIdx w = walk_idx(w0);
+    const gcT g = (gcT)row;
+    constexpr int H = 8;
+    for (int h = 0; h < L / H; ++h) {
+      T v[H];
+#pragma unroll
+      for (int k = 0; k < H; ++k) v[k] = g[(h * H + k) * w.nt + w.t];
+#pragma unroll
+      for (int k = 0; k < H; ++k) stage[(h * H + k) * w.nt + w.t + ((h * H + k) * w.nt + w.t) / L] = v[k];
+    }
+  }
+  __syncthreads();
+  const int base = (int)threadIdx.x * L;
+#pragma unroll
+  for (int j = 0; j < L; ++j) x[j] = stage[base + j + (base + j) / L];
+  __syncthreads();
+}
+
+template <int L, class T, class U>
+__device__ __forceinline__ void staged_store(U *row, const T (&x)[L], T *stage, const WalkIdx &w0) {
+  typedef __attribute__((address_space(1))) U *gU;
+  __syncthreads();  // the staging words are free
+  const int base = (int)threadIdx.x * L;
+#pragma unroll
+  for (int j = 0; j < L; ++j) stage[base + j + (base + j) / L] = x[j];
+  __syncthreads();
+  {
+    const WalkIdx w = walk_idx(w0);
+    const gU g = (gU)row;
+#pragma unroll 8
+    for (int k = 0; k < L; ++k) {
+      const int i = k * w.nt + w.t;
+      g[i] = (U)stage[i + i / L];
+    }
+  }
+  __syncthreads();
+}
+
+template <int L, class T, int PREFETCH = (L <= 16 ? 3 : 0), bool STAGED = false, class Step>
+__device__ __forceinline__ void run_chain(const PassArgsT<T> &pa, int nx, int cnt, double *red, Step step,
+                                          T *stage = nullptr) {
   const int tid = threadIdx.x;
   const int base = tid * L;
   const int64_t b = blockIdx.x;
@@ -362,6 +426,31 @@ __device__ __forceinline__ void run_chain(const PassArgsT<T> &pa, int nx, int cn
   const int m = pa.m;
   const int mode = pa.mode;
   T u[L];
+  // STAGED (nx = NT L, every chunk full): rows move through the LDS staging
+  // vector, coalesced
+  const WalkIdx w0{(int)threadIdx.x, STAGED ? __builtin_amdgcn_readfirstlane((int)blockDim.x) : 0};
+  auto ld = [&](const T *row, T(&x)[L]) {
+    if constexpr (STAGED)
+      staged_load<L>(row, x, stage, w0);
+    else
+      load_chunk<L>(row, base, cnt, x);
+  };
+  auto st = [&](T *row, const T(&x)[L]) {
+    if constexpr (STAGED)
+      staged_store<L>(row, x, stage, w0);
+    else
+      store_chunk<L>(row, base, cnt, x);
+  };
+  auto st32 = [&](float *row, const T(&x)[L]) {  // the row rounded to float32
+    if constexpr (STAGED) {
+      staged_store<L>(row, x, stage, w0);
+    } else {
+      float xs[L];
+#pragma unroll
+      for (int q = 0; q < L; ++q) xs[q] = (float)x[q];
+      store_chunk<L>(row, base, cnt, xs);
+    }
+  };
 
   int nsteps;
   switch (mode) {
@@ -379,11 +468,11 @@ __device__ __forceinline__ void run_chain(const PassArgsT<T> &pa, int nx, int cn
 #pragma unroll
     for (int j = 0; j < L; ++j) u[j] = 0.0;
   } else {
-    load_chunk<L>(pa.cin + row0 * nxl, base, cnt, u);
+    ld(pa.cin + row0 * nxl, u);
   }
-  if (mode == MODE_PASS_A && b == 0) store_chunk<L>(pa.cout, base, cnt, u);
-  if (mode == MODE_FINAL_F) store_chunk<L>(pa.out + (b * m) * nxl, base, cnt, u);
-  if (mode == MODE_SEQ && pa.out) store_chunk<L>(pa.out, base, cnt, u);
+  if (mode == MODE_PASS_A && b == 0) st(pa.cout, u);
+  if (mode == MODE_FINAL_F) st(pa.out + (b * m) * nxl, u);
+  if (mode == MODE_SEQ && pa.out) st(pa.out, u);
   const bool add_g = pa.g && mode != MODE_APPLY && mode != MODE_RESID;
   const bool add_parent = mode == MODE_POST_F || (mode == MODE_SEQ && pa.parent);
   const bool store_out = mode == MODE_FINAL_F || (mode == MODE_SEQ && pa.out);
@@ -429,23 +518,18 @@ __device__ __forceinline__ void run_chain(const PassArgsT<T> &pa, int nx, int cn
           if (q < cnt) pr[q] += u[q];
       }
     }
-    if (store_out) store_chunk<L>(pa.out + n * nxl, base, cnt, u);
+    if (store_out) st(pa.out + n * nxl, u);
     if (mode == MODE_RESID) {
       // r_{n-1} = Phi u_{n-1} - u_n; the next step starts from u_n itself
       T c1[L];
-      load_chunk<L>(pa.cin + n * nxl, base, cnt, c1);
+      ld(pa.cin + n * nxl, c1);
 #pragma unroll
       for (int q = 0; q < L; ++q) {
         u[q] -= c1[q];
         if (q < cnt) rss = fma((double)u[q], (double)u[q], rss);
       }
-      if (pa.r) store_chunk<L>(pa.r + (n - 1) * nxl, base, cnt, u);
-      if (pa.r32) {
-        float u32[L];
-#pragma unroll
-        for (int q = 0; q < L; ++q) u32[q] = (float)u[q];
-        store_chunk<L>(pa.r32 + (n - 1) * nxl, base, cnt, u32);
-      }
+      if (pa.r) st(pa.r + (n - 1) * nxl, u);
+      if (pa.r32) st32(pa.r32 + (n - 1) * nxl, u);
 #pragma unroll
       for (int q = 0; q < L; ++q) u[q] = c1[q];
     }
@@ -453,18 +537,28 @@ __device__ __forceinline__ void run_chain(const PassArgsT<T> &pa, int nx, int cn
 
   // post-chain actions
   if (mode == MODE_PASS_A) {
-    store_chunk<L>(pa.cout + (b + 1) * nxl, base, cnt, u);
+    st(pa.cout + (b + 1) * nxl, u);
   } else if (mode == MODE_PASS_B) {
-    const T *__restrict__ c1 = pa.cin + (b + 1) * nxl;
     double ss = 0.0;
+    if constexpr (STAGED) {
+      T c1[L];
+      ld(pa.cin + (b + 1) * nxl, c1);
 #pragma unroll
-    for (int j = 0; j < L; ++j) {
-      if (j < cnt) {
-        u[j] -= c1[base + j];
+      for (int j = 0; j < L; ++j) {
+        u[j] -= c1[j];
         ss = fma((double)u[j], (double)u[j], ss);
       }
+    } else {
+      const T *__restrict__ c1 = pa.cin + (b + 1) * nxl;
+#pragma unroll
+      for (int j = 0; j < L; ++j) {
+        if (j < cnt) {
+          u[j] -= c1[base + j];
+          ss = fma((double)u[j], (double)u[j], ss);
+        }
+      }
     }
-    if (pa.r) store_chunk<L>(pa.r + b * nxl, base, cnt, u);
+    if (pa.r) st(pa.r + b * nxl, u);
     const double tot = block_sum(ss, red);
     if (tid == 0) pa.normpart[b] = tot;
   } else if (mode == MODE_RESID) {
@@ -472,19 +566,19 @@ __device__ __forceinline__ void run_chain(const PassArgsT<T> &pa, int nx, int cn
     if (tid == 0) pa.normpart[b] = tot;
   } else if (mode == MODE_POST_F || mode == MODE_FINAL_F) {
     if (b == pa.nint - 1) {
-      load_chunk<L>(pa.cin + pa.nint * nxl, base, cnt, u);
+      ld(pa.cin + pa.nint * nxl, u);
       T *row = (mode == MODE_POST_F ? pa.parent : pa.out) + (pa.nint * m) * nxl;
       if (mode == MODE_POST_F) {
         T pv[L];
-        load_chunk<L>(row, base, cnt, pv);
+        ld(row, pv);
 #pragma unroll
         for (int j = 0; j < L; ++j) u[j] += pv[j];
       }
-      store_chunk<L>(row, base, cnt, u);
+      st(row, u);
     }
   } else if (mode == MODE_APPLY) {
     __syncthreads();  // in-place use: every thread has read its input row
-    store_chunk<L>(pa.cout + b * nxl, base, cnt, u);
+    st(pa.cout + b * nxl, u);
   }
 }
 

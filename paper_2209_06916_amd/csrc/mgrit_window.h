@@ -162,20 +162,6 @@ __device__ __forceinline__ void win_gather(const T *vec, int start, int nx, cons
 // rows written out) walks the vector in the coalesced order i = k NT + t:
 // consecutive lanes touch consecutive words, where the chunk layout would
 // touch one cache line per lane.  Modes and row roles as in run_chain.
-// The coalesced walks recompute their addresses from an opaque copy of the
-// thread index in every phase: hoisted out of the step loop, the 2 x L
-// addresses of a walk would stay live across the step, which already needs
-// nearly every register.
-struct WalkIdx {
-  int t;   // thread index
-  int nt;  // threads (wave-uniform)
-};
-__device__ __forceinline__ WalkIdx walk_idx(const WalkIdx &w0) {
-  WalkIdx w = w0;
-  asm volatile("" : "+v"(w.t), "+s"(w.nt));
-  return w;
-}
-
 // p[0] += v as a device-scope atomic whose result is not returned: the add
 // happens in the L2 cache, so the lane never waits for the old value.  Each
 // element receives one such add per launch, so the sum is the plain
@@ -375,7 +361,7 @@ __global__ void __launch_bounds__(MAXT) wstep_kernel(const LevelDesc *__restrict
   const int tid = threadIdx.x;
   const WinLds lo = win_lds(KIND, nx, NT, KW, (int)sizeof(T), L);
   T *sm = reinterpret_cast<T *>(smem);
-  T *vec = sm;  // OP_SLC: the padded vector
+  T *vec = sm;  // the padded vector (OP_SLC: the gather's; OP_POLY_W: row staging)
   T *pub0 = sm + lo.pub0, *pub1 = sm + lo.pub1;
   double *red = smem + lo.red;
 
@@ -415,9 +401,10 @@ __global__ void __launch_bounds__(MAXT) wstep_kernel(const LevelDesc *__restrict
     });
     return;
   }
-  // the rows a step adds are read after the step: loading them before it
-  // (into registers) measured slower at 32 points per thread
-  run_chain<L, T, 0>(pa, nx, L, red, [&](T (&u)[L]) {
+  // OP_POLY_W: rows move through the padded LDS vector (coalesced); the rows
+  // a step adds are read after the step: loading them before it (into
+  // registers) measured slower at 32 points per thread
+  run_chain<L, T, 0, KIND == OP_POLY_W>(pa, nx, L, red, [&](T (&u)[L]) {
     const int base = tid * L;
     for (int rep = 0; rep < R.repeat; ++rep) {
       T y[L];
@@ -444,5 +431,5 @@ __global__ void __launch_bounds__(MAXT) wstep_kernel(const LevelDesc *__restrict
 #pragma unroll
       for (int j = 0; j < L; ++j) u[j] = y[j];
     }
-  });
+  }, vec);
 }
