@@ -87,8 +87,13 @@ __device__ __forceinline__ void win_mv(ConstPtr<T> A, const T (&x)[K], T (&acc)[
 // The halves of a chunk run as two chains: the chunk's zero-state end state
 // is Z_b + G Z_a, and the state entering the second half is Z_a + G E, with
 // G = M^{L/2} and Z_a, Z_b the halves' zero-state end states.
-template <int L, int K, bool REV, class T>
-__device__ __forceinline__ void win_rec(T (&y)[L], const WinDir<K, T> &W, T *pub, int tid, int NT) {
+struct NoHook {
+  __device__ void operator()() const {}
+};
+
+template <int L, int K, bool REV, class T, class Hook = NoHook>
+__device__ __forceinline__ void win_rec(T (&y)[L], const WinDir<K, T> &W, T *pub, int tid, int NT,
+                                        Hook hook = NoHook()) {
   const ConstPtr<T> G = W.tab + (W.D - 1) * K * K;
   // 1. end state of the chunk from a zero state
   T za[K], zb[K];
@@ -101,6 +106,7 @@ __device__ __forceinline__ void win_rec(T (&y)[L], const WinDir<K, T> &W, T *pub
 #pragma unroll
   for (int m = 0; m < K; ++m) pub[tid * K + m] = zb[m];
   __syncthreads();
+  hook();  // every thread of the workgroup is past its step's gather
   int src = REV ? (tid + 1 == NT ? 0 : tid + 1) : (tid == 0 ? NT - 1 : tid - 1);
   T E[K];
 #pragma unroll
@@ -171,8 +177,25 @@ __device__ __forceinline__ void add_in_cache(T *p, T v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The right-hand-side row of a step straight into the padded LDS vector, 32
+// doubles per thread: wavefront w copies the 64 padded segments of 32 doubles
+// its own threads own (one dword per lane per instruction, 256 bytes = one
+// segment), holding no registers, so the copy runs while the step's solve
+// does; after a wait for its own loads (vmcnt) each wavefront reads its
+// threads' segments with no barrier.
+__device__ __forceinline__ void row_to_lds_async(const double *row, double *vec) {
+  const int seg0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~(WAVE - 1)));
+  const unsigned *src = reinterpret_cast<const unsigned *>(row) + (threadIdx.x & (WAVE - 1));
+  for (int i = 0; i < WAVE; ++i) {
+    const int seg = seg0 + i;
+    __builtin_amdgcn_global_load_lds(src + seg * 64, (__attribute__((address_space(3))) void *)(vec + seg * 33), 4,
+                                     0, 0);
+  }
+}
+
 template <int L, class T, class Step>
-__device__ __forceinline__ void run_chain_slc(const PassArgsT<T> &pa, int nx, T *vec, double *red, Step step) {
+__device__ __forceinline__ void run_chain_slc(const PassArgsT<T> &pa, int nx, T *vec, double *red, bool alias,
+                                              Step step) {
   typedef __attribute__((address_space(1))) T *gT;
   typedef const __attribute__((address_space(1))) T *gcT;
   // rows move in NB batches of H loads per thread issued together (larger
@@ -229,17 +252,56 @@ __device__ __forceinline__ void run_chain_slc(const PassArgsT<T> &pa, int nx, T 
   }
   __syncthreads();
 
+  // 32 doubles per thread with separate published states: the right-hand
+  // side goes straight into the vector while the solve runs (issued once
+  // every thread is past its gather, added to the result after the solve)
+  const bool direct_g = sizeof(T) == 8 && L == 32 && !alias && add_g;
   for (int j = 1; j <= nsteps; ++j) {
     const int64_t n = (mode == MODE_SEQ) ? (int64_t)j : b * m + j;  // level point index
     {
       T y[L];
-      step(y);
-      __syncthreads();  // every thread has finished its gather (and, aliased, its solve)
+      step(y, [&] {  // every thread is past its gather: the vector's words are free
+        if constexpr (sizeof(T) == 8 && L == 32) {
+          if (direct_g) row_to_lds_async(pa.g + (n - 1) * nxl, vec);
+        }
+      });
       const int base = (int)threadIdx.x * L;
+      if (direct_g) {
+        __builtin_amdgcn_s_waitcnt(0);  // this wavefront's segments of the right-hand side have landed
 #pragma unroll
-      for (int q = 0; q < L; ++q) vec[win_pad<L>(base + q)] = y[q];
+        for (int q = 0; q < L; ++q) {
+          const int pq = win_pad<L>(base + q);
+          vec[pq] = y[q] + vec[pq];
+        }
+      } else {
+        // every thread is past its gather (the first recurrence's barrier);
+        // aliased, the solve's published states must be read first
+        if (alias) __syncthreads();
+#pragma unroll
+        for (int q = 0; q < L; ++q) vec[win_pad<L>(base + q)] = y[q];
+      }
     }
     __syncthreads();
+    if (direct_g) {
+      if (add_parent || store_out) {
+        const WalkIdx w = walk_idx(w0);
+        const gT o = (gT)(pa.out + n * nxl);
+        for (int h = 0; h < NB; ++h) {
+          T x[H];
+#pragma unroll
+          for (int k = 0; k < H; ++k) x[k] = vec[win_pad<L>((h * H + k) * w.nt + w.t)];
+          if (add_parent) {
+#pragma unroll
+            for (int k = 0; k < H; ++k) add_in_cache(pa.parent + n * nxl + (h * H + k) * w.nt + w.t, x[k]);
+          }
+          if (store_out) {
+#pragma unroll
+            for (int k = 0; k < H; ++k) o[(h * H + k) * w.nt + w.t] = x[k];
+          }
+        }
+      }
+      continue;
+    }
     if (add_g || add_parent || store_out) {
       const gcT g = (gcT)(pa.g + (n - 1) * nxl);
       const gT o = (gT)(pa.out + n * nxl);
@@ -340,14 +402,21 @@ struct WinOp {
 // y <- B^{-1} F^{-1} y.  pub0/pub1: the published-state areas.  With no
 // anti-causal factor the causal recurrence alternates between them (flip), so
 // that a recurrence never overwrites words another thread has yet to read.
-template <int L, int KF, int KB, class T>
+// hook: run once by every thread right after the first recurrence's barrier
+// (every thread is then past the gather that preceded the solve).
+template <int L, int KF, int KB, class T, class Hook = NoHook>
 __device__ __forceinline__ void win_solve(T (&y)[L], const WinOp<KF, KB, T> &R, T *pub0, T *pub1, int &flip,
-                                          int tid, int NT) {
+                                          int tid, int NT, Hook hook = NoHook()) {
   if constexpr (KF > 0) {
-    win_rec<L, KF, false>(y, R.f, flip ? pub1 : pub0, tid, NT);
+    win_rec<L, KF, false>(y, R.f, flip ? pub1 : pub0, tid, NT, hook);
     if constexpr (KB == 0) flip ^= 1;
   }
-  if constexpr (KB > 0) win_rec<L, KB, true>(y, R.b, pub1, tid, NT);
+  if constexpr (KB > 0) {
+    if constexpr (KF > 0)
+      win_rec<L, KB, true>(y, R.b, pub1, tid, NT);
+    else
+      win_rec<L, KB, true>(y, R.b, pub1, tid, NT, hook);
+  }
 }
 
 template <int L, int KIND, int KF, int KB, int MAXT, class T>
@@ -384,7 +453,7 @@ __global__ void __launch_bounds__(MAXT) wstep_kernel(const LevelDesc *__restrict
   if constexpr (KIND == OP_SLC && MAXT <= 512) {
     const int base = tid * L;
     // y = Psi^repeat of the vector; the vector holds the input on entry
-    run_chain_slc<L, T>(pa, nx, vec, red, [&](T (&y)[L]) {
+    run_chain_slc<L, T>(pa, nx, vec, red, lo.alias != 0, [&](T (&y)[L], auto after_gather) {
       for (int rep = 0; rep < R.repeat; ++rep) {
         if (rep > 0) {
           __syncthreads();  // every thread has finished the previous gather
@@ -396,7 +465,10 @@ __global__ void __launch_bounds__(MAXT) wstep_kernel(const LevelDesc *__restrict
         for (int j = 0; j < L; ++j) y[j] = T(0);
         win_gather<L, 2 * KF>(vec, wrap_lo(base - R.off, nx), nx, R.w, y);
         if (lo.alias) __syncthreads();  // the published states reuse the vector's words
-        win_solve<L, KF, KB>(y, R, pub0, pub1, flip, tid, NT);
+        const bool last = rep + 1 == R.repeat;
+        win_solve<L, KF, KB>(y, R, pub0, pub1, flip, tid, NT, [&] {
+          if (last) after_gather();
+        });
       }
     });
     return;
