@@ -49,6 +49,11 @@ CASES = [
     dict(nx=512, nt=128, p=3, kind="sdirk", q=3, c=5.0, ms=[4, 4]),
     dict(nx=1024, nt=512, p=5, kind="sdirk", q=3, c=0.5, ms=[16, 4]),
     dict(nx=300, nt=64, p=1, kind="sdirk", q=1, c=2.0, ms=[2, 2, 2]),
+    # nt >= 2048: each outer-residual workgroup takes several consecutive
+    # time points (the staged rows of the windowed SDIRK kernel, the generic
+    # ERK kernel)
+    dict(nx=1024, nt=4096, p=5, kind="sdirk", q=3, c=0.5, ms=[16, 16]),
+    dict(nx=512, nt=2048, p=3, kind="erk", q=3, c=0.85, ms=[8, 8]),
 ]
 
 

@@ -155,3 +155,28 @@ def test_windowed_mixed_precision_matches_oracle():
     seq = omg.sequential(disc.MOLStep(5, "sdirk", 3, 0.5), u0, nt)
     err = np.linalg.norm(_np(out) - seq) / np.linalg.norm(seq)
     assert err <= 1e-10, err
+
+
+def test_lds_state_and_chunk_chains_agree(monkeypatch):
+    """The coarse steps at nx = 16384 on the chain that keeps its state in the
+    LDS vector (512 threads: coalesced rows, the right-hand side loaded
+    straight into LDS during the solve, parent adds as atomics) and on the
+    chunk-layout chain (1024 threads, forced): full V-cycle solves take the
+    same iterations and agree to 1e-13 per time point."""
+    nx, nt, ms = 16384, 64, [16, 4]
+    _announce("window lds-state vs chunk chain")
+    u0 = inputs.u0_fourier(nx, 1301)
+    v0 = inputs.initial_iterate(nt, nx, u0, 1301)
+    outs, infos = [], []
+    for lc in (None, "16"):
+        if lc:
+            monkeypatch.setenv("MGRIT_WIN_L_COARSE", lc)
+        s = mgrit.Solver(mgrit.make_problem(nx, nt, 0.5, 5, "sdirk", 3), mgrit.make_options(ms, max_levels=3))
+        assert s.level_info(1)["win_L"] == (int(lc) if lc else 32)
+        out = torch.empty((nt + 1, nx), dtype=torch.float64, device=DEV)
+        infos.append(s.solve(_t(u0), _t(v0), u_out=out))
+        outs.append(_np(out))
+        s.close()
+    assert infos[0]["iterations"] == infos[1]["iterations"]
+    per_t = np.linalg.norm(outs[0] - outs[1], axis=1) / np.linalg.norm(outs[1], axis=1)
+    assert np.max(per_t) <= 1e-13, np.max(per_t)
