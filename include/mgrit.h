@@ -274,8 +274,9 @@ mgrit_status mgrit_solve_noalloc(const mgrit_problem *problem, const mgrit_optio
  * end (driving it if needed), fills stats and returns the status mgrit_solve
  * would have returned.  Arguments as for mgrit_solve; the device buffers must
  * stay valid until mgrit_solve_finish returns.  One solve at a time per handle
- * (MGRIT_EINVAL otherwise).  mgrit_solve is start + finish.  Float64 handles
- * only: MGRIT_EINVAL for MGRIT_PREC_MIXED. */
+ * (MGRIT_EINVAL otherwise).  mgrit_solve is start + finish.  Mixed-precision
+ * handles advance one float32 inner iteration (or one outer step) per
+ * decision; stats.iterations counts the outer steps. */
 mgrit_status mgrit_solve_start(mgrit_handle *h, const double *u0_dev, const double *v_init_dev, double *u_out_dev,
                                double *u_final_dev);
 mgrit_status mgrit_solve_advance(mgrit_handle *h, int32_t *done);

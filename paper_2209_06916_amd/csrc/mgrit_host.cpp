@@ -749,10 +749,16 @@ struct mgrit_handle {
     double *u_out = nullptr, *u_final = nullptr;
     int cur = 0;
     double prev = NAN;
-    SolveCtl hc{};
+    SolveCtl hc{};  // float64: the iteration state; mixed: the outer state
     std::vector<double> hist;
     mgrit_status status = MGRIT_OK;
     std::chrono::steady_clock::time_point t0;
+    // mixed precision
+    bool mixed = false;
+    double *U = nullptr;  // the outer iterate
+    int rk = 1;           // time points per residual workgroup
+    int icur = 0;         // the inner C-point buffer
+    int outer = 0, inner_total = 0;
   } ss;
   // profiler
   uint32_t prof_mask = 0;
@@ -2003,135 +2009,136 @@ mgrit_status vcycle32(mgrit_handle *h, int l, const float *g, float *parent) {
 // launch skips itself once *gate (the outer stop flag) is set, which the
 // inner state reports as STOP_OUTER.  Returns the iterations performed in
 // *iters and the inner stop code in *stop.
-mgrit_status inner_solve(mgrit_handle *h, const int *gate, int *iters, int *stop) {
+// Mixed precision in steps (mgrit_solve and mgrit_solve_start/_advance/
+// _finish): an outer step queues the float64 residual with its norm and
+// stopping test, then the float32 inner solve of A e = r from zero, one
+// iteration at a time (each skips itself once the inner state, or the outer
+// one through the gate, has stopped); the host reads each inner decision
+// from pinned memory behind an event while the correction runs.  When the
+// inner solve stops, its final F-pass writes e, the host reads the outer
+// decision (current by then) and either finishes or queues u += e and the
+// next outer step.
+mgrit_status mp_queue_inner_iteration(mgrit_handle *h) {
+  auto &ss = h->ss;
   Level &L0 = h->lv[0];
-  const int nx = (int)h->prob.nx;
   const int64_t nc = L0.nt / L0.m;
-  // a float32 residual cannot fall much below float32 rounding of the
-  // iterate: an iteration that gains less than a factor 2 ends the solve
   const StopRule rule{h->opt.inner_rtol, h->opt.diverge_factor, h->opt.inner_max_iter, 0.5};
-  int cur = 0;
-  HIPCHK(h, launch_ctl_reset(h->ctl, gate, h->stream));
   h->guard = &h->ctl->stop;
-  HIPCHK(h, launch_fill32(L0.c32[0], (nc + 1) * (int64_t)nx, h->stream, h->guard));
-  for (;;) {
-    // every launch of the iteration skips itself once the inner state has
-    // stopped (its correction is queued before the decision is known)
-    h->guard = &h->ctl->stop;
-    for (int s = 0; s < h->opt.nu; ++s) {
-      HIPCHK(h, run_pass32(h, L0, MGRIT_PROF_FINE_RELAX, MODE_PASS_A, L0.m, nc, L0.c32[cur], L0.c32[1 - cur], h->g32,
-                           nullptr, nullptr, nullptr, 0));
-      cur = 1 - cur;
-    }
-    HIPCHK(h, run_pass32(h, L0, MGRIT_PROF_FINE_RELAX, MODE_PASS_B, L0.m, nc, L0.c32[cur], nullptr, h->g32, L0.r32,
-                         nullptr, nullptr, 0));
-    HIPCHK(h, launch_solve_ctl(h->normpart, nc, h->ctl, h->ctl_host_dev, nullptr, rule, h->stream));
-    HIPCHK(h, hipEventRecord(h->ctl_ev, h->stream));
-    const mgrit_status st = vcycle32(h, 1, L0.r32, L0.c32[cur]);
-    h->guard = nullptr;
-    if (st != MGRIT_OK) return st;
-    HIPCHK(h, hipEventSynchronize(h->ctl_ev));
-    const SolveCtl hc = *h->ctl_host;
-    if (hc.stop != STOP_NONE) {
-      *iters = hc.it;
-      *stop = hc.stop;
-      break;
-    }
+  for (int s = 0; s < h->opt.nu; ++s) {
+    HIPCHK(h, run_pass32(h, L0, MGRIT_PROF_FINE_RELAX, MODE_PASS_A, L0.m, nc, L0.c32[ss.icur], L0.c32[1 - ss.icur],
+                         h->g32, nullptr, nullptr, nullptr, 0));
+    ss.icur = 1 - ss.icur;
   }
-  h->guard = gate;
-  HIPCHK(h, run_pass32(h, L0, MGRIT_PROF_FINAL, MODE_FINAL_F, L0.m, nc, L0.c32[cur], nullptr, h->g32, nullptr, nullptr,
-                       h->e32, 0));
+  HIPCHK(h, run_pass32(h, L0, MGRIT_PROF_FINE_RELAX, MODE_PASS_B, L0.m, nc, L0.c32[ss.icur], nullptr, h->g32, L0.r32,
+                       nullptr, nullptr, 0));
+  HIPCHK(h, launch_solve_ctl(h->normpart, nc, h->ctl, h->ctl_host_dev, nullptr, rule, h->stream));
+  HIPCHK(h, hipEventRecord(h->ctl_ev, h->stream));
+  const mgrit_status st = vcycle32(h, 1, L0.r32, L0.c32[ss.icur]);
   h->guard = nullptr;
-  return MGRIT_OK;
+  return st;
 }
 
-mgrit_status mp_solve(mgrit_handle *h, const double *u0, const double *v_init, double *u_out, double *u_final,
-                      mgrit_stats *stats) {
-  const auto t0 = std::chrono::steady_clock::now();
+// the outer step: float64 r = g - A u at every time point (written rounded
+// to float32 as the inner right-hand side), its norm and the test; then the
+// inner solve's start
+mgrit_status mp_queue_outer(mgrit_handle *h) {
+  auto &ss = h->ss;
+  Level &L0 = h->lv[0];
+  const int nx = (int)h->prob.nx;
+  const int64_t nt = h->prob.nt;
+  const int64_t nc = L0.nt / L0.m;
+  const StopRule orule{h->opt.rtol, h->opt.diverge_factor, h->opt.max_iter, 0.0};
+  HIPCHK(h, run_pass(h, L0, MGRIT_PROF_RESIDUAL, MODE_RESID, ss.rk, nt / ss.rk, ss.U, nullptr, nullptr, nullptr,
+                     nullptr, nullptr, 0, h->g32));
+  HIPCHK(h, launch_solve_ctl(h->normpart, nt / ss.rk, h->octl, h->octl_host_dev, nullptr, orule, h->stream));
+  const int *ostop = &h->octl->stop;
+  HIPCHK(h, launch_ctl_reset(h->ctl, ostop, h->stream));
+  ss.icur = 0;
+  HIPCHK(h, launch_fill32(L0.c32[0], (nc + 1) * (int64_t)nx, h->stream, &h->ctl->stop));
+  return mp_queue_inner_iteration(h);
+}
+
+mgrit_status mp_start(mgrit_handle *h, const double *u0, const double *v_init, double *u_out, double *u_final) {
+  auto &ss = h->ss;
+  ss = {};
+  ss.t0 = std::chrono::steady_clock::now();
+  ss.mixed = true;
+  ss.u_out = u_out;
+  ss.u_final = u_final;
+  ss.hc.rho = NAN;
   const int nx = (int)h->prob.nx;
   const int64_t nt = h->prob.nt;
   const int64_t pts = nt * nx;
-  const Level &L0 = h->lv[0];
-  double *U = u_out ? u_out : h->u64;
-  // outer iterate: v_init (or zero) with row 0 = u0
-  if (v_init && v_init != U) {
-    HIPCHK(h, hipMemcpyAsync(U, v_init, (pts + nx) * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  ss.U = u_out ? u_out : h->u64;
+  // outer iterate: v_init (or the seeded U[0,1), or zero) with row 0 = u0
+  if (v_init && v_init != ss.U) {
+    HIPCHK(h, hipMemcpyAsync(ss.U, v_init, (pts + nx) * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
   } else if (!v_init && h->opt.init_seed) {
-    HIPCHK(h, launch_splitmix_rows(U + nx, nt, 1, 1, nx, h->opt.init_seed, h->stream));
+    HIPCHK(h, launch_splitmix_rows(ss.U + nx, nt, 1, 1, nx, h->opt.init_seed, h->stream));
   } else if (!v_init) {
-    HIPCHK(h, launch_fill(U, pts + nx, 0.0, h->stream));
+    HIPCHK(h, launch_fill(ss.U, pts + nx, 0.0, h->stream));
   }
-  HIPCHK(h, hipMemcpyAsync(U, u0, nx * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
-  std::vector<double> hist;
-  double res0 = NAN, rho = NAN, prev = NAN;
-  int outer = 0, inner_total = 0;
-  mgrit_status status = MGRIT_OK;
-  // the outer loop's state lives on the device: its norm and stopping test
-  // (then max_iter, then growth) run in solve_ctl_kernel, and the refinement
-  // step queued behind it skips itself once the test says stop; the host
-  // reads the decision from pinned memory while that step runs
-  const StopRule orule{h->opt.rtol, h->opt.diverge_factor, h->opt.max_iter, 0.0};
-  const int *ostop = &h->octl->stop;
+  HIPCHK(h, hipMemcpyAsync(ss.U, u0, nx * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
   // each residual workgroup takes rk consecutive time points, so that every
   // row of the iterate is read once (plus one row per workgroup), while
   // keeping at least 1024 workgroups (four per CU)
-  int rk = 1;
+  ss.rk = 1;
   for (int k : {16, 8, 4, 2})
     if (nt % k == 0 && nt / k >= 1024) {
-      rk = k;
+      ss.rk = k;
       break;
     }
   HIPCHK(h, hipMemsetAsync(h->octl, 0, sizeof(SolveCtl), h->stream));
-  for (;;) {
-    // float64: r = g - A u at every time point, its norm and the test; the
-    // kernel writes r rounded to float32, the inner right-hand side
-    HIPCHK(h, run_pass(h, L0, MGRIT_PROF_RESIDUAL, MODE_RESID, rk, nt / rk, U, nullptr, nullptr, nullptr, nullptr,
-                       nullptr, 0, h->g32));
-    HIPCHK(h, launch_solve_ctl(h->normpart, nt / rk, h->octl, h->octl_host_dev, nullptr, orule, h->stream));
-    // float32: A e = r, then u += e in float64; all skipped after a stop
-    int iters = 0, stop = 0;
-    const mgrit_status st = inner_solve(h, ostop, &iters, &stop);
-    if (st != MGRIT_OK) return st;
-    // the inner solve's first decision came after the outer one: the outer
-    // state in pinned memory is current
-    const SolveCtl oc = *h->octl_host;
-    prev = rho;
-    rho = oc.rho;
-    res0 = oc.res0;
-    hist.push_back(rho);
-    if (oc.stop != STOP_NONE) {
-      if (oc.stop == STOP_NONFINITE) status = fail(h, MGRIT_EDIVERGED, "non-finite residual");
-      if (oc.stop == STOP_MAX_ITER) {
-        status = MGRIT_ENOTCONVERGED;
-        h->err = "max_iter reached";
-      }
-      if (oc.stop == STOP_DIVERGED) status = fail(h, MGRIT_EDIVERGED, "residual grew past diverge_factor * res0");
-      break;
+  ss.active = true;
+  const mgrit_status st = mp_queue_outer(h);
+  if (st != MGRIT_OK) ss.active = false;
+  return st;
+}
+
+// The inner decision of the last queued iteration (its event has completed).
+mgrit_status mp_take_decision(mgrit_handle *h) {
+  auto &ss = h->ss;
+  Level &L0 = h->lv[0];
+  const int nx = (int)h->prob.nx;
+  const int64_t nt = h->prob.nt;
+  const int64_t nc = L0.nt / L0.m;
+  const SolveCtl ic = *h->ctl_host;
+  if (ic.stop == STOP_NONE) return mp_queue_inner_iteration(h);
+  // the inner solve has stopped: its final F-pass writes e at every point
+  // (skipped after an outer stop)
+  const int *ostop = &h->octl->stop;
+  h->guard = ostop;
+  HIPCHK(h, run_pass32(h, L0, MGRIT_PROF_FINAL, MODE_FINAL_F, L0.m, nc, L0.c32[ss.icur], nullptr, h->g32, nullptr,
+                       nullptr, h->e32, 0));
+  h->guard = nullptr;
+  // the outer state in pinned memory is current: the inner decisions came
+  // after it
+  const SolveCtl oc = *h->octl_host;
+  ss.prev = ss.hc.rho;
+  ss.hc = oc;
+  ss.hist.push_back(oc.rho);
+  if (oc.stop != STOP_NONE) {
+    ss.finished = true;
+    if (oc.stop == STOP_NONFINITE) ss.status = fail(h, MGRIT_EDIVERGED, "non-finite residual");
+    if (oc.stop == STOP_MAX_ITER) {
+      ss.status = MGRIT_ENOTCONVERGED;
+      h->err = "max_iter reached";
     }
-    inner_total += iters;
-    if (stop == STOP_NONFINITE || stop == STOP_DIVERGED) {
-      status = fail(h, MGRIT_EDIVERGED, "the float32 inner solve diverged");
-      break;
-    }
-    HIPCHK(h, launch_add32(U, h->e32, pts + nx, h->stream, ostop));
-    ++outer;
+    if (oc.stop == STOP_DIVERGED) ss.status = fail(h, MGRIT_EDIVERGED, "residual grew past diverge_factor * res0");
+    if (ss.u_final)
+      HIPCHK(h, hipMemcpyAsync(ss.u_final, ss.U + nt * (int64_t)nx, nx * sizeof(double), hipMemcpyDeviceToDevice,
+                               h->stream));
+    return MGRIT_OK;
   }
-  if (u_final) HIPCHK(h, hipMemcpyAsync(u_final, U + pts, nx * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
-  HIPCHK(h, hipStreamSynchronize(h->stream));
-  harvest_events(h);
-  if (stats) {
-    stats->iterations = outer;
-    stats->inner_iterations = inner_total;
-    stats->res0 = res0;
-    stats->res_final = rho;
-    stats->conv_factor = prev > 0 ? rho / prev : NAN;
-    const int len = (int)hist.size();
-    if (stats->res_history)
-      for (int i = 0; i < std::min(len, stats->res_history_cap); ++i) stats->res_history[i] = hist[i];
-    stats->res_history_len = std::min(len, std::max(stats->res_history_cap, 0));
-    stats->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  ss.inner_total += ic.it;
+  if (ic.stop == STOP_NONFINITE || ic.stop == STOP_DIVERGED) {
+    ss.finished = true;
+    ss.status = fail(h, MGRIT_EDIVERGED, "the float32 inner solve diverged");
+    return MGRIT_OK;
   }
-  return status;
+  HIPCHK(h, launch_add32(ss.U, h->e32, nt * (int64_t)nx + nx, h->stream, ostop));
+  ++ss.outer;
+  return mp_queue_outer(h);
 }
 
 }  // namespace
@@ -2143,8 +2150,7 @@ mgrit_status mgrit_solve_start(mgrit_handle *h, const double *u0, const double *
   if (!h) return MGRIT_EINVAL;
   if (!u0) return fail(h, MGRIT_EINVAL, "u0 is required");
   if (h->ss.active) return fail(h, MGRIT_EINVAL, "a solve is already in progress on this handle");
-  if (h->opt.precision != MGRIT_PREC_FP64)
-    return fail(h, MGRIT_EINVAL, "the incremental solve runs float64 handles only");
+  if (h->opt.precision == MGRIT_PREC_MIXED) return mp_start(h, u0, v_init, u_out, u_final);
   auto &ss = h->ss;
   ss = {};
   ss.t0 = std::chrono::steady_clock::now();
@@ -2182,6 +2188,12 @@ mgrit_status mgrit_solve_advance(mgrit_handle *h, int32_t *done) {
   const hipError_t q = hipEventQuery(h->ctl_ev);
   if (q == hipErrorNotReady) return MGRIT_OK;
   if (q != hipSuccess) return hipfail(h, q, "stopping-test event");
+  if (ss.mixed) {
+    const mgrit_status st = mp_take_decision(h);
+    if (st != MGRIT_OK) return st;
+    *done = ss.finished ? 1 : 0;
+    return MGRIT_OK;
+  }
   const mgrit_status st = take_decision(h);
   if (st != MGRIT_OK) return st;
   if (ss.finished) {
@@ -2210,8 +2222,8 @@ mgrit_status mgrit_solve_finish(mgrit_handle *h, mgrit_stats *stats) {
   harvest_events(h);
   if (stats) {
     const auto &hc = ss.hc;
-    stats->iterations = hc.it;
-    stats->inner_iterations = 0;
+    stats->iterations = ss.mixed ? ss.outer : hc.it;
+    stats->inner_iterations = ss.mixed ? ss.inner_total : 0;
     stats->res0 = hc.res0;
     stats->res_final = hc.rho;
     stats->conv_factor = ss.prev > 0 ? hc.rho / ss.prev : NAN;
@@ -2226,11 +2238,6 @@ mgrit_status mgrit_solve_finish(mgrit_handle *h, mgrit_stats *stats) {
 
 mgrit_status mgrit_solve(mgrit_handle *h, const double *u0, const double *v_init, double *u_out, double *u_final,
                          mgrit_stats *stats) {
-  if (h && h->opt.precision == MGRIT_PREC_MIXED) {
-    if (!u0) return fail(h, MGRIT_EINVAL, "u0 is required");
-    if (h->ss.active) return fail(h, MGRIT_EINVAL, "a solve is already in progress on this handle");
-    return mp_solve(h, u0, v_init, u_out, u_final, stats);
-  }
   const mgrit_status st = mgrit_solve_start(h, u0, v_init, u_out, u_final);
   if (st != MGRIT_OK) return st;
   return mgrit_solve_finish(h, stats);

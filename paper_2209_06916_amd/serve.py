@@ -40,7 +40,7 @@ class Request:
     max_levels: int = 16
     arrival: float = 0.0  # seconds after the start of the run
     tag: object = None
-    precision: str = "fp64"  # "mixed": float32 inner cycles in float64 refinement (ThreadedServer only)
+    precision: str = "fp64"  # "mixed": float32 inner cycles in float64 refinement
     rtol: float = None  # default: 1e-10 of the float64 C-point residual; 1e-12 of the mixed-precision
     #                     full space-time residual, which gives the same solution error
 

@@ -106,13 +106,29 @@ def test_mixed_and_float64_solutions_agree():
     assert np.linalg.norm(outs[0] - outs[1]) <= 1e-10 * np.linalg.norm(outs[0])
 
 
-def test_incremental_solve_rejects_mixed_handles():
+def test_incremental_mixed_solve_matches_the_blocking_one():
+    """mgrit_solve_start / _advance / _finish on a mixed handle (one inner
+    iteration or outer step per decision) gives the blocking solve's bits,
+    iteration counts and outer residual history."""
     _announce("mixed incremental")
-    s = mgrit.Solver(mgrit.make_problem(256, 64, 0.8, 1), mgrit.make_options([4], precision="mixed"))
-    u0 = _t(inputs.u0_fourier(256, 3))
-    with pytest.raises(mgrit.MgritError) as e:
-        s.solve_start(u0)
-    assert e.value.status == mgrit.EINVAL
+    nx, nt = 1024, 512
+    s = mgrit.Solver(mgrit.make_problem(nx, nt, 0.5, 5, "sdirk", 3),
+                     mgrit.make_options([16, 4], max_levels=3, precision="mixed", rtol=1e-12))
+    u0 = _t(inputs.u0_fourier(nx, 7))
+    a = torch.empty((nt + 1, nx), dtype=torch.float64, device=DEV)
+    b = torch.empty_like(a)
+    ia = s.solve(u0, u_out=a)
+    s.solve_start(u0, None, b, None)
+    steps = 0
+    while not s.solve_advance():
+        steps += 1
+    ib = s.solve_finish()
+    torch.cuda.synchronize()
+    assert ia["status"] == ib["status"] == mgrit.OK
+    assert (ia["iterations"], ia["inner_iterations"]) == (ib["iterations"], ib["inner_iterations"])
+    assert ia["res_history"] == ib["res_history"]
+    assert torch.equal(a, b)
+    assert steps >= 1
 
 
 def test_mixed_solve_keeps_the_iterate_in_its_workspace_without_u_out():

@@ -155,3 +155,18 @@ def test_threaded_server_serves_mixed_precision_requests():
         assert got[r.tag].status == mgrit.OK, r.tag
         ref = omg.sequential(disc.MOLStep(r.p, "erk", r.p, r.c), r.u0, r.nt)[-1]
         assert np.linalg.norm(got[r.tag].u_final - ref) <= 1e-10 * np.linalg.norm(ref), r.tag
+
+
+def test_polling_server_serves_mixed_precision_requests():
+    """The single-thread polling loop drives mixed-precision handles through
+    mgrit_solve_start/_advance and gives the threaded loop's bits."""
+    _announce("serving mixed, polling loop")
+    reqs = serve.synthetic_stream(5, seed=9, rate_hz=0, sizes=(256, 512), orders=(1, 3, 5), ms=(4, 8),
+                                  precision="mixed")
+    polled = _by_tag(serve.Server(max_inflight=5).run(reqs, realtime=False))
+    threaded = _by_tag(serve.ThreadedServer(max_inflight=5).run(reqs, realtime=False))
+    for r in reqs:
+        assert polled[r.tag].status == mgrit.OK, r.tag
+        np.testing.assert_array_equal(polled[r.tag].u_final, threaded[r.tag].u_final)
+        ref = omg.sequential(disc.MOLStep(r.p, "erk", r.p, r.c), r.u0, r.nt)[-1]
+        assert np.linalg.norm(polled[r.tag].u_final - ref) <= 1e-10 * np.linalg.norm(ref), r.tag
