@@ -454,6 +454,44 @@ def precision_bench(steps):
         torch.cuda.empty_cache()
 
 
+def gmres_bench(steps):
+    """Exact against GMRES coarse solves (Sec. 6.3: zero start, 1e-2 relative
+    residual, at most 20 iterations) on the Table 3 grid (256 x 1024,
+    ERK3+U3 at 0.85 c_max, m = 8), config 2 and config 3, each from the
+    seeded U[0,1) initial iterate: wall time per solve, iterations, and the
+    coarse levels' GPU time from the library's event profiler."""
+    import torch
+    from paper_2209_06916_amd import inputs, mgrit
+    dev = torch.device("cuda:0")
+    cases = [("advection1d-256x1024-erk3u3-vcycle-m8", 256, 1024, 0.85 * 1.6258907, 3, "erk", 3, [8, 8, 8], 1002),
+             ("advection1d-4096x4096-erk3u3-vcycle-m8", 4096, 4096, 0.85, 3, "erk", 3, [8, 8, 8], 1002),
+             ("advection1d-16384x16384-sdirk3u5-vcycle-m16", 16384, 16384, 0.5, 5, "sdirk", 3, [16, 16, 16], 1003)]
+    for name, nx, nt, c, p, kind, q, ms, seed in cases:
+        line = {"workload": name}
+        u0 = torch.from_numpy(inputs.u0_fourier(nx, seed)).to(dev)
+        out = torch.empty((nt + 1, nx), dtype=torch.float64, device=dev)
+        for key, gm in (("exact", None), ("gmres", (1e-2, 20))):
+            s = mgrit.Solver(mgrit.make_problem(nx, nt, c, p, kind, q),
+                             mgrit.make_options(ms, max_levels=len(ms) + 1, init_seed=seed, gmres=gm))
+            info = s.solve(u0, None, u_out=out)  # warm-up
+            n = 1 if (gm and nx >= 16384) else steps
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(n):
+                info = s.solve(u0, None, u_out=out)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t) / n
+            s.profile_enable(["coarse"])
+            s.solve(u0, None, u_out=out)
+            coarse = s.profile_read()["coarse"]["total_ms"]
+            line[key] = {"ms_per_solve": 1e3 * wall, "iterations": info["iterations"], "coarse_ms": coarse}
+            s.close()
+        line["gmres_cost"] = line["gmres"]["ms_per_solve"] / line["exact"]["ms_per_solve"]
+        print(json.dumps(line), flush=True)
+        del out
+        torch.cuda.empty_cache()
+
+
 def twod_bench(steps):
     """Config 4: u_t + a.grad u = 0 on [-1, 1)^2, a = (0.85, 1.0),
     nx = ny = nt = 1024, dt = h/2 (c = (0.425, 0.5)), ERK3 + U3, m = 8,
@@ -704,6 +742,8 @@ def main():
                     help="the 2D extension (config 4) against 2D sequential stepping instead of the single-solve bench")
     ap.add_argument("--precision", action="store_true",
                     help="float64 against mixed-precision MGRIT on configs 2 and 3 instead of the single-solve bench")
+    ap.add_argument("--gmres", action="store_true",
+                    help="exact against GMRES coarse solves (Sec. 6.3) on the Table 3 grid and configs 2 and 3")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="CPU only: turn the rocprofv3 runs under DIR into the profiles/ summaries")
     args = ap.parse_args()
@@ -724,6 +764,9 @@ def main():
         return
     if args.twod:
         twod_bench(max(1, min(args.steps, 5)))
+        return
+    if args.gmres:
+        gmres_bench(max(1, min(args.steps, 3)))
         return
 
     wl = HEADLINE
