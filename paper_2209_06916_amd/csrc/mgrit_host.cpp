@@ -1977,6 +1977,39 @@ hipError_t run_pass32(mgrit_handle *h, const Level &L, int phase, int mode, int 
   return err;
 }
 
+// Level-0 float32 pass (inner solves of mixed precision) through the tile
+// kernel when the float64 passes use it, else the slab kernel; g: the inner
+// right-hand side at every point.
+hipError_t run_fine32(mgrit_handle *h, int phase, int mode, const float *cin, float *cout, const float *g, float *r,
+                      float *out) {
+  const Level &L0 = h->lv[0];
+  const int64_t nc = L0.nt / L0.m;
+  if (!L0.tiles) return run_pass32(h, L0, phase, mode, L0.m, nc, cin, cout, g, r, nullptr, out, 0);
+  TileArgs32 ta{};
+  ta.mode = mode;
+  ta.m = L0.m;
+  ta.nint = nc;
+  ta.cin = cin;
+  ta.cout = cout;
+  ta.r = r;
+  ta.out = out;
+  ta.g = g;
+  ta.normpart = h->normpart;
+  ta.stop = h->guard;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->prof_mask & (1u << phase)) {
+    e0 = take_event(h);
+    e1 = take_event(h);
+    if (e0 && e1) (void)hipEventRecord(e0, h->stream);
+  }
+  hipError_t err = launch_tiles32(L0.desc, L0.tg, ta, h->stream);
+  if (e0 && e1) {
+    (void)hipEventRecord(e1, h->stream);
+    h->ev_pending.push_back({phase, {e0, e1}});
+  }
+  return err;
+}
+
 // The float32 coarse-grid correction below level l-1: the passes of
 // vcycle_plan, one launch each.
 mgrit_status vcycle32(mgrit_handle *h, int l, const float *g, float *parent) {
@@ -2021,17 +2054,15 @@ mgrit_status vcycle32(mgrit_handle *h, int l, const float *g, float *parent) {
 mgrit_status mp_queue_inner_iteration(mgrit_handle *h) {
   auto &ss = h->ss;
   Level &L0 = h->lv[0];
-  const int64_t nc = L0.nt / L0.m;
   const StopRule rule{h->opt.inner_rtol, h->opt.diverge_factor, h->opt.inner_max_iter, 0.5};
   h->guard = &h->ctl->stop;
   for (int s = 0; s < h->opt.nu; ++s) {
-    HIPCHK(h, run_pass32(h, L0, MGRIT_PROF_FINE_RELAX, MODE_PASS_A, L0.m, nc, L0.c32[ss.icur], L0.c32[1 - ss.icur],
-                         h->g32, nullptr, nullptr, nullptr, 0));
+    HIPCHK(h, run_fine32(h, MGRIT_PROF_FINE_RELAX, MODE_PASS_A, L0.c32[ss.icur], L0.c32[1 - ss.icur], h->g32, nullptr,
+                         nullptr));
     ss.icur = 1 - ss.icur;
   }
-  HIPCHK(h, run_pass32(h, L0, MGRIT_PROF_FINE_RELAX, MODE_PASS_B, L0.m, nc, L0.c32[ss.icur], nullptr, h->g32, L0.r32,
-                       nullptr, nullptr, 0));
-  HIPCHK(h, launch_solve_ctl(h->normpart, nc, h->ctl, h->ctl_host_dev, nullptr, rule, h->stream));
+  HIPCHK(h, run_fine32(h, MGRIT_PROF_FINE_RELAX, MODE_PASS_B, L0.c32[ss.icur], nullptr, h->g32, L0.r32, nullptr));
+  HIPCHK(h, launch_solve_ctl(h->normpart, fine_norm_parts(h), h->ctl, h->ctl_host_dev, nullptr, rule, h->stream));
   HIPCHK(h, hipEventRecord(h->ctl_ev, h->stream));
   const mgrit_status st = vcycle32(h, 1, L0.r32, L0.c32[ss.icur]);
   h->guard = nullptr;
@@ -2101,15 +2132,13 @@ mgrit_status mp_take_decision(mgrit_handle *h) {
   Level &L0 = h->lv[0];
   const int nx = (int)h->prob.nx;
   const int64_t nt = h->prob.nt;
-  const int64_t nc = L0.nt / L0.m;
   const SolveCtl ic = *h->ctl_host;
   if (ic.stop == STOP_NONE) return mp_queue_inner_iteration(h);
   // the inner solve has stopped: its final F-pass writes e at every point
   // (skipped after an outer stop)
   const int *ostop = &h->octl->stop;
   h->guard = ostop;
-  HIPCHK(h, run_pass32(h, L0, MGRIT_PROF_FINAL, MODE_FINAL_F, L0.m, nc, L0.c32[ss.icur], nullptr, h->g32, nullptr,
-                       nullptr, h->e32, 0));
+  HIPCHK(h, run_fine32(h, MGRIT_PROF_FINAL, MODE_FINAL_F, L0.c32[ss.icur], nullptr, h->g32, nullptr, h->e32));
   h->guard = nullptr;
   // the outer state in pinned memory is current: the inner decisions came
   // after it

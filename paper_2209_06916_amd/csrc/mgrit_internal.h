@@ -251,22 +251,31 @@ struct TileGeom {
   int comp;    // 1: one application of the written-out step (ct_l, ct_r), else Horner
 };
 
-struct TileArgs {
+template <class T>
+struct TileArgsT {
   int mode;           // MODE_PASS_A, MODE_PASS_B, MODE_FINAL_F or MODE_SEQ (one block
                       // of m sequential steps: nint = 1, cin = out = the block's first row)
   int m;              // steps per interval
   int64_t nint;       // intervals
-  const double *cin;  // [nint+1][nx]
-  double *cout;       // PASS_A: [nint+1][nx]
-  double *r;          // PASS_B: [nint][nx]
-  double *out;        // FINAL_F: [nint*m+1][nx]
+  const T *cin;       // [nint+1][nx]
+  T *cout;            // PASS_A: [nint+1][nx]
+  T *r;               // PASS_B: [nint][nx]
+  T *out;             // FINAL_F: [nint*m+1][nx]
+  const T *g;         // right-hand side rows, g[n-1] added after the step to level point n; NULL = 0
   double *normpart;   // PASS_B: [nint*ntiles]
+  const int *stop;    // non-NULL: the launch does nothing once *stop != 0
 };
+using TileArgs = TileArgsT<double>;
+using TileArgs32 = TileArgsT<float>;  // the float32 inner passes of mixed precision
 
 hipError_t launch_tiles(const LevelDesc *desc, const TileGeom &tg, const TileArgs &ta, hipStream_t stream);
 hipError_t launch_tiles_4(const LevelDesc *desc, const TileGeom &tg, const TileArgs &ta, hipStream_t stream);
 hipError_t launch_tiles_8(const LevelDesc *desc, const TileGeom &tg, const TileArgs &ta, hipStream_t stream);
 hipError_t launch_tiles_16(const LevelDesc *desc, const TileGeom &tg, const TileArgs &ta, hipStream_t stream);
+hipError_t launch_tiles32(const LevelDesc *desc, const TileGeom &tg, const TileArgs32 &ta, hipStream_t stream);
+hipError_t launch_tiles_4(const LevelDesc *desc, const TileGeom &tg, const TileArgs32 &ta, hipStream_t stream);
+hipError_t launch_tiles_8(const LevelDesc *desc, const TileGeom &tg, const TileArgs32 &ta, hipStream_t stream);
+hipError_t launch_tiles_16(const LevelDesc *desc, const TileGeom &tg, const TileArgs32 &ta, hipStream_t stream);
 
 // 2D extension (mgrit_2d.hip).  One explicit Runge-Kutta step of the
 // dimension-split operator on a batch of nb [ny][nx] slabs: dst = Phi(src)

@@ -231,6 +231,16 @@ hipError_t launch_tiles(const LevelDesc *desc, const TileGeom &tg, const TileArg
   }
 }
 
+hipError_t launch_tiles32(const LevelDesc *desc, const TileGeom &tg, const TileArgs32 &ta, hipStream_t stream) {
+  if (ta.nint <= 0) return hipSuccess;
+  switch (tg.P) {
+    case 4: return launch_tiles_4(desc, tg, ta, stream);
+    case 8: return launch_tiles_8(desc, tg, ta, stream);
+    case 16: return launch_tiles_16(desc, tg, ta, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_reduce(const double *part, int64_t n, double *out, hipStream_t stream) {
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(RED_T), 0, stream, part, n, out);
   return hipGetLastError();
