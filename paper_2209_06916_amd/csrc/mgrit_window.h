@@ -192,6 +192,20 @@ __device__ __forceinline__ void row_to_lds_async(const double *row, double *vec)
                                      0, 0);
   }
 }
+// The float32 form: a segment is 32 floats, so one instruction per segment
+// with the lower half-wavefront active (an instruction has one LDS base).
+__device__ __forceinline__ void row_to_lds_async(const float *row, float *vec) {
+  const int seg0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~(WAVE - 1)));
+  const int lane = threadIdx.x & (WAVE - 1);
+  const unsigned *src = reinterpret_cast<const unsigned *>(row) + lane;
+  if (lane < WAVE / 2) {
+    for (int i = 0; i < WAVE; ++i) {
+      const int seg = seg0 + i;
+      __builtin_amdgcn_global_load_lds(src + seg * 32, (__attribute__((address_space(3))) void *)(vec + seg * 33), 4,
+                                       0, 0);
+    }
+  }
+}
 
 template <int L, class T, class Step>
 __device__ __forceinline__ void run_chain_slc(const PassArgsT<T> &pa, int nx, T *vec, double *red, bool alias,
@@ -252,16 +266,16 @@ __device__ __forceinline__ void run_chain_slc(const PassArgsT<T> &pa, int nx, T 
   }
   __syncthreads();
 
-  // 32 doubles per thread with separate published states: the right-hand
+  // 32 points per thread with separate published states: the right-hand
   // side goes straight into the vector while the solve runs (issued once
   // every thread is past its gather, added to the result after the solve)
-  const bool direct_g = sizeof(T) == 8 && L == 32 && !alias && add_g;
+  const bool direct_g = L == 32 && !alias && add_g;
   for (int j = 1; j <= nsteps; ++j) {
     const int64_t n = (mode == MODE_SEQ) ? (int64_t)j : b * m + j;  // level point index
     {
       T y[L];
       step(y, [&] {  // every thread is past its gather: the vector's words are free
-        if constexpr (sizeof(T) == 8 && L == 32) {
+        if constexpr (L == 32) {
           if (direct_g) row_to_lds_async(pa.g + (n - 1) * nxl, vec);
         }
       });

@@ -54,6 +54,9 @@ CASES = [
     # ERK kernel)
     dict(nx=1024, nt=4096, p=5, kind="sdirk", q=3, c=0.5, ms=[16, 16]),
     dict(nx=512, nt=2048, p=3, kind="erk", q=3, c=0.85, ms=[8, 8]),
+    # the float32 coarse chain at 32 points per thread (right-hand side
+    # loaded straight into LDS)
+    dict(nx=16384, nt=128, p=5, kind="sdirk", q=3, c=0.5, ms=[16, 4]),
 ]
 
 
