@@ -96,10 +96,8 @@ struct LaneMats {
 // One Kogge-Stone step inside 16-lane rows: add H^D times the state D lanes
 // back in processing order (row_shr forward, row_shl backward; lanes without
 // such a neighbour receive 0 and keep their value).
-template <int K, bool REV, int D, class TP>
-__device__ __forceinline__ void row_step(double (&inc)[K], TP tab) {
-  double M[K * K];
-  ld_mat<K>(tab + D * K * K, M);
+template <int K, bool REV, int D>
+__device__ __forceinline__ void row_step(double (&inc)[K], const double (&M)[K * K]) {
   double o[K];
 #pragma unroll
   for (int m = 0; m < K; ++m) o[m] = REV ? dpp_d<0x100 + D>(inc[m]) : dpp_d<0x110 + D>(inc[m]);
@@ -107,13 +105,24 @@ __device__ __forceinline__ void row_step(double (&inc)[K], TP tab) {
 }
 
 // Periodic recurrence x_i += sum_m a[m] x_{i-1-m} (REV: x_{i+1+m}) over the
-// workgroup's 16-point chunks; pre_barrier() runs just before the barrier.
-template <int L, int K, int NW, bool REV, bool HOIST, class TP, class Hook>
+// workgroup's 16-point chunks; pre_barrier() runs just before the barrier,
+// post_barrier() right after it.
+template <int L, int K, int NW, bool REV, bool HOIST, class TP, class Hook, class PostHook>
 __device__ __forceinline__ void lean_rec(double (&x)[L], const double (&a)[K], TP tab,
-                                         const LaneMats<K, HOIST> &lm, double *Q, Hook pre_barrier) {
+                                         const LaneMats<K, HOIST> &lm, double *Q, Hook pre_barrier,
+                                         PostHook post_barrier) {
   constexpr int KK = K * K;
   constexpr int LH = L / 2;  // two interleaved sub-chains per lane
   const int vl = lm.vl, vw = lm.vw, vrow = vl >> 4;
+  // the scan's wave-uniform matrices, requested before the zero-state pass
+  // so that their scalar loads are in flight together and arrive during it
+  double Mh[KK], M1[KK], M2[KK], M4[KK], M8[KK], M16[KK];
+  ld_mat<K>(tab + TAB_HHALF * KK, Mh);
+  ld_mat<K>(tab + KK, M1);
+  ld_mat<K>(tab + 2 * KK, M2);
+  ld_mat<K>(tab + 4 * KK, M4);
+  ld_mat<K>(tab + 8 * KK, M8);
+  ld_mat<K>(tab + 16 * KK, M16);
   // zero-state passes of both halves (processing order: REV walks down)
   double sa[K], sb[K];
 #pragma unroll
@@ -138,22 +147,20 @@ __device__ __forceinline__ void lean_rec(double (&x)[L], const double (&a)[K], T
     x[ja] = ya;
     x[jb] = yb;
   }
-  double M[KK];
   // chunk total q = Hhalf sa + sb
   double q[K];
 #pragma unroll
   for (int m = 0; m < K; ++m) q[m] = sb[m];
-  ld_mat<K>(tab + TAB_HHALF * KK, M);
-  mv_acc<K>(M, sa, q);
+  mv_acc<K>(Mh, sa, q);
 
   // inclusive scan inside 16-lane rows
   double inc[K];
 #pragma unroll
   for (int m = 0; m < K; ++m) inc[m] = q[m];
-  row_step<K, REV, 1>(inc, tab);
-  row_step<K, REV, 2>(inc, tab);
-  row_step<K, REV, 4>(inc, tab);
-  row_step<K, REV, 8>(inc, tab);
+  row_step<K, REV, 1>(inc, M1);
+  row_step<K, REV, 2>(inc, M2);
+  row_step<K, REV, 4>(inc, M4);
+  row_step<K, REV, 8>(inc, M8);
   // exclusive value in the row, then the row carries (uniform over the
   // wavefront): ex = ex_row + H^{lr} C_row
   double ex[K], C1[K], C2[K], C3[K];
@@ -164,9 +171,8 @@ __device__ __forceinline__ void lean_rec(double (&x)[L], const double (&a)[K], T
     C2[m] = readlane_d(inc[m], REV ? 32 : 31);
     C3[m] = readlane_d(inc[m], REV ? 16 : 47);
   }
-  ld_mat<K>(tab + 16 * KK, M);
-  mv_acc<K>(M, C1, C2);
-  mv_acc<K>(M, C2, C3);
+  mv_acc<K>(M16, C1, C2);
+  mv_acc<K>(M16, C2, C3);
   double cr[K];
 #pragma unroll
   for (int m = 0; m < K; ++m) cr[m] = vrow == 0 ? 0.0 : (vrow == 1 ? C1[m] : (vrow == 2 ? C2[m] : C3[m]));
@@ -180,8 +186,7 @@ __device__ __forceinline__ void lean_rec(double (&x)[L], const double (&a)[K], T
     double tot[K];
 #pragma unroll
     for (int m = 0; m < K; ++m) tot[m] = q[m];
-    ld_mat<K>(tab + KK, M);
-    mv_acc<K>(M, ex, tot);
+    mv_acc<K>(M1, ex, tot);
 #pragma unroll
     for (int m = 0; m < K; ++m) Q[vw * K + m] = tot[m];
     if (vw == NW - 1) {
@@ -192,20 +197,27 @@ __device__ __forceinline__ void lean_rec(double (&x)[L], const double (&a)[K], T
       }
     }
   }
+  // the fold's matrices, requested before the barrier so that they arrive
+  // while it waits
+  double Mw[KK], Mw1[KK], Mlast[KK], Mwrap[KK];
+  ld_mat<K>(tab + WAVE * KK, Mw);
+  ld_mat<K>(tab + (WAVE - 1) * KK, Mw1);
+  ld_mat<K>(tab + TAB_HLAST * KK, Mlast);
+  ld_mat<K>(tab + TAB_WWRAP * KK, Mwrap);
   pre_barrier();
   __syncthreads();
+  post_barrier();
 
   // zero-start carries X_w entering each wavefront; keep X_vw and X_{NW-1}
   double X[K], Xv[K];
 #pragma unroll
   for (int m = 0; m < K; ++m) X[m] = Xv[m] = 0.0;
-  ld_mat<K>(tab + WAVE * KK, M);
 #pragma unroll
   for (int w2 = 0; w2 < NW - 1; ++w2) {
     double nxt[K];
 #pragma unroll
     for (int m = 0; m < K; ++m) nxt[m] = Q[w2 * K + m];
-    mv_acc<K>(M, X, nxt);
+    mv_acc<K>(Mw, X, nxt);
 #pragma unroll
     for (int m = 0; m < K; ++m) {
       X[m] = nxt[m];
@@ -220,12 +232,9 @@ __device__ __forceinline__ void lean_rec(double (&x)[L], const double (&a)[K], T
     tq[m] = Q[(NW + 1) * K + m];
     s0[m] = 0.0;
   }
-  ld_mat<K>(tab + (WAVE - 1) * KK, M);
-  mv_acc<K>(M, X, E);
-  ld_mat<K>(tab + TAB_HLAST * KK, M);
-  mv_acc<K>(M, E, tq);
-  ld_mat<K>(tab + TAB_WWRAP * KK, M);
-  mv_acc<K>(M, tq, s0);
+  mv_acc<K>(Mw1, X, E);
+  mv_acc<K>(Mlast, E, tq);
+  mv_acc<K>(Mwrap, tq, s0);
   // carry into this wavefront, this lane, and both halves of its chunk
   lm.get(2, P);
   mv_acc<K>(P, s0, Xv);
@@ -237,8 +246,7 @@ __device__ __forceinline__ void lean_rec(double (&x)[L], const double (&a)[K], T
   }
   lm.get(1, P);
   mv_acc<K>(P, Xv, ta);
-  ld_mat<K>(tab + TAB_HHALF * KK, M);
-  mv_acc<K>(M, ta, tb);
+  mv_acc<K>(Mh, ta, tb);
   // homogeneous corrections
 #pragma unroll
   for (int e = 0; e < LH; ++e) {
@@ -271,7 +279,7 @@ __device__ __forceinline__ void load_segs(const double *__restrict__ row, double
 }
 
 // One pass (PassMode) of one CF-interval b with the coarse step of `op`.
-// LDS: v the padded vector (it also stages the right-hand-side row), tab_f /
+// LDS: v the padded vector, tab_f /
 // tab_b the scan tables, qf / qb the wavefront totals, red the reduction
 // scratch.  hsrc_f / hsrc_b: where the lane-dependent powers are loaded from.
 // prologue() runs once the first loads are in flight; false ends the pass.
@@ -349,7 +357,9 @@ __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, 
   // of it at the start of a step and reads only its own chunk at the end; the
   // cross-thread reads (gather, parent update) precede the forward
   // recurrence's barrier and the cross-thread writes (right-hand side, in the
-  // backward recurrence's hook) follow it.
+  // backward recurrence's pre-barrier hook) follow it.  Each thread reads its
+  // chunk of the right-hand side back right after the backward recurrence's
+  // barrier, so those reads overlap the carry fold and the corrections.
   // pseg: the pending parent row's segments; in the last step it is refilled
   // with what the epilogue needs (the next parent row, or pass B's C'_{k+1})
   // so that load overlaps the step.
@@ -357,10 +367,22 @@ __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, 
   // ahead (right after the previous row is consumed) so its latency is hidden.
   int64_t pend = -1;  // parent row whose update waits for the next LDS copy
   double2 pseg[L / 2], gseg[L / 2];
+  const unsigned long long ctf_bits = (unsigned long long)ctf, ctb_bits = (unsigned long long)ctb;
+  const unsigned tf_lo = __builtin_amdgcn_readfirstlane((unsigned)ctf_bits);
+  const unsigned tf_hi = __builtin_amdgcn_readfirstlane((unsigned)(ctf_bits >> 32));
+  const unsigned tb_lo = __builtin_amdgcn_readfirstlane((unsigned)ctb_bits);
+  const unsigned tb_hi = __builtin_amdgcn_readfirstlane((unsigned)(ctb_bits >> 32));
   if (mode == MODE_PASS_B && nsteps == 0) load_segs<L, T>(pa.cin + (b + 1) * nxl, pseg);
   if (add_g && nsteps >= 1) load_segs<L, T>(pa.g + ((mode == MODE_SEQ) ? 0 : b * m) * nxl, gseg);
   for (int j = 1; j <= nsteps; ++j) {
     const int64_t n = (mode == MODE_SEQ) ? (int64_t)j : b * m + j;  // level point index
+    // The scan matrices are read afresh in every step: an opaque copy of the
+    // table pointers keeps their scalar loads inside the step, where they are
+    // short-lived, instead of being hoisted out of the loop and spilled.
+    unsigned tfl = tf_lo, tfh = tf_hi, tbl = tb_lo, tbh = tb_hi;
+    asm volatile("" : "+s"(tfl), "+s"(tfh), "+s"(tbl), "+s"(tbh));
+    const ConstTab tf = (ConstTab)(((unsigned long long)tfh << 32) | tfl);
+    const ConstTab tb = (ConstTab)(((unsigned long long)tbh << 32) | tbl);
     if (pend >= 0) load_segs<L, T>(pa.parent + pend * nxl, pseg);
     if (mode == MODE_PASS_B && j == nsteps) load_segs<L, T>(pa.cin + (b + 1) * nxl, pseg);
 #pragma unroll
@@ -382,21 +404,28 @@ __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, 
         if (jj >= 0 && jj < L) y[jj] = fma(w[t], val, y[jj]);
       }
     }
-    lean_rec<L, K, NW, false>(y, af, ctf, lmf, qf, [] {});
-    lean_rec<L, K, NW, true>(y, ab, ctb, lmb, qb, [&] {
-      if (add_g) {  // g_n -> v in chunk order, then fetch the next step's row
+    double gch[L];
+    lean_rec<L, K, NW, false>(y, af, tf, lmf, qf, [] {}, [] {});
+    lean_rec<L, K, NW, true>(
+        y, ab, tb, lmb, qb,
+        [&] {
+          if (add_g) {  // g_n -> v in coalesced segments, then fetch the next step's row
 #pragma unroll
-        for (int q = 0; q < L / 2; ++q) {
-          const int i = 2 * (tid + T * q);
-          v[padix(i)] = gseg[q].x;
-          v[padix(i + 1)] = gseg[q].y;
-        }
-        if (j < nsteps) load_segs<L, T>(pa.g + n * nxl, gseg);
-      }
-    });
+            for (int q = 0; q < L / 2; ++q) {
+              const int i = 2 * (tid + T * q);
+              v[padix(i)] = gseg[q].x;
+              v[padix(i + 1)] = gseg[q].y;
+            }
+            if (j < nsteps) load_segs<L, T>(pa.g + n * nxl, gseg);
+          }
+        },
+        [&] {  // this thread's chunk of g_n (unused without a right-hand side)
+#pragma unroll
+          for (int jj = 0; jj < L; ++jj) gch[jj] = v[padix(base + jj)];
+        });
     if (add_g) {
 #pragma unroll
-      for (int jj = 0; jj < L; ++jj) u[jj] = y[jj] + v[padix(base + jj)];
+      for (int jj = 0; jj < L; ++jj) u[jj] = y[jj] + gch[jj];
     } else {
 #pragma unroll
       for (int jj = 0; jj < L; ++jj) u[jj] = y[jj];
