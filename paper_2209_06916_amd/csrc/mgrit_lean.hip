@@ -104,25 +104,36 @@ __device__ __forceinline__ void row_step(double (&inc)[K], const double (&M)[K *
   mv_acc<K>(M, o, inc);
 }
 
+// The wave-uniform matrices of one direction's in-row scan: M^{L/2} and the
+// chunk transfer powers H, H^2, H^4, H^8, H^16.  The caller requests them
+// well ahead of the scan (their scalar loads then arrive while other work
+// runs) and passes them in.
+template <int K>
+struct ScanMats {
+  double h[K * K], m1[K * K], m2[K * K], m4[K * K], m8[K * K], m16[K * K];
+  template <class TP>
+  __device__ __forceinline__ void load(TP tab) {
+    ld_mat<K>(tab + TAB_HHALF * K * K, h);
+    ld_mat<K>(tab + K * K, m1);
+    ld_mat<K>(tab + 2 * K * K, m2);
+    ld_mat<K>(tab + 4 * K * K, m4);
+    ld_mat<K>(tab + 8 * K * K, m8);
+    ld_mat<K>(tab + 16 * K * K, m16);
+  }
+};
+
 // Periodic recurrence x_i += sum_m a[m] x_{i-1-m} (REV: x_{i+1+m}) over the
 // workgroup's 16-point chunks; pre_barrier() runs just before the barrier,
-// post_barrier() right after it.
-template <int L, int K, int NW, bool REV, bool HOIST, class TP, class Hook, class PostHook>
+// post_barrier() right after it, pre_corr() once the carries are folded
+// (after the last LDS read of the published totals).
+template <int L, int K, int NW, bool REV, bool HOIST, class TP, class Hook, class PostHook, class CorrHook>
 __device__ __forceinline__ void lean_rec(double (&x)[L], const double (&a)[K], TP tab,
-                                         const LaneMats<K, HOIST> &lm, double *Q, Hook pre_barrier,
-                                         PostHook post_barrier) {
+                                         const LaneMats<K, HOIST> &lm, const ScanMats<K> &sm, double *Q,
+                                         Hook pre_barrier, PostHook post_barrier, CorrHook pre_corr) {
   constexpr int KK = K * K;
   constexpr int LH = L / 2;  // two interleaved sub-chains per lane
   const int vl = lm.vl, vw = lm.vw, vrow = vl >> 4;
-  // the scan's wave-uniform matrices, requested before the zero-state pass
-  // so that their scalar loads are in flight together and arrive during it
-  double Mh[KK], M1[KK], M2[KK], M4[KK], M8[KK], M16[KK];
-  ld_mat<K>(tab + TAB_HHALF * KK, Mh);
-  ld_mat<K>(tab + KK, M1);
-  ld_mat<K>(tab + 2 * KK, M2);
-  ld_mat<K>(tab + 4 * KK, M4);
-  ld_mat<K>(tab + 8 * KK, M8);
-  ld_mat<K>(tab + 16 * KK, M16);
+  const auto &Mh = sm.h, &M1 = sm.m1, &M2 = sm.m2, &M4 = sm.m4, &M8 = sm.m8, &M16 = sm.m16;
   // zero-state passes of both halves (processing order: REV walks down)
   double sa[K], sb[K];
 #pragma unroll
@@ -173,9 +184,12 @@ __device__ __forceinline__ void lean_rec(double (&x)[L], const double (&a)[K], T
   }
   mv_acc<K>(M16, C1, C2);
   mv_acc<K>(M16, C2, C3);
+  // the carry into this lane's row (zero in row 0), selected with 0/1
+  // weights: a data-dependent select here would be lowered to branches
+  const double s1 = vrow == 1 ? 1.0 : 0.0, s2 = vrow == 2 ? 1.0 : 0.0, s3 = vrow == 3 ? 1.0 : 0.0;
   double cr[K];
 #pragma unroll
-  for (int m = 0; m < K; ++m) cr[m] = vrow == 0 ? 0.0 : (vrow == 1 ? C1[m] : (vrow == 2 ? C2[m] : C3[m]));
+  for (int m = 0; m < K; ++m) cr[m] = fma(s3, C3[m], fma(s2, C2[m], s1 * C1[m]));
   double P[KK];
   lm.get(0, P);
   mv_acc<K>(P, cr, ex);
@@ -247,6 +261,7 @@ __device__ __forceinline__ void lean_rec(double (&x)[L], const double (&a)[K], T
   lm.get(1, P);
   mv_acc<K>(P, Xv, ta);
   mv_acc<K>(Mh, ta, tb);
+  pre_corr();
   // homogeneous corrections
 #pragma unroll
   for (int e = 0; e < LH; ++e) {
@@ -331,6 +346,11 @@ __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, 
   if (start < 0) start += NX;
   if (mode == MODE_PASS_A && b == 0) store_chunk<L>(pa.cout, base, L, u);
   const bool add_g = pa.g && mode != MODE_APPLY;
+  const double gsc = add_g ? 1.0 : 0.0;
+  // read the right-hand-side chunk right after the backward barrier (its
+  // latency then overlaps the fold); at 8 wavefronts the registers it holds
+  // meanwhile would spill, so it is read at the end there
+  constexpr bool EARLY_G = NW < 8;
   const bool add_parent = mode == MODE_POST_F || (mode == MODE_SEQ && pa.parent);
   if (mode == MODE_POST_F) {
     double pv[L];
@@ -385,6 +405,8 @@ __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, 
     const ConstTab tb = (ConstTab)(((unsigned long long)tbh << 32) | tbl);
     if (pend >= 0) load_segs<L, T>(pa.parent + pend * nxl, pseg);
     if (mode == MODE_PASS_B && j == nsteps) load_segs<L, T>(pa.cin + (b + 1) * nxl, pseg);
+    ScanMats<K> smf, smb;
+    smf.load(tf);  // arrives while the vector is written and the barrier waits
 #pragma unroll
     for (int jj = 0; jj < L; ++jj) v[padix(base + jj)] = u[jj];
     __syncthreads();
@@ -405,9 +427,15 @@ __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, 
       }
     }
     double gch[L];
-    lean_rec<L, K, NW, false>(y, af, tf, lmf, qf, [] {}, [] {});
+    lean_rec<L, K, NW, false>(y, af, tf, lmf, smf, qf, [] {}, [] {}, [&] {
+      // the backward scan's matrices: issued here (the scheduling barrier
+      // keeps the compiler from sinking them to their use), they arrive
+      // during the corrections and the backward zero-state pass
+      smb.load(tb);
+      __builtin_amdgcn_sched_barrier(0);
+    });
     lean_rec<L, K, NW, true>(
-        y, ab, tb, lmb, qb,
+        y, ab, tb, lmb, smb, qb,
         [&] {
           if (add_g) {  // g_n -> v in coalesced segments, then fetch the next step's row
 #pragma unroll
@@ -419,17 +447,21 @@ __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, 
             if (j < nsteps) load_segs<L, T>(pa.g + n * nxl, gseg);
           }
         },
-        [&] {  // this thread's chunk of g_n (unused without a right-hand side)
+        [&] {  // this thread's chunk of g_n (the vector itself without a right-hand side)
+          if constexpr (EARLY_G) {
 #pragma unroll
-          for (int jj = 0; jj < L; ++jj) gch[jj] = v[padix(base + jj)];
-        });
-    if (add_g) {
+            for (int jj = 0; jj < L; ++jj) gch[jj] = v[padix(base + jj)];
+          }
+        },
+        [] {});
+    if constexpr (!EARLY_G) {
 #pragma unroll
-      for (int jj = 0; jj < L; ++jj) u[jj] = y[jj] + gch[jj];
-    } else {
-#pragma unroll
-      for (int jj = 0; jj < L; ++jj) u[jj] = y[jj];
+      for (int jj = 0; jj < L; ++jj) gch[jj] = v[padix(base + jj)];
     }
+    // u = y + g, or y: fma with a 0/1 weight is exact either way (the chunk
+    // read is finite), and no branch lets the reads sink past the corrections
+#pragma unroll
+    for (int jj = 0; jj < L; ++jj) u[jj] = fma(gsc, gch[jj], y[jj]);
     pend = add_parent ? n : -1;
   }
   if (pend >= 0) {  // the last step's parent update (row prefetched into pseg)
