@@ -103,7 +103,11 @@ LEAN_CASES = [(nx, p) for nx in (256, 512, 1024, 2048, 4096, 8192) for p in (1, 
 
 
 @pytest.mark.parametrize("nx,p", LEAN_CASES)
-def test_lean_coarse_steps_match_oracle(nx, p):
+def test_lean_coarse_steps_match_oracle(monkeypatch, nx, p):
+    # the 16-point shapes pinned: by default setup takes 8 points per lane up
+    # to nx = 2048 and the windowed kernel from nx = 8192
+    monkeypatch.setenv("MGRIT_L_COARSE", "16")
+    monkeypatch.setenv("MGRIT_NO_LEAN", "0")
     _announce("lean coarse", nx, p)
     c = {1: 0.85, 3: 1.2, 5: 0.9}[p]
     ms = [8, 16]
