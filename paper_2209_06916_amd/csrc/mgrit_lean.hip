@@ -294,9 +294,9 @@ __device__ __forceinline__ void load_segs(const double *__restrict__ row, double
 }
 
 // One pass (PassMode) of one CF-interval b with the coarse step of `op`.
-// LDS: v the padded vector, tab_f /
-// tab_b the scan tables, qf / qb the wavefront totals, red the reduction
-// scratch.  hsrc_f / hsrc_b: where the lane-dependent powers are loaded from.
+// LDS: v the padded vector, tab_f / tab_b the scan tables, qf / qb the
+// wavefront totals, red the reduction scratch.  hsrc_f / hsrc_b: where the
+// lane-dependent powers are loaded from.
 // prologue() runs once the first loads are in flight; false ends the pass.
 template <int W, int K, int L, int NW, class Prologue>
 __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, int64_t b, double *v, double *tab_f,
