@@ -448,6 +448,10 @@ hipError_t configure_window_kernels32(size_t bytes);
 // lean_slc_applies() holds, and its LDS attribute.
 hipError_t launch_lean(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs &pa,
                        hipStream_t stream);
+// The same kernel in float32 (one launch per pass) for the inner solves of
+// mixed precision; desc holds the float32 copy of the tables.
+hipError_t launch_lean32(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs32 &pa,
+                         hipStream_t stream);
 hipError_t configure_lean_kernels(size_t bytes);
 // The generic step kernel, one translation unit per operator kind.
 hipError_t launch_step_poly_z(const LevelDesc *desc, const Layout &lay, const PassArgs &pa, size_t lds,

@@ -173,6 +173,7 @@ hipError_t configure_kernels(size_t bytes) {
 hipError_t launch_pass32(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs32 &pa,
                          hipStream_t stream) {
   if (pa.nint <= 0) return hipSuccess;
+  if (lean_slc_applies(op, lay)) return launch_lean32(desc, op, lay, pa, stream);
   if (window_applies(op, lay)) return launch_window32(desc, op, lay, pa, stream);
   const size_t lds = lds_bytes_for(lay, op.has_solve);
   switch (op.kind) {

@@ -39,18 +39,32 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
   return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
 }
 
-template <int K, class TP>
-__device__ __forceinline__ void ld_mat(TP p, double (&M)[K * K]) {
+// The same moves for either precision (a float is one 32-bit move).
+template <int CTRL>
+__device__ __forceinline__ double dpp_t(double v) {
+  return dpp_d<CTRL>(v);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_t(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double readlane_t(double v, int lane) { return readlane_d(v, lane); }
+__device__ __forceinline__ float readlane_t(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+template <int K, class TP, class E>
+__device__ __forceinline__ void ld_mat(TP p, E (&M)[K * K]) {
 #pragma unroll
   for (int i = 0; i < K * K; ++i) M[i] = p[i];
 }
 
 // acc += M x (M row-major K x K)
-template <int K>
-__device__ __forceinline__ void mv_acc(const double (&M)[K * K], const double (&x)[K], double (&acc)[K]) {
+template <int K, class E>
+__device__ __forceinline__ void mv_acc(const E (&M)[K * K], const E (&x)[K], E (&acc)[K]) {
 #pragma unroll
   for (int r = 0; r < K; ++r) {
-    double s = acc[r];
+    E s = acc[r];
 #pragma unroll
     for (int c = 0; c < K; ++c) s = fma(M[r * K + c], x[c], s);
     acc[r] = s;
@@ -61,16 +75,16 @@ __device__ __forceinline__ void mv_acc(const double (&M)[K * K], const double (&
 // in the 16-lane row, processing order), H^{vl} (position in the wavefront)
 // and H^{64 vw} (vw = wavefront position).  HOIST keeps them in registers;
 // otherwise they are read from the LDS table where used.
-template <int K, bool HOIST>
+template <int K, bool HOIST, class E>
 struct LaneMats {
   static constexpr int N = HOIST ? K * K : 1;
-  double lr_[N], vl_[N], vw_[N];
-  const double *tab;
+  E lr_[N], vl_[N], vw_[N];
+  const E *tab;
   int lr, vl, vw;
   // t: the LDS copy of the table (read in the loop when not hoisted); src:
   // the same table in device memory (hoisted values are loaded from there, so
   // they do not wait for the LDS copy)
-  __device__ __forceinline__ void init(const double *t, const double *src, int lr0, int vl0, int vw0) {
+  __device__ __forceinline__ void init(const E *t, const E *src, int lr0, int vl0, int vw0) {
     tab = t;
     lr = lr0;
     vl = vl0;
@@ -81,9 +95,9 @@ struct LaneMats {
       ld_mat<K>(src + (TAB_HWAVE + vw) * K * K, vw_);
     }
   }
-  __device__ __forceinline__ void get(int which, double (&M)[K * K]) const {
+  __device__ __forceinline__ void get(int which, E (&M)[K * K]) const {
     if constexpr (HOIST) {
-      const double *src = which == 0 ? lr_ : (which == 1 ? vl_ : vw_);
+      const E *src = which == 0 ? lr_ : (which == 1 ? vl_ : vw_);
 #pragma unroll
       for (int i = 0; i < K * K; ++i) M[i] = src[i];
     } else {
@@ -96,11 +110,11 @@ struct LaneMats {
 // One Kogge-Stone step inside 16-lane rows: add H^D times the state D lanes
 // back in processing order (row_shr forward, row_shl backward; lanes without
 // such a neighbour receive 0 and keep their value).
-template <int K, bool REV, int D>
-__device__ __forceinline__ void row_step(double (&inc)[K], const double (&M)[K * K]) {
-  double o[K];
+template <int K, bool REV, int D, class E>
+__device__ __forceinline__ void row_step(E (&inc)[K], const E (&M)[K * K]) {
+  E o[K];
 #pragma unroll
-  for (int m = 0; m < K; ++m) o[m] = REV ? dpp_d<0x100 + D>(inc[m]) : dpp_d<0x110 + D>(inc[m]);
+  for (int m = 0; m < K; ++m) o[m] = REV ? dpp_t<0x100 + D>(inc[m]) : dpp_t<0x110 + D>(inc[m]);
   mv_acc<K>(M, o, inc);
 }
 
@@ -108,9 +122,9 @@ __device__ __forceinline__ void row_step(double (&inc)[K], const double (&M)[K *
 // chunk transfer powers H, H^2, H^4, H^8, H^16.  The caller requests them
 // well ahead of the scan (their scalar loads then arrive while other work
 // runs) and passes them in.
-template <int K>
+template <int K, class E>
 struct ScanMats {
-  double h[K * K], m1[K * K], m2[K * K], m4[K * K], m8[K * K], m16[K * K];
+  E h[K * K], m1[K * K], m2[K * K], m4[K * K], m8[K * K], m16[K * K];
   template <class TP>
   __device__ __forceinline__ void load(TP tab) {
     ld_mat<K>(tab + TAB_HHALF * K * K, h);
@@ -126,23 +140,23 @@ struct ScanMats {
 // workgroup's 16-point chunks; pre_barrier() runs just before the barrier,
 // post_barrier() right after it, pre_corr() once the carries are folded
 // (after the last LDS read of the published totals).
-template <int L, int K, int NW, bool REV, bool HOIST, class TP, class Hook, class PostHook, class CorrHook>
-__device__ __forceinline__ void lean_rec(double (&x)[L], const double (&a)[K], TP tab,
-                                         const LaneMats<K, HOIST> &lm, const ScanMats<K> &sm, double *Q,
+template <int L, int K, int NW, bool REV, bool HOIST, class E, class TP, class Hook, class PostHook, class CorrHook>
+__device__ __forceinline__ void lean_rec(E (&x)[L], const E (&a)[K], TP tab,
+                                         const LaneMats<K, HOIST, E> &lm, const ScanMats<K, E> &sm, E *Q,
                                          Hook pre_barrier, PostHook post_barrier, CorrHook pre_corr) {
   constexpr int KK = K * K;
   constexpr int LH = L / 2;  // two interleaved sub-chains per lane
   const int vl = lm.vl, vw = lm.vw, vrow = vl >> 4;
   const auto &Mh = sm.h, &M1 = sm.m1, &M2 = sm.m2, &M4 = sm.m4, &M8 = sm.m8, &M16 = sm.m16;
   // zero-state passes of both halves (processing order: REV walks down)
-  double sa[K], sb[K];
+  E sa[K], sb[K];
 #pragma unroll
-  for (int m = 0; m < K; ++m) sa[m] = sb[m] = 0.0;
+  for (int m = 0; m < K; ++m) sa[m] = sb[m] = E(0);
 #pragma unroll
   for (int e = 0; e < LH; ++e) {
     const int ja = REV ? (L - 1 - e) : e;
     const int jb = REV ? (LH - 1 - e) : (LH + e);
-    double ya = x[ja], yb = x[jb];
+    E ya = x[ja], yb = x[jb];
 #pragma unroll
     for (int m = 0; m < K; ++m) {
       ya = fma(a[m], sa[m], ya);
@@ -159,13 +173,13 @@ __device__ __forceinline__ void lean_rec(double (&x)[L], const double (&a)[K], T
     x[jb] = yb;
   }
   // chunk total q = Hhalf sa + sb
-  double q[K];
+  E q[K];
 #pragma unroll
   for (int m = 0; m < K; ++m) q[m] = sb[m];
   mv_acc<K>(Mh, sa, q);
 
   // inclusive scan inside 16-lane rows
-  double inc[K];
+  E inc[K];
 #pragma unroll
   for (int m = 0; m < K; ++m) inc[m] = q[m];
   row_step<K, REV, 1>(inc, M1);
@@ -174,30 +188,30 @@ __device__ __forceinline__ void lean_rec(double (&x)[L], const double (&a)[K], T
   row_step<K, REV, 8>(inc, M8);
   // exclusive value in the row, then the row carries (uniform over the
   // wavefront): ex = ex_row + H^{lr} C_row
-  double ex[K], C1[K], C2[K], C3[K];
+  E ex[K], C1[K], C2[K], C3[K];
 #pragma unroll
   for (int m = 0; m < K; ++m) {
-    ex[m] = REV ? dpp_d<0x101>(inc[m]) : dpp_d<0x111>(inc[m]);
-    C1[m] = readlane_d(inc[m], REV ? 48 : 15);
-    C2[m] = readlane_d(inc[m], REV ? 32 : 31);
-    C3[m] = readlane_d(inc[m], REV ? 16 : 47);
+    ex[m] = REV ? dpp_t<0x101>(inc[m]) : dpp_t<0x111>(inc[m]);
+    C1[m] = readlane_t(inc[m], REV ? 48 : 15);
+    C2[m] = readlane_t(inc[m], REV ? 32 : 31);
+    C3[m] = readlane_t(inc[m], REV ? 16 : 47);
   }
   mv_acc<K>(M16, C1, C2);
   mv_acc<K>(M16, C2, C3);
   // the carry into this lane's row (zero in row 0), selected with 0/1
   // weights: a data-dependent select here would be lowered to branches
-  const double s1 = vrow == 1 ? 1.0 : 0.0, s2 = vrow == 2 ? 1.0 : 0.0, s3 = vrow == 3 ? 1.0 : 0.0;
-  double cr[K];
+  const E s1 = vrow == 1 ? E(1) : E(0), s2 = vrow == 2 ? E(1) : E(0), s3 = vrow == 3 ? E(1) : E(0);
+  E cr[K];
 #pragma unroll
   for (int m = 0; m < K; ++m) cr[m] = fma(s3, C3[m], fma(s2, C2[m], s1 * C1[m]));
-  double P[KK];
+  E P[KK];
   lm.get(0, P);
   mv_acc<K>(P, cr, ex);
 
   // publish the wavefront total (last lane: q + H ex) and, from the last
   // chunk of the vector, its exclusive state and zero-state total
   if (vl == WAVE - 1) {
-    double tot[K];
+    E tot[K];
 #pragma unroll
     for (int m = 0; m < K; ++m) tot[m] = q[m];
     mv_acc<K>(M1, ex, tot);
@@ -213,7 +227,7 @@ __device__ __forceinline__ void lean_rec(double (&x)[L], const double (&a)[K], T
   }
   // the fold's matrices, requested before the barrier so that they arrive
   // while it waits
-  double Mw[KK], Mw1[KK], Mlast[KK], Mwrap[KK];
+  E Mw[KK], Mw1[KK], Mlast[KK], Mwrap[KK];
   ld_mat<K>(tab + WAVE * KK, Mw);
   ld_mat<K>(tab + (WAVE - 1) * KK, Mw1);
   ld_mat<K>(tab + TAB_HLAST * KK, Mlast);
@@ -223,12 +237,12 @@ __device__ __forceinline__ void lean_rec(double (&x)[L], const double (&a)[K], T
   post_barrier();
 
   // zero-start carries X_w entering each wavefront; keep X_vw and X_{NW-1}
-  double X[K], Xv[K];
+  E X[K], Xv[K];
 #pragma unroll
-  for (int m = 0; m < K; ++m) X[m] = Xv[m] = 0.0;
+  for (int m = 0; m < K; ++m) X[m] = Xv[m] = E(0);
 #pragma unroll
   for (int w2 = 0; w2 < NW - 1; ++w2) {
-    double nxt[K];
+    E nxt[K];
 #pragma unroll
     for (int m = 0; m < K; ++m) nxt[m] = Q[w2 * K + m];
     mv_acc<K>(Mw, X, nxt);
@@ -238,21 +252,22 @@ __device__ __forceinline__ void lean_rec(double (&x)[L], const double (&a)[K], T
       Xv[m] = (vw == w2 + 1) ? nxt[m] : Xv[m];
     }
   }
-  // periodic wrap: state entering point 0, s0 = Wwrap (Hlast E + q_last)
-  double E[K], tq[K], s0[K];
+  // periodic wrap: state entering point 0, s0 = Wwrap (Hlast Ex + q_last),
+  // Ex the last chunk's exclusive state
+  E Ex[K], tq[K], s0[K];
 #pragma unroll
   for (int m = 0; m < K; ++m) {
-    E[m] = Q[NW * K + m];
+    Ex[m] = Q[NW * K + m];
     tq[m] = Q[(NW + 1) * K + m];
-    s0[m] = 0.0;
+    s0[m] = E(0);
   }
-  mv_acc<K>(Mw1, X, E);
-  mv_acc<K>(Mlast, E, tq);
+  mv_acc<K>(Mw1, X, Ex);
+  mv_acc<K>(Mlast, Ex, tq);
   mv_acc<K>(Mwrap, tq, s0);
   // carry into this wavefront, this lane, and both halves of its chunk
   lm.get(2, P);
   mv_acc<K>(P, s0, Xv);
-  double ta[K], tb[K];
+  E ta[K], tb[K];
 #pragma unroll
   for (int m = 0; m < K; ++m) {
     ta[m] = ex[m];
@@ -267,7 +282,7 @@ __device__ __forceinline__ void lean_rec(double (&x)[L], const double (&a)[K], T
   for (int e = 0; e < LH; ++e) {
     const int ja = REV ? (L - 1 - e) : e;
     const int jb = REV ? (LH - 1 - e) : (LH + e);
-    double ha = 0.0, hb = 0.0;
+    E ha = E(0), hb = E(0);
 #pragma unroll
     for (int m = 0; m < K; ++m) {
       ha = fma(a[m], ta[m], ha);
@@ -285,12 +300,19 @@ __device__ __forceinline__ void lean_rec(double (&x)[L], const double (&a)[K], T
   }
 }
 
-// Coalesced row segments: thread t owns the 16-byte pairs t + T q, q < L/2.
-template <int L, int T>
-__device__ __forceinline__ void load_segs(const double *__restrict__ row, double2 (&seg)[L / 2]) {
-  const double2 *r2 = reinterpret_cast<const double2 *>(row);
+// Coalesced row segments of 16 bytes (SEG_N elements): thread t of NTH owns
+// the segments t + NTH q, q < L / SEG_N.
+template <class E>
+struct Seg {
+  E e[16 / sizeof(E)];
+};
+template <class E>
+constexpr int SEG_N = 16 / sizeof(E);
+template <int L, int NTH, class E>
+__device__ __forceinline__ void load_segs(const E *__restrict__ row, Seg<E> (&seg)[L / SEG_N<E>]) {
+  const Seg<E> *r = reinterpret_cast<const Seg<E> *>(row);
 #pragma unroll
-  for (int q = 0; q < L / 2; ++q) seg[q] = r2[threadIdx.x + T * q];
+  for (int q = 0; q < L / SEG_N<E>; ++q) seg[q] = r[threadIdx.x + NTH * q];
 }
 
 // One pass (PassMode) of one CF-interval b with the coarse step of `op`.
@@ -298,23 +320,24 @@ __device__ __forceinline__ void load_segs(const double *__restrict__ row, double
 // wavefront totals, red the reduction scratch.  hsrc_f / hsrc_b: where the
 // lane-dependent powers are loaded from.
 // prologue() runs once the first loads are in flight; false ends the pass.
-template <int W, int K, int L, int NW, class Prologue>
-__device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, int64_t b, double *v, double *tab_f,
-                                          double *tab_b, const double *hsrc_f, const double *hsrc_b, double *qf,
-                                          double *qb, double *red, Prologue prologue) {
-  constexpr int T = WAVE * NW;
-  constexpr int NX = L * T;
+template <int W, int K, int L, int NW, class E, class Prologue>
+__device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgsT<E> &pa, int64_t b, E *v, E *tab_f,
+                                          E *tab_b, const E *hsrc_f, const E *hsrc_b, E *qf, E *qb, double *red,
+                                          Prologue prologue) {
+  constexpr int NTH = WAVE * NW;
+  constexpr int NX = L * NTH;
   constexpr bool HOIST = K <= 2;
+  constexpr int SN = SEG_N<E>;
 
   // interpolation weights with the 1/C of the factorisation folded in
-  double w[W], af[K], ab[K];
+  E w[W], af[K], ab[K];
   const double cinv = op.cinv;
 #pragma unroll
-  for (int t = 0; t < W; ++t) w[t] = op.slw[t] * cinv;
+  for (int t = 0; t < W; ++t) w[t] = (E)(op.slw[t] * cinv);
 #pragma unroll
   for (int m = 0; m < K; ++m) {
-    af[m] = op.fw.a[m];
-    ab[m] = op.bw.a[m];
+    af[m] = (E)op.fw.a[m];
+    ab[m] = (E)op.bw.a[m];
   }
   const int tid = threadIdx.x;
   const int base = tid * L;
@@ -324,10 +347,10 @@ __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, 
   const int nsteps = (mode == MODE_POST_F) ? m - 1 : m;  // PASS_A, PASS_B, SEQ, APPLY: m
   const int64_t row0 = (mode == MODE_SEQ) ? 0 : b;
   // start vector (loads issued before the table copy so their latencies overlap)
-  double u[L];
+  E u[L];
   if (pa.zero_init) {
 #pragma unroll
-    for (int j = 0; j < L; ++j) u[j] = 0.0;
+    for (int j = 0; j < L; ++j) u[j] = E(0);
   } else {
     load_chunk<L>(pa.cin + row0 * nxl, base, L, u);
   }
@@ -335,9 +358,9 @@ __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, 
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   // the wave-uniform scan matrices are read through the scalar cache from
   // the device copy of the tables (constant address space)
-  typedef const __attribute__((address_space(4))) double *ConstTab;
+  typedef const __attribute__((address_space(4))) E *ConstTab;
   const ConstTab ctf = (ConstTab)op.fw.tab, ctb = (ConstTab)op.bw.tab;
-  LaneMats<K, HOIST> lmf, lmb;
+  LaneMats<K, HOIST, E> lmf, lmb;
   lmf.init(tab_f, hsrc_f, lane & 15, lane, wave);
   lmb.init(tab_b, hsrc_b, (WAVE - 1 - lane) & 15, WAVE - 1 - lane, NW - 1 - wave);
   if (!prologue()) return;
@@ -346,14 +369,14 @@ __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, 
   if (start < 0) start += NX;
   if (mode == MODE_PASS_A && b == 0) store_chunk<L>(pa.cout, base, L, u);
   const bool add_g = pa.g && mode != MODE_APPLY;
-  const double gsc = add_g ? 1.0 : 0.0;
+  const E gsc = add_g ? E(1) : E(0);
   // read the right-hand-side chunk right after the backward barrier (its
   // latency then overlaps the fold); at 8 wavefronts the registers it holds
   // meanwhile would spill, so it is read at the end there
   constexpr bool EARLY_G = NW < 8;
   const bool add_parent = mode == MODE_POST_F || (mode == MODE_SEQ && pa.parent);
   if (mode == MODE_POST_F) {
-    double pv[L];
+    E pv[L];
     load_chunk<L>(pa.parent + (b * m) * nxl, base, L, pv);
 #pragma unroll
     for (int j = 0; j < L; ++j) pv[j] += u[j];
@@ -361,15 +384,15 @@ __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, 
   }
 
   // parent[prow] += the vector in v, coalesced, with the row's segments in pseg
-  auto parent_update = [&](int64_t prow, const double2 (&pseg)[L / 2]) {
-    double2 *p2 = reinterpret_cast<double2 *>(pa.parent + prow * nxl);
+  auto parent_update = [&](int64_t prow, const Seg<E> (&pseg)[L / SN]) {
+    Seg<E> *p2 = reinterpret_cast<Seg<E> *>(pa.parent + prow * nxl);
 #pragma unroll
-    for (int q = 0; q < L / 2; ++q) {
-      const int i = 2 * (tid + T * q);
-      double2 r = pseg[q];
-      r.x += v[padix(i)];
-      r.y += v[padix(i + 1)];
-      p2[tid + T * q] = r;
+    for (int q = 0; q < L / SN; ++q) {
+      const int i = SN * (tid + NTH * q);
+      Seg<E> r = pseg[q];
+#pragma unroll
+      for (int c = 0; c < SN; ++c) r.e[c] += v[padix(i + c)];
+      p2[tid + NTH * q] = r;
     }
   };
 
@@ -386,14 +409,14 @@ __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, 
   // gseg: the right-hand-side row of the coming step, loaded a whole step
   // ahead (right after the previous row is consumed) so its latency is hidden.
   int64_t pend = -1;  // parent row whose update waits for the next LDS copy
-  double2 pseg[L / 2], gseg[L / 2];
+  Seg<E> pseg[L / SN], gseg[L / SN];
   const unsigned long long ctf_bits = (unsigned long long)ctf, ctb_bits = (unsigned long long)ctb;
   const unsigned tf_lo = __builtin_amdgcn_readfirstlane((unsigned)ctf_bits);
   const unsigned tf_hi = __builtin_amdgcn_readfirstlane((unsigned)(ctf_bits >> 32));
   const unsigned tb_lo = __builtin_amdgcn_readfirstlane((unsigned)ctb_bits);
   const unsigned tb_hi = __builtin_amdgcn_readfirstlane((unsigned)(ctb_bits >> 32));
-  if (mode == MODE_PASS_B && nsteps == 0) load_segs<L, T>(pa.cin + (b + 1) * nxl, pseg);
-  if (add_g && nsteps >= 1) load_segs<L, T>(pa.g + ((mode == MODE_SEQ) ? 0 : b * m) * nxl, gseg);
+  if (mode == MODE_PASS_B && nsteps == 0) load_segs<L, NTH>(pa.cin + (b + 1) * nxl, pseg);
+  if (add_g && nsteps >= 1) load_segs<L, NTH>(pa.g + ((mode == MODE_SEQ) ? 0 : b * m) * nxl, gseg);
   for (int j = 1; j <= nsteps; ++j) {
     const int64_t n = (mode == MODE_SEQ) ? (int64_t)j : b * m + j;  // level point index
     // The scan matrices are read afresh in every step: an opaque copy of the
@@ -403,30 +426,30 @@ __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, 
     asm volatile("" : "+s"(tfl), "+s"(tfh), "+s"(tbl), "+s"(tbh));
     const ConstTab tf = (ConstTab)(((unsigned long long)tfh << 32) | tfl);
     const ConstTab tb = (ConstTab)(((unsigned long long)tbh << 32) | tbl);
-    if (pend >= 0) load_segs<L, T>(pa.parent + pend * nxl, pseg);
-    if (mode == MODE_PASS_B && j == nsteps) load_segs<L, T>(pa.cin + (b + 1) * nxl, pseg);
-    ScanMats<K> smf, smb;
+    if (pend >= 0) load_segs<L, NTH>(pa.parent + pend * nxl, pseg);
+    if (mode == MODE_PASS_B && j == nsteps) load_segs<L, NTH>(pa.cin + (b + 1) * nxl, pseg);
+    ScanMats<K, E> smf, smb;
     smf.load(tf);  // arrives while the vector is written and the barrier waits
 #pragma unroll
     for (int jj = 0; jj < L; ++jj) v[padix(base + jj)] = u[jj];
     __syncthreads();
     if (pend >= 0) parent_update(pend, pseg);
-    if (add_parent && j == nsteps) load_segs<L, T>(pa.parent + n * nxl, pseg);
-    double y[L];
+    if (add_parent && j == nsteps) load_segs<L, NTH>(pa.parent + n * nxl, pseg);
+    E y[L];
 #pragma unroll
-    for (int jj = 0; jj < L; ++jj) y[jj] = 0.0;
+    for (int jj = 0; jj < L; ++jj) y[jj] = E(0);
 #pragma unroll
     for (int e = 0; e < L + W - 1; ++e) {
       int idx = start + e;
       idx = idx >= NX ? idx - NX : idx;
-      const double val = v[padix(idx)];
+      const E val = v[padix(idx)];
 #pragma unroll
       for (int t = 0; t < W; ++t) {
         const int jj = e - t;
         if (jj >= 0 && jj < L) y[jj] = fma(w[t], val, y[jj]);
       }
     }
-    double gch[L];
+    E gch[L];
     lean_rec<L, K, NW, false>(y, af, tf, lmf, smf, qf, [] {}, [] {}, [&] {
       // the backward scan's matrices: issued here (the scheduling barrier
       // keeps the compiler from sinking them to their use), they arrive
@@ -439,12 +462,12 @@ __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, 
         [&] {
           if (add_g) {  // g_n -> v in coalesced segments, then fetch the next step's row
 #pragma unroll
-            for (int q = 0; q < L / 2; ++q) {
-              const int i = 2 * (tid + T * q);
-              v[padix(i)] = gseg[q].x;
-              v[padix(i + 1)] = gseg[q].y;
+            for (int q = 0; q < L / SN; ++q) {
+              const int i = SN * (tid + NTH * q);
+#pragma unroll
+              for (int c = 0; c < SN; ++c) v[padix(i + c)] = gseg[q].e[c];
             }
-            if (j < nsteps) load_segs<L, T>(pa.g + n * nxl, gseg);
+            if (j < nsteps) load_segs<L, NTH>(pa.g + n * nxl, gseg);
           }
         },
         [&] {  // this thread's chunk of g_n (the vector itself without a right-hand side)
@@ -478,23 +501,26 @@ __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, 
 #pragma unroll
     for (int jj = 0; jj < L; ++jj) v[padix(base + jj)] = u[jj];
     __syncthreads();
-    double2 *r2 = reinterpret_cast<double2 *>(pa.r + b * nxl);
-    double ss = 0.0;
+    Seg<E> *r2 = reinterpret_cast<Seg<E> *>(pa.r + b * nxl);
+    double ss = 0.0;  // the partial norms are float64 in both precisions
 #pragma unroll
-    for (int q = 0; q < L / 2; ++q) {
-      const int i = 2 * (tid + T * q);
-      const double2 rr = make_double2(v[padix(i)] - pseg[q].x, v[padix(i + 1)] - pseg[q].y);
-      r2[tid + T * q] = rr;
-      ss = fma(rr.x, rr.x, ss);
-      ss = fma(rr.y, rr.y, ss);
+    for (int q = 0; q < L / SN; ++q) {
+      const int i = SN * (tid + NTH * q);
+      Seg<E> rr;
+#pragma unroll
+      for (int c = 0; c < SN; ++c) {
+        rr.e[c] = v[padix(i + c)] - pseg[q].e[c];
+        ss = fma((double)rr.e[c], (double)rr.e[c], ss);
+      }
+      r2[tid + NTH * q] = rr;
     }
     const double tot = block_sum(ss, red);
     if (tid == 0) pa.normpart[b] = tot;
   } else if (mode == MODE_POST_F) {
     if (b == pa.nint - 1) {
       load_chunk<L>(pa.cin + pa.nint * nxl, base, L, u);
-      double *row = pa.parent + (pa.nint * m) * nxl;
-      double pv[L];
+      E *row = pa.parent + (pa.nint * m) * nxl;
+      E pv[L];
       load_chunk<L>(row, base, L, pv);
 #pragma unroll
       for (int jj = 0; jj < L; ++jj) u[jj] += pv[jj];
@@ -506,15 +532,20 @@ __device__ __forceinline__ void lean_pass(const StepOp &op, const PassArgs &pa, 
   }
 }
 
-template <int W, int K, int L, int NW>
-__global__ void __launch_bounds__(WAVE * NW) slc_kernel(const LevelDesc *__restrict__ desc, PassArgs pa) {
+// One launch per pass (float64, or float32 for the inner solves of mixed
+// precision).  The LDS holds the elements at the offsets of lean_lds_offsets
+// counted in E and the float64 reduction scratch at its float64 offset,
+// which lies past the float32 data.
+template <int W, int K, int L, int NW, class E>
+__global__ void __launch_bounds__(WAVE * NW) slc_kernel(const LevelDesc *__restrict__ desc, PassArgsT<E> pa) {
   extern __shared__ double smem[];
   constexpr LeanLds lo = lean_lds_offsets(L * WAVE * NW, K);
   const StepOp &op = desc->op;
-  double *tab_f = smem + lo.tab_f;
-  double *tab_b = smem + lo.tab_b;
-  const double *gtab_f = static_cast<const double *>(op.fw.tab), *gtab_b = static_cast<const double *>(op.bw.tab);
-  lean_pass<W, K, L, NW>(op, pa, blockIdx.x, smem, tab_f, tab_b, gtab_f, gtab_b, smem + lo.qf, smem + lo.qb,
+  E *sm = reinterpret_cast<E *>(smem);
+  E *tab_f = sm + lo.tab_f;
+  E *tab_b = sm + lo.tab_b;
+  const E *gtab_f = static_cast<const E *>(op.fw.tab), *gtab_b = static_cast<const E *>(op.bw.tab);
+  lean_pass<W, K, L, NW>(op, pa, blockIdx.x, sm, tab_f, tab_b, gtab_f, gtab_b, sm + lo.qf, sm + lo.qb,
                       smem + lo.red, [&] {
                         // Scan tables to LDS.  No barrier here: the first step's
                         // barrier (after the vector is written to LDS) comes
@@ -660,10 +691,10 @@ int coarse_vcycle_grid(size_t lds) {
   return per_cu * cus;
 }
 
-template <int W, int K, int L, int NW>
-hipError_t slc_launch(const LevelDesc *desc, const PassArgs &pa, hipStream_t stream) {
+template <int W, int K, int L, int NW, class E>
+hipError_t slc_launch(const LevelDesc *desc, const PassArgsT<E> &pa, hipStream_t stream) {
   constexpr size_t lds = (size_t)lean_lds_offsets(L * WAVE * NW, K).total * sizeof(double);
-  hipLaunchKernelGGL((slc_kernel<W, K, L, NW>), dim3((unsigned)pa.nint), dim3(WAVE * NW), lds, stream, desc, pa);
+  hipLaunchKernelGGL((slc_kernel<W, K, L, NW, E>), dim3((unsigned)pa.nint), dim3(WAVE * NW), lds, stream, desc, pa);
   return hipGetLastError();
 }
 
@@ -672,12 +703,13 @@ hipError_t slc_launch(const LevelDesc *desc, const PassArgs &pa, hipStream_t str
   X(W, K, 16, 1) X(W, K, 16, 2) X(W, K, 16, 4) X(W, K, 16, 8) X(W, K, 8, 1) X(W, K, 8, 2) X(W, K, 8, 4) \
   X(W, K, 8, 8) X(W, K, 4, 1)
 
-hipError_t slc_launch_any(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs &pa,
+template <class E>
+hipError_t slc_launch_any(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgsT<E> &pa,
                           hipStream_t stream) {
   const int W = op.sl_l + op.sl_r + 1;
   const int key = lean_key(W, op.fw.k, lay.L, lay.nx / (WAVE * lay.L));
 #define MGRIT_SLC_CASE(Wv, Kv, Lv, NWv) \
-  case lean_key(Wv, Kv, Lv, NWv): return slc_launch<Wv, Kv, Lv, NWv>(desc, pa, stream);
+  case lean_key(Wv, Kv, Lv, NWv): return slc_launch<Wv, Kv, Lv, NWv, E>(desc, pa, stream);
   switch (key) {
     MGRIT_LEAN_SHAPES(MGRIT_SLC_CASE, 2, 1)
     MGRIT_LEAN_SHAPES(MGRIT_SLC_CASE, 4, 2)
@@ -689,10 +721,13 @@ hipError_t slc_launch_any(const LevelDesc *desc, const StepOp &op, const Layout 
 
 hipError_t slc_set_lds(size_t bytes) {
   hipError_t e = hipSuccess;
-#define MGRIT_SLC_LDS(Wv, Kv, Lv, NWv)                                                                           \
-  if (e == hipSuccess)                                                                                          \
-    e = hipFuncSetAttribute((const void *)slc_kernel<Wv, Kv, Lv, NWv>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                            (int)bytes);
+#define MGRIT_SLC_LDS(Wv, Kv, Lv, NWv)                                                                    \
+  if (e == hipSuccess)                                                                                   \
+    e = hipFuncSetAttribute((const void *)slc_kernel<Wv, Kv, Lv, NWv, double>,                             \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);                       \
+  if (e == hipSuccess)                                                                                   \
+    e = hipFuncSetAttribute((const void *)slc_kernel<Wv, Kv, Lv, NWv, float>,                              \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   MGRIT_LEAN_SHAPES(MGRIT_SLC_LDS, 2, 1)
   MGRIT_LEAN_SHAPES(MGRIT_SLC_LDS, 4, 2)
   MGRIT_LEAN_SHAPES(MGRIT_SLC_LDS, 6, 3)
@@ -719,6 +754,11 @@ hipError_t slc_set_lds(size_t bytes) {
 
 hipError_t launch_lean(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs &pa,
                        hipStream_t stream) {
+  return slc_launch_any(desc, op, lay, pa, stream);
+}
+
+hipError_t launch_lean32(const LevelDesc *desc, const StepOp &op, const Layout &lay, const PassArgs32 &pa,
+                         hipStream_t stream) {
   return slc_launch_any(desc, op, lay, pa, stream);
 }
 
