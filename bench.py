@@ -151,6 +151,9 @@ PROFILE_COMMANDS = {
     "sq": "rocprofv3 --pmc SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_INSTS_VALU "
           "SQ_ACTIVE_INST_VALU SQ_INSTS_LDS --output-format csv -d <dir>/sq -o run -- "
           "python3 bench.py --steps 1 --warmup 0 --traffic-probe",
+    "sq2": "rocprofv3 --pmc SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_INSTS_VALU "
+           "SQ_ACTIVE_INST_VALU SQ_INSTS_LDS --output-format csv -d <dir>/sq2 -o run -- "
+           "python3 bench.py --steps 1 --warmup 0 --traffic-probe --probe-workload config2",
 }
 SQ_COUNTERS = ["SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_INSTS_VALU",
                "SQ_ACTIVE_INST_VALU", "SQ_INSTS_LDS"]
@@ -160,6 +163,41 @@ SERVE_WORKLOAD = "served-advection1d-512-requests"
 def _short(name):
     name = name.replace("void ", "").replace("mgrit::(anonymous namespace)::", "")
     return name.split("(")[0]
+
+
+def _write_sq_summary(sq_csv, prof_dir, wl_name, what, command):
+    """profiles/counters_<workload>.txt from one rocprofv3 --pmc run of the SQ counters."""
+    import csv
+    per = {}
+    for r in csv.DictReader(open(sq_csv)):
+        k = _short(r["Kernel_Name"])
+        if k.startswith("at::") or k.startswith("__amd"):
+            continue
+        key = (r.get("Dispatch_Id") or r.get("Correlation_Id"), r["Counter_Name"])
+        per.setdefault(k, {}).setdefault(r["Counter_Name"], {})
+        per[k][r["Counter_Name"]][key[0]] = per[k][r["Counter_Name"]].get(key[0], 0.0) + float(r["Counter_Value"])
+    lines = [f"# rocprofv3 SQ counters -- workload {wl_name}",
+             f"# ({what}, no warm-up; values summed over the device per dispatch, then averaged over",
+             "# dispatches; wave-cycle counters as the hardware counts them)",
+             "# command (repository root on the GPU box, after cd /tmp && export TMPDIR=/tmp):",
+             "#   " + command,
+             "#", "# kernel: dispatches; " + ", ".join(SQ_COUNTERS) + " (per dispatch)",
+             "#   derived: VALU and LDS instructions per wavefront; WAIT_ANY / WAVE_CYCLES (any wait);",
+             "#   WAIT_INST_ANY / WAVE_CYCLES (dependency waits); ACTIVE_INST_VALU / WAVE_CYCLES (VALU issue)"]
+    for k, cs in sorted(per.items()):
+        avg = {c: float(np.mean(list(cs[c].values()))) for c in SQ_COUNTERS if c in cs}
+        nd = max(len(v) for v in cs.values())
+        lines.append(f"  {k}: {nd} dispatches; " + ", ".join(f"{avg.get(c, float('nan')):.4g}" for c in SQ_COUNTERS))
+        w = avg.get("SQ_WAVES", 0.0)
+        wc = avg.get("SQ_WAVE_CYCLES", 0.0)
+        if w > 0 and wc > 0:
+            lines.append(f"    VALU/wave {avg.get('SQ_INSTS_VALU', 0.0) / w:.0f}, LDS/wave "
+                         f"{avg.get('SQ_INSTS_LDS', 0.0) / w:.0f}, any wait "
+                         f"{avg.get('SQ_WAIT_ANY', 0.0) / wc:.2f}, dependency waits "
+                         f"{avg.get('SQ_WAIT_INST_ANY', 0.0) / wc:.2f}, VALU issue "
+                         f"{avg.get('SQ_ACTIVE_INST_VALU', 0.0) / wc:.2f} of wave-cycles")
+    with open(os.path.join(prof_dir, f"counters_{wl_name}.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
 
 
 def summarize_profiles(d):
@@ -227,37 +265,11 @@ def summarize_profiles(d):
         with open(os.path.join(prof_dir, f"kernel_stats_{SERVE_WORKLOAD}.txt"), "w") as fh:
             fh.write("\n".join(lines) + "\n")
 
-    sq_csv = os.path.join(d, "sq", "run_counter_collection.csv")
-    if os.path.exists(sq_csv):
-        per = {}
-        for r in csv.DictReader(open(sq_csv)):
-            k = _short(r["Kernel_Name"])
-            if k.startswith("at::") or k.startswith("__amd"):
-                continue
-            key = (r.get("Dispatch_Id") or r.get("Correlation_Id"), r["Counter_Name"])
-            per.setdefault(k, {}).setdefault(r["Counter_Name"], {})
-            per[k][r["Counter_Name"]][key[0]] = per[k][r["Counter_Name"]].get(key[0], 0.0) + float(r["Counter_Value"])
-        lines = [f"# rocprofv3 SQ counters -- workload {WORKLOAD}",
-                 "# (one MGRIT solve, no warm-up; values summed over the device per dispatch, then averaged over",
-                 "# dispatches; wave-cycle counters as the hardware counts them)",
-                 "# command (repository root on the GPU box, after cd /tmp && export TMPDIR=/tmp):",
-                 "#   " + PROFILE_COMMANDS["sq"].replace("<dir>", "gpurun_out/prof"),
-                 "#", "# kernel: dispatches; " + ", ".join(SQ_COUNTERS) + " (per dispatch)",
-                 "#   derived: VALU and LDS instructions per wavefront; WAIT_INST_ANY / WAVE_CYCLES (dependency",
-                 "#   waits); ACTIVE_INST_VALU / WAVE_CYCLES (VALU issue)"]
-        for k, cs in sorted(per.items()):
-            avg = {c: float(np.mean(list(cs[c].values()))) for c in SQ_COUNTERS if c in cs}
-            nd = max(len(v) for v in cs.values())
-            lines.append(f"  {k}: {nd} dispatches; " + ", ".join(f"{avg.get(c, float('nan')):.4g}" for c in SQ_COUNTERS))
-            w = avg.get("SQ_WAVES", 0.0)
-            wc = avg.get("SQ_WAVE_CYCLES", 0.0)
-            if w > 0 and wc > 0:
-                lines.append(f"    VALU/wave {avg.get('SQ_INSTS_VALU', 0.0) / w:.0f}, LDS/wave "
-                             f"{avg.get('SQ_INSTS_LDS', 0.0) / w:.0f}, dependency waits "
-                             f"{avg.get('SQ_WAIT_INST_ANY', 0.0) / wc:.2f}, VALU issue "
-                             f"{avg.get('SQ_ACTIVE_INST_VALU', 0.0) / wc:.2f} of wave-cycles")
-        with open(os.path.join(prof_dir, f"counters_{WORKLOAD}.txt"), "w") as fh:
-            fh.write("\n".join(lines) + "\n")
+    for sub, wl_name, what in (("sq", WORKLOAD, "one MGRIT solve"),
+                               ("sq2", WORKLOADS["config2"]["name"], "one MGRIT solve of config 2")):
+        sq_csv = os.path.join(d, sub, "run_counter_collection.csv")
+        if os.path.exists(sq_csv):
+            _write_sq_summary(sq_csv, prof_dir, wl_name, what, PROFILE_COMMANDS[sub].replace("<dir>", "gpurun_out/prof"))
 
     if not (os.path.exists(os.path.join(d, "fetch", "run_counter_collection.csv")) and
             os.path.exists(os.path.join(d, "write", "run_counter_collection.csv"))):
@@ -733,6 +745,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline workload (no mixed-precision and 4096 x 4096 keys); with --serve: "
                          "no mixed-precision stream")
+    ap.add_argument("--probe-workload", choices=sorted(WORKLOADS), default="config3",
+                    help="the workload the --traffic-probe solves run (default: the headline)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for hardware-counter runs: a few solves plus one elementwise copy of "
                          "COPY_BYTES read + COPY_BYTES written (the counter calibration)")
@@ -771,6 +785,7 @@ def main():
 
     wl = HEADLINE
     if args.traffic_probe:
+        wl = WORKLOADS[args.probe_workload]
         from paper_2209_06916_amd import inputs, mgrit
         dev = torch.device("cuda:0")
         u0 = inputs.u0_fourier(wl["nx"], wl["seed"])
