@@ -1,7 +1,8 @@
 // gfx950 kernel for the coarse-level time step of MGRIT (Sec. 2.2 with the
 // corrected semi-Lagrangian operator, eqs. MOL-SL-corrected and
-// MOL-SL-corrected-multilevel) on vectors of 64 L NW points: L = 16 with
-// NW = 1, 2, 4, 8 wavefronts, and one wavefront with L = 4 or 8.
+// MOL-SL-corrected-multilevel) on vectors of 64 L NW points: L = 16 or 8
+// with NW = 1, 2, 4, 8 wavefronts, and one wavefront with L = 4; in float64,
+// and in float32 for the inner solves of mixed precision.
 #include "mgrit_internal.h"
 
 namespace mgrit {
@@ -303,7 +304,7 @@ __device__ __forceinline__ void lean_rec(E (&x)[L], const E (&a)[K], TP tab,
 // Coalesced row segments of 16 bytes (SEG_N elements): thread t of NTH owns
 // the segments t + NTH q, q < L / SEG_N.
 template <class E>
-struct Seg {
+struct alignas(16) Seg {
   E e[16 / sizeof(E)];
 };
 template <class E>
