@@ -57,6 +57,11 @@ CASES = [
     # the float32 coarse chain at 32 points per thread (right-hand side
     # loaded straight into LDS)
     dict(nx=16384, nt=128, p=5, kind="sdirk", q=3, c=0.5, ms=[16, 4]),
+    # the float32 lean coarse kernel at 16 points on 4 wavefronts and 8
+    # points on 4 wavefronts, and the windowed coarse kernel at nx = 8192
+    dict(nx=4096, nt=256, p=3, kind="erk", q=3, c=0.85, ms=[8, 8]),
+    dict(nx=2048, nt=256, p=5, kind="erk", q=5, c=0.9, ms=[4, 4, 4]),
+    dict(nx=8192, nt=128, p=3, kind="erk", q=3, c=0.85, ms=[4, 4]),
 ]
 
 
